@@ -1,0 +1,188 @@
+/*
+ * morph.h - C ABI of the MI355X (gfx950) grayscale morphology library.
+ *
+ * Erosion and dilation of a 2-D image by a rectangular w_x-by-w_y structuring
+ * element (Limonova et al., arXiv:2002.09474, §2 Eq. (1) and the sentence after
+ * it), computed separably as a vertical 1-D pass and a horizontal 1-D pass
+ * (§1, §5).  Each pass runs either a direct sliding min/max (the paper's
+ * "linear" pass, §5.1.2 and §5.2.2) or van Herk/Gil-Werman prefix/suffix
+ * extrema (§5.1.1, §5.2.1); a per-pass window threshold picks between them
+ * (§5.3).  Both passes run in one kernel through an LDS tile.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Layout: row-major, H rows of W elements, `pitch` BYTES between the starts of
+ *   consecutive rows, the same pitch for src and dst.  x is the column (contiguous
+ *   in memory), y the row.  Elements are uint8 (unsuffixed names, the paper's
+ *   8-bit type) or uint16 (`_u16` names).
+ * Window: w_x columns by w_y rows, w >= 1, no upper bound.  The rectangle for
+ *   output (x, y) covers columns x - anchor_x .. x - anchor_x + w_x - 1 and rows
+ *   y - anchor_y .. y - anchor_y + w_y - 1.  anchor in [0, w-1], or -1 for the
+ *   placement of Eq. (1): anchor = w - 1 - floor(w / 2) (the centre for odd w).
+ * Border: MORPH_BORDER_NEUTRAL only: pixels outside the image count as the
+ *   identity of the operation (the type's maximum for erosion, 0 for dilation),
+ *   i.e. the extremum is taken over the in-image part of the rectangle.
+ * Pointers: device pointers (hipMalloc / torch allocations) on the current
+ *   device.  src and dst byte ranges must not overlap (MORPH_EALIAS).  uint16
+ *   pointers and pitch must be 2-byte aligned.  Any other alignment is accepted;
+ *   4-byte aligned rows take the faster load/store path.
+ * Ownership: the caller owns src, dst and workspace and keeps them alive until
+ *   the stream has passed the enqueued work.  The library keeps no pointer after
+ *   a call returns, and the single-image entry points allocate nothing.
+ * Streams and errors: arguments are checked before anything is enqueued; on an
+ *   error nothing is enqueued.  Kernels are enqueued on `stream` (0 = the null
+ *   stream) and the call returns without synchronizing.  A failed launch returns
+ *   MORPH_EHIP and morph_last_hip_error() gives the hipError_t (per thread).
+ *   Device faults surface at the caller's next synchronization.  Calls on
+ *   distinct streams may run concurrently from different threads.
+ * Empty images (H == 0 or W == 0) are a no-op returning MORPH_OK.
+ */
+#ifndef MORPH_H
+#define MORPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MORPH_OK 0
+#define MORPH_EINVAL (-1)       /* bad size, pitch, window, anchor or null pointer */
+#define MORPH_EALIAS (-2)       /* src and dst byte ranges overlap */
+#define MORPH_EUNSUPPORTED (-3) /* border rule or dtype not supported */
+#define MORPH_EHIP (-4)         /* a HIP call failed; see morph_last_hip_error() */
+#define MORPH_ENOMEM (-5)       /* workspace too small / device table too small */
+
+/* border rules */
+#define MORPH_BORDER_NEUTRAL 0
+
+/* operations (morph_apply, batch descriptors) */
+#define MORPH_OP_ERODE 0
+#define MORPH_OP_DILATE 1
+#define MORPH_OP_OPEN 2  /* dilate(erode(src)), same rectangle and anchor (§2) */
+#define MORPH_OP_CLOSE 3 /* erode(dilate(src)), same rectangle and anchor (§2) */
+
+/* element types */
+#define MORPH_U8 0
+#define MORPH_U16 1
+
+/* per-pass method (morph_plan) */
+#define MORPH_METHOD_AUTO 0
+#define MORPH_METHOD_DIRECT 1 /* sliding min/max, O(w) per pixel (§5.1.2, §5.2.2) */
+#define MORPH_METHOD_VHGW 2   /* van Herk/Gil-Werman, O(1) per pixel (§5.1.1, §5.2.1) */
+
+/* Optional launch plan.  Fields left 0 are filled from the tuning table.
+ * method_x / method_y force the horizontal / vertical pass algorithm (a window of
+ * 1 always skips its pass); tile_w / tile_h set the output tile of one workgroup
+ * (tile_w a multiple of 4, tile_h a multiple of 2).  A plan never changes the
+ * result, only how it is computed. */
+typedef struct morph_plan {
+    int32_t method_x;
+    int32_t method_y;
+    int32_t tile_w;
+    int32_t tile_h;
+} morph_plan;
+
+/* Erosion, uint8 (§2 Eq. (1)).  See the conventions above for every argument. */
+int morph_erode(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                int anchor_x, int anchor_y, int border, hipStream_t stream);
+/* Dilation, uint8: Eq. (1) with max in place of min (§2). */
+int morph_dilate(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                 int anchor_x, int anchor_y, int border, hipStream_t stream);
+/* uint16 siblings (the paper covers 8-bit only; the definition is unchanged). */
+int morph_erode_u16(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                    int anchor_x, int anchor_y, int border, hipStream_t stream);
+int morph_dilate_u16(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                     int anchor_x, int anchor_y, int border, hipStream_t stream);
+
+/* Bytes of device workspace that morph_open / morph_close need for an image of
+ * this shape: one intermediate image with the same pitch (H * pitch bytes).
+ * Returns 0 for an empty image. */
+size_t morph_workspace_bytes(int H, int W, size_t pitch, int elem_bytes);
+
+/* Opening and closing (§2: compositions of erosion and dilation).  The
+ * intermediate image goes to `workspace` (at least morph_workspace_bytes(),
+ * else MORPH_ENOMEM), which must not overlap src or dst (MORPH_EALIAS). */
+int morph_open(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+               int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+               hipStream_t stream);
+int morph_close(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                hipStream_t stream);
+int morph_open_u16(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                   int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                   hipStream_t stream);
+int morph_close_u16(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                    int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* General entry: any op (MORPH_OP_*) and dtype (MORPH_U8 / MORPH_U16) with an
+ * optional plan (NULL = tuned defaults).  workspace is needed only for OPEN and
+ * CLOSE.  The named entry points above are this call with plan = NULL. */
+int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
+                int wx, int wy, int anchor_x, int anchor_y, int border,
+                const morph_plan *plan, void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---- batched persistent launch --------------------------------------------
+ * Many images of uneven sizes, windows and ops in one launch of a persistent
+ * kernel whose workgroups take tiles from an atomic work queue.  Not in the
+ * paper (which handles one image at a time); it applies the same per-image
+ * computation, so every image's result equals its single-image call. */
+typedef struct morph_desc {
+    const void *src;
+    void *dst;
+    int32_t H, W;
+    int64_t pitch;   /* bytes */
+    int32_t wx, wy;
+    int32_t ax, ay;  /* -1 = Eq. (1) placement */
+    int32_t op;      /* MORPH_OP_ERODE or MORPH_OP_DILATE */
+    int32_t dtype;   /* MORPH_U8 or MORPH_U16 */
+} morph_desc;
+
+typedef struct morph_batch *morph_batch_t;
+
+/* Create a batch object able to hold up to max_images descriptors and max_tiles
+ * tiles in total.  It owns small device tables (descriptors, tile prefix sums,
+ * a queue counter) allocated here, once; nothing is allocated per launch. */
+int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out);
+/* Validate n descriptors (as the single-image calls do; overlapping src/dst of one
+ * descriptor -> MORPH_EALIAS), plan their tiles and copy the tables to the device
+ * on `stream` (the host copy is staged in pinned memory owned by the batch; do
+ * not call set again before the previous enqueue on that stream has been
+ * issued).  Too many images or tiles -> MORPH_ENOMEM. */
+int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream);
+/* Enqueue the whole batch on `stream`: reset the queue counter and launch the
+ * persistent kernel.  The first call on a stream captures both into a hipGraph
+ * that later calls replay.  workspace / ws_bytes are reserved (pass NULL, 0). */
+int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream);
+/* Number of tiles of the current batch (after morph_batch_set), or -1. */
+int64_t morph_batch_tiles(morph_batch_t b);
+/* Free the device tables and graphs.  The caller must have synchronized. */
+int morph_batch_destroy(morph_batch_t b);
+
+/* ---- misc ------------------------------------------------------------------ */
+/* Load a tuning table (JSON written by the autotuner) replacing the current one:
+ * per-dtype direct/vHGW thresholds and tile shapes per window bucket, e.g.
+ *   {"u8": {"t_x": 5, "t_y": 5, "tiles": [{"wmax": 16, "tw": 128, "tb": 64}, ...]}}
+ * A dtype missing from the file keeps its table.  NULL restores the built-in
+ * defaults.  A malformed file returns MORPH_EINVAL and changes nothing. */
+int morph_load_tuning(const char *json_path);
+/* Current per-pass direct->vHGW thresholds for a dtype (direct when w <= t). */
+int morph_get_thresholds(int dtype, int *t_x, int *t_y);
+/* Override the thresholds (for sweeps); t <= 0 leaves a value unchanged. */
+int morph_set_thresholds(int dtype, int t_x, int t_y);
+/* Resolve the plan the library would use for these arguments (after threshold
+ * and tuning lookup); fills *plan with concrete methods and tile shape. */
+int morph_resolve_plan(int dtype, int H, int W, int wx, int wy, morph_plan *plan);
+const char *morph_strerror(int status);
+int morph_last_hip_error(void);
+/* Library version string. */
+const char *morph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MORPH_H */

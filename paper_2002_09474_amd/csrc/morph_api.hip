@@ -1,0 +1,607 @@
+// Host side of the HIP morphology library: argument checks, per-pass method
+// choice (direct below a window threshold, van Herk/Gil-Werman above it, the
+// paper's hybrid of §5.3), tile planning, launches, open/close compositions, the
+// batched persistent launch and the tuning table.
+#include "../../include/morph.h"
+#include "morph_internal.h"
+
+#include <algorithm>
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace morph;
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e)
+{
+    g_last_hip_error = (int)e;
+    return MORPH_EHIP;
+}
+
+// ---------------- tuning table ----------------
+struct TileRule {
+    int wmax; // applies when max(wx, wy) <= wmax
+    int tw, tb;
+};
+
+struct DtypeTuning {
+    int t_x, t_y; // direct when w <= t (per pass)
+    std::vector<TileRule> tiles;
+};
+
+std::mutex g_tuning_mu;
+const DtypeTuning k_builtin_tuning[2] = {
+    {5, 5, {{4, 128, 64}, {16, 128, 64}, {64, 256, 64}, {1 << 30, 256, 32}}},
+    {5, 5, {{4, 128, 64}, {16, 128, 64}, {64, 256, 64}, {1 << 30, 256, 32}}},
+};
+DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
+
+DtypeTuning tuning_for(int dtype)
+{
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    return g_tuning[dtype];
+}
+
+// Minimal JSON reader for the tuning file (objects, arrays, numbers, strings).
+struct JVal {
+    enum Kind { NUL, NUM, STR, ARR, OBJ } k = NUL;
+    double num = 0;
+    std::string str;
+    std::vector<JVal> arr;
+    std::map<std::string, JVal> obj;
+};
+
+struct JParser {
+    const char *p, *e;
+    bool ok = true;
+    void ws()
+    {
+        while (p < e && std::isspace((unsigned char)*p)) p++;
+    }
+    bool parse(JVal &v)
+    {
+        ws();
+        if (p >= e) return false;
+        if (*p == '{') {
+            v.k = JVal::OBJ;
+            p++;
+            ws();
+            if (p < e && *p == '}') { p++; return true; }
+            for (;;) {
+                JVal key;
+                ws();
+                if (!parse(key) || key.k != JVal::STR) return false;
+                ws();
+                if (p >= e || *p != ':') return false;
+                p++;
+                JVal val;
+                if (!parse(val)) return false;
+                v.obj[key.str] = val;
+                ws();
+                if (p < e && *p == ',') { p++; continue; }
+                if (p < e && *p == '}') { p++; return true; }
+                return false;
+            }
+        }
+        if (*p == '[') {
+            v.k = JVal::ARR;
+            p++;
+            ws();
+            if (p < e && *p == ']') { p++; return true; }
+            for (;;) {
+                JVal el;
+                if (!parse(el)) return false;
+                v.arr.push_back(el);
+                ws();
+                if (p < e && *p == ',') { p++; continue; }
+                if (p < e && *p == ']') { p++; return true; }
+                return false;
+            }
+        }
+        if (*p == '"') {
+            v.k = JVal::STR;
+            p++;
+            while (p < e && *p != '"') {
+                if (*p == '\\' && p + 1 < e) p++;
+                v.str.push_back(*p++);
+            }
+            if (p >= e) return false;
+            p++;
+            return true;
+        }
+        if (!std::strncmp(p, "null", 4)) { p += 4; v.k = JVal::NUL; return true; }
+        if (!std::strncmp(p, "true", 4)) { p += 4; v.k = JVal::NUM; v.num = 1; return true; }
+        if (!std::strncmp(p, "false", 5)) { p += 5; v.k = JVal::NUM; v.num = 0; return true; }
+        char *end = nullptr;
+        v.num = std::strtod(p, &end);
+        if (end == p) return false;
+        v.k = JVal::NUM;
+        p = end;
+        return true;
+    }
+};
+
+bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
+{
+    if (o.k != JVal::OBJ) return false;
+    auto it = o.obj.find("t_x");
+    if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_x = (int)it->second.num;
+    it = o.obj.find("t_y");
+    if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_y = (int)it->second.num;
+    it = o.obj.find("tiles");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::ARR) return false;
+        std::vector<TileRule> rules;
+        for (const JVal &r : it->second.arr) {
+            if (r.k != JVal::OBJ) return false;
+            auto w = r.obj.find("wmax"), a = r.obj.find("tw"), b = r.obj.find("tb");
+            if (w == r.obj.end() || a == r.obj.end() || b == r.obj.end()) return false;
+            TileRule tr{(int)w->second.num, (int)a->second.num, (int)b->second.num};
+            if (tr.tw < 4 || tr.tw % 4 || tr.tb < 2 || tr.tb % 2) return false;
+            rules.push_back(tr);
+        }
+        std::sort(rules.begin(), rules.end(),
+                  [](const TileRule &x, const TileRule &y) { return x.wmax < y.wmax; });
+        if (!rules.empty()) {
+            rules.back().wmax = std::max(rules.back().wmax, 1 << 30);
+            t.tiles = rules;
+        }
+    }
+    return t.t_x >= 1 && t.t_y >= 1;
+}
+
+// ---------------- planning ----------------
+size_t elem_bytes(int dtype) { return dtype == MORPH_U16 ? 2 : 1; }
+
+int check_image(int dtype, const void *src, const void *dst, int H, int W, size_t pitch, int wx,
+                int wy, int ax, int ay, int border)
+{
+    if (dtype != MORPH_U8 && dtype != MORPH_U16) return MORPH_EUNSUPPORTED;
+    if (border != MORPH_BORDER_NEUTRAL) return MORPH_EUNSUPPORTED;
+    if (H < 0 || W < 0) return MORPH_EINVAL;
+    if (wx < 1 || wy < 1) return MORPH_EINVAL;
+    if (ax < -1 || ax >= wx || ay < -1 || ay >= wy) return MORPH_EINVAL;
+    if (H == 0 || W == 0) return MORPH_OK;
+    const size_t es = elem_bytes(dtype);
+    if (!src || !dst) return MORPH_EINVAL;
+    if (pitch < (size_t)W * es || pitch % es) return MORPH_EINVAL;
+    if (pitch > (size_t)1 << 40) return MORPH_EINVAL;
+    if (es == 2 && (((uintptr_t)src | (uintptr_t)dst) & 1)) return MORPH_EINVAL;
+    return MORPH_OK;
+}
+
+bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+size_t image_span(int H, int W, size_t pitch, int dtype)
+{
+    return (size_t)(H - 1) * pitch + (size_t)W * elem_bytes(dtype);
+}
+
+int default_anchor(int w) { return w - 1 - w / 2; }
+
+// Fill a TileJob for one erosion/dilation.  Windows are clipped to the image: with
+// anchor a and right extent r = w - 1 - a, only min(a, W-1) columns to the left and
+// min(r, W-1) to the right can ever be inside the image.
+int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch, int wx,
+             int wy, int ax, int ay, const morph_plan *plan, TileJob &j)
+{
+    if (ax < 0) ax = default_anchor(wx);
+    if (ay < 0) ay = default_anchor(wy);
+    const int axe = std::min(ax, W - 1), rxe = std::min(wx - 1 - ax, W - 1);
+    const int aye = std::min(ay, H - 1), rye = std::min(wy - 1 - ay, H - 1);
+    j.src = (const uint8_t *)src;
+    j.dst = (uint8_t *)dst;
+    j.H = H;
+    j.W = W;
+    j.pitch = (int64_t)pitch;
+    j.wx = axe + rxe + 1;
+    j.wy = aye + rye + 1;
+    j.ax = axe;
+    j.ay = aye;
+    j.op = op;
+    j.dtype = dtype;
+
+    const DtypeTuning tu = tuning_for(dtype);
+    const int mx = plan ? plan->method_x : MORPH_METHOD_AUTO;
+    const int my = plan ? plan->method_y : MORPH_METHOD_AUTO;
+    if (mx < 0 || mx > 2 || my < 0 || my > 2) return MORPH_EINVAL;
+    // horizontal pass
+    if (j.wx == 1) j.hm = PASS_NONE;
+    else if (mx == MORPH_METHOD_DIRECT) j.hm = PASS_DIRECT;
+    else if (mx == MORPH_METHOD_VHGW) j.hm = PASS_VHGW;
+    else j.hm = (j.wx <= std::min(tu.t_x, kDirectMax)) ? PASS_DIRECT : PASS_VHGW;
+    // vertical pass (a window of 1 is the direct pass's plain load)
+    if (j.wy == 1) j.vm = PASS_DIRECT;
+    else if (my == MORPH_METHOD_DIRECT) j.vm = PASS_DIRECT;
+    else if (my == MORPH_METHOD_VHGW) j.vm = PASS_VHGW;
+    else j.vm = (j.wy <= std::min(tu.t_y, kDirectMax)) ? PASS_DIRECT : PASS_VHGW;
+    if ((j.hm == PASS_DIRECT && j.wx > kDirectMax) || (j.vm == PASS_DIRECT && j.wy > kDirectMax))
+        return MORPH_EUNSUPPORTED;
+
+    // tile shape
+    int tw = plan && plan->tile_w > 0 ? plan->tile_w : 0;
+    int tb = plan && plan->tile_h > 0 ? plan->tile_h : 0;
+    if ((tw && tw % 4) || (tb && tb % 2)) return MORPH_EINVAL;
+    if (!tw || !tb) {
+        const int wm = std::max(j.wx, j.wy);
+        for (const TileRule &r : tu.tiles)
+            if (wm <= r.wmax) {
+                if (!tw) tw = r.tw;
+                if (!tb) tb = r.tb;
+                break;
+            }
+        if (!tw) tw = 128;
+        if (!tb) tb = 64;
+    }
+    const int w4 = (W + 3) & ~3;
+    tw = std::min(tw, std::max(4, w4));
+    tb = std::min(tb, std::max(2, (H + 1) & ~1));
+    const bool user_tile = plan && (plan->tile_w > 0 || plan->tile_h > 0);
+    for (;;) {
+        j.TW = tw;
+        j.TB = tb;
+        j.SA = ((tw + j.wx - 1 + 3) & ~3) + 1;
+        j.SB = (j.hm == PASS_NONE) ? 0 : ((tw + 3) & ~3) + 1;
+        const int lds = lds_bytes(j);
+        if (lds <= 64 * 1024) break;
+        if (user_tile && lds <= kMaxLdsBytes) break;
+        if (tb > 2) {
+            tb = std::max(2, (tb / 2) & ~1);
+        } else if (lds <= kMaxLdsBytes) {
+            break;
+        } else if (tw > 4) {
+            tw = std::max(4, (tw / 2) & ~3);
+        } else {
+            return MORPH_EUNSUPPORTED; // the window's row segment does not fit in LDS
+        }
+    }
+    j.tiles_x = (W + j.TW - 1) / j.TW;
+    j.tiles_y = (H + j.TB - 1) / j.TB;
+    return MORPH_OK;
+}
+
+int run_single(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch, int wx,
+               int wy, int ax, int ay, const morph_plan *plan, hipStream_t stream)
+{
+    TileJob j;
+    int rc = plan_job(op, dtype, src, dst, H, W, pitch, wx, wy, ax, ay, plan, j);
+    if (rc != MORPH_OK) return rc;
+    hipError_t e = launch_tile_job(j, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return MORPH_OK;
+}
+
+} // namespace
+
+// ---------------- C ABI ----------------
+extern "C" {
+
+int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
+                int wx, int wy, int anchor_x, int anchor_y, int border, const morph_plan *plan,
+                void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    if (op < MORPH_OP_ERODE || op > MORPH_OP_CLOSE) return MORPH_EINVAL;
+    int rc = check_image(dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, border);
+    if (rc != MORPH_OK || H == 0 || W == 0) return rc;
+    const size_t span = image_span(H, W, pitch, dtype);
+    if (ranges_overlap(src, span, dst, span)) return MORPH_EALIAS;
+    if (op == MORPH_OP_ERODE || op == MORPH_OP_DILATE)
+        return run_single(op, dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
+                          stream);
+    // opening = dilate(erode(src)), closing = erode(dilate(src)) (§2)
+    if (!workspace || ws_bytes < morph_workspace_bytes(H, W, pitch, (int)elem_bytes(dtype)))
+        return MORPH_ENOMEM;
+    if (ranges_overlap(workspace, span, src, span) || ranges_overlap(workspace, span, dst, span))
+        return MORPH_EALIAS;
+    const int first = (op == MORPH_OP_OPEN) ? MORPH_OP_ERODE : MORPH_OP_DILATE;
+    rc = run_single(first, dtype, src, workspace, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
+                    stream);
+    if (rc != MORPH_OK) return rc;
+    return run_single(1 - first, dtype, workspace, dst, H, W, pitch, wx, wy, anchor_x, anchor_y,
+                      plan, stream);
+}
+
+#define MORPH_SINGLE(name, op, dt)                                                            \
+    int name(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy, int ax,   \
+             int ay, int border, hipStream_t stream)                                          \
+    {                                                                                          \
+        return morph_apply(op, dt, src, dst, H, W, pitch, wx, wy, ax, ay, border, nullptr,    \
+                           nullptr, 0, stream);                                                \
+    }
+MORPH_SINGLE(morph_erode, MORPH_OP_ERODE, MORPH_U8)
+MORPH_SINGLE(morph_dilate, MORPH_OP_DILATE, MORPH_U8)
+MORPH_SINGLE(morph_erode_u16, MORPH_OP_ERODE, MORPH_U16)
+MORPH_SINGLE(morph_dilate_u16, MORPH_OP_DILATE, MORPH_U16)
+#undef MORPH_SINGLE
+
+#define MORPH_COMPOSED(name, op, dt)                                                          \
+    int name(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy, int ax,   \
+             int ay, int border, void *ws, size_t ws_bytes, hipStream_t stream)               \
+    {                                                                                          \
+        return morph_apply(op, dt, src, dst, H, W, pitch, wx, wy, ax, ay, border, nullptr,    \
+                           ws, ws_bytes, stream);                                              \
+    }
+MORPH_COMPOSED(morph_open, MORPH_OP_OPEN, MORPH_U8)
+MORPH_COMPOSED(morph_close, MORPH_OP_CLOSE, MORPH_U8)
+MORPH_COMPOSED(morph_open_u16, MORPH_OP_OPEN, MORPH_U16)
+MORPH_COMPOSED(morph_close_u16, MORPH_OP_CLOSE, MORPH_U16)
+#undef MORPH_COMPOSED
+
+size_t morph_workspace_bytes(int H, int W, size_t pitch, int elem_bytes_)
+{
+    (void)elem_bytes_;
+    if (H <= 0 || W <= 0) return 0;
+    return (size_t)H * pitch;
+}
+
+int morph_load_tuning(const char *json_path)
+{
+    if (!json_path) {
+        std::lock_guard<std::mutex> lk(g_tuning_mu);
+        g_tuning[0] = k_builtin_tuning[0];
+        g_tuning[1] = k_builtin_tuning[1];
+        return MORPH_OK;
+    }
+    FILE *f = std::fopen(json_path, "rb");
+    if (!f) return MORPH_EINVAL;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    JVal root;
+    JParser jp{text.data(), text.data() + text.size()};
+    if (!jp.parse(root) || root.k != JVal::OBJ) return MORPH_EINVAL;
+    DtypeTuning next[2];
+    {
+        std::lock_guard<std::mutex> lk(g_tuning_mu);
+        next[0] = g_tuning[0];
+        next[1] = g_tuning[1];
+    }
+    const char *keys[2] = {"u8", "u16"};
+    for (int d = 0; d < 2; d++) {
+        auto it = root.obj.find(keys[d]);
+        if (it != root.obj.end() && !read_dtype_tuning(it->second, next[d])) return MORPH_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning[0] = next[0];
+    g_tuning[1] = next[1];
+    return MORPH_OK;
+}
+
+int morph_get_thresholds(int dtype, int *t_x, int *t_y)
+{
+    if (dtype != MORPH_U8 && dtype != MORPH_U16) return MORPH_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    if (t_x) *t_x = g_tuning[dtype].t_x;
+    if (t_y) *t_y = g_tuning[dtype].t_y;
+    return MORPH_OK;
+}
+
+int morph_set_thresholds(int dtype, int t_x, int t_y)
+{
+    if (dtype != MORPH_U8 && dtype != MORPH_U16) return MORPH_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    if (t_x > 0) g_tuning[dtype].t_x = t_x;
+    if (t_y > 0) g_tuning[dtype].t_y = t_y;
+    return MORPH_OK;
+}
+
+int morph_resolve_plan(int dtype, int H, int W, int wx, int wy, morph_plan *plan)
+{
+    if (!plan || H <= 0 || W <= 0 || wx < 1 || wy < 1) return MORPH_EINVAL;
+    if (dtype != MORPH_U8 && dtype != MORPH_U16) return MORPH_EUNSUPPORTED;
+    TileJob j;
+    const morph_plan in = *plan;
+    int rc = plan_job(MORPH_OP_ERODE, dtype, (const void *)16, (void *)16, H, W,
+                      (size_t)W * elem_bytes(dtype), wx, wy, -1, -1, &in, j);
+    if (rc != MORPH_OK) return rc;
+    plan->method_x = j.hm == PASS_NONE ? MORPH_METHOD_AUTO
+                                       : (j.hm == PASS_DIRECT ? MORPH_METHOD_DIRECT : MORPH_METHOD_VHGW);
+    plan->method_y = (j.wy == 1) ? MORPH_METHOD_AUTO
+                                 : (j.vm == PASS_DIRECT ? MORPH_METHOD_DIRECT : MORPH_METHOD_VHGW);
+    plan->tile_w = j.TW;
+    plan->tile_h = j.TB;
+    return MORPH_OK;
+}
+
+const char *morph_strerror(int status)
+{
+    switch (status) {
+    case MORPH_OK: return "ok";
+    case MORPH_EINVAL: return "invalid argument";
+    case MORPH_EALIAS: return "source and destination overlap";
+    case MORPH_EUNSUPPORTED: return "unsupported border, dtype or window";
+    case MORPH_EHIP: return "HIP call failed";
+    case MORPH_ENOMEM: return "workspace or table too small";
+    default: return "unknown status";
+    }
+}
+
+int morph_last_hip_error(void) { return g_last_hip_error; }
+
+const char *morph_version(void) { return "morph-gfx950 0.1"; }
+
+// ---------------- batched persistent launch ----------------
+struct morph_batch {
+    int max_images = 0;
+    int64_t max_tiles = 0;
+    TileJob *d_jobs = nullptr;
+    int64_t *d_tile_start = nullptr;
+    unsigned long long *d_counter = nullptr;
+    TileJob *h_jobs = nullptr;       // pinned staging
+    int64_t *h_tile_start = nullptr; // pinned staging
+    int n = 0;
+    int64_t n_tiles = -1;
+    int lds = 0;
+    int grid = 0;
+    // captured graph (reset kernel + persistent kernel), valid for one stream and
+    // one (n, n_tiles, lds, grid)
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t graph_stream = nullptr;
+    int g_n = -1, g_lds = -1, g_grid = -1;
+    int64_t g_tiles = -1;
+};
+
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 256;
+    return cus > 0 ? cus : 256;
+}
+
+int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
+{
+    if (!out || max_images < 1 || max_tiles < 1) return MORPH_EINVAL;
+    *out = nullptr;
+    morph_batch *b = new morph_batch();
+    b->max_images = max_images;
+    b->max_tiles = max_tiles;
+    hipError_t e;
+    if ((e = hipMalloc((void **)&b->d_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_tile_start, sizeof(int64_t) * (max_images + 1))) !=
+            hipSuccess ||
+        (e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * (max_images + 1))) !=
+            hipSuccess) {
+        morph_batch_destroy(b);
+        return hip_fail(e);
+    }
+    *out = b;
+    return MORPH_OK;
+}
+
+int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream)
+{
+    if (!b || n < 0 || (n > 0 && !descs)) return MORPH_EINVAL;
+    if (n > b->max_images) return MORPH_ENOMEM;
+    int64_t tiles = 0;
+    int lds = 0, m = 0;
+    for (int i = 0; i < n; i++) {
+        const morph_desc &d = descs[i];
+        if (d.op != MORPH_OP_ERODE && d.op != MORPH_OP_DILATE) return MORPH_EINVAL;
+        if (d.pitch < 0) return MORPH_EINVAL;
+        int rc = check_image(d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, d.wx, d.wy, d.ax,
+                             d.ay, MORPH_BORDER_NEUTRAL);
+        if (rc != MORPH_OK) return rc;
+        if (d.H == 0 || d.W == 0) continue;
+        const size_t span = image_span(d.H, d.W, (size_t)d.pitch, d.dtype);
+        if (ranges_overlap(d.src, span, d.dst, span)) return MORPH_EALIAS;
+        TileJob j;
+        rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, d.wx, d.wy, d.ax,
+                      d.ay, nullptr, j);
+        if (rc != MORPH_OK) return rc;
+        b->h_tile_start[m] = tiles;
+        b->h_jobs[m++] = j;
+        tiles += (int64_t)j.tiles_x * j.tiles_y;
+        lds = std::max(lds, lds_bytes(j));
+    }
+    if (tiles > b->max_tiles) return MORPH_ENOMEM;
+    b->h_tile_start[m] = tiles;
+    b->n = m;
+    b->n_tiles = tiles;
+    b->lds = lds;
+    const int per_cu = std::max(1, std::min(8, kMaxLdsBytes / std::max(lds + 64, 1)));
+    b->grid = (int)std::min<int64_t>((int64_t)device_cus() * per_cu, std::max<int64_t>(tiles, 1));
+    hipError_t e;
+    if (m > 0) {
+        if ((e = hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(TileJob) * m, hipMemcpyHostToDevice,
+                                stream)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipMemcpyAsync(b->d_tile_start, b->h_tile_start, sizeof(int64_t) * (m + 1),
+                                hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(e);
+    }
+    return MORPH_OK;
+}
+
+__global__ void morph_reset_counter(unsigned long long *c) { *c = 0ull; }
+
+int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    (void)workspace;
+    (void)ws_bytes;
+    if (!b || b->n_tiles < 0) return MORPH_EINVAL;
+    if (b->n_tiles == 0) return MORPH_OK;
+    const bool reuse = b->exec && b->graph_stream == stream && b->g_n == b->n &&
+                       b->g_tiles == b->n_tiles && b->g_lds == b->lds && b->g_grid == b->grid;
+    hipError_t e;
+    if (stream == nullptr) {
+        // the legacy null stream cannot be captured: launch directly
+        BatchTables t{b->d_jobs, b->d_tile_start, b->n, b->n_tiles, b->d_counter};
+        hipLaunchKernelGGL(morph_reset_counter, dim3(1), dim3(1), 0, stream, b->d_counter);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+        if ((e = launch_batch(t, b->grid, b->lds, stream)) != hipSuccess) return hip_fail(e);
+        return MORPH_OK;
+    }
+    if (!reuse) {
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->graph) {
+            (void)hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        BatchTables t{b->d_jobs, b->d_tile_start, b->n, b->n_tiles, b->d_counter};
+        if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e);
+        hipLaunchKernelGGL(morph_reset_counter, dim3(1), dim3(1), 0, stream, b->d_counter);
+        hipError_t le = hipGetLastError();
+        if (le == hipSuccess) le = launch_batch(t, b->grid, b->lds, stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(stream, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(le);
+        }
+        if (e != hipSuccess) return hip_fail(e);
+        b->graph = g;
+        if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            b->exec = nullptr;
+            return hip_fail(e);
+        }
+        b->graph_stream = stream;
+        b->g_n = b->n;
+        b->g_tiles = b->n_tiles;
+        b->g_lds = b->lds;
+        b->g_grid = b->grid;
+    }
+    if ((e = hipGraphLaunch(b->exec, stream)) != hipSuccess) return hip_fail(e);
+    return MORPH_OK;
+}
+
+int64_t morph_batch_tiles(morph_batch_t b) { return b ? b->n_tiles : -1; }
+
+int morph_batch_destroy(morph_batch_t b)
+{
+    if (!b) return MORPH_EINVAL;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->d_tile_start) (void)hipFree(b->d_tile_start);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+    if (b->h_tile_start) (void)hipHostFree(b->h_tile_start);
+    delete b;
+    return MORPH_OK;
+}
+
+} // extern "C"

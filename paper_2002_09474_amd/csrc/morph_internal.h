@@ -1,0 +1,49 @@
+// Internal declarations shared by the host planner and the kernels of the HIP
+// morphology library.  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace morph {
+
+constexpr int kThreads = 256;  // threads per workgroup of every kernel
+constexpr int kDirectMax = 16; // largest window the direct (sliding) passes take
+constexpr int kMaxLdsBytes = 160 * 1024;
+
+enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2 };
+
+// One image as the tile kernels see it.  Windows and anchors are the effective
+// ones: both extents of the rectangle are clipped to the image size, which does
+// not change any result (pixels beyond the far edge never take part).
+struct TileJob {
+    const uint8_t *src;
+    uint8_t *dst;
+    int32_t H, W;
+    int64_t pitch;   // bytes
+    int32_t wx, wy;  // effective window
+    int32_t ax, ay;  // effective anchors
+    int32_t TW, TB;  // output tile: TW columns (multiple of 4), TB rows (even)
+    int32_t tiles_x, tiles_y;
+    int32_t SA, SB;  // LDS row-pair strides in dwords (odd)
+    int32_t vm, hm;  // PassMode of the vertical / horizontal pass
+    int32_t op;      // 0 erode, 1 dilate
+    int32_t dtype;   // 0 u8, 1 u16
+};
+
+inline int lds_bytes(const TileJob &j) { return (j.TB / 2) * (j.SA + j.SB) * 4; }
+
+// kernels (morph_kernels.hip)
+hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);
+
+// persistent batch kernel
+struct BatchTables {
+    const TileJob *jobs;       // device array of jobs
+    const int64_t *tile_start; // device prefix sums of tiles per job (n + 1 entries)
+    int32_t n_jobs;
+    int64_t n_tiles;
+    unsigned long long *counter; // device work-queue counter
+};
+hipError_t launch_batch(const BatchTables &t, int grid, int lds, hipStream_t stream);
+int batch_kernel_max_lds();
+
+} // namespace morph

@@ -1,0 +1,132 @@
+"""The C-ABI boundary without a GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before anything touches the device
+(validation runs first, so fake pointers never reach HIP)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_2002_09474_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "morph.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(morph_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_matches_exports():
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+FAKE_SRC = 0x10000
+FAKE_DST = 0x20000000
+
+
+def _erode(src=FAKE_SRC, dst=FAKE_DST, H=8, W=8, pitch=8, wx=3, wy=3, ax=-1, ay=-1, border=0):
+    return _lib.lib().morph_erode(src, dst, H, W, pitch, wx, wy, ax, ay, border, None)
+
+
+def test_validation_errors():
+    E = _lib
+    assert _erode(H=-1) == E.MORPH_EINVAL
+    assert _erode(W=-3) == E.MORPH_EINVAL
+    assert _erode(wx=0) == E.MORPH_EINVAL
+    assert _erode(wy=0) == E.MORPH_EINVAL
+    assert _erode(ax=3) == E.MORPH_EINVAL
+    assert _erode(ay=-2) == E.MORPH_EINVAL
+    assert _erode(pitch=7) == E.MORPH_EINVAL
+    assert _erode(src=0) == E.MORPH_EINVAL
+    assert _erode(border=1) == E.MORPH_EUNSUPPORTED
+    assert _erode(dst=FAKE_SRC + 7 * 8) == E.MORPH_EALIAS      # last row overlaps
+    assert _erode(H=0, src=0, dst=0) == E.MORPH_OK              # empty image: no-op
+    assert _erode(W=0) == E.MORPH_OK
+    L = _lib.lib()
+    # uint16 rows must be 2-byte aligned, pitch a multiple of 2
+    assert L.morph_erode_u16(FAKE_SRC + 1, FAKE_DST, 8, 8, 16, 3, 3, -1, -1, 0, None) == E.MORPH_EINVAL
+    assert L.morph_dilate_u16(FAKE_SRC, FAKE_DST, 8, 8, 17, 3, 3, -1, -1, 0, None) == E.MORPH_EINVAL
+    assert L.morph_dilate_u16(FAKE_SRC, FAKE_DST, 8, 8, 15, 3, 3, -1, -1, 0, None) == E.MORPH_EINVAL
+    # bad op / dtype through the general entry
+    assert L.morph_apply(7, 0, FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, None, 0,
+                         None) == E.MORPH_EINVAL
+    assert L.morph_apply(0, 5, FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, None, 0,
+                         None) == E.MORPH_EUNSUPPORTED
+
+
+def test_open_close_workspace_checks():
+    L = _lib.lib()
+    E = _lib
+    assert L.morph_workspace_bytes(8, 8, 8, 1) == 64
+    assert L.morph_workspace_bytes(0, 8, 8, 1) == 0
+    ws = 0x40000000
+    assert L.morph_open(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, 0, None) == E.MORPH_ENOMEM
+    assert L.morph_close(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, ws, 63, None) == E.MORPH_ENOMEM
+    assert L.morph_open(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, FAKE_SRC + 8, 64,
+                        None) == E.MORPH_EALIAS
+    assert L.morph_close_u16(FAKE_SRC, FAKE_DST, 8, 8, 16, 3, 3, -1, -1, 0, FAKE_DST - 16, 128,
+                             None) == E.MORPH_EALIAS
+
+
+def test_forced_direct_beyond_its_range_is_unsupported():
+    p = _lib.Plan(_lib.METHOD_DIRECT, 0, 0, 0)
+    rc = _lib.lib().morph_apply(0, 0, FAKE_SRC, FAKE_DST, 64, 64, 64, 17, 1, -1, -1, 0,
+                                ctypes.byref(p), None, 0, None)
+    assert rc == _lib.MORPH_EUNSUPPORTED
+    p = _lib.Plan(0, 0, 6, 0)  # tile width must be a multiple of 4
+    rc = _lib.lib().morph_apply(0, 0, FAKE_SRC, FAKE_DST, 64, 64, 64, 3, 3, -1, -1, 0,
+                                ctypes.byref(p), None, 0, None)
+    assert rc == _lib.MORPH_EINVAL
+
+
+def test_plan_resolution_and_thresholds(tmp_path):
+    import paper_2002_09474_amd as morph
+    t0 = morph.get_thresholds("u8")
+    try:
+        morph.set_thresholds("u8", 9, 7)
+        assert morph.get_thresholds("u8") == (9, 7)
+        p = morph.resolve_plan("u8", 1080, 1920, 9, 9)
+        assert p["method_x"] == "direct" and p["method_y"] == "vhgw"
+        p = morph.resolve_plan("u8", 1080, 1920, 7, 7)
+        assert p["method_x"] == "direct" and p["method_y"] == "direct"
+        # a window of 1 skips the pass
+        assert morph.resolve_plan("u8", 100, 100, 1, 31)["method_x"] is None
+        # windows are clipped to the image: 255x1 on a 4-wide image is a 7-wide window
+        p = morph.resolve_plan("u8", 4, 4, 255, 1, method_x="direct")
+        assert p["method_x"] == "direct"
+        # a tuning file replaces thresholds and tiles
+        f = tmp_path / "t.json"
+        f.write_text(json.dumps({"u8": {"t_x": 3, "t_y": 4, "tiles": [
+            {"wmax": 8, "tw": 64, "tb": 32}, {"wmax": 1000000, "tw": 128, "tb": 16}]}}))
+        morph.load_tuning(str(f))
+        assert morph.get_thresholds("u8") == (3, 4)
+        p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
+        assert (p["tile_w"], p["tile_h"]) == (64, 32)
+        p = morph.resolve_plan("u8", 1000, 1000, 30, 30)
+        assert (p["tile_w"], p["tile_h"]) == (128, 16)
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"u8": {"t_x": 3, "tiles": [{"wmax": 8, "tw": 6, "tb": 32}]}}')
+        with pytest.raises(morph.MorphError):
+            morph.load_tuning(str(bad))
+        with pytest.raises(morph.MorphError):
+            morph.load_tuning(str(tmp_path / "missing.json"))
+    finally:
+        assert _lib.lib().morph_load_tuning(None) == 0  # built-in defaults back
+        morph.set_thresholds("u8", *t0)
+
+
+def test_strerror():
+    L = _lib.lib()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert L.morph_strerror(s)
+    assert L.morph_strerror(-99) == b"unknown status"

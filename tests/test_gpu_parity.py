@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for
+bit (min/max of integers has exactly one correct result), on seeded inputs at
+sizes that span several tiles with ragged edges, with each pass method forced so
+the threshold cannot hide a bug, at the full benchmark sizes, and on the edge
+cases (tiny and empty images, windows larger than the image, off-centre and
+even-window anchors, odd pitches and unaligned rows, values 0 and max)."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2002_09474_amd as morph  # noqa: E402
+from paper_2002_09474_amd import synth  # noqa: E402
+from gpuutil import empty_like_dev, to_dev, to_host  # noqa: E402
+
+OPN = {"erode": oracle.ERODE, "dilate": oracle.DILATE}
+
+
+def _ref(img, op, wx, wy, ax=-1, ay=-1):
+    return oracle.morph(img, OPN[op], wx, wy, ax, ay, method="hybrid", thresholds=(16, 16),
+                        nthreads=8)
+
+
+def _gpu(img, op, wx, wy, ax=-1, ay=-1, **kw):
+    d, _ = to_dev(img)
+    out = morph.apply(op, d, wx, wy, ax, ay, **kw)
+    torch.cuda.synchronize()
+    return to_host(out)
+
+
+def _check(img, op, wx, wy, ax=-1, ay=-1, **kw):
+    got = _gpu(img, op, wx, wy, ax, ay, **kw)
+    want = _ref(img, op, wx, wy, ax, ay)
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        y, x = bad[0]
+        raise AssertionError("mismatch %s %dx%d a=(%d,%d) %s shape=%s at (%d,%d): got %d want %d "
+                             "(%d bad)" % (op, wx, wy, ax, ay, kw, img.shape, y, x, got[y, x],
+                                           want[y, x], len(bad)))
+
+
+SHAPES = [(1, 1), (1, 7), (7, 1), (2, 3), (3, 2), (15, 17), (16, 16), (17, 15), (63, 65),
+          (64, 64), (65, 63), (129, 257), (200, 131)]
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_small_shapes_all_methods(dtype):
+    rng = np.random.default_rng(100)
+    for i, (H, W) in enumerate(SHAPES):
+        img = synth.uniform(H, W, dtype, seed=200 + i)
+        img.flat[0] = 0
+        img.flat[-1] = np.iinfo(dtype).max
+        for wx, wy in ((1, 1), (3, 3), (2, 5), (7, 4), (16, 1), (1, 16), (5, 13)):
+            ax = int(rng.integers(-1, wx))
+            ay = int(rng.integers(-1, wy))
+            for op in ("erode", "dilate"):
+                for mx, my in (("direct", "direct"), ("vhgw", "vhgw"), ("direct", "vhgw"),
+                               ("vhgw", "direct")):
+                    _check(img, op, wx, wy, ax, ay, method_x=mx, method_y=my)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_every_window_1_to_64_both_methods(axis):
+    img = synth.document(150, 333, seed=21, n_rect=60)
+    for w in range(1, 65):
+        wx, wy = (w, 1) if axis == "x" else (1, w)
+        for op in ("erode", "dilate"):
+            methods = ("vhgw",) if w > 16 else ("direct", "vhgw")
+            for m in methods:
+                kw = {"method_x": m} if axis == "x" else {"method_y": m}
+                _check(img, op, wx, wy, **kw)
+
+
+def test_all_anchors_and_even_windows():
+    img = synth.uniform(70, 90, np.uint8, seed=22)
+    for w in (2, 4, 6, 9, 20):
+        for a in sorted({0, 1, w // 2, w - 1}):
+            for m in ("direct", "vhgw") if w <= 16 else ("vhgw",):
+                _check(img, "erode", w, 3, a, 1, method_x=m)
+                _check(img, "dilate", 3, w, 0, a, method_y=m)
+
+
+def test_windows_larger_than_image():
+    img = synth.uniform(40, 50, np.uint16, seed=23)
+    for wx, wy, ax, ay in ((101, 101, -1, -1), (255, 1, -1, -1), (1, 255, -1, -1),
+                           (99, 97, 0, 96), (120, 3, 119, 0), (3, 300, 1, 0)):
+        for op in ("erode", "dilate"):
+            _check(img, op, wx, wy, ax, ay)
+    # the whole image under every window: a constant
+    g = _gpu(img, "erode", 99, 79)
+    assert (g == img.min()).all()
+
+
+@pytest.mark.parametrize("tile", [(4, 2), (8, 6), (128, 64), (256, 32), (64, 128)])
+def test_tile_shapes_do_not_change_results(tile):
+    img = synth.document(157, 203, seed=24, n_rect=40)
+    for wx, wy in ((3, 3), (15, 9), (31, 31), (2, 40)):
+        for op in ("erode", "dilate"):
+            _check(img, op, wx, wy, tile=tile)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_pitch_offset_and_guard_bytes(dtype):
+    """Strided rows, a base pointer off by one element, and sentinel bytes around
+    the image and in the pitch gap that must stay untouched."""
+    img = synth.uniform(45, 61, dtype, seed=25)
+    for pitch, off in ((61, 0), (64, 0), (67, 1), (80, 3), (61, 1)):
+        src, _ = to_dev(img, pitch_elems=pitch, offset_elems=off)
+        for wx, wy in ((3, 3), (9, 1), (1, 21), (33, 5)):
+            for op in ("erode", "dilate"):
+                out, buf = empty_like_dev(src)
+                before = to_host(buf).copy()
+                morph.apply(op, src, wx, wy, out=out)
+                torch.cuda.synchronize()
+                got = to_host(out)
+                assert np.array_equal(got, _ref(img, op, wx, wy)), (pitch, off, wx, wy, op)
+                after = to_host(buf)
+                mask = np.ones(after.shape, bool)
+                rows = off + np.arange(45)[:, None] * pitch + np.arange(61)[None, :]
+                mask[rows.ravel()] = False
+                assert np.array_equal(after[mask], before[mask]), "bytes outside the image changed"
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_open_close(dtype):
+    img = synth.document(130, 170, seed=26, n_rect=30)
+    if dtype == np.uint16:
+        img = img.astype(np.uint16) * 257
+    for w in (3, 5, 15, 31):
+        for op, f in (("open", oracle.opening), ("close", oracle.closing)):
+            got = _gpu(img, op, w, w)
+            want = f(img, w, w, method="hybrid", thresholds=(16, 16), nthreads=8)
+            assert np.array_equal(got, want), (op, w)
+
+
+def test_empty_images_and_errors():
+    e = torch.empty((0, 5), dtype=torch.uint8, device="cuda")
+    assert morph.erode(e, 3).shape == (0, 5)
+    img = to_dev(synth.uniform(8, 8, np.uint8, seed=1))[0]
+    with pytest.raises(morph.MorphError) as ei:
+        morph.erode(img, 3, 3, ax=3)
+    assert ei.value.status == -1
+    with pytest.raises(morph.MorphError) as ei:
+        morph.apply("erode", img, 3, 3, out=img)
+    assert ei.value.status == -2
+
+
+# ---------------- full benchmark sizes ----------------
+def test_config_640x480_uniform():
+    img = synth.uniform(480, 640, np.uint8, seed=1)
+    for wx, wy in ((3, 3), (15, 15), (1, 31)):
+        for op in ("erode", "dilate"):
+            _check(img, op, wx, wy)
+
+
+def test_config_1920x1080_document_sweep():
+    img = synth.document(1080, 1920, seed=2)
+    for w in (3, 5, 7, 9, 15, 21, 31, 45, 63):
+        for op in ("erode", "dilate"):
+            _check(img, op, w, w)
+            if w <= 16:
+                _check(img, op, w, w, method_x="vhgw", method_y="vhgw")
+                _check(img, op, w, w, method_x="direct", method_y="direct")
+
+
+@pytest.mark.parametrize("dtype,seed", [(np.uint8, 3), (np.uint16, 4)])
+def test_config_4096_square_all_ops(dtype, seed):
+    img = synth.uniform(4096, 4096, dtype, seed=seed)
+    d, _ = to_dev(img)
+    ws = None
+    for wx, wy in ((101, 101), (1, 255), (255, 1), (7, 63)):
+        for op in ("erode", "dilate", "open", "close"):
+            out = morph.apply(op, d, wx, wy, workspace=ws)
+            torch.cuda.synchronize()
+            got = to_host(out)
+            kw = dict(method="hybrid", thresholds=(16, 16), nthreads=8)
+            want = oracle.apply(op, img, wx, wy, **kw)
+            assert np.array_equal(got, want), (op, wx, wy, dtype)
