@@ -28,9 +28,12 @@ int hip_fail(hipError_t e)
 }
 
 // ---------------- tuning table ----------------
+// Tile shape for windows up to wmax: the tile's input row spans tq quads of 4
+// pixels (so the vertical pass has tq work units per band of rows) and the tile
+// has tb output rows.
 struct TileRule {
     int wmax; // applies when max(wx, wy) <= wmax
-    int tw, tb;
+    int tq, tb;
 };
 
 struct DtypeTuning {
@@ -40,8 +43,8 @@ struct DtypeTuning {
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {5, 5, {{4, 128, 64}, {16, 128, 64}, {64, 256, 64}, {1 << 30, 256, 32}}},
-    {5, 5, {{4, 128, 64}, {16, 128, 64}, {64, 256, 64}, {1 << 30, 256, 32}}},
+    {5, 5, {{16, 32, 64}, {64, 64, 32}, {1 << 30, 96, 32}}},
+    {5, 5, {{16, 32, 64}, {64, 64, 32}, {1 << 30, 96, 32}}},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -143,10 +146,10 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         std::vector<TileRule> rules;
         for (const JVal &r : it->second.arr) {
             if (r.k != JVal::OBJ) return false;
-            auto w = r.obj.find("wmax"), a = r.obj.find("tw"), b = r.obj.find("tb");
+            auto w = r.obj.find("wmax"), a = r.obj.find("tq"), b = r.obj.find("tb");
             if (w == r.obj.end() || a == r.obj.end() || b == r.obj.end()) return false;
             TileRule tr{(int)w->second.num, (int)a->second.num, (int)b->second.num};
-            if (tr.tw < 4 || tr.tw % 4 || tr.tb < 2 || tr.tb % 2) return false;
+            if (tr.tq < 2 || tr.tq > 4096 || tr.tb < 2 || tr.tb % 2) return false;
             rules.push_back(tr);
         }
         std::sort(rules.begin(), rules.end(),
@@ -230,6 +233,8 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     else j.vm = (j.wy <= std::min(tu.t_y, kDirectMax)) ? PASS_DIRECT : PASS_VHGW;
     if ((j.hm == PASS_DIRECT && j.wx > kDirectMax) || (j.vm == PASS_DIRECT && j.wy > kDirectMax))
         return MORPH_EUNSUPPORTED;
+    j.vcode = (j.vm == PASS_DIRECT) ? j.wy : 0;
+    j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
 
     // tile shape
     int tw = plan && plan->tile_w > 0 ? plan->tile_w : 0;
@@ -239,11 +244,13 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         const int wm = std::max(j.wx, j.wy);
         for (const TileRule &r : tu.tiles)
             if (wm <= r.wmax) {
-                if (!tw) tw = r.tw;
+                // the tile input (tw + wx - 1 columns, plus up to 3 for the origin
+                // rounded down to a quad) fills exactly tq quads
+                if (!tw) tw = std::max(4, 4 * r.tq - ((j.wx + 2 + 3) & ~3));
                 if (!tb) tb = r.tb;
                 break;
             }
-        if (!tw) tw = 128;
+        if (!tw) tw = 120;
         if (!tb) tb = 64;
     }
     const int w4 = (W + 3) & ~3;
@@ -253,8 +260,13 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     for (;;) {
         j.TW = tw;
         j.TB = tb;
-        j.SA = ((tw + j.wx - 1 + 3) & ~3) + 1;
-        j.SB = (j.hm == PASS_NONE) ? 0 : ((tw + 3) & ~3) + 1;
+        // A: 16-bit rows covering the tile input columns (+ 3 for the origin rounded
+        // down to a quad) and the columns a direct horizontal unit reads past the
+        // last one; odd stride in dwords.  B: row pairs of the output columns (+ 3 for
+        // the store's last quad); odd stride.
+        const int acols = std::max(tw + j.wx - 1 + 3, tw + kDirectChunkX + kDirectMax + 3) + 4;
+        j.SA = ((acols + 1) / 2) | 1;
+        j.SB = (j.hm == PASS_NONE) ? 0 : ((tw + 4) | 1);
         const int lds = lds_bytes(j);
         if (lds <= 64 * 1024) break;
         if (user_tile && lds <= kMaxLdsBytes) break;
@@ -270,6 +282,13 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     }
     j.tiles_x = (W + j.TW - 1) / j.TW;
     j.tiles_y = (H + j.TB - 1) / j.TB;
+    // the kernels split work-unit indices u by a divisor d with a multiply-high,
+    // exact while u * d < 2^32 (largest u is units - 1 of each loop)
+    const uint64_t nq = (uint64_t)(j.TW + j.wx - 1 + 3 + 3) / 4, np = (uint64_t)(j.TB + 1) / 2;
+    const uint64_t nrow_blocks = (uint64_t)j.TB + j.wy; // >= row chunks / blocks of any loop
+    const uint64_t ncol_blocks = (uint64_t)j.TW + j.wx; // >= column chunks / blocks
+    if (nq * nq * nrow_blocks >= (1ull << 32) || np * np * ncol_blocks >= (1ull << 32))
+        return MORPH_EUNSUPPORTED;
     return MORPH_OK;
 }
 

@@ -7,7 +7,8 @@
 namespace morph {
 
 constexpr int kThreads = 256;  // threads per workgroup of every kernel
-constexpr int kDirectMax = 16; // largest window the direct (sliding) passes take
+constexpr int kDirectMax = 9;  // largest window the direct (sliding) passes take
+constexpr int kDirectChunkX = 8; // output columns per direct horizontal work unit
 constexpr int kMaxLdsBytes = 160 * 1024;
 
 enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2 };
@@ -26,11 +27,13 @@ struct TileJob {
     int32_t tiles_x, tiles_y;
     int32_t SA, SB;  // LDS row-pair strides in dwords (odd)
     int32_t vm, hm;  // PassMode of the vertical / horizontal pass
+    int32_t vcode;   // vertical pass: 1..9 direct with that window, 0 vHGW
+    int32_t hcode;   // horizontal pass: 1 none, 2..9 direct with that window, 0 vHGW
     int32_t op;      // 0 erode, 1 dilate
     int32_t dtype;   // 0 u8, 1 u16
 };
 
-inline int lds_bytes(const TileJob &j) { return (j.TB / 2) * (j.SA + j.SB) * 4; }
+inline int lds_bytes(const TileJob &j) { return (j.TB * j.SA + (j.TB / 2) * j.SB) * 4; }
 
 // kernels (morph_kernels.hip)
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);

@@ -37,7 +37,7 @@ namespace morph {
 constexpr int NT = kThreads;
 constexpr int DMAX = kDirectMax;
 constexpr int KV = 8; // output rows per direct vertical work unit
-constexpr int KH = 8; // output columns per direct horizontal work unit
+constexpr int KH = kDirectChunkX; // output columns per direct horizontal work unit
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
@@ -179,175 +179,447 @@ __device__ __forceinline__ void get_row(const uint32_t *L, int S, int s, int c, 
     x23 = (uint32_t)b[4] | ((uint32_t)b[6] << 16);
 }
 
-template <typename T, bool MAXOP, int VM, int HM>
-__device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *lds)
-{
-    const int tid = threadIdx.x;
-    const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
-    const int x0 = tx * J.TW, y0 = ty * J.TB;
-    const int out_w = min(J.TW, J.W - x0), out_h = min(J.TB, J.H - y0);
-    const int wx = J.wx, wy = J.wy;
-    const int IW = out_w + wx - 1; // tile input columns
-    const int cx0 = x0 - J.ax, cy0 = y0 - J.ay;
-    const int SA = J.SA, SB = J.SB;
-    uint32_t *A = lds;                    // [TB/2][SA]: vertical-pass output (row pairs)
-    uint32_t *B = lds + (J.TB >> 1) * SA; // [TB/2][SB]: g of the horizontal pass / its output
-    const uint32_t id = MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16));
-    const uint8_t *src = J.src;
-    const int H = J.H, W = J.W;
-    const int64_t pitch = J.pitch;
-    const int NQ = (IW + 3) >> 2; // column quads of the tile input
+// Reads of one image row quad for the vertical pass.  The tile's input columns
+// start at cxa, rounded down to a multiple of 4 pixels, so every quad starts at a
+// multiple of 4.  With AL (rows 4-byte aligned for uint8, 8-byte for uint16) each
+// quad is one naturally aligned load.  Loads are split in two steps so that a
+// batch of them can be issued before any is waited on: issue() reads (a quad
+// outside the image, or a slot not wanted, reads the image's first element
+// instead) and finish() widens and replaces pixels outside the image by the
+// identity with selects, never branches.
+template <typename T> struct RawQuad;
+template <> struct RawQuad<uint8_t> { uint32_t d; };
+template <> struct RawQuad<uint16_t> { uint2 d; };
 
-    // input row `pos` of the tile (image row cy0 + pos), quad q
-    auto ld = [&](int pos, int q, uint32_t &a, uint32_t &b) {
-        const int gy = cy0 + pos;
-        if (gy >= 0 && gy < H)
-            Px<T>::load(src + (int64_t)gy * pitch, cx0 + 4 * q, W, id, a, b);
-        else {
-            a = id;
-            b = id;
+template <typename T, bool AL> struct RowLoader {
+    const uint8_t *src;
+    int64_t pitch;
+    int H, W;
+    uint32_t id;
+
+    // AL: images whose rows are aligned and whose whole span is below 4 GiB are
+    // addressed with 32-bit offsets from the uniform base pointer.
+    __device__ __forceinline__ RawQuad<T> at(uint32_t off) const
+    {
+        RawQuad<T> r;
+        if constexpr (sizeof(T) == 1) r.d = *(const uint32_t *)(src + off);
+        else r.d = *(const uint2 *)(src + off);
+        return r;
+    }
+    __device__ __forceinline__ uint32_t offset(int gy, int gx) const
+    {
+        return (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx * (uint32_t)sizeof(T);
+    }
+    static __device__ __forceinline__ void widen(const RawQuad<T> &r, uint32_t &a, uint32_t &b)
+    {
+        if constexpr (sizeof(T) == 1) {
+            a = perm(0u, r.d, SEL_U8_01);
+            b = perm(0u, r.d, SEL_U8_23);
+        } else {
+            a = r.d.x;
+            b = r.d.y;
         }
-    };
+    }
+    // 16-bit lane masks of the quad at gx: pixels gx + j < W (all lanes off when
+    // the quad is outside the image)
+    __device__ __forceinline__ void col_masks(int gx, uint32_t &m01, uint32_t &m23) const
+    {
+        const int n = (unsigned)gx < (unsigned)W ? min(W - gx, 4) : 0;
+        m01 = n >= 2 ? 0xffffffffu : (n == 1 ? 0x0000ffffu : 0u);
+        m23 = n >= 4 ? 0xffffffffu : (n == 3 ? 0x0000ffffu : 0u);
+    }
+    __device__ __forceinline__ uint32_t sel(uint32_t m, uint32_t x) const
+    {
+        return (x & m) | (id & ~m);
+    }
+    // one quad, any alignment (slow path)
+    __device__ __forceinline__ void load_any(int gy, int gx, bool want, uint32_t &a,
+                                             uint32_t &b) const
+    {
+        if (want && (unsigned)gy < (unsigned)H)
+            Px<T>::load(src + (int64_t)gy * pitch, gx, W, id, a, b);
+        else
+            a = b = id;
+    }
+};
 
-    // ---------------- vertical pass: A[rows 0..out_h) x [cols 0..IW) ----------------
-    if constexpr (VM == PASS_DIRECT) {
-        // Sliding window over KV + wy - 1 rows held in registers (direct method);
-        // wy == 1 is a plain load.
-        const int NKV = (out_h + KV - 1) / KV;
-        for (int u = tid; u < NQ * NKV; u += NT) {
-            const int q = u % NQ, s0 = (u / NQ) * KV;
-            uint32_t r01[KV + DMAX - 1], r23[KV + DMAX - 1];
+// NR rows gy0, gy0 + step, ... of the quad at column gx; rows k >= n are not wanted
+// and come back as the identity.  Every load is issued before any is used.  Units
+// whose rows and columns all lie inside the image skip every check.
+template <int NR, typename T, bool AL>
+__device__ __forceinline__ void load_rows(const RowLoader<T, AL> &L, int gy0, int step, int gx,
+                                          int n, uint32_t *v01, uint32_t *v23)
+{
+    if constexpr (AL) {
+        RawQuad<T> raw[NR];
+        const int glast = gy0 + step * (min(n, NR) - 1);
+        const bool interior = gx >= 0 && gx + 4 <= L.W && min(gy0, glast) >= 0 &&
+                              max(gy0, glast) < L.H && n > 0;
+        if (interior) {
+            const uint32_t off = L.offset(gy0, gx);
+            const int32_t d = step * (int32_t)L.pitch;
 #pragma unroll
-            for (int j = 0; j < KV + DMAX - 1; j++) {
-                if (j < KV + wy - 1)
-                    ld(s0 + j, q, r01[j], r23[j]);
-                else
-                    r01[j] = r23[j] = id;
+            for (int k = 0; k < NR; k++)
+                if (k < n) raw[k] = L.at(off + (uint32_t)(k * d));
+#pragma unroll
+            for (int k = 0; k < NR; k++) {
+                if (k < n) L.widen(raw[k], v01[k], v23[k]);
+                else v01[k] = v23[k] = L.id;
+            }
+        } else {
+            uint32_t m01, m23;
+            L.col_masks(gx, m01, m23);
+            bool ok[NR];
+#pragma unroll
+            for (int k = 0; k < NR; k++) {
+                const int gy = gy0 + step * k;
+                ok[k] = k < n && (unsigned)gy < (unsigned)L.H && (m01 & 1u);
+                raw[k] = L.at(ok[k] ? L.offset(gy, gx) : 0u);
             }
 #pragma unroll
-            for (int m = 0; m < KV; m += 2) {
-                if (s0 + m >= out_h) break;
-                uint32_t a01 = r01[m], a23 = r23[m], b01 = r01[m + 1], b23 = r23[m + 1];
-#pragma unroll
-                for (int j = 1; j < DMAX; j++) {
-                    if (j < wy) {
-                        a01 = pk<MAXOP>(a01, r01[m + j]);
-                        a23 = pk<MAXOP>(a23, r23[m + j]);
-                        b01 = pk<MAXOP>(b01, r01[m + 1 + j]);
-                        b23 = pk<MAXOP>(b23, r23[m + 1 + j]);
-                    }
-                }
-                uint32_t *d = A + ((s0 + m) >> 1) * SA + 4 * q;
-                d[0] = perm(b01, a01, SEL_LO16_PAIR);
-                d[1] = perm(b01, a01, SEL_HI16_PAIR);
-                d[2] = perm(b23, a23, SEL_LO16_PAIR);
-                d[3] = perm(b23, a23, SEL_HI16_PAIR);
+            for (int k = 0; k < NR; k++) {
+                uint32_t a, b;
+                L.widen(raw[k], a, b);
+                v01[k] = L.sel(ok[k] ? m01 : 0u, a);
+                v23[k] = L.sel(ok[k] ? m23 : 0u, b);
             }
         }
     } else {
-        // vHGW along y.  Phase F: g over each block of wy input rows, stored in the
-        // output row it pairs with (s = i - wy + 1).
-        const int NBF = (out_h + wy - 1 + wy - 1) / wy;
-        for (int u = tid; u < NQ * NBF; u += NT) {
-            const int q = u % NQ, i0 = (u / NQ) * wy;
-            const int i1 = min(i0 + wy, out_h + wy - 1);
-            uint32_t g01 = id, g23 = id;
-            for (int i = i0; i < i1; i++) {
-                uint32_t v01, v23;
-                ld(i, q, v01, v23);
-                g01 = pk<MAXOP>(g01, v01);
-                g23 = pk<MAXOP>(g23, v23);
-                const int s = i - wy + 1;
-                if (s >= 0) put_row(A, SA, s, 4 * q, g01, g23);
+#pragma unroll
+        for (int k = 0; k < NR; k++) L.load_any(gy0 + step * k, gx, k < n, v01[k], v23[k]);
+    }
+}
+
+// Division of work-unit indices by a per-tile divisor d without an integer divide:
+// with m = ceil(2^32 / d), floor(u / d) = mulhi(u, m) exactly whenever u * d < 2^32,
+// which the host planner guarantees for every loop below.
+struct FastDiv {
+    uint32_t d, m;
+    __device__ __forceinline__ explicit FastDiv(int d_)
+        : d((uint32_t)d_), m(d_ > 1 ? (uint32_t)__builtin_ceil(4294967296.0 / (double)d_) : 0u)
+    {
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t u) const { return d > 1 ? __umulhi(u, m) : u; }
+};
+
+// Everything one tile's passes share.  LDS holds two arrays:
+//   A  [TB rows][SA dwords]  vertical-pass output, row-major 16-bit pixels; LDS column
+//                            c is image column cxa + c (cxa rounded down to a quad);
+//   B  [TB/2][SB dwords]     horizontal pass, "row-pair" layout: dword (p, c) holds
+//                            rows 2p (low half) and 2p+1 (high half) of column c.
+// Both strides are odd, so the row-pair walks of the horizontal pass (one lane per
+// row pair) spread over the banks.
+template <typename T, bool AL> struct TileCtx {
+    int tid, x0, y0, out_w, out_h, wx, wy, cy0, co, cxa, IWL, SA, SB, NQ, NP;
+    uint32_t id;
+    uint32_t *A, *B;
+    RowLoader<T, AL> L;
+    FastDiv fq, fp;
+    __device__ __forceinline__ TileCtx(const TileJob &J, int tile, uint32_t *lds, uint32_t id_)
+        : tid(threadIdx.x), id(id_), L{J.src, J.pitch, J.H, J.W, id_}, fq(1), fp(1)
+    {
+        const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
+        x0 = tx * J.TW;
+        y0 = ty * J.TB;
+        out_w = min(J.TW, J.W - x0);
+        out_h = min(J.TB, J.H - y0);
+        wx = J.wx;
+        wy = J.wy;
+        const int cx0 = x0 - J.ax;
+        cy0 = y0 - J.ay;
+        co = cx0 & 3;
+        cxa = cx0 - co;
+        IWL = out_w + wx - 1 + co;
+        SA = J.SA;
+        SB = J.SB;
+        NQ = (IWL + 3) >> 2;
+        NP = (out_h + 1) >> 1;
+        A = lds;
+        B = lds + J.TB * SA;
+        fq = FastDiv(NQ);
+        fp = FastDiv(NP);
+    }
+    // row s, quad q of A (two dwords: pixels 0,1 and 2,3)
+    __device__ __forceinline__ uint32_t *arow(int s, int q) const { return A + s * SA + 2 * q; }
+};
+
+// Outputs for window starts 0 and 1 over x[0 .. W]: the two windows share the W-1
+// inputs x[1 .. W-1] (the paper's pairing of adjacent outputs in its direct pass).
+template <int W, bool MAXOP>
+__device__ __forceinline__ void pair_window(const uint32_t *x, uint32_t &o0, uint32_t &o1)
+{
+    if constexpr (W == 1) {
+        o0 = x[0];
+        o1 = x[1];
+    } else {
+        uint32_t core = x[1];
+#pragma unroll
+        for (int j = 2; j < W; j++) core = pk<MAXOP>(core, x[j]);
+        o0 = pk<MAXOP>(core, x[0]);
+        o1 = pk<MAXOP>(core, x[W]);
+    }
+}
+
+// ---- vertical pass, direct, window W: A rows [0, out_h) ----
+// Work unit: one quad of columns and KV output rows; its KV + W - 1 input rows are
+// loaded at once.
+template <int W, bool MAXOP, typename T, bool AL>
+__device__ __forceinline__ void vpass_direct(const TileCtx<T, AL> &c)
+{
+    constexpr int NR = KV + W - 1;
+    const int NKV = (c.out_h + KV - 1) / KV;
+    for (int u = c.tid; u < c.NQ * NKV; u += NT) {
+        const int k = c.fq.div(u), q = u - k * c.NQ, s0 = k * KV;
+        uint32_t r01[NR], r23[NR];
+        load_rows<NR>(c.L, c.cy0 + s0, 1, c.cxa + 4 * q, NR, r01, r23);
+#pragma unroll
+        for (int m = 0; m < KV; m += 2) {
+            uint32_t a01, a23, b01, b23;
+            pair_window<W, MAXOP>(r01 + m, a01, b01);
+            pair_window<W, MAXOP>(r23 + m, a23, b23);
+            if (s0 + m < c.out_h) {
+                uint32_t *d = c.arow(s0 + m, q);
+                d[0] = a01;
+                d[1] = a23;
+                d[c.SA] = b01; // row s0 + m + 1 (A has TB rows, TB even)
+                d[c.SA + 1] = b23;
             }
         }
-        __syncthreads();
-        // Phase B: walk each block backwards; h[s] = op of rows s .. block end,
-        // out[s] = op(h[s], g[s + wy - 1]).
-        const int NBB = (out_h + wy - 1) / wy;
-        for (int u = tid; u < NQ * NBB; u += NT) {
-            const int q = u % NQ, i0 = (u / NQ) * wy;
-            uint32_t h01 = id, h23 = id;
-            for (int i = i0 + wy - 1; i >= i0; i--) {
-                uint32_t v01, v23;
-                ld(i, q, v01, v23);
-                h01 = pk<MAXOP>(h01, v01);
-                h23 = pk<MAXOP>(h23, v23);
-                if (i < out_h) {
-                    uint32_t g01, g23;
-                    get_row(A, SA, i, 4 * q, g01, g23);
-                    put_row(A, SA, i, 4 * q, pk<MAXOP>(h01, g01), pk<MAXOP>(h23, g23));
+    }
+}
+
+// ---- vertical pass, vHGW ----
+// Phase F: g over each block of wy input rows, stored in the output row it pairs with
+// (s = i - wy + 1).  Phase B: walk each block backwards; h[s] = op of rows s .. block
+// end; out[s] = op(h[s], g[s + wy - 1]), in place.  Rows are read VB at a time.
+template <bool MAXOP, typename T, bool AL>
+__device__ __forceinline__ void vpass_vhgw(const TileCtx<T, AL> &c)
+{
+    constexpr int VB = 8;
+    const int wy = c.wy;
+    const int NBF = (c.out_h + wy - 1 + wy - 1) / wy;
+    for (int u = c.tid; u < c.NQ * NBF; u += NT) {
+        const int b = c.fq.div(u), q = u - b * c.NQ, i0 = b * wy;
+        const int gx = c.cxa + 4 * q;
+        const int i1 = min(i0 + wy, c.out_h + wy - 1);
+        uint32_t g01 = c.id, g23 = c.id;
+        for (int i = i0; i < i1; i += VB) {
+            uint32_t v01[VB], v23[VB];
+            load_rows<VB>(c.L, c.cy0 + i, 1, gx, i1 - i, v01, v23);
+#pragma unroll
+            for (int k = 0; k < VB; k++) {
+                g01 = pk<MAXOP>(g01, v01[k]);
+                g23 = pk<MAXOP>(g23, v23[k]);
+                const int s = i + k - wy + 1;
+                if (i + k < i1 && s >= 0) {
+                    uint32_t *d = c.arow(s, q);
+                    d[0] = g01;
+                    d[1] = g23;
                 }
             }
         }
     }
     __syncthreads();
-
-    // ---------------- horizontal pass over row pairs ----------------
-    const int NP = (out_h + 1) >> 1;
-    if constexpr (HM == PASS_DIRECT) {
-        const int NKH = (out_w + KH - 1) / KH;
-        for (int u = tid; u < NP * NKH; u += NT) {
-            const int p = u % NP, c0 = (u / NP) * KH;
-            const uint32_t *a = A + p * SA;
-            uint32_t r[KH + DMAX - 1];
+    const int NBB = (c.out_h + wy - 1) / wy;
+    for (int u = c.tid; u < c.NQ * NBB; u += NT) {
+        const int b = c.fq.div(u), q = u - b * c.NQ, i0 = b * wy;
+        const int gx = c.cxa + 4 * q;
+        uint32_t h01 = c.id, h23 = c.id;
+        for (int i = i0 + wy - 1; i >= i0; i -= VB) {
+            uint32_t v01[VB], v23[VB];
+            load_rows<VB>(c.L, c.cy0 + i, -1, gx, i - i0 + 1, v01, v23);
 #pragma unroll
-            for (int j = 0; j < KH + DMAX - 1; j++)
-                r[j] = (j < KH + wx - 1 && c0 + j < IW) ? a[c0 + j] : id;
-#pragma unroll
-            for (int m = 0; m < KH; m++) {
-                uint32_t acc = r[m];
-#pragma unroll
-                for (int j = 1; j < DMAX; j++)
-                    if (j < wx) acc = pk<MAXOP>(acc, r[m + j]);
-                if (c0 + m < out_w) B[p * SB + c0 + m] = acc;
+            for (int k = 0; k < VB; k++) {
+                h01 = pk<MAXOP>(h01, v01[k]);
+                h23 = pk<MAXOP>(h23, v23[k]);
+                const int s = i - k;
+                if (s >= i0 && s < c.out_h) {
+                    uint32_t *d = c.arow(s, q);
+                    d[0] = pk<MAXOP>(h01, d[0]);
+                    d[1] = pk<MAXOP>(h23, d[1]);
+                }
             }
         }
-        __syncthreads();
-    } else if constexpr (HM == PASS_VHGW) {
-        const int NBF = (IW + wx - 1) / wx;
-        for (int u = tid; u < NP * NBF; u += NT) {
-            const int p = u % NP, i0 = (u / NP) * wx;
-            const int i1 = min(i0 + wx, IW);
-            const uint32_t *a = A + p * SA;
-            uint32_t *g = B + p * SB;
-            uint32_t acc = id;
-            for (int i = i0; i < i1; i++) {
-                acc = pk<MAXOP>(acc, a[i]);
-                const int s = i - wx + 1;
-                if (s >= 0) g[s] = acc;
-            }
-        }
-        __syncthreads();
-        const int NBB = (out_w + wx - 1) / wx;
-        for (int u = tid; u < NP * NBB; u += NT) {
-            const int p = u % NP, i0 = (u / NP) * wx;
-            uint32_t *a = A + p * SA;
-            const uint32_t *g = B + p * SB;
-            uint32_t h = id;
-            for (int i = i0 + wx - 1; i >= i0; i--) {
-                h = pk<MAXOP>(h, a[i]);
-                if (i < out_w) a[i] = pk<MAXOP>(h, g[i]);
-            }
-        }
-        __syncthreads();
     }
+}
 
-    // ---------------- store: row pairs back to rows ----------------
-    const uint32_t *O = (HM == PASS_DIRECT) ? B : A;
-    const int SO = (HM == PASS_DIRECT) ? SB : SA;
-    const int NQo = (out_w + 3) >> 2;
-    for (int u = tid; u < NQo * NP; u += NT) {
-        const int q = u % NQo, p = u / NQo;
-        const uint32_t *o = O + p * SO + 4 * q;
+// Column `col` (LDS coordinates) of row pair p of A as one row-pair dword.
+template <typename T, bool AL>
+__device__ __forceinline__ uint32_t col_pair(const TileCtx<T, AL> &c, const uint32_t *r0, int col)
+{
+    const uint32_t x = r0[col >> 1], y = r0[(col >> 1) + c.SA];
+    return (col & 1) ? perm(y, x, SEL_HI16_PAIR) : perm(y, x, SEL_LO16_PAIR);
+}
+
+// ---- horizontal pass, direct, window W: B (row pairs) columns [0, out_w) ----
+// Work unit: one row pair and KH output columns.  The unit reads the dwords that
+// cover its KH + W - 1 input columns from both rows and transposes them to row-pair
+// form.  The parity of the first input column (co) is the same for every unit of a
+// tile, so each parity has its own fully unrolled code.
+template <int W, bool MAXOP, int PAR, typename T, bool AL>
+__device__ __forceinline__ void hpass_direct_par(const TileCtx<T, AL> &c)
+{
+    constexpr int NC = KH + W - 1;        // input columns per unit
+    constexpr int ND = (NC + PAR + 1) / 2; // dwords covering them
+    const int NKH = (c.out_w + KH - 1) / KH;
+    for (int u = c.tid; u < c.NP * NKH; u += NT) {
+        const int k = c.fp.div(u), p = u - k * c.NP, c0 = k * KH;
+        const uint32_t *r0 = c.A + 2 * p * c.SA + ((c.co + c0) >> 1);
+        uint32_t x[NC + 1];
+#pragma unroll
+        for (int d = 0; d < ND; d++) {
+            const uint32_t lo = r0[d], hi = r0[d + c.SA];
+            const int e0 = 2 * d - PAR; // column (relative to c0) of the low half
+            if (e0 >= 0 && e0 < NC + 1) x[e0] = perm(hi, lo, SEL_LO16_PAIR);
+            if (e0 + 1 >= 0 && e0 + 1 < NC + 1) x[e0 + 1] = perm(hi, lo, SEL_HI16_PAIR);
+        }
+        uint32_t *o = c.B + p * c.SB + c0;
+#pragma unroll
+        for (int m = 0; m < KH; m += 2) {
+            uint32_t o0, o1;
+            pair_window<W, MAXOP>(x + m, o0, o1);
+            if (c0 + m < c.out_w) o[m] = o0;
+            if (c0 + m + 1 < c.out_w) o[m + 1] = o1;
+        }
+    }
+}
+
+template <int W, bool MAXOP, typename T, bool AL>
+__device__ __forceinline__ void hpass_direct(const TileCtx<T, AL> &c)
+{
+    if (c.co & 1) hpass_direct_par<W, MAXOP, 1>(c);
+    else hpass_direct_par<W, MAXOP, 0>(c);
+}
+
+// ---- horizontal pass, vHGW ----
+// Work unit: one row pair and one block of wx input columns.  Phase F writes g
+// shifted by wx - 1 into B; phase B walks the block backwards and combines h with g
+// in place in B.  Columns are read HB at a time.
+template <bool MAXOP, typename T, bool AL>
+__device__ __forceinline__ void hpass_vhgw(const TileCtx<T, AL> &c)
+{
+    constexpr int HB = 8;
+    const int wx = c.wx;
+    const int IW = c.out_w + wx - 1;
+    const int NBF = (IW + wx - 1) / wx;
+    for (int u = c.tid; u < c.NP * NBF; u += NT) {
+        const int b = c.fp.div(u), p = u - b * c.NP, i0 = b * wx;
+        const int i1 = min(i0 + wx, IW);
+        const uint32_t *r0 = c.A + 2 * p * c.SA;
+        uint32_t *g = c.B + p * c.SB;
+        uint32_t acc = c.id;
+        for (int i = i0; i < i1; i += HB) {
+            uint32_t v[HB];
+#pragma unroll
+            for (int k = 0; k < HB; k++) {
+                const bool ok = i + k < i1;
+                const uint32_t x = col_pair(c, r0, c.co + (ok ? i + k : i0));
+                v[k] = ok ? x : c.id;
+            }
+#pragma unroll
+            for (int k = 0; k < HB; k++) {
+                acc = pk<MAXOP>(acc, v[k]);
+                const int s = i + k - wx + 1;
+                if (i + k < i1 && s >= 0) g[s] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    const int NBB = (c.out_w + wx - 1) / wx;
+    for (int u = c.tid; u < c.NP * NBB; u += NT) {
+        const int b = c.fp.div(u), p = u - b * c.NP, i0 = b * wx;
+        const uint32_t *r0 = c.A + 2 * p * c.SA;
+        uint32_t *g = c.B + p * c.SB;
+        uint32_t h = c.id;
+        for (int i = i0 + wx - 1; i >= i0; i -= HB) {
+            uint32_t v[HB], gg[HB];
+#pragma unroll
+            for (int k = 0; k < HB; k++) {
+                const bool in = i - k >= i0;
+                const bool og = in && i - k < c.out_w;
+                const uint32_t x = col_pair(c, r0, c.co + (in ? i - k : i0));
+                const uint32_t y = g[og ? i - k : 0];
+                v[k] = in ? x : c.id;
+                gg[k] = og ? y : c.id;
+            }
+#pragma unroll
+            for (int k = 0; k < HB; k++) {
+                h = pk<MAXOP>(h, v[k]);
+                if (i - k >= i0 && i - k < c.out_w) g[i - k] = pk<MAXOP>(h, gg[k]);
+            }
+        }
+    }
+}
+
+// ---- store ----
+template <typename T, bool AL>
+__device__ __forceinline__ void store_pairs(const TileCtx<T, AL> &c, const TileJob &J)
+{
+    // from B (row pairs): a quad of columns of two rows per unit
+    const int NQo = (c.out_w + 3) >> 2;
+    const FastDiv fo(NQo);
+    for (int u = c.tid; u < NQo * c.NP; u += NT) {
+        const int p = fo.div(u), q = u - p * NQo;
+        const uint32_t *o = c.B + p * c.SB + 4 * q;
         const uint32_t c0 = o[0], c1 = o[1], c2 = o[2], c3 = o[3];
-        const int y = y0 + 2 * p, x = x0 + 4 * q;
-        uint8_t *row = J.dst + (int64_t)y * pitch;
-        Px<T>::store(row, x, W, perm(c1, c0, SEL_LO16_PAIR), perm(c3, c2, SEL_LO16_PAIR));
-        if (2 * p + 1 < out_h)
-            Px<T>::store(row + pitch, x, W, perm(c1, c0, SEL_HI16_PAIR),
+        const int y = c.y0 + 2 * p, x = c.x0 + 4 * q;
+        uint8_t *row = J.dst + (int64_t)y * J.pitch;
+        Px<T>::store(row, x, J.W, perm(c1, c0, SEL_LO16_PAIR), perm(c3, c2, SEL_LO16_PAIR));
+        if (2 * p + 1 < c.out_h)
+            Px<T>::store(row + J.pitch, x, J.W, perm(c1, c0, SEL_HI16_PAIR),
                          perm(c3, c2, SEL_HI16_PAIR));
     }
+}
+
+template <typename T, bool AL>
+__device__ __forceinline__ void store_rows(const TileCtx<T, AL> &c, const TileJob &J)
+{
+    // from A (rows), when there is no horizontal pass (co == 0 then, as wx == 1 and
+    // ax == 0 put the tile origin on x0, a multiple of 4)
+    const int NQo = (c.out_w + 3) >> 2;
+    const FastDiv fo(NQo);
+    for (int u = c.tid; u < NQo * c.out_h; u += NT) {
+        const int s = fo.div(u), q = u - s * NQo;
+        const uint32_t *a = c.arow(s, q);
+        Px<T>::store(J.dst + (int64_t)(c.y0 + s) * J.pitch, c.x0 + 4 * q, J.W, a[0], a[1]);
+    }
+}
+
+template <typename T, bool MAXOP, bool AL>
+__device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *lds)
+{
+    const uint32_t id = MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16));
+    const TileCtx<T, AL> c(J, tile, lds, id);
+    switch (J.vcode) {
+    case 1: vpass_direct<1, MAXOP>(c); break;
+    case 2: vpass_direct<2, MAXOP>(c); break;
+    case 3: vpass_direct<3, MAXOP>(c); break;
+    case 4: vpass_direct<4, MAXOP>(c); break;
+    case 5: vpass_direct<5, MAXOP>(c); break;
+    case 6: vpass_direct<6, MAXOP>(c); break;
+    case 7: vpass_direct<7, MAXOP>(c); break;
+    case 8: vpass_direct<8, MAXOP>(c); break;
+    case 9: vpass_direct<9, MAXOP>(c); break;
+    default: vpass_vhgw<MAXOP>(c); break;
+    }
+    __syncthreads();
+    if (J.hcode == 1) {
+        store_rows(c, J);
+        return;
+    }
+    switch (J.hcode) {
+    case 2: hpass_direct<2, MAXOP>(c); break;
+    case 3: hpass_direct<3, MAXOP>(c); break;
+    case 4: hpass_direct<4, MAXOP>(c); break;
+    case 5: hpass_direct<5, MAXOP>(c); break;
+    case 6: hpass_direct<6, MAXOP>(c); break;
+    case 7: hpass_direct<7, MAXOP>(c); break;
+    case 8: hpass_direct<8, MAXOP>(c); break;
+    case 9: hpass_direct<9, MAXOP>(c); break;
+    default: hpass_vhgw<MAXOP>(c); break;
+    }
+    __syncthreads();
+    store_pairs(c, J);
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  Give each
@@ -359,33 +631,34 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-template <typename T, bool MAXOP, int VM, int HM>
+template <typename T, bool MAXOP, bool AL>
 __global__ __launch_bounds__(NT) void tile_kernel(TileJob J)
 {
     extern __shared__ uint32_t lds[];
-    tile_body<T, MAXOP, VM, HM>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+    tile_body<T, MAXOP, AL>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 typedef void (*TileKernelFn)(TileJob);
 
-template <typename T, bool MAXOP>
-static TileKernelFn pick(int vm, int hm)
+// Rows are "aligned" when every row starts on a 4-byte (uint8) or 8-byte (uint16)
+// boundary, so each quad of 4 pixels is one natural load, and the image spans less
+// than 4 GiB, so 32-bit offsets address it.
+__host__ __device__ inline bool rows_aligned(const TileJob &j)
 {
-    if (vm == PASS_DIRECT) {
-        if (hm == PASS_NONE) return tile_kernel<T, MAXOP, PASS_DIRECT, PASS_NONE>;
-        if (hm == PASS_DIRECT) return tile_kernel<T, MAXOP, PASS_DIRECT, PASS_DIRECT>;
-        return tile_kernel<T, MAXOP, PASS_DIRECT, PASS_VHGW>;
-    }
-    if (hm == PASS_NONE) return tile_kernel<T, MAXOP, PASS_VHGW, PASS_NONE>;
-    if (hm == PASS_DIRECT) return tile_kernel<T, MAXOP, PASS_VHGW, PASS_DIRECT>;
-    return tile_kernel<T, MAXOP, PASS_VHGW, PASS_VHGW>;
+    const uintptr_t m = j.dtype == 0 ? 3u : 7u;
+    const uint64_t span = (uint64_t)(j.H - 1) * (uint64_t)j.pitch + (uint64_t)j.W * (j.dtype ? 2 : 1);
+    return (((uintptr_t)j.src | (uintptr_t)j.pitch) & m) == 0 && span < (1ull << 32);
 }
 
 static TileKernelFn pick_kernel(const TileJob &j)
 {
-    if (j.dtype == 0)
-        return j.op ? pick<uint8_t, true>(j.vm, j.hm) : pick<uint8_t, false>(j.vm, j.hm);
-    return j.op ? pick<uint16_t, true>(j.vm, j.hm) : pick<uint16_t, false>(j.vm, j.hm);
+    const bool al = rows_aligned(j);
+    if (j.dtype == 0) {
+        if (j.op) return al ? tile_kernel<uint8_t, true, true> : tile_kernel<uint8_t, true, false>;
+        return al ? tile_kernel<uint8_t, false, true> : tile_kernel<uint8_t, false, false>;
+    }
+    if (j.op) return al ? tile_kernel<uint16_t, true, true> : tile_kernel<uint16_t, true, false>;
+    return al ? tile_kernel<uint16_t, false, true> : tile_kernel<uint16_t, false, false>;
 }
 
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
@@ -410,15 +683,8 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
 template <typename T, bool MAXOP>
 __device__ void run_job_tile(const TileJob &J, int t, uint32_t *lds)
 {
-    if (J.vm == PASS_DIRECT) {
-        if (J.hm == PASS_NONE) tile_body<T, MAXOP, PASS_DIRECT, PASS_NONE>(J, t, lds);
-        else if (J.hm == PASS_DIRECT) tile_body<T, MAXOP, PASS_DIRECT, PASS_DIRECT>(J, t, lds);
-        else tile_body<T, MAXOP, PASS_DIRECT, PASS_VHGW>(J, t, lds);
-    } else {
-        if (J.hm == PASS_NONE) tile_body<T, MAXOP, PASS_VHGW, PASS_NONE>(J, t, lds);
-        else if (J.hm == PASS_DIRECT) tile_body<T, MAXOP, PASS_VHGW, PASS_DIRECT>(J, t, lds);
-        else tile_body<T, MAXOP, PASS_VHGW, PASS_VHGW>(J, t, lds);
-    }
+    if (rows_aligned(J)) tile_body<T, MAXOP, true>(J, t, lds);
+    else tile_body<T, MAXOP, false>(J, t, lds);
 }
 
 __global__ __launch_bounds__(NT) void batch_kernel(BatchTables bt)

@@ -107,15 +107,16 @@ def test_plan_resolution_and_thresholds(tmp_path):
         # a tuning file replaces thresholds and tiles
         f = tmp_path / "t.json"
         f.write_text(json.dumps({"u8": {"t_x": 3, "t_y": 4, "tiles": [
-            {"wmax": 8, "tw": 64, "tb": 32}, {"wmax": 1000000, "tw": 128, "tb": 16}]}}))
+            {"wmax": 8, "tq": 16, "tb": 32}, {"wmax": 1000000, "tq": 40, "tb": 16}]}}))
         morph.load_tuning(str(f))
         assert morph.get_thresholds("u8") == (3, 4)
+        # the input row of a tile fills tq quads: tw + wx - 1 + 3 <= 4 tq
         p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
-        assert (p["tile_w"], p["tile_h"]) == (64, 32)
+        assert (p["tile_w"], p["tile_h"]) == (64 - 8, 32)
         p = morph.resolve_plan("u8", 1000, 1000, 30, 30)
-        assert (p["tile_w"], p["tile_h"]) == (128, 16)
+        assert (p["tile_w"], p["tile_h"]) == (160 - 32, 16)
         bad = tmp_path / "bad.json"
-        bad.write_text('{"u8": {"t_x": 3, "tiles": [{"wmax": 8, "tw": 6, "tb": 32}]}}')
+        bad.write_text('{"u8": {"t_x": 3, "tiles": [{"wmax": 8, "tq": 1, "tb": 32}]}}')
         with pytest.raises(morph.MorphError):
             morph.load_tuning(str(bad))
         with pytest.raises(morph.MorphError):
@@ -130,3 +131,16 @@ def test_strerror():
     for s in (0, -1, -2, -3, -4, -5):
         assert L.morph_strerror(s)
     assert L.morph_strerror(-99) == b"unknown status"
+
+
+def test_multiply_high_division_is_exact():
+    """The kernels divide work-unit indices u by d as mulhi(u, ceil(2^32 / d)); this
+    is exact whenever u * d < 2^32 (the planner's guarantee)."""
+    import math
+    import random
+    rnd = random.Random(5)
+    for d in list(range(2, 600)) + [rnd.randrange(2, 1 << 16) for _ in range(300)]:
+        m = math.ceil((1 << 32) / d)
+        umax = ((1 << 32) - 1) // d
+        for u in [0, 1, d - 1, d, d + 1, umax, umax - 1] + [rnd.randrange(0, umax + 1) for _ in range(40)]:
+            assert (u * m) >> 32 == u // d, (u, d)
