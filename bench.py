@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the HIP erosion/dilation path on one MI355X.
+
+Workload (one "step"): the mixed-size batch -- 512 uint8 document-like images,
+H and W each log-uniform in [64, 2048], a square window per image drawn from
+{3, 5, 9, 15, 31, 63}, erosion or dilation at random (seed 5) -- run as one
+persistent, graph-replayed launch.  Images are resident in HBM before timing;
+rows are padded to a 64-byte pitch.  Reported beside it: the same 512 images as
+512 separate launches (eager and captured in one graph), the 4096x4096 uint8 and
+uint16 erosion/dilation kernels at the four large windows, and the CPU oracle
+timed on a bounded sample of the batch on the host's cores.
+
+Prints ONE JSON line.  ``--gpus`` other than 1 exits with a message: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("Gpixel/s and % peak HBM GB/s, erode/dilate uint8; batched vs per-image; p50/p99")
+PEAK_HBM_GBS = 8000.0
+PITCH_ALIGN = 64
+
+
+def _log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("morph_kernels.hip", "morph_api.hip", "morph_internal.h"):
+        with open(os.path.join(ROOT, "paper_2002_09474_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM traffic per launch of the batch kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "batch512_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("workload") != workload or t.get("kernel_digest") != kernel_source_digest():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def build_batch(torch, morph, synth, dev):
+    specs = synth.batch_specs(512, seed=5)
+    imgs = synth.batch_images(specs, seed=5)
+    # one pool: every image padded to a 64-byte row pitch, src then dst
+    offs, total = [], 0
+    for s in specs:
+        pitch = (s["W"] + PITCH_ALIGN - 1) // PITCH_ALIGN * PITCH_ALIGN
+        offs.append((total, pitch))
+        total += pitch * s["H"]
+    import numpy as np
+    host = np.zeros(total, np.uint8)
+    for (o, pitch), s, im in zip(offs, specs, imgs):
+        host[o:o + pitch * s["H"]].reshape(s["H"], pitch)[:, :s["W"]] = im
+    src_pool = torch.from_numpy(host).to(dev)
+    dst_pool = torch.zeros(total, dtype=torch.uint8, device=dev)
+    items = []
+    for (o, pitch), s in zip(offs, specs):
+        sv = src_pool[o:o + pitch * s["H"]].view(s["H"], pitch)[:, :s["W"]]
+        dv = dst_pool[o:o + pitch * s["H"]].view(s["H"], pitch)[:, :s["W"]]
+        items.append(dict(src=sv, dst=dv, wx=s["w"], wy=s["w"], op=s["op"]))
+    npx = sum(s["H"] * s["W"] for s in specs)
+    return specs, imgs, items, npx, (src_pool, dst_pool)
+
+
+def time_launches(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in ev]  # ms
+    return per, wall
+
+
+def cpu_baseline(specs, imgs, budget_s):
+    """The oracle's per-pass hybrid (direct below the paper's thresholds, 59 along x
+    and 69 along y, vHGW above) on the host's cores, over images of the batch in
+    order until about budget_s of CPU time has been spent."""
+    import oracle
+    nthreads = os.cpu_count() or 1
+    # warm (loads the library, starts the OpenMP pool)
+    oracle.erode(imgs[0][:64, :64].copy(), 3, 3, method="hybrid", thresholds=(59, 69),
+                 nthreads=nthreads)
+    done_px, t_used, n = 0, 0.0, 0
+    for s, im in zip(specs, imgs):
+        t0 = time.perf_counter()
+        oracle.apply(s["op"], im, s["w"], s["w"], method="hybrid", thresholds=(59, 69),
+                     nthreads=nthreads)
+        t_used += time.perf_counter() - t0
+        done_px += s["H"] * s["W"]
+        n += 1
+        if t_used >= budget_s:
+            break
+    return dict(value=round(done_px / t_used / 1e9, 4), unit="Gpixel/s", cores=nthreads,
+                kind="oracle",
+                sample="first %d of 512 batch images (%.1f Mpx), oracle hybrid direct/vHGW "
+                       "with the paper's thresholds (x 59, y 69), %.1f s" %
+                       (n, done_px / 1e6, t_used))
+
+
+def c3_lines(torch, morph, dev, steps):
+    """4096x4096 erosion/dilation kernels at the large windows, uint8 and uint16."""
+    out = []
+    for dt, tdt, es in (("u8", torch.uint8, 1), ("u16", torch.uint16, 2)):
+        nbuf = 10  # distinct src/dst pairs so most reads miss the 256 MB Infinity Cache
+        g = torch.Generator(device=dev).manual_seed(3 if dt == "u8" else 4)
+        srcs = [torch.randint(0, 256 if dt == "u8" else 65536, (4096, 4096), generator=g,
+                              dtype=torch.int32, device=dev).to(torch.uint8 if dt == "u8"
+                                                                else torch.int16)
+                for _ in range(nbuf)]
+        if dt == "u16":
+            srcs = [s.view(torch.uint16) for s in srcs]
+        dsts = [torch.empty_like(s) for s in srcs]
+        stream = torch.cuda.current_stream()
+        for wx, wy in ((101, 101), (1, 255), (255, 1), (7, 63), (3, 3)):
+            for op in ("erode", "dilate"):
+                k = [0]
+
+                def fn():
+                    i = k[0] % nbuf
+                    k[0] += 1
+                    morph.apply(op, srcs[i], wx, wy, out=dsts[i])
+                per, _ = time_launches(torch, fn, steps, 5, stream)
+                per.sort()
+                med_us = per[len(per) // 2] * 1e3
+                gbs = 2 * es * 4096 * 4096 / (med_us * 1e-6) / 1e9
+                out.append(dict(dtype=dt, op=op, w="%dx%d" % (wx, wy), us=round(med_us, 2),
+                                gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4)))
+        del srcs, dsts
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle time for the CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-image baselines and the 4096x4096 lines")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2002_09474_amd as morph
+    from paper_2002_09474_amd import synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    _log("building the 512-image batch")
+    specs, imgs, items, npx, _pools = build_batch(torch, morph, synth, dev)
+    batch = morph.Batch(len(items), 1 << 22)
+    ntiles = batch.set(items)
+    torch.cuda.synchronize()
+
+    _log("timing %d batched steps (%d tiles, %.1f Mpx per step)" % (args.steps, ntiles, npx / 1e6))
+    per, wall = time_launches(torch, lambda: batch.enqueue(), args.steps, args.warmup, stream)
+    ms_per_step = sum(per) / len(per)
+    value = npx / (ms_per_step * 1e-3) / 1e9
+    algo_bytes = 2 * npx  # one read and one write of every uint8 pixel
+    achieved = algo_bytes / (ms_per_step * 1e-3) / 1e9
+    sp = sorted(per)
+    workload = "batch512_mixed_u8"
+    traffic = load_traffic(workload)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": workload, "images": len(items),
+                   "sizes": "H, W log-uniform 64..2048 (seed 5)",
+                   "windows": "square, from 3,5,9,15,31,63", "ops": "erode or dilate",
+                   "content": "document-like: white page, black rectangles, noise sigma 12",
+                   "pixels_per_step": npx, "tiles": ntiles, "row_pitch": "64-byte aligned",
+                   "launch": "one persistent kernel, hipGraph replay"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic},
+        "latency_ms": {"p50": round(sp[len(sp) // 2], 4), "p99": round(sp[min(len(sp) - 1,
+                       int(0.99 * len(sp)))], 4)},
+    }
+
+    if not args.no_extras:
+        _log("per-image baselines")
+
+        def per_image():
+            for it in items:
+                morph.apply(it["op"], it["src"], it["wx"], it["wy"], out=it["dst"])
+        pi, _ = time_launches(torch, per_image, max(3, args.steps // 4), 2, stream)
+        pi_ms = sum(pi) / len(pi)
+        g = torch.cuda.CUDAGraph()
+        per_image()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            per_image()
+        pg, _ = time_launches(torch, lambda: g.replay(), max(3, args.steps // 2), 2, stream)
+        pg_ms = sum(pg) / len(pg)
+        res["per_image"] = {
+            "eager_ms_per_step": round(pi_ms, 4),
+            "eager_gpixel_s": round(npx / (pi_ms * 1e-3) / 1e9, 3),
+            "graph_ms_per_step": round(pg_ms, 4),
+            "graph_gpixel_s": round(npx / (pg_ms * 1e-3) / 1e9, 3),
+            "batched_over_eager": round(pi_ms / ms_per_step, 2),
+            "batched_over_graph": round(pg_ms / ms_per_step, 2),
+        }
+        _log("4096x4096 kernels")
+        res["c3_4096"] = c3_lines(torch, morph, dev, max(10, args.steps))
+
+    if not args.no_cpu_baseline:
+        _log("CPU oracle baseline")
+        res["cpu_baseline"] = cpu_baseline(specs, imgs, args.cpu_budget)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

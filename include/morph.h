@@ -154,9 +154,12 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out);
  * not call set again before the previous enqueue on that stream has been
  * issued).  Too many images or tiles -> MORPH_ENOMEM. */
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream);
-/* Enqueue the whole batch on `stream`: reset the queue counter and launch the
- * persistent kernel.  The first call on a stream captures both into a hipGraph
- * that later calls replay.  workspace / ws_bytes are reserved (pass NULL, 0). */
+/* Enqueue the whole batch on `stream`: launch the persistent kernel (its last
+ * workgroup leaves the queue counter at zero for the next launch).  The first call
+ * on a stream captures the launch into a hipGraph that later calls replay; the
+ * graph is re-captured when the stream or the batch's shape changes.  Launches of
+ * one batch object must not overlap (they share the counter).  workspace /
+ * ws_bytes are reserved (pass NULL, 0). */
 int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream);
 /* Number of tiles of the current batch (after morph_batch_set), or -1. */
 int64_t morph_batch_tiles(morph_batch_t b);

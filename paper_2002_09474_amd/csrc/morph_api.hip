@@ -43,8 +43,8 @@ struct DtypeTuning {
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {5, 5, {{16, 32, 64}, {64, 64, 32}, {1 << 30, 96, 32}}},
-    {5, 5, {{16, 32, 64}, {64, 64, 32}, {1 << 30, 96, 32}}},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -246,7 +246,10 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
             if (wm <= r.wmax) {
                 // the tile input (tw + wx - 1 columns, plus up to 3 for the origin
                 // rounded down to a quad) fills exactly tq quads
-                if (!tw) tw = std::max(4, 4 * r.tq - ((j.wx + 2 + 3) & ~3));
+                // (but at least about twice the window wide, so that wide windows do
+                // not leave a tile mostly halo)
+                if (!tw)
+                    tw = std::max(4 * r.tq - ((j.wx + 2 + 3) & ~3), (2 * j.wx + 3) & ~3);
                 if (!tb) tb = r.tb;
                 break;
             }
@@ -264,7 +267,9 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         // down to a quad) and the columns a direct horizontal unit reads past the
         // last one; odd stride in dwords.  B: row pairs of the output columns (+ 3 for
         // the store's last quad); odd stride.
-        const int acols = std::max(tw + j.wx - 1 + 3, tw + kDirectChunkX + kDirectMax + 3) + 4;
+        const int acols = std::max(tw + j.wx - 1 + 3,
+                                   j.hm == PASS_DIRECT ? tw + kDirectChunkX + kDirectMax + 3 : 0) +
+                          4;
         j.SA = ((acols + 1) / 2) | 1;
         j.SB = (j.hm == PASS_NONE) ? 0 : ((tw + 4) | 1);
         const int lds = lds_bytes(j);
@@ -455,26 +460,33 @@ int morph_last_hip_error(void) { return g_last_hip_error; }
 const char *morph_version(void) { return "morph-gfx950 0.1"; }
 
 // ---------------- batched persistent launch ----------------
+// Jobs are grouped by element type and row alignment (one persistent kernel per
+// group); within a group, tiles are numbered by a prefix sum over the jobs.
+struct BatchGroup {
+    int job0 = 0, njobs = 0; // jobs [job0, job0 + njobs) of the (group-sorted) table
+    int64_t tiles = 0;
+    int lds = 0, grid = 0, dtype = 0;
+    bool aligned = true;
+};
+
 struct morph_batch {
     int max_images = 0;
     int64_t max_tiles = 0;
     TileJob *d_jobs = nullptr;
-    int64_t *d_tile_start = nullptr;
-    unsigned long long *d_counter = nullptr;
-    TileJob *h_jobs = nullptr;       // pinned staging
-    int64_t *h_tile_start = nullptr; // pinned staging
-    int n = 0;
+    int64_t *d_tile_start = nullptr;      // per group: njobs + 1 prefix sums
+    unsigned long long *d_counter = nullptr; // per group: next tile, finished workgroups
+    TileJob *h_jobs = nullptr;            // pinned staging
+    int64_t *h_tile_start = nullptr;      // pinned staging
+    std::vector<BatchGroup> groups;
     int64_t n_tiles = -1;
-    int lds = 0;
-    int grid = 0;
-    // captured graph (reset kernel + persistent kernel), valid for one stream and
-    // one (n, n_tiles, lds, grid)
+    // captured graph of the group launches, valid for one stream and one layout
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     hipStream_t graph_stream = nullptr;
-    int g_n = -1, g_lds = -1, g_grid = -1;
-    int64_t g_tiles = -1;
+    bool graph_valid = false;
 };
+
+static constexpr int kBatchGroups = 4;
 
 static int device_cus()
 {
@@ -485,6 +497,15 @@ static int device_cus()
     return cus > 0 ? cus : 256;
 }
 
+static void drop_graph(morph_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_valid = false;
+}
+
 int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
 {
     if (!out || max_images < 1 || max_tiles < 1) return MORPH_EINVAL;
@@ -492,14 +513,16 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
     morph_batch *b = new morph_batch();
     b->max_images = max_images;
     b->max_tiles = max_tiles;
+    const size_t nstart = (size_t)max_images + kBatchGroups;
+    const size_t ncount = 2 * kBatchGroups;
     hipError_t e;
     if ((e = hipMalloc((void **)&b->d_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
-        (e = hipMalloc((void **)&b->d_tile_start, sizeof(int64_t) * (max_images + 1))) !=
+        (e = hipMalloc((void **)&b->d_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long) * ncount)) !=
             hipSuccess ||
-        (e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMemset(b->d_counter, 0, sizeof(unsigned long long) * ncount)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * (max_images + 1))) !=
-            hipSuccess) {
+        (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * nstart)) != hipSuccess) {
         morph_batch_destroy(b);
         return hip_fail(e);
     }
@@ -511,8 +534,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
 {
     if (!b || n < 0 || (n > 0 && !descs)) return MORPH_EINVAL;
     if (n > b->max_images) return MORPH_ENOMEM;
-    int64_t tiles = 0;
-    int lds = 0, m = 0;
+    std::vector<TileJob> jobs[kBatchGroups];
     for (int i = 0; i < n; i++) {
         const morph_desc &d = descs[i];
         if (d.op != MORPH_OP_ERODE && d.op != MORPH_OP_DILATE) return MORPH_EINVAL;
@@ -527,31 +549,69 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, d.wx, d.wy, d.ax,
                       d.ay, nullptr, j);
         if (rc != MORPH_OK) return rc;
-        b->h_tile_start[m] = tiles;
-        b->h_jobs[m++] = j;
-        tiles += (int64_t)j.tiles_x * j.tiles_y;
-        lds = std::max(lds, lds_bytes(j));
+        jobs[2 * d.dtype + (job_rows_aligned(j) ? 0 : 1)].push_back(j);
+    }
+    std::vector<BatchGroup> groups;
+    int64_t tiles = 0;
+    int m = 0, starts = 0;
+    const int cus = device_cus();
+    for (int g = 0; g < kBatchGroups; g++) {
+        if (jobs[g].empty()) continue;
+        BatchGroup G;
+        G.job0 = m;
+        G.njobs = (int)jobs[g].size();
+        G.dtype = g / 2;
+        G.aligned = (g % 2) == 0;
+        int64_t t = 0;
+        for (const TileJob &j : jobs[g]) {
+            b->h_tile_start[starts++] = t;
+            b->h_jobs[m++] = j;
+            t += (int64_t)j.tiles_x * j.tiles_y;
+            G.lds = std::max(G.lds, lds_bytes(j));
+        }
+        b->h_tile_start[starts++] = t;
+        G.tiles = t;
+        const int per_cu = std::max(1, std::min(8, kMaxLdsBytes / std::max(G.lds + 64, 1)));
+        G.grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(t, 1));
+        tiles += t;
+        groups.push_back(G);
     }
     if (tiles > b->max_tiles) return MORPH_ENOMEM;
-    b->h_tile_start[m] = tiles;
-    b->n = m;
+    const bool same_layout = b->graph_valid && groups.size() == b->groups.size() &&
+        std::equal(groups.begin(), groups.end(), b->groups.begin(),
+                   [](const BatchGroup &x, const BatchGroup &y) {
+                       return x.job0 == y.job0 && x.njobs == y.njobs && x.tiles == y.tiles &&
+                              x.lds == y.lds && x.grid == y.grid && x.dtype == y.dtype &&
+                              x.aligned == y.aligned;
+                   });
+    if (!same_layout) drop_graph(b);
+    b->groups = groups;
     b->n_tiles = tiles;
-    b->lds = lds;
-    const int per_cu = std::max(1, std::min(8, kMaxLdsBytes / std::max(lds + 64, 1)));
-    b->grid = (int)std::min<int64_t>((int64_t)device_cus() * per_cu, std::max<int64_t>(tiles, 1));
     hipError_t e;
     if (m > 0) {
         if ((e = hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(TileJob) * m, hipMemcpyHostToDevice,
                                 stream)) != hipSuccess)
             return hip_fail(e);
-        if ((e = hipMemcpyAsync(b->d_tile_start, b->h_tile_start, sizeof(int64_t) * (m + 1),
+        if ((e = hipMemcpyAsync(b->d_tile_start, b->h_tile_start, sizeof(int64_t) * starts,
                                 hipMemcpyHostToDevice, stream)) != hipSuccess)
             return hip_fail(e);
     }
     return MORPH_OK;
 }
 
-__global__ void morph_reset_counter(unsigned long long *c) { *c = 0ull; }
+static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
+{
+    int start = 0;
+    for (size_t g = 0; g < b->groups.size(); g++) {
+        const BatchGroup &G = b->groups[g];
+        BatchTables t{b->d_jobs + G.job0, b->d_tile_start + start, G.njobs, G.tiles,
+                      b->d_counter + 2 * g};
+        start += G.njobs + 1;
+        hipError_t e = launch_batch(t, G.dtype, G.aligned, G.grid, G.lds, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream)
 {
@@ -559,32 +619,17 @@ int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipSt
     (void)ws_bytes;
     if (!b || b->n_tiles < 0) return MORPH_EINVAL;
     if (b->n_tiles == 0) return MORPH_OK;
-    const bool reuse = b->exec && b->graph_stream == stream && b->g_n == b->n &&
-                       b->g_tiles == b->n_tiles && b->g_lds == b->lds && b->g_grid == b->grid;
     hipError_t e;
     if (stream == nullptr) {
         // the legacy null stream cannot be captured: launch directly
-        BatchTables t{b->d_jobs, b->d_tile_start, b->n, b->n_tiles, b->d_counter};
-        hipLaunchKernelGGL(morph_reset_counter, dim3(1), dim3(1), 0, stream, b->d_counter);
-        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
-        if ((e = launch_batch(t, b->grid, b->lds, stream)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_groups(b, stream)) != hipSuccess) return hip_fail(e);
         return MORPH_OK;
     }
-    if (!reuse) {
-        if (b->exec) {
-            (void)hipGraphExecDestroy(b->exec);
-            b->exec = nullptr;
-        }
-        if (b->graph) {
-            (void)hipGraphDestroy(b->graph);
-            b->graph = nullptr;
-        }
-        BatchTables t{b->d_jobs, b->d_tile_start, b->n, b->n_tiles, b->d_counter};
+    if (!(b->graph_valid && b->graph_stream == stream)) {
+        drop_graph(b);
         if ((e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e);
-        hipLaunchKernelGGL(morph_reset_counter, dim3(1), dim3(1), 0, stream, b->d_counter);
-        hipError_t le = hipGetLastError();
-        if (le == hipSuccess) le = launch_batch(t, b->grid, b->lds, stream);
+        hipError_t le = launch_groups(b, stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(stream, &g);
         if (le != hipSuccess) {
@@ -595,13 +640,11 @@ int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipSt
         b->graph = g;
         if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
             b->exec = nullptr;
+            drop_graph(b);
             return hip_fail(e);
         }
         b->graph_stream = stream;
-        b->g_n = b->n;
-        b->g_tiles = b->n_tiles;
-        b->g_lds = b->lds;
-        b->g_grid = b->grid;
+        b->graph_valid = true;
     }
     if ((e = hipGraphLaunch(b->exec, stream)) != hipSuccess) return hip_fail(e);
     return MORPH_OK;
@@ -612,8 +655,7 @@ int64_t morph_batch_tiles(morph_batch_t b) { return b ? b->n_tiles : -1; }
 int morph_batch_destroy(morph_batch_t b)
 {
     if (!b) return MORPH_EINVAL;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    drop_graph(b);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_tile_start) (void)hipFree(b->d_tile_start);
     if (b->d_counter) (void)hipFree(b->d_counter);

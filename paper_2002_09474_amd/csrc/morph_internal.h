@@ -44,9 +44,11 @@ struct BatchTables {
     const int64_t *tile_start; // device prefix sums of tiles per job (n + 1 entries)
     int32_t n_jobs;
     int64_t n_tiles;
-    unsigned long long *counter; // device work-queue counter
+    unsigned long long *counter; // device: [0] next tile, [1] workgroups finished (both 0
+                                 // between launches)
 };
-hipError_t launch_batch(const BatchTables &t, int grid, int lds, hipStream_t stream);
-int batch_kernel_max_lds();
+hipError_t launch_batch(const BatchTables &t, int dtype, bool aligned, int grid, int lds,
+                        hipStream_t stream);
+bool job_rows_aligned(const TileJob &j);
 
 } // namespace morph

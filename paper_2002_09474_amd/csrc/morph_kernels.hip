@@ -196,37 +196,53 @@ template <typename T, bool AL> struct RowLoader {
     int64_t pitch;
     int H, W;
     uint32_t id;
+    uint32_t flip; // XOR applied to every loaded pixel (complement for dilation-as-erosion)
+    // AL: the pitch is a multiple of the quad size (4 bytes for uint8, 8 for uint16)
+    // and the image spans less than 4 GiB.  Quads are then addressed as 32-bit
+    // offsets from abase, src rounded down to the quad size, and mis is how many
+    // pixels src lies past abase; quad columns gx are chosen with gx + mis a
+    // multiple of 4, so every quad is one naturally aligned load.
+    const uint8_t *abase;
+    int mis;
 
-    // AL: images whose rows are aligned and whose whole span is below 4 GiB are
-    // addressed with 32-bit offsets from the uniform base pointer.
+    __device__ __forceinline__ RowLoader(const uint8_t *src_, int64_t pitch_, int H_, int W_,
+                                         uint32_t id_, uint32_t flip_)
+        : src(src_), pitch(pitch_), H(H_), W(W_), id(id_), flip(flip_)
+    {
+        const uintptr_t m = (uintptr_t)src_ & (4 * sizeof(T) - 1);
+        abase = src_ - m;
+        mis = (int)(m / sizeof(T));
+    }
     __device__ __forceinline__ RawQuad<T> at(uint32_t off) const
     {
         RawQuad<T> r;
-        if constexpr (sizeof(T) == 1) r.d = *(const uint32_t *)(src + off);
-        else r.d = *(const uint2 *)(src + off);
+        if constexpr (sizeof(T) == 1) r.d = *(const uint32_t *)(abase + off);
+        else r.d = *(const uint2 *)(abase + off);
         return r;
     }
+    // offset of the quad at (gy, gx); gx + mis >= 0 for every quad that touches the
+    // image, as gx > -4 and gx + mis is a multiple of 4
     __device__ __forceinline__ uint32_t offset(int gy, int gx) const
     {
-        return (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx * (uint32_t)sizeof(T);
+        return (uint32_t)gy * (uint32_t)pitch + (uint32_t)(gx + mis) * (uint32_t)sizeof(T);
     }
-    static __device__ __forceinline__ void widen(const RawQuad<T> &r, uint32_t &a, uint32_t &b)
+    __device__ __forceinline__ static bool touches(int gx, int W) { return gx > -4 && gx < W; }
+    __device__ __forceinline__ void widen(const RawQuad<T> &r, uint32_t &a, uint32_t &b) const
     {
         if constexpr (sizeof(T) == 1) {
-            a = perm(0u, r.d, SEL_U8_01);
-            b = perm(0u, r.d, SEL_U8_23);
+            a = perm(0u, r.d, SEL_U8_01) ^ flip;
+            b = perm(0u, r.d, SEL_U8_23) ^ flip;
         } else {
-            a = r.d.x;
-            b = r.d.y;
+            a = r.d.x ^ flip;
+            b = r.d.y ^ flip;
         }
     }
-    // 16-bit lane masks of the quad at gx: pixels gx + j < W (all lanes off when
-    // the quad is outside the image)
+    // 16-bit lane masks of the quad at gx: lane j survives when 0 <= gx + j < W
     __device__ __forceinline__ void col_masks(int gx, uint32_t &m01, uint32_t &m23) const
     {
-        const int n = (unsigned)gx < (unsigned)W ? min(W - gx, 4) : 0;
-        m01 = n >= 2 ? 0xffffffffu : (n == 1 ? 0x0000ffffu : 0u);
-        m23 = n >= 4 ? 0xffffffffu : (n == 3 ? 0x0000ffffu : 0u);
+        const int lo = max(-gx, 0), hi = min(W - gx, 4); // surviving lanes [lo, hi)
+        m01 = (lo <= 0 && hi > 0 ? 0x0000ffffu : 0u) | (lo <= 1 && hi > 1 ? 0xffff0000u : 0u);
+        m23 = (lo <= 2 && hi > 2 ? 0x0000ffffu : 0u) | (lo <= 3 && hi > 3 ? 0xffff0000u : 0u);
     }
     __device__ __forceinline__ uint32_t sel(uint32_t m, uint32_t x) const
     {
@@ -236,10 +252,14 @@ template <typename T, bool AL> struct RowLoader {
     __device__ __forceinline__ void load_any(int gy, int gx, bool want, uint32_t &a,
                                              uint32_t &b) const
     {
-        if (want && (unsigned)gy < (unsigned)H)
-            Px<T>::load(src + (int64_t)gy * pitch, gx, W, id, a, b);
-        else
+        if (want && (unsigned)gy < (unsigned)H) {
+            // masked pixels come back as id ^ flip, so after the flip they are id
+            Px<T>::load(src + (int64_t)gy * pitch, gx, W, id ^ flip, a, b);
+            a ^= flip;
+            b ^= flip;
+        } else {
             a = b = id;
+        }
     }
 };
 
@@ -273,7 +293,7 @@ __device__ __forceinline__ void load_rows(const RowLoader<T, AL> &L, int gy0, in
 #pragma unroll
             for (int k = 0; k < NR; k++) {
                 const int gy = gy0 + step * k;
-                ok[k] = k < n && (unsigned)gy < (unsigned)L.H && (m01 & 1u);
+                ok[k] = k < n && (unsigned)gy < (unsigned)L.H && L.touches(gx, L.W);
                 raw[k] = L.at(ok[k] ? L.offset(gy, gx) : 0u);
             }
 #pragma unroll
@@ -289,6 +309,49 @@ __device__ __forceinline__ void load_rows(const RowLoader<T, AL> &L, int gy0, in
         for (int k = 0; k < NR; k++) L.load_any(gy0 + step * k, gx, k < n, v01[k], v23[k]);
     }
 }
+
+// A batch of NR rows of one quad, split so that the next batch's loads can be in
+// flight while the current one is used: issue() sends every load without a branch
+// (rows not wanted or outside the image read the image's first element), finish()
+// widens and masks.  Used by the vHGW vertical pass, which walks long runs of rows.
+template <int NR, typename T, bool AL> struct RowBatch {
+    RawQuad<T> raw[NR];
+    uint32_t ok; // bit k: row k wanted and inside the image (column validity aside)
+    __device__ __forceinline__ void issue(const RowLoader<T, AL> &L, int gy0, int step, int gx,
+                                          int n)
+    {
+        const bool colok = L.touches(gx, L.W);
+        const uint32_t off0 = L.offset(gy0, gx); // unused (and possibly wrapped) when !ok
+        const int32_t d = step * (int32_t)L.pitch;
+        ok = 0u;
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            const int gy = gy0 + step * k;
+            const bool o = colok && k < n && (unsigned)gy < (unsigned)L.H;
+            ok |= (uint32_t)o << k;
+            raw[k] = L.at(o ? off0 + (uint32_t)(k * d) : 0u);
+        }
+    }
+    __device__ __forceinline__ void finish(const RowLoader<T, AL> &L, int gx, uint32_t *v01,
+                                           uint32_t *v23) const
+    {
+        if (ok == (1u << NR) - 1u && gx >= 0 && gx + 4 <= L.W) { // all rows and pixels inside
+#pragma unroll
+            for (int k = 0; k < NR; k++) L.widen(raw[k], v01[k], v23[k]);
+        } else {
+            uint32_t m01, m23;
+            L.col_masks(gx, m01, m23);
+#pragma unroll
+            for (int k = 0; k < NR; k++) {
+                uint32_t a, b;
+                L.widen(raw[k], a, b);
+                const bool o = (ok >> k) & 1u;
+                v01[k] = L.sel(o ? m01 : 0u, a);
+                v23[k] = L.sel(o ? m23 : 0u, b);
+            }
+        }
+    }
+};
 
 // Division of work-unit indices by a per-tile divisor d without an integer divide:
 // with m = ceil(2^32 / d), floor(u / d) = mulhi(u, m) exactly whenever u * d < 2^32,
@@ -311,12 +374,14 @@ struct FastDiv {
 // row pair) spread over the banks.
 template <typename T, bool AL> struct TileCtx {
     int tid, x0, y0, out_w, out_h, wx, wy, cy0, co, cxa, IWL, SA, SB, NQ, NP;
-    uint32_t id;
+    uint32_t id, flip;
     uint32_t *A, *B;
     RowLoader<T, AL> L;
     FastDiv fq, fp;
-    __device__ __forceinline__ TileCtx(const TileJob &J, int tile, uint32_t *lds, uint32_t id_)
-        : tid(threadIdx.x), id(id_), L{J.src, J.pitch, J.H, J.W, id_}, fq(1), fp(1)
+    __device__ __forceinline__ TileCtx(const TileJob &J, int tile, uint32_t *lds, uint32_t id_,
+                                       uint32_t flip_)
+        : tid(threadIdx.x), id(id_), flip(flip_), L(J.src, J.pitch, J.H, J.W, id_, flip_), fq(1),
+          fp(1)
     {
         const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
         x0 = tx * J.TW;
@@ -327,7 +392,7 @@ template <typename T, bool AL> struct TileCtx {
         wy = J.wy;
         const int cx0 = x0 - J.ax;
         cy0 = y0 - J.ay;
-        co = cx0 & 3;
+        co = (cx0 + (AL ? L.mis : 0)) & 3; // quads start where image column + mis is 4k
         cxa = cx0 - co;
         IWL = out_w + wx - 1 + co;
         SA = J.SA;
@@ -403,9 +468,17 @@ __device__ __forceinline__ void vpass_vhgw(const TileCtx<T, AL> &c)
         const int gx = c.cxa + 4 * q;
         const int i1 = min(i0 + wy, c.out_h + wy - 1);
         uint32_t g01 = c.id, g23 = c.id;
+        RowBatch<VB, T, AL> nxt;
+        if constexpr (AL) nxt.issue(c.L, c.cy0 + i0, 1, gx, i1 - i0);
         for (int i = i0; i < i1; i += VB) {
             uint32_t v01[VB], v23[VB];
-            load_rows<VB>(c.L, c.cy0 + i, 1, gx, i1 - i, v01, v23);
+            if constexpr (AL) {
+                const RowBatch<VB, T, AL> cur = nxt;
+                nxt.issue(c.L, c.cy0 + i + VB, 1, gx, i1 - i - VB); // in flight meanwhile
+                cur.finish(c.L, gx, v01, v23);
+            } else {
+                load_rows<VB>(c.L, c.cy0 + i, 1, gx, i1 - i, v01, v23);
+            }
 #pragma unroll
             for (int k = 0; k < VB; k++) {
                 g01 = pk<MAXOP>(g01, v01[k]);
@@ -425,9 +498,17 @@ __device__ __forceinline__ void vpass_vhgw(const TileCtx<T, AL> &c)
         const int b = c.fq.div(u), q = u - b * c.NQ, i0 = b * wy;
         const int gx = c.cxa + 4 * q;
         uint32_t h01 = c.id, h23 = c.id;
+        RowBatch<VB, T, AL> nxt;
+        if constexpr (AL) nxt.issue(c.L, c.cy0 + i0 + wy - 1, -1, gx, wy);
         for (int i = i0 + wy - 1; i >= i0; i -= VB) {
             uint32_t v01[VB], v23[VB];
-            load_rows<VB>(c.L, c.cy0 + i, -1, gx, i - i0 + 1, v01, v23);
+            if constexpr (AL) {
+                const RowBatch<VB, T, AL> cur = nxt;
+                nxt.issue(c.L, c.cy0 + i - VB, -1, gx, i - VB - i0 + 1);
+                cur.finish(c.L, gx, v01, v23);
+            } else {
+                load_rows<VB>(c.L, c.cy0 + i, -1, gx, i - i0 + 1, v01, v23);
+            }
 #pragma unroll
             for (int k = 0; k < VB; k++) {
                 h01 = pk<MAXOP>(h01, v01[k]);
@@ -564,32 +645,44 @@ __device__ __forceinline__ void store_pairs(const TileCtx<T, AL> &c, const TileJ
         const uint32_t c0 = o[0], c1 = o[1], c2 = o[2], c3 = o[3];
         const int y = c.y0 + 2 * p, x = c.x0 + 4 * q;
         uint8_t *row = J.dst + (int64_t)y * J.pitch;
-        Px<T>::store(row, x, J.W, perm(c1, c0, SEL_LO16_PAIR), perm(c3, c2, SEL_LO16_PAIR));
+        Px<T>::store(row, x, J.W, perm(c1, c0, SEL_LO16_PAIR) ^ c.flip,
+                     perm(c3, c2, SEL_LO16_PAIR) ^ c.flip);
         if (2 * p + 1 < c.out_h)
-            Px<T>::store(row + J.pitch, x, J.W, perm(c1, c0, SEL_HI16_PAIR),
-                         perm(c3, c2, SEL_HI16_PAIR));
+            Px<T>::store(row + J.pitch, x, J.W, perm(c1, c0, SEL_HI16_PAIR) ^ c.flip,
+                         perm(c3, c2, SEL_HI16_PAIR) ^ c.flip);
     }
 }
 
 template <typename T, bool AL>
 __device__ __forceinline__ void store_rows(const TileCtx<T, AL> &c, const TileJob &J)
 {
-    // from A (rows), when there is no horizontal pass (co == 0 then, as wx == 1 and
-    // ax == 0 put the tile origin on x0, a multiple of 4)
+    // from A (rows), when there is no horizontal pass: output column x0 + k is LDS
+    // column co + k, so odd co shifts every quad by half a dword
     const int NQo = (c.out_w + 3) >> 2;
     const FastDiv fo(NQo);
     for (int u = c.tid; u < NQo * c.out_h; u += NT) {
         const int s = fo.div(u), q = u - s * NQo;
-        const uint32_t *a = c.arow(s, q);
-        Px<T>::store(J.dst + (int64_t)(c.y0 + s) * J.pitch, c.x0 + 4 * q, J.W, a[0], a[1]);
+        const uint32_t *a = c.A + s * c.SA + ((c.co + 4 * q) >> 1);
+        uint32_t x = a[0], y = a[1];
+        if (c.co & 1) {
+            const uint32_t z = a[2];
+            x = __builtin_amdgcn_alignbit(y, x, 16);
+            y = __builtin_amdgcn_alignbit(z, y, 16);
+        }
+        Px<T>::store(J.dst + (int64_t)(c.y0 + s) * J.pitch, c.x0 + 4 * q, J.W, x ^ c.flip,
+                     y ^ c.flip);
     }
 }
 
+// One tile.  flip = 0 computes op MAXOP directly; the batch kernel instead runs every
+// job as an erosion (MAXOP false) and passes flip = the type's all-ones value for
+// dilations: max(x) = maxv - min(maxv - x), and maxv - x is x ^ maxv.
 template <typename T, bool MAXOP, bool AL>
-__device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *lds)
+__device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *lds,
+                                          uint32_t flip = 0u)
 {
     const uint32_t id = MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16));
-    const TileCtx<T, AL> c(J, tile, lds, id);
+    const TileCtx<T, AL> c(J, tile, lds, id, flip);
     switch (J.vcode) {
     case 1: vpass_direct<1, MAXOP>(c); break;
     case 2: vpass_direct<2, MAXOP>(c); break;
@@ -640,14 +733,15 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileJob J)
 
 typedef void (*TileKernelFn)(TileJob);
 
-// Rows are "aligned" when every row starts on a 4-byte (uint8) or 8-byte (uint16)
-// boundary, so each quad of 4 pixels is one natural load, and the image spans less
-// than 4 GiB, so 32-bit offsets address it.
+// Rows are "aligned" when the pitch is a multiple of 4 bytes (uint8) or 8 bytes
+// (uint16): with the tile origin placed where the address is a multiple of the quad
+// size, each quad of 4 pixels in every row is then one natural load.  The image
+// must also span less than 4 GiB, so 32-bit offsets address it.
 __host__ __device__ inline bool rows_aligned(const TileJob &j)
 {
     const uintptr_t m = j.dtype == 0 ? 3u : 7u;
     const uint64_t span = (uint64_t)(j.H - 1) * (uint64_t)j.pitch + (uint64_t)j.W * (j.dtype ? 2 : 1);
-    return (((uintptr_t)j.src | (uintptr_t)j.pitch) & m) == 0 && span < (1ull << 32);
+    return ((uintptr_t)j.pitch & m) == 0 && span + 8 < (1ull << 32);
 }
 
 static TileKernelFn pick_kernel(const TileJob &j)
@@ -676,21 +770,18 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
 }
 
 // ---------------- persistent batch kernel ----------------
-// Every workgroup takes tile indices from one atomic counter until the batch is
-// exhausted; a tile index is mapped to its image by binary search over the prefix
+// One launch per group of jobs sharing the element type and row alignment; erosion
+// and dilation jobs share it through the complement (tile_body's flip).  Every
+// workgroup takes tile indices from one atomic counter (counter[0]) until the group
+// is exhausted; a tile index is mapped to its image by binary search over the prefix
 // sums of tiles per image.  Every wave leaves the loop once the counter passes the
 // tile count, so the grid always drains.
-template <typename T, bool MAXOP>
-__device__ void run_job_tile(const TileJob &J, int t, uint32_t *lds)
-{
-    if (rows_aligned(J)) tile_body<T, MAXOP, true>(J, t, lds);
-    else tile_body<T, MAXOP, false>(J, t, lds);
-}
-
+template <typename T, bool AL>
 __global__ __launch_bounds__(NT) void batch_kernel(BatchTables bt)
 {
     extern __shared__ uint32_t lds[];
     __shared__ long long next_tile;
+    constexpr uint32_t all_ones = Px<T>::maxv | (Px<T>::maxv << 16);
     for (;;) {
         if (threadIdx.x == 0) next_tile = (long long)atomicAdd(bt.counter, 1ull);
         __syncthreads();
@@ -704,29 +795,39 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchTables bt)
             else hi = mid - 1;
         }
         const TileJob J = bt.jobs[lo];
-        const int lt = (int)(t - bt.tile_start[lo]);
-        if (J.dtype == 0) {
-            if (J.op) run_job_tile<uint8_t, true>(J, lt, lds);
-            else run_job_tile<uint8_t, false>(J, lt, lds);
-        } else {
-            if (J.op) run_job_tile<uint16_t, true>(J, lt, lds);
-            else run_job_tile<uint16_t, false>(J, lt, lds);
-        }
+        tile_body<T, false, AL>(J, (int)(t - bt.tile_start[lo]), lds, J.op ? all_ones : 0u);
         __syncthreads(); // LDS is reused by the next tile
+    }
+    // The last workgroup to finish puts both counters back to zero for the next
+    // launch (every other workgroup has left the loop by then), so a replayed graph
+    // needs no separate reset.
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(bt.counter + 1, 1ull) == (unsigned long long)gridDim.x - 1) {
+            atomicExch(bt.counter, 0ull);
+            atomicExch(bt.counter + 1, 0ull);
+        }
     }
 }
 
-int batch_kernel_max_lds() { return kMaxLdsBytes - 64; }
 
-hipError_t launch_batch(const BatchTables &t, int grid, int lds, hipStream_t stream)
+// Batches are launched per group of jobs with the same element type and row
+// alignment (dtype 0/1, aligned or not).
+hipError_t launch_batch(const BatchTables &t, int dtype, bool aligned, int grid, int lds,
+                        hipStream_t stream)
 {
+    typedef void (*BatchFn)(BatchTables);
+    BatchFn fn = dtype == 0 ? (aligned ? batch_kernel<uint8_t, true> : batch_kernel<uint8_t, false>)
+                            : (aligned ? batch_kernel<uint16_t, true> : batch_kernel<uint16_t, false>);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)batch_kernel,
+        hipError_t e = hipFuncSetAttribute((const void *)fn,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(NT), lds, stream, t);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, stream, t);
     return hipGetLastError();
 }
+
+bool job_rows_aligned(const TileJob &j) { return rows_aligned(j); }
 
 } // namespace morph

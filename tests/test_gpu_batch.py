@@ -1,0 +1,116 @@
+"""GPU parity of the batched persistent launch: every image of a mixed batch (sizes,
+windows, anchors, ops, uint8 and uint16, aligned and unaligned rows) equals the
+CPU oracle and the single-image call, on the first launch and on graph replays,
+after re-setting the batch to a smaller one, and on a non-default stream."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2002_09474_amd as morph  # noqa: E402
+from paper_2002_09474_amd import synth  # noqa: E402
+from gpuutil import to_dev, to_host  # noqa: E402
+
+
+def _items(n, seed, dtype_mix=True):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        H = int(rng.integers(1, 300))
+        W = int(rng.integers(1, 300))
+        dt = np.uint16 if (dtype_mix and i % 3 == 2) else np.uint8
+        img = synth.uniform(H, W, dt, seed=seed * 1000 + i)
+        w = int(rng.choice([1, 2, 3, 5, 9, 15, 31, 63]))
+        wy = int(rng.choice([w, 1, 3]))
+        ax = int(rng.integers(-1, w))
+        ay = int(rng.integers(-1, wy))
+        op = "erode" if rng.integers(0, 2) else "dilate"
+        pitch = W + int(rng.choice([0, 0, 1, 3, 61]))
+        off = int(rng.choice([0, 0, 1]))
+        src, _ = to_dev(img, pitch_elems=pitch, offset_elems=off)
+        dst, _ = to_dev(np.zeros_like(img), pitch_elems=pitch, offset_elems=off)
+        out.append(dict(img=img, src=src, dst=dst, wx=w, wy=wy, ax=ax, ay=ay, op=op))
+    return out
+
+
+def _want(it):
+    return oracle.morph(it["img"], 0 if it["op"] == "erode" else 1, it["wx"], it["wy"],
+                        it["ax"], it["ay"], method="direct")
+
+
+def test_batch_matches_oracle_and_single_calls():
+    items = _items(40, seed=1)
+    b = morph.Batch(64, 1 << 20)
+    ntiles = b.set(items)
+    assert ntiles > len(items) // 2
+    for rep in range(3):  # first launch captures the graph, then two replays
+        for it in items:
+            it["dst"].zero_()
+        torch.cuda.synchronize()
+        b.enqueue()
+        torch.cuda.synchronize()
+        for k, it in enumerate(items):
+            got = to_host(it["dst"])
+            assert np.array_equal(got, _want(it)), (rep, k, it["img"].shape, it["wx"], it["wy"])
+    # the single-image call gives the same bytes
+    for it in items[:10]:
+        single = morph.apply(it["op"], it["src"], it["wx"], it["wy"], it["ax"], it["ay"])
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(single), to_host(it["dst"]))
+    # a smaller batch on the same object, on another stream
+    small = _items(5, seed=2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.set(small, stream=s)
+        b.enqueue(stream=s)
+        b.enqueue(stream=s)
+    s.synchronize()
+    for it in small:
+        assert np.array_equal(to_host(it["dst"]), _want(it))
+    b.close()
+
+
+def test_batch_limits_and_errors():
+    items = _items(3, seed=3, dtype_mix=False)
+    b = morph.Batch(2, 1 << 20)
+    with pytest.raises(morph.MorphError) as ei:
+        b.set(items)
+    assert ei.value.status == -5  # too many images
+    b.close()
+    b = morph.Batch(8, 1)
+    with pytest.raises(morph.MorphError) as ei:
+        b.set(items)
+    assert ei.value.status == -5  # too many tiles
+    b.close()
+    b = morph.Batch(8, 1 << 20)
+    bad = dict(items[0])
+    bad["dst"] = bad["src"]
+    with pytest.raises(morph.MorphError) as ei:
+        b.set([bad])
+    assert ei.value.status == -2  # src and dst overlap
+    assert b.set([]) == 0
+    b.enqueue()  # empty batch: nothing to do
+    b.close()
+
+
+def test_batch_of_document_images_like_the_benchmark():
+    specs = synth.batch_specs(24, seed=5, hi=700)
+    imgs = synth.batch_images(specs, seed=5)
+    items = []
+    for s, im in zip(specs, imgs):
+        src, _ = to_dev(im, pitch_elems=(s["W"] + 63) // 64 * 64)
+        dst, _ = to_dev(np.zeros_like(im), pitch_elems=(s["W"] + 63) // 64 * 64)
+        items.append(dict(img=im, src=src, dst=dst, wx=s["w"], wy=s["w"], ax=-1, ay=-1,
+                          op=s["op"]))
+    b = morph.Batch(32, 1 << 20)
+    b.set(items)
+    b.enqueue()
+    torch.cuda.synchronize()
+    for it in items:
+        assert np.array_equal(to_host(it["dst"]), _want(it))
+    b.close()
