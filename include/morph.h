@@ -135,11 +135,12 @@ typedef struct morph_desc {
     const void *src;
     void *dst;
     int32_t H, W;
-    int64_t pitch;   /* bytes */
+    int64_t pitch;     /* bytes between source rows */
     int32_t wx, wy;
-    int32_t ax, ay;  /* -1 = Eq. (1) placement */
-    int32_t op;      /* MORPH_OP_ERODE or MORPH_OP_DILATE */
-    int32_t dtype;   /* MORPH_U8 or MORPH_U16 */
+    int32_t ax, ay;    /* -1 = Eq. (1) placement */
+    int32_t op;        /* MORPH_OP_ERODE or MORPH_OP_DILATE */
+    int32_t dtype;     /* MORPH_U8 or MORPH_U16 */
+    int64_t dst_pitch; /* bytes between destination rows; 0 = pitch */
 } morph_desc;
 
 typedef struct morph_batch *morph_batch_t;
@@ -150,9 +151,10 @@ typedef struct morph_batch *morph_batch_t;
 int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out);
 /* Validate n descriptors (as the single-image calls do; overlapping src/dst of one
  * descriptor -> MORPH_EALIAS), plan their tiles and copy the tables to the device
- * on `stream` (the host copy is staged in pinned memory owned by the batch; do
- * not call set again before the previous enqueue on that stream has been
- * issued).  Too many images or tiles -> MORPH_ENOMEM. */
+ * on `stream`, staged through pinned memory owned by the batch (a later set first
+ * waits, on the host, for that copy to finish).  Launches enqueued before a set
+ * on the same stream read the old tables.  Too many images or tiles ->
+ * MORPH_ENOMEM. */
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream);
 /* Enqueue the whole batch on `stream`: launch the persistent kernel (its last
  * workgroup leaves the queue counter at zero for the next launch).  The first call
@@ -161,6 +163,9 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
  * one batch object must not overlap (they share the counter).  workspace /
  * ws_bytes are reserved (pass NULL, 0). */
 int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream);
+/* Enqueue the batch on `stream` as plain kernel launches, without a graph: for
+ * callers whose batch changes on every launch (a serving loop). */
+int morph_batch_launch(morph_batch_t b, hipStream_t stream);
 /* Number of tiles of the current batch (after morph_batch_set), or -1. */
 int64_t morph_batch_tiles(morph_batch_t b);
 /* Free the device tables and graphs.  The caller must have synchronized. */

@@ -127,21 +127,22 @@ class Batch:
         self._keep = []
 
     def set(self, items, stream=None) -> int:
-        """items: iterable of dicts with src, dst (tensors), wx, wy, op ("erode" /
-        "dilate") and optional ax, ay.  Returns the number of tiles."""
+        """items: iterable of dicts with src, dst (tensors of the same shape and dtype;
+        each may have its own row pitch), wx, wy, op ("erode" / "dilate") and
+        optional ax, ay.  Returns the number of tiles."""
         items = list(items)
         arr = (_lib.Desc * max(1, len(items)))()
         keep = []
         for i, it in enumerate(items):
             s, d = it["src"], it["dst"]
             H, W, pitch = _geom(s)
-            if _geom(d)[2] != pitch or d.shape != s.shape or d.dtype != s.dtype:
-                raise ValueError("dst must match src in shape, dtype and pitch")
+            if d.shape != s.shape or d.dtype != s.dtype:
+                raise ValueError("dst must match src in shape and dtype")
             wx = int(it["wx"])
             wy = int(it.get("wy", wx))
             arr[i] = _lib.Desc(s.data_ptr(), d.data_ptr(), H, W, pitch, wx, wy,
                                int(it.get("ax", -1)), int(it.get("ay", -1)),
-                               _lib.OP_CODES[it["op"]], dtype_code(s.dtype))
+                               _lib.OP_CODES[it["op"]], dtype_code(s.dtype), _geom(d)[2])
             keep.append((s, d))
         _lib.check(_lib.lib().morph_batch_set(self._h, arr, len(items), _stream_ptr(stream)),
                    "morph_batch_set")
@@ -153,8 +154,14 @@ class Batch:
         return int(_lib.lib().morph_batch_tiles(self._h))
 
     def enqueue(self, stream=None) -> None:
+        """Graph-replayed launch (captured on first use per stream and layout)."""
         _lib.check(_lib.lib().morph_batch_enqueue(self._h, None, 0, _stream_ptr(stream)),
                    "morph_batch_enqueue")
+
+    def launch(self, stream=None) -> None:
+        """Plain launch without a graph, for batches that change every time."""
+        _lib.check(_lib.lib().morph_batch_launch(self._h, _stream_ptr(stream)),
+                   "morph_batch_launch")
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -12,6 +12,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_build", "libmorph_hip.so")
+TUNING_PATH = os.path.join(HERE, "tuning_gfx950.json")
 
 MORPH_OK = 0
 MORPH_EINVAL = -1
@@ -31,6 +32,7 @@ EXPORTS = (
     "morph_erode", "morph_dilate", "morph_erode_u16", "morph_dilate_u16",
     "morph_workspace_bytes", "morph_open", "morph_close", "morph_open_u16", "morph_close_u16",
     "morph_apply", "morph_batch_create", "morph_batch_set", "morph_batch_enqueue",
+    "morph_batch_launch",
     "morph_batch_tiles", "morph_batch_destroy", "morph_load_tuning", "morph_get_thresholds",
     "morph_set_thresholds", "morph_resolve_plan", "morph_strerror", "morph_last_hip_error",
     "morph_version",
@@ -59,7 +61,8 @@ class Desc(ctypes.Structure):
                 ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("pitch", ctypes.c_int64),
                 ("wx", ctypes.c_int32), ("wy", ctypes.c_int32),
                 ("ax", ctypes.c_int32), ("ay", ctypes.c_int32),
-                ("op", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+                ("op", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("dst_pitch", ctypes.c_int64)]
 
 
 _lib = None
@@ -96,6 +99,8 @@ def lib():
     L.morph_batch_set.restype = I
     L.morph_batch_enqueue.argtypes = [P, P, Z, P]
     L.morph_batch_enqueue.restype = I
+    L.morph_batch_launch.argtypes = [P, P]
+    L.morph_batch_launch.restype = I
     L.morph_batch_tiles.argtypes = [P]
     L.morph_batch_tiles.restype = I64
     L.morph_batch_destroy.argtypes = [P]
@@ -115,6 +120,8 @@ def lib():
     L.morph_version.argtypes = []
     L.morph_version.restype = ctypes.c_char_p
     _lib = L
+    if os.path.exists(TUNING_PATH):  # the autotuner's table for this GPU, if committed
+        L.morph_load_tuning(TUNING_PATH.encode())
     return L
 
 

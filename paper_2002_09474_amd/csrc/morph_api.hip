@@ -198,8 +198,8 @@ int default_anchor(int w) { return w - 1 - w / 2; }
 // Fill a TileJob for one erosion/dilation.  Windows are clipped to the image: with
 // anchor a and right extent r = w - 1 - a, only min(a, W-1) columns to the left and
 // min(r, W-1) to the right can ever be inside the image.
-int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch, int wx,
-             int wy, int ax, int ay, const morph_plan *plan, TileJob &j)
+int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
+             size_t dpitch, int wx, int wy, int ax, int ay, const morph_plan *plan, TileJob &j)
 {
     if (ax < 0) ax = default_anchor(wx);
     if (ay < 0) ay = default_anchor(wy);
@@ -210,6 +210,7 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     j.H = H;
     j.W = W;
     j.pitch = (int64_t)pitch;
+    j.dpitch = (int64_t)dpitch;
     j.wx = axe + rxe + 1;
     j.wy = aye + rye + 1;
     j.ax = axe;
@@ -301,7 +302,7 @@ int run_single(int op, int dtype, const void *src, void *dst, int H, int W, size
                int wy, int ax, int ay, const morph_plan *plan, hipStream_t stream)
 {
     TileJob j;
-    int rc = plan_job(op, dtype, src, dst, H, W, pitch, wx, wy, ax, ay, plan, j);
+    int rc = plan_job(op, dtype, src, dst, H, W, pitch, pitch, wx, wy, ax, ay, plan, j);
     if (rc != MORPH_OK) return rc;
     hipError_t e = launch_tile_job(j, stream);
     if (e != hipSuccess) return hip_fail(e);
@@ -430,8 +431,9 @@ int morph_resolve_plan(int dtype, int H, int W, int wx, int wy, morph_plan *plan
     if (dtype != MORPH_U8 && dtype != MORPH_U16) return MORPH_EUNSUPPORTED;
     TileJob j;
     const morph_plan in = *plan;
-    int rc = plan_job(MORPH_OP_ERODE, dtype, (const void *)16, (void *)16, H, W,
-                      (size_t)W * elem_bytes(dtype), wx, wy, -1, -1, &in, j);
+    const size_t p = (size_t)W * elem_bytes(dtype);
+    int rc = plan_job(MORPH_OP_ERODE, dtype, (const void *)16, (void *)16, H, W, p, p, wx, wy, -1,
+                      -1, &in, j);
     if (rc != MORPH_OK) return rc;
     plan->method_x = j.hm == PASS_NONE ? MORPH_METHOD_AUTO
                                        : (j.hm == PASS_DIRECT ? MORPH_METHOD_DIRECT : MORPH_METHOD_VHGW);
@@ -484,6 +486,10 @@ struct morph_batch {
     hipGraph_t graph = nullptr;
     hipStream_t graph_stream = nullptr;
     bool graph_valid = false;
+    // the pinned staging tables are copied asynchronously: set() waits for the
+    // previous copy before it overwrites them
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
 };
 
 static constexpr int kBatchGroups = 4;
@@ -522,7 +528,8 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
             hipSuccess ||
         (e = hipMemset(b->d_counter, 0, sizeof(unsigned long long) * ncount)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * nstart)) != hipSuccess) {
+        (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess) {
         morph_batch_destroy(b);
         return hip_fail(e);
     }
@@ -534,19 +541,27 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
 {
     if (!b || n < 0 || (n > 0 && !descs)) return MORPH_EINVAL;
     if (n > b->max_images) return MORPH_ENOMEM;
+    if (b->staged_pending) {
+        hipError_t e = hipEventSynchronize(b->staged);
+        if (e != hipSuccess) return hip_fail(e);
+        b->staged_pending = false;
+    }
     std::vector<TileJob> jobs[kBatchGroups];
     for (int i = 0; i < n; i++) {
         const morph_desc &d = descs[i];
         if (d.op != MORPH_OP_ERODE && d.op != MORPH_OP_DILATE) return MORPH_EINVAL;
-        if (d.pitch < 0) return MORPH_EINVAL;
+        if (d.pitch < 0 || d.dst_pitch < 0) return MORPH_EINVAL;
+        const size_t dp = d.dst_pitch ? (size_t)d.dst_pitch : (size_t)d.pitch;
         int rc = check_image(d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, d.wx, d.wy, d.ax,
                              d.ay, MORPH_BORDER_NEUTRAL);
         if (rc != MORPH_OK) return rc;
         if (d.H == 0 || d.W == 0) continue;
-        const size_t span = image_span(d.H, d.W, (size_t)d.pitch, d.dtype);
-        if (ranges_overlap(d.src, span, d.dst, span)) return MORPH_EALIAS;
+        if (dp < (size_t)d.W * elem_bytes(d.dtype) || dp % elem_bytes(d.dtype)) return MORPH_EINVAL;
+        if (ranges_overlap(d.src, image_span(d.H, d.W, (size_t)d.pitch, d.dtype), d.dst,
+                           image_span(d.H, d.W, dp, d.dtype)))
+            return MORPH_EALIAS;
         TileJob j;
-        rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, d.wx, d.wy, d.ax,
+        rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, dp, d.wx, d.wy, d.ax,
                       d.ay, nullptr, j);
         if (rc != MORPH_OK) return rc;
         jobs[2 * d.dtype + (job_rows_aligned(j) ? 0 : 1)].push_back(j);
@@ -595,6 +610,8 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         if ((e = hipMemcpyAsync(b->d_tile_start, b->h_tile_start, sizeof(int64_t) * starts,
                                 hipMemcpyHostToDevice, stream)) != hipSuccess)
             return hip_fail(e);
+        if ((e = hipEventRecord(b->staged, stream)) != hipSuccess) return hip_fail(e);
+        b->staged_pending = true;
     }
     return MORPH_OK;
 }
@@ -650,12 +667,21 @@ int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipSt
     return MORPH_OK;
 }
 
+int morph_batch_launch(morph_batch_t b, hipStream_t stream)
+{
+    if (!b || b->n_tiles < 0) return MORPH_EINVAL;
+    if (b->n_tiles == 0) return MORPH_OK;
+    hipError_t e = launch_groups(b, stream);
+    return e == hipSuccess ? MORPH_OK : hip_fail(e);
+}
+
 int64_t morph_batch_tiles(morph_batch_t b) { return b ? b->n_tiles : -1; }
 
 int morph_batch_destroy(morph_batch_t b)
 {
     if (!b) return MORPH_EINVAL;
     drop_graph(b);
+    if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_tile_start) (void)hipFree(b->d_tile_start);
     if (b->d_counter) (void)hipFree(b->d_counter);

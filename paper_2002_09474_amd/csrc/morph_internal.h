@@ -20,7 +20,8 @@ struct TileJob {
     const uint8_t *src;
     uint8_t *dst;
     int32_t H, W;
-    int64_t pitch;   // bytes
+    int64_t pitch;   // bytes between source rows
+    int64_t dpitch;  // bytes between destination rows
     int32_t wx, wy;  // effective window
     int32_t ax, ay;  // effective anchors
     int32_t TW, TB;  // output tile: TW columns (multiple of 4), TB rows (even)

@@ -644,11 +644,11 @@ __device__ __forceinline__ void store_pairs(const TileCtx<T, AL> &c, const TileJ
         const uint32_t *o = c.B + p * c.SB + 4 * q;
         const uint32_t c0 = o[0], c1 = o[1], c2 = o[2], c3 = o[3];
         const int y = c.y0 + 2 * p, x = c.x0 + 4 * q;
-        uint8_t *row = J.dst + (int64_t)y * J.pitch;
+        uint8_t *row = J.dst + (int64_t)y * J.dpitch;
         Px<T>::store(row, x, J.W, perm(c1, c0, SEL_LO16_PAIR) ^ c.flip,
                      perm(c3, c2, SEL_LO16_PAIR) ^ c.flip);
         if (2 * p + 1 < c.out_h)
-            Px<T>::store(row + J.pitch, x, J.W, perm(c1, c0, SEL_HI16_PAIR) ^ c.flip,
+            Px<T>::store(row + J.dpitch, x, J.W, perm(c1, c0, SEL_HI16_PAIR) ^ c.flip,
                          perm(c3, c2, SEL_HI16_PAIR) ^ c.flip);
     }
 }
@@ -669,7 +669,7 @@ __device__ __forceinline__ void store_rows(const TileCtx<T, AL> &c, const TileJo
             x = __builtin_amdgcn_alignbit(y, x, 16);
             y = __builtin_amdgcn_alignbit(z, y, 16);
         }
-        Px<T>::store(J.dst + (int64_t)(c.y0 + s) * J.pitch, c.x0 + 4 * q, J.W, x ^ c.flip,
+        Px<T>::store(J.dst + (int64_t)(c.y0 + s) * J.dpitch, c.x0 + 4 * q, J.W, x ^ c.flip,
                      y ^ c.flip);
     }
 }

@@ -33,7 +33,9 @@ def _items(n, seed, dtype_mix=True):
         pitch = W + int(rng.choice([0, 0, 1, 3, 61]))
         off = int(rng.choice([0, 0, 1]))
         src, _ = to_dev(img, pitch_elems=pitch, offset_elems=off)
-        dst, _ = to_dev(np.zeros_like(img), pitch_elems=pitch, offset_elems=off)
+        # the destination may have a row pitch of its own
+        dpitch = W + int(rng.choice([0, 5, 64])) if i % 2 else pitch
+        dst, _ = to_dev(np.zeros_like(img), pitch_elems=dpitch, offset_elems=off)
         out.append(dict(img=img, src=src, dst=dst, wx=w, wy=wy, ax=ax, ay=ay, op=op))
     return out
 
