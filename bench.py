@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-image baselines and the 4096x4096 lines")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run --steps plain device copies of MIB mebibytes (the known-size "
+                         "reference for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -181,6 +184,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        per, _ = time_launches(torch, lambda: b.copy_(a), args.steps, args.warmup, stream)
+        ms = sum(per) / len(per)
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms": round(ms, 5),
+                          "gbs": round(2 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
+        return
 
     _log("building the 512-image batch")
     specs, imgs, items, npx, _pools = build_batch(torch, morph, synth, dev)
