@@ -126,11 +126,14 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
                 int wx, int wy, int anchor_x, int anchor_y, int border,
                 const morph_plan *plan, void *workspace, size_t ws_bytes, hipStream_t stream);
 
-/* ---- batched persistent launch --------------------------------------------
- * Many images of uneven sizes, windows and ops in one launch of a persistent
- * kernel whose workgroups take tiles from an atomic work queue.  Not in the
- * paper (which handles one image at a time); it applies the same per-image
- * computation, so every image's result equals its single-image call. */
+/* ---- batched launch ---------------------------------------------------------
+ * Many images of uneven sizes, windows and ops in a few kernel launches, one per
+ * group of images sharing a kernel kind, element type and row alignment.  Images
+ * whose two passes are both direct go to a kernel with one wave per strip unit
+ * (a unit table, no shared state); the others to a persistent kernel whose
+ * workgroups take tiles from an atomic work queue.  Not in the paper (which
+ * handles one image at a time); it applies the same per-image computation, so
+ * every image's result equals its single-image call. */
 typedef struct morph_desc {
     const void *src;
     void *dst;
@@ -146,8 +149,9 @@ typedef struct morph_desc {
 typedef struct morph_batch *morph_batch_t;
 
 /* Create a batch object able to hold up to max_images descriptors and max_tiles
- * tiles in total.  It owns small device tables (descriptors, tile prefix sums,
- * a queue counter) allocated here, once; nothing is allocated per launch. */
+ * tiles (work units) in total, 1 <= max_tiles < 2^31 - 4, else MORPH_EINVAL.  It owns device tables (descriptors, tile prefix sums, a job
+ * index per tile: 4 bytes per tile, queue counters) and pinned staging copies of
+ * them, allocated here, once; nothing is allocated per launch. */
 int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out);
 /* Validate n descriptors (as the single-image calls do; overlapping src/dst of one
  * descriptor -> MORPH_EALIAS), plan their tiles and copy the tables to the device
@@ -156,8 +160,9 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out);
  * on the same stream read the old tables.  Too many images or tiles ->
  * MORPH_ENOMEM. */
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream);
-/* Enqueue the whole batch on `stream`: launch the persistent kernel (its last
- * workgroup leaves the queue counter at zero for the next launch).  The first call
+/* Enqueue the whole batch on `stream`: launch the group kernels (the last
+ * workgroup of a persistent one leaves its queue counter at zero for the next
+ * launch).  The first call
  * on a stream captures the launch into a hipGraph that later calls replay; the
  * graph is re-captured when the stream or the batch's shape changes.  Launches of
  * one batch object must not overlap (they share the counter).  workspace /
@@ -173,9 +178,12 @@ int morph_batch_destroy(morph_batch_t b);
 
 /* ---- misc ------------------------------------------------------------------ */
 /* Load a tuning table (JSON written by the autotuner) replacing the current one:
- * per-dtype direct/vHGW thresholds and tile shapes per window bucket, e.g.
- *   {"u8": {"t_x": 5, "t_y": 5, "tiles": [{"wmax": 16, "tw": 128, "tb": 64}, ...]}}
- * A dtype missing from the file keeps its table.  NULL restores the built-in
+ * per-dtype direct/vHGW thresholds, tile shapes per window bucket (tq = input
+ * quads of a tile row, tb = output rows) and the output rows of a wave unit
+ * (a multiple of 8, at most 64), e.g.
+ *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16,
+ *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
+ * A dtype missing from the file keeps its table; a key missing keeps its value.  NULL restores the built-in
  * defaults.  A malformed file returns MORPH_EINVAL and changes nothing. */
 int morph_load_tuning(const char *json_path);
 /* Current per-pass direct->vHGW thresholds for a dtype (direct when w <= t). */

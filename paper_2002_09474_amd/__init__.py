@@ -14,6 +14,7 @@ image count as the identity (max for erosion, 0 for dilation).
 from __future__ import annotations
 
 import ctypes
+import os
 
 from . import _lib
 from ._lib import MorphError, Plan  # noqa: F401
@@ -175,8 +176,17 @@ class Batch:
             pass
 
 
-def load_tuning(path: str) -> None:
-    _lib.check(_lib.lib().morph_load_tuning(path.encode()), "morph_load_tuning(%s)" % path)
+def load_tuning(path=None) -> None:
+    """Load a tuning table (JSON, as the autotuner writes it).  ``None`` restores the
+    package default: the built-in table, then ``tuning_gfx950.json`` if it exists."""
+    L = _lib.lib()
+    if path is None:
+        _lib.check(L.morph_load_tuning(None), "morph_load_tuning(NULL)")
+        if os.path.exists(_lib.TUNING_PATH):
+            path = _lib.TUNING_PATH
+        else:
+            return
+    _lib.check(L.morph_load_tuning(path.encode()), "morph_load_tuning(%s)" % path)
 
 
 def get_thresholds(dtype_name: str = "u8"):

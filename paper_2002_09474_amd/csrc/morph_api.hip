@@ -39,12 +39,13 @@ struct TileRule {
 struct DtypeTuning {
     int t_x, t_y; // direct when w <= t (per pass)
     std::vector<TileRule> tiles;
+    int wave_rows; // output rows of a wave unit (both passes direct), multiple of kWaveRows
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -140,6 +141,13 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_x = (int)it->second.num;
     it = o.obj.find("t_y");
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_y = (int)it->second.num;
+    it = o.obj.find("wave_rows");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
+        t.wave_rows = r;
+    }
     it = o.obj.find("tiles");
     if (it != o.obj.end()) {
         if (it->second.k != JVal::ARR) return false;
@@ -237,6 +245,19 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     j.vcode = (j.vm == PASS_DIRECT) ? j.wy : 0;
     j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
 
+    // both passes direct and no tile asked for: the register-only wave kernel
+    j.kind = KIND_TILE;
+    if (j.vm == PASS_DIRECT && j.hm != PASS_VHGW && !(plan && (plan->tile_w > 0 || plan->tile_h > 0))) {
+        j.kind = KIND_WAVE;
+        j.TW = 4 * kWaveQuads;
+        j.TB = std::min(tu.wave_rows, (H + kWaveRows - 1) / kWaveRows * kWaveRows);
+        j.SA = j.SB = 0;
+        j.vrun = j.vtt = 0;
+        j.tiles_x = (W + j.TW - 1) / j.TW;
+        j.tiles_y = (H + j.TB - 1) / j.TB;
+        if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
+        return MORPH_OK;
+    }
     // tile shape
     int tw = plan && plan->tile_w > 0 ? plan->tile_w : 0;
     int tb = plan && plan->tile_h > 0 ? plan->tile_h : 0;
@@ -273,6 +294,22 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
                           4;
         j.SA = ((acols + 1) / 2) | 1;
         j.SB = (j.hm == PASS_NONE) ? 0 : ((tw + 4) | 1);
+        // vertical vHGW: split each block into runs so that a tile has about one run per
+        // thread; run totals (2 dwords per run and quad) live where B is, before the
+        // horizontal pass needs it
+        j.vrun = 0;
+        j.vtt = 0;
+        if (j.vm == PASS_VHGW) {
+            const int nq = (tw + j.wx - 1 + 3 + 3) / 4;           // quads, upper bound
+            const int nbf = (tb + j.wy - 1 + j.wy - 1) / j.wy;    // blocks, upper bound
+            int ns = std::max(1, (kThreads + nq * nbf - 1) / (nq * nbf));
+            ns = std::min(ns, (j.wy + kVhgwBatch - 1) / kVhgwBatch);
+            int run = (j.wy + ns - 1) / ns;
+            run = (run + kVhgwBatch - 1) / kVhgwBatch * kVhgwBatch;
+            ns = (j.wy + run - 1) / run;
+            j.vrun = run;
+            j.vtt = ns > 1 ? 2 * nq * nbf * ns : 0;
+        }
         const int lds = lds_bytes(j);
         if (lds <= 64 * 1024) break;
         if (user_tile && lds <= kMaxLdsBytes) break;
@@ -467,7 +504,7 @@ const char *morph_version(void) { return "morph-gfx950 0.1"; }
 struct BatchGroup {
     int job0 = 0, njobs = 0; // jobs [job0, job0 + njobs) of the (group-sorted) table
     int64_t tiles = 0;
-    int lds = 0, grid = 0, dtype = 0;
+    int lds = 0, grid = 0, dtype = 0, kind = 0;
     bool aligned = true;
 };
 
@@ -476,6 +513,8 @@ struct morph_batch {
     int64_t max_tiles = 0;
     TileJob *d_jobs = nullptr;
     int64_t *d_tile_start = nullptr;      // per group: njobs + 1 prefix sums
+    int32_t *d_tile_job = nullptr;        // per group: job (within the group) of each tile
+    int32_t *h_tile_job = nullptr;        // pinned staging
     unsigned long long *d_counter = nullptr; // per group: next tile, finished workgroups
     TileJob *h_jobs = nullptr;            // pinned staging
     int64_t *h_tile_start = nullptr;      // pinned staging
@@ -492,7 +531,7 @@ struct morph_batch {
     bool staged_pending = false;
 };
 
-static constexpr int kBatchGroups = 4;
+static constexpr int kBatchGroups = 8; // kernel kind x element type x row alignment
 
 static int device_cus()
 {
@@ -514,7 +553,7 @@ static void drop_graph(morph_batch *b)
 
 int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
 {
-    if (!out || max_images < 1 || max_tiles < 1) return MORPH_EINVAL;
+    if (!out || max_images < 1 || max_tiles < 1 || max_tiles > INT32_MAX - 4) return MORPH_EINVAL;
     *out = nullptr;
     morph_batch *b = new morph_batch();
     b->max_images = max_images;
@@ -524,6 +563,10 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
     hipError_t e;
     if ((e = hipMalloc((void **)&b->d_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
         (e = hipMalloc((void **)&b->d_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_tile_job, sizeof(int32_t) * (size_t)max_tiles)) !=
+            hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_tile_job, sizeof(int32_t) * (size_t)max_tiles)) !=
+            hipSuccess ||
         (e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long) * ncount)) !=
             hipSuccess ||
         (e = hipMemset(b->d_counter, 0, sizeof(unsigned long long) * ncount)) != hipSuccess ||
@@ -564,7 +607,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, dp, d.wx, d.wy, d.ax,
                       d.ay, nullptr, j);
         if (rc != MORPH_OK) return rc;
-        jobs[2 * d.dtype + (job_rows_aligned(j) ? 0 : 1)].push_back(j);
+        jobs[4 * j.kind + 2 * d.dtype + (job_rows_aligned(j) ? 0 : 1)].push_back(j);
     }
     std::vector<BatchGroup> groups;
     int64_t tiles = 0;
@@ -575,7 +618,8 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         BatchGroup G;
         G.job0 = m;
         G.njobs = (int)jobs[g].size();
-        G.dtype = g / 2;
+        G.kind = g / 4;
+        G.dtype = (g / 2) % 2;
         G.aligned = (g % 2) == 0;
         int64_t t = 0;
         for (const TileJob &j : jobs[g]) {
@@ -586,18 +630,32 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         }
         b->h_tile_start[starts++] = t;
         G.tiles = t;
-        const int per_cu = std::max(1, std::min(8, kMaxLdsBytes / std::max(G.lds + 64, 1)));
-        G.grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(t, 1));
+        if (G.kind == KIND_WAVE) {
+            // one wave per unit, four per workgroup: the grid covers every unit
+            G.grid = (int)std::max<int64_t>((t + 3) / 4, 1);
+        } else {
+            const int per_cu = std::max(1, std::min(8, kMaxLdsBytes / std::max(G.lds + 64, 1)));
+            G.grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(t, 1));
+        }
         tiles += t;
         groups.push_back(G);
     }
     if (tiles > b->max_tiles) return MORPH_ENOMEM;
+    {
+        int64_t at = 0;
+        for (const BatchGroup &G : groups)
+            for (int jj = 0; jj < G.njobs; jj++) {
+                const TileJob &j = b->h_jobs[G.job0 + jj];
+                const int64_t nt = (int64_t)j.tiles_x * j.tiles_y;
+                for (int64_t k = 0; k < nt; k++) b->h_tile_job[at++] = jj;
+            }
+    }
     const bool same_layout = b->graph_valid && groups.size() == b->groups.size() &&
         std::equal(groups.begin(), groups.end(), b->groups.begin(),
                    [](const BatchGroup &x, const BatchGroup &y) {
                        return x.job0 == y.job0 && x.njobs == y.njobs && x.tiles == y.tiles &&
                               x.lds == y.lds && x.grid == y.grid && x.dtype == y.dtype &&
-                              x.aligned == y.aligned;
+                              x.aligned == y.aligned && x.kind == y.kind;
                    });
     if (!same_layout) drop_graph(b);
     b->groups = groups;
@@ -610,6 +668,9 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         if ((e = hipMemcpyAsync(b->d_tile_start, b->h_tile_start, sizeof(int64_t) * starts,
                                 hipMemcpyHostToDevice, stream)) != hipSuccess)
             return hip_fail(e);
+        if ((e = hipMemcpyAsync(b->d_tile_job, b->h_tile_job, sizeof(int32_t) * (size_t)tiles,
+                                hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(e);
         if ((e = hipEventRecord(b->staged, stream)) != hipSuccess) return hip_fail(e);
         b->staged_pending = true;
     }
@@ -619,12 +680,14 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
 static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
 {
     int start = 0;
+    int64_t tstart = 0;
     for (size_t g = 0; g < b->groups.size(); g++) {
         const BatchGroup &G = b->groups[g];
-        BatchTables t{b->d_jobs + G.job0, b->d_tile_start + start, G.njobs, G.tiles,
-                      b->d_counter + 2 * g};
+        BatchTables t{b->d_jobs + G.job0, b->d_tile_start + start, b->d_tile_job + tstart,
+                      G.njobs, G.tiles, b->d_counter + 2 * g};
         start += G.njobs + 1;
-        hipError_t e = launch_batch(t, G.dtype, G.aligned, G.grid, G.lds, stream);
+        tstart += G.tiles;
+        hipError_t e = launch_batch(t, G.kind, G.dtype, G.aligned, G.grid, G.lds, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -684,6 +747,8 @@ int morph_batch_destroy(morph_batch_t b)
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_tile_start) (void)hipFree(b->d_tile_start);
+    if (b->d_tile_job) (void)hipFree(b->d_tile_job);
+    if (b->h_tile_job) (void)hipHostFree(b->h_tile_job);
     if (b->d_counter) (void)hipFree(b->d_counter);
     if (b->h_jobs) (void)hipHostFree(b->h_jobs);
     if (b->h_tile_start) (void)hipHostFree(b->h_tile_start);

@@ -9,9 +9,16 @@ namespace morph {
 constexpr int kThreads = 256;  // threads per workgroup of every kernel
 constexpr int kDirectMax = 9;  // largest window the direct (sliding) passes take
 constexpr int kDirectChunkX = 8; // output columns per direct horizontal work unit
+constexpr int kVhgwBatch = 8;    // rows the vertical vHGW pass loads at a time
 constexpr int kMaxLdsBytes = 160 * 1024;
 
 enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2 };
+// KIND_TILE: a workgroup per tile through LDS (any windows).  KIND_WAVE: both passes
+// direct, a wave per strip of kWaveQuads output quads and TB rows (a multiple of
+// kWaveRows, done kWaveRows at a time), in registers.
+enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1 };
+constexpr int kWaveQuads = 60;
+constexpr int kWaveRows = 8;
 
 // One image as the tile kernels see it.  Windows and anchors are the effective
 // ones: both extents of the rectangle are clipped to the image size, which does
@@ -30,11 +37,19 @@ struct TileJob {
     int32_t vm, hm;  // PassMode of the vertical / horizontal pass
     int32_t vcode;   // vertical pass: 1..9 direct with that window, 0 vHGW
     int32_t hcode;   // horizontal pass: 1 none, 2..9 direct with that window, 0 vHGW
+    int32_t vrun;    // vertical vHGW: rows per run (a multiple of kVhgwBatch); a block of wy
+                     // rows is scanned as ceil(wy / vrun) runs joined by their totals
+    int32_t vtt;     // dwords of LDS for the run totals (shares B's space)
+    int32_t kind;    // KernelKind
     int32_t op;      // 0 erode, 1 dilate
     int32_t dtype;   // 0 u8, 1 u16
 };
 
-inline int lds_bytes(const TileJob &j) { return (j.TB * j.SA + (j.TB / 2) * j.SB) * 4; }
+inline int lds_bytes(const TileJob &j)
+{
+    const int b = (j.TB / 2) * j.SB;
+    return (j.TB * j.SA + (b > j.vtt ? b : j.vtt)) * 4;
+}
 
 // kernels (morph_kernels.hip)
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);
@@ -43,12 +58,13 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);
 struct BatchTables {
     const TileJob *jobs;       // device array of jobs
     const int64_t *tile_start; // device prefix sums of tiles per job (n + 1 entries)
+    const int32_t *tile_job;   // device: job of every tile (n_tiles entries)
     int32_t n_jobs;
     int64_t n_tiles;
     unsigned long long *counter; // device: [0] next tile, [1] workgroups finished (both 0
-                                 // between launches)
+                                 // between launches); not used by wave groups
 };
-hipError_t launch_batch(const BatchTables &t, int dtype, bool aligned, int grid, int lds,
+hipError_t launch_batch(const BatchTables &t, int kind, int dtype, bool aligned, int grid, int lds,
                         hipStream_t stream);
 bool job_rows_aligned(const TileJob &j);
 

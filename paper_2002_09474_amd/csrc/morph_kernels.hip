@@ -62,7 +62,14 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
-__device__ __forceinline__ uint32_t load_u32(uintptr_t a) { return *(const uint32_t *)a; }
+// Image memory is always device (global) memory: address it as such, so that the
+// compiler emits global_* rather than flat_* accesses also where the pointer comes
+// from a table in memory (the batch kernels).
+#define GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ uint32_t load_u32(uintptr_t a) { return *(const GLOBAL uint32_t *)a; }
+__device__ __forceinline__ void store_u32(uintptr_t a, uint32_t v) { *(GLOBAL uint32_t *)a = v; }
+__device__ __forceinline__ void store_u8(uintptr_t a, uint8_t v) { *(GLOBAL uint8_t *)a = v; }
+__device__ __forceinline__ void store_u16(uintptr_t a, uint16_t v) { *(GLOBAL uint16_t *)a = v; }
 
 // Replace the 16-bit lanes of pixels outside [0, W) by the identity.
 __device__ __forceinline__ void mask_quad(int gx, int W, uint32_t id, uint32_t &p01,
@@ -110,12 +117,11 @@ template <> struct Px<uint8_t> {
         const uintptr_t ba = (uintptr_t)row + gx;
         const uint32_t d = perm(p23, p01, SEL_NARROW);
         if (gx + 4 <= W && (ba & 3u) == 0) {
-            *(uint32_t *)ba = d;
+            store_u32(ba, d);
         } else {
-            uint8_t *b = (uint8_t *)ba;
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                if (gx + j < W) b[j] = (uint8_t)(d >> (8 * j));
+                if (gx + j < W) store_u8(ba + j, (uint8_t)(d >> (8 * j)));
         }
     }
 };
@@ -147,14 +153,13 @@ template <> struct Px<uint16_t> {
     {
         const uintptr_t ba = (uintptr_t)row + 2 * (uintptr_t)gx;
         if (gx + 4 <= W && (ba & 3u) == 0) {
-            *(uint32_t *)ba = p01;
-            *(uint32_t *)(ba + 4) = p23;
+            store_u32(ba, p01);
+            store_u32(ba + 4, p23);
         } else {
-            uint16_t *b = (uint16_t *)ba;
             const uint32_t v[2] = {p01, p23};
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                if (gx + j < W) b[j] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+                if (gx + j < W) store_u16(ba + 2 * j, (uint16_t)(v[j >> 1] >> (16 * (j & 1))));
         }
     }
 };
@@ -216,8 +221,8 @@ template <typename T, bool AL> struct RowLoader {
     __device__ __forceinline__ RawQuad<T> at(uint32_t off) const
     {
         RawQuad<T> r;
-        if constexpr (sizeof(T) == 1) r.d = *(const uint32_t *)(abase + off);
-        else r.d = *(const uint2 *)(abase + off);
+        if constexpr (sizeof(T) == 1) r.d = *(const GLOBAL uint32_t *)(abase + off);
+        else r.d = __builtin_bit_cast(uint2, *(const GLOBAL uint64_t *)(abase + off));
         return r;
     }
     // offset of the quad at (gy, gx); gx + mis >= 0 for every quad that touches the
@@ -457,16 +462,30 @@ __device__ __forceinline__ void vpass_direct(const TileCtx<T, AL> &c)
 // Phase F: g over each block of wy input rows, stored in the output row it pairs with
 // (s = i - wy + 1).  Phase B: walk each block backwards; h[s] = op of rows s .. block
 // end; out[s] = op(h[s], g[s + wy - 1]), in place.  Rows are read VB at a time.
+// Work unit: one quad of columns and one run of R = vrun rows of a block (a block is
+// scanned as NS = ceil(wy / R) runs).  Phase F walks its run forward keeping the
+// running extremum from the run start, stores it in the output row it pairs with
+// (s = i - wy + 1) and records the run total.  Phase B walks a run of output rows
+// backwards: h = (suffix within the run) op (totals of the later runs of the block),
+// g = (stored prefix) op (totals of the earlier runs of its block), out = op(h, g).
+// With NS = 1 this is the plain two-phase vHGW.  Rows are read VB at a time and the
+// next batch's loads are in flight while the current one is used.
 template <bool MAXOP, typename T, bool AL>
-__device__ __forceinline__ void vpass_vhgw(const TileCtx<T, AL> &c)
+__device__ __forceinline__ void vpass_vhgw(const TileCtx<T, AL> &c, int R, int tt_quads)
 {
-    constexpr int VB = 8;
+    constexpr int VB = kVhgwBatch;
     const int wy = c.wy;
-    const int NBF = (c.out_h + wy - 1 + wy - 1) / wy;
-    for (int u = c.tid; u < c.NQ * NBF; u += NT) {
-        const int b = c.fq.div(u), q = u - b * c.NQ, i0 = b * wy;
+    const int IH = c.out_h + wy - 1;
+    const int NS = (wy + R - 1) / R;
+    const int NBF = (IH + wy - 1) / wy;
+    const int NRF = NBF * NS; // runs over all blocks of the input rows
+    uint32_t *TT = c.B;       // run totals: [(b * NS + j) * tt_quads + q] x 2 dwords
+    for (int u = c.tid; u < c.NQ * NRF; u += NT) {
+        const int r = c.fq.div(u), q = u - r * c.NQ;
+        const int b = r / NS, j = r - b * NS; // NS is small; a plain divide here is rare
         const int gx = c.cxa + 4 * q;
-        const int i1 = min(i0 + wy, c.out_h + wy - 1);
+        const int i0 = b * wy + j * R;
+        const int i1 = min(min(i0 + R, (b + 1) * wy), IH);
         uint32_t g01 = c.id, g23 = c.id;
         RowBatch<VB, T, AL> nxt;
         if constexpr (AL) nxt.issue(c.L, c.cy0 + i0, 1, gx, i1 - i0);
@@ -491,33 +510,75 @@ __device__ __forceinline__ void vpass_vhgw(const TileCtx<T, AL> &c)
                 }
             }
         }
+        if (NS > 1) {
+            uint32_t *t = TT + 2 * (r * tt_quads + q);
+            t[0] = g01;
+            t[1] = g23;
+        }
     }
     __syncthreads();
     const int NBB = (c.out_h + wy - 1) / wy;
-    for (int u = c.tid; u < c.NQ * NBB; u += NT) {
-        const int b = c.fq.div(u), q = u - b * c.NQ, i0 = b * wy;
+    for (int u = c.tid; u < c.NQ * NBB * NS; u += NT) {
+        const int r = c.fq.div(u), q = u - r * c.NQ;
+        const int b = r / NS, j = r - b * NS;
         const int gx = c.cxa + 4 * q;
+        const int s0 = b * wy + j * R;
+        if (s0 >= c.out_h) continue;
+        const int i_hi = min(min(s0 + R, (b + 1) * wy), IH); // rows of this run
+        // totals of the later runs of block b
+        uint32_t ch01 = c.id, ch23 = c.id;
+        // g carries for the runs holding p = s + wy - 1 over this run's outputs s: the
+        // first output's p is the last row of the run before run j of block b + 1 (rA);
+        // every later p lies in run j of block b + 1 (rB)
+        uint32_t cA01 = c.id, cA23 = c.id, cB01 = c.id, cB23 = c.id;
+        int pB0 = 0x7fffffff; // first p of run rB
+        if (NS > 1) {
+            for (int jj = j + 1; jj < NS; jj++) {
+                const uint32_t *t = TT + 2 * ((b * NS + jj) * tt_quads + q);
+                ch01 = pk<MAXOP>(ch01, t[0]);
+                ch23 = pk<MAXOP>(ch23, t[1]);
+            }
+            const int pA = s0 + wy - 1, pLast = min(i_hi, c.out_h) - 1 + wy - 1;
+            const int bA = pA / wy, jA = (pA - bA * wy) / R;
+            const int bB = pLast / wy, jB = (pLast - bB * wy) / R;
+            for (int jj = 0; jj < jA; jj++) {
+                const uint32_t *t = TT + 2 * ((bA * NS + jj) * tt_quads + q);
+                cA01 = pk<MAXOP>(cA01, t[0]);
+                cA23 = pk<MAXOP>(cA23, t[1]);
+            }
+            if (bB != bA || jB != jA) {
+                for (int jj = 0; jj < jB; jj++) {
+                    const uint32_t *t = TT + 2 * ((bB * NS + jj) * tt_quads + q);
+                    cB01 = pk<MAXOP>(cB01, t[0]);
+                    cB23 = pk<MAXOP>(cB23, t[1]);
+                }
+                pB0 = bB * wy + jB * R;
+            }
+        }
         uint32_t h01 = c.id, h23 = c.id;
         RowBatch<VB, T, AL> nxt;
-        if constexpr (AL) nxt.issue(c.L, c.cy0 + i0 + wy - 1, -1, gx, wy);
-        for (int i = i0 + wy - 1; i >= i0; i -= VB) {
+        if constexpr (AL) nxt.issue(c.L, c.cy0 + i_hi - 1, -1, gx, i_hi - s0);
+        for (int i = i_hi - 1; i >= s0; i -= VB) {
             uint32_t v01[VB], v23[VB];
             if constexpr (AL) {
                 const RowBatch<VB, T, AL> cur = nxt;
-                nxt.issue(c.L, c.cy0 + i - VB, -1, gx, i - VB - i0 + 1);
+                nxt.issue(c.L, c.cy0 + i - VB, -1, gx, i - VB - s0 + 1);
                 cur.finish(c.L, gx, v01, v23);
             } else {
-                load_rows<VB>(c.L, c.cy0 + i, -1, gx, i - i0 + 1, v01, v23);
+                load_rows<VB>(c.L, c.cy0 + i, -1, gx, i - s0 + 1, v01, v23);
             }
 #pragma unroll
             for (int k = 0; k < VB; k++) {
                 h01 = pk<MAXOP>(h01, v01[k]);
                 h23 = pk<MAXOP>(h23, v23[k]);
                 const int s = i - k;
-                if (s >= i0 && s < c.out_h) {
+                if (s >= s0 && s < c.out_h) {
+                    const bool inB = s + wy - 1 >= pB0;
                     uint32_t *d = c.arow(s, q);
-                    d[0] = pk<MAXOP>(h01, d[0]);
-                    d[1] = pk<MAXOP>(h23, d[1]);
+                    const uint32_t g01 = pk<MAXOP>(d[0], inB ? cB01 : cA01);
+                    const uint32_t g23 = pk<MAXOP>(d[1], inB ? cB23 : cA23);
+                    d[0] = pk<MAXOP>(pk<MAXOP>(h01, ch01), g01);
+                    d[1] = pk<MAXOP>(pk<MAXOP>(h23, ch23), g23);
                 }
             }
         }
@@ -693,7 +754,7 @@ __device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *
     case 7: vpass_direct<7, MAXOP>(c); break;
     case 8: vpass_direct<8, MAXOP>(c); break;
     case 9: vpass_direct<9, MAXOP>(c); break;
-    default: vpass_vhgw<MAXOP>(c); break;
+    default: vpass_vhgw<MAXOP>(c, J.vrun, (J.TW + J.wx - 1 + 3 + 3) / 4); break;
     }
     __syncthreads();
     if (J.hcode == 1) {
@@ -714,6 +775,160 @@ __device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *
     __syncthreads();
     store_pairs(c, J);
 }
+
+// ======================= both passes direct: one wave per strip ==================
+// When both windows are at most kDirectMax, a wave works alone on a strip of 64
+// column quads and J.TB output rows, KR rows at a time: the vertical pass in
+// registers (as above), then the horizontal pass in registers too, taking the
+// columns right of its own quad from the next lanes with wave-wide DPP shifts
+// (v_mov_b32_dpp wave_shl:1).  No LDS, no barrier.  The last lanes of the wave only
+// supply those columns: a wave stores WQ = 60 quads.  Input quad Q starts at image
+// column cxa + 4Q, where cxa = -ax - co puts the quad grid on multiples of the load
+// size; output quad Q (columns 4Q .. 4Q + 3) reads input pixels 4Q + co ..
+// 4Q + co + 3 + wx - 1.  The wy - 1 input rows that two chunks of KR rows share stay
+// in registers: a ring of KR + wy - 1 rows moves down KR rows per chunk.
+constexpr int WQ = kWaveQuads;
+constexpr int KR = kWaveRows;
+constexpr int RING = KR + kDirectMax - 1;
+
+template <int WY, typename T, bool AL>
+__device__ __forceinline__ void wv_first(const RowLoader<T, AL> &L, int gy0, int gx,
+                                         uint32_t *r01, uint32_t *r23)
+{
+    load_rows<KR + WY - 1>(L, gy0, 1, gx, KR + WY - 1, r01, r23);
+}
+
+// Output rows of this chunk from the ring; then, if another chunk follows, move the
+// ring down and issue the loads of its KR new rows (input row gnext onwards), which
+// complete while this chunk's horizontal pass and stores run.
+template <int WY, bool MAXOP, typename T, bool AL>
+__device__ __forceinline__ void wv_vertical(const RowLoader<T, AL> &L, int gnext, int gx, bool more,
+                                            uint32_t *r01, uint32_t *r23, uint32_t *o01,
+                                            uint32_t *o23)
+{
+#pragma unroll
+    for (int m = 0; m < KR; m += 2) {
+        pair_window<WY, MAXOP>(r01 + m, o01[m], o01[m + 1]);
+        pair_window<WY, MAXOP>(r23 + m, o23[m], o23[m + 1]);
+    }
+    if (more) {
+#pragma unroll
+        for (int k = 0; k < WY - 1; k++) {
+            r01[k] = r01[k + KR];
+            r23[k] = r23[k + KR];
+        }
+        load_rows<KR>(L, gnext, 1, gx, KR, r01 + WY - 1, r23 + WY - 1);
+    }
+}
+
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
+{
+    return __builtin_amdgcn_update_dpp(0u, x, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+
+template <int WX, int CO, bool MAXOP>
+__device__ __forceinline__ void wv_horizontal(uint32_t *v01, uint32_t *v23)
+{
+    constexpr int NPX = CO + WX + 3; // pixels 0 .. CO + WX + 2 of the span
+    constexpr int NQ = (NPX + 3) / 4;
+#pragma unroll
+    for (int m = 0; m < KR; m++) {
+        uint32_t d[2 * NQ]; // d[k] = pixels (2k, 2k + 1)
+        d[0] = v01[m];
+        d[1] = v23[m];
+#pragma unroll
+        for (int q = 1; q < NQ; q++) {
+            d[2 * q] = from_next_lane(d[2 * q - 2]);
+            d[2 * q + 1] = from_next_lane(d[2 * q - 1]);
+        }
+        uint32_t p[NPX - 1]; // p[k] = pixels (k, k + 1)
+#pragma unroll
+        for (int k = 0; k < NPX - 1; k++)
+            p[k] = (k & 1) ? __builtin_amdgcn_alignbit(d[(k + 1) / 2], d[(k - 1) / 2], 16)
+                           : d[k / 2];
+        uint32_t o01, o23;
+        if constexpr (WX == 1) {
+            o01 = p[CO];
+            o23 = p[CO + 2];
+        } else if constexpr (WX == 2) {
+            o01 = pk<MAXOP>(p[CO], p[CO + 1]);
+            o23 = pk<MAXOP>(p[CO + 2], p[CO + 3]);
+        } else {
+            // the two output pairs share the window starts CO + 2 .. CO + WX - 1
+            uint32_t core = p[CO + 2];
+#pragma unroll
+            for (int t = CO + 3; t < CO + WX; t++) core = pk<MAXOP>(core, p[t]);
+            o01 = pk<MAXOP>(pk<MAXOP>(core, p[CO]), p[CO + 1]);
+            o23 = pk<MAXOP>(pk<MAXOP>(core, p[CO + WX]), p[CO + WX + 1]);
+        }
+        v01[m] = o01;
+        v23[m] = o23;
+    }
+}
+
+template <bool MAXOP>
+__device__ __forceinline__ void wv_horizontal_any(int wx, int co, uint32_t *v01, uint32_t *v23)
+{
+#define MORPH_WH(W)                                                                          \
+    case W * 4 + 0: wv_horizontal<W, 0, MAXOP>(v01, v23); break;                             \
+    case W * 4 + 1: wv_horizontal<W, 1, MAXOP>(v01, v23); break;                             \
+    case W * 4 + 2: wv_horizontal<W, 2, MAXOP>(v01, v23); break;                             \
+    case W * 4 + 3: wv_horizontal<W, 3, MAXOP>(v01, v23); break;
+    switch (wx * 4 + co) {
+        MORPH_WH(1) MORPH_WH(2) MORPH_WH(3) MORPH_WH(4) MORPH_WH(5) MORPH_WH(6) MORPH_WH(7)
+        MORPH_WH(8) MORPH_WH(9)
+    default: break;
+    }
+#undef MORPH_WH
+}
+
+#define MORPH_WY_SWITCH(WYV, CALL)                                                           \
+    switch (WYV) {                                                                           \
+    case 1: CALL(1); break;                                                                  \
+    case 2: CALL(2); break;                                                                  \
+    case 3: CALL(3); break;                                                                  \
+    case 4: CALL(4); break;                                                                  \
+    case 5: CALL(5); break;                                                                  \
+    case 6: CALL(6); break;                                                                  \
+    case 7: CALL(7); break;                                                                  \
+    case 8: CALL(8); break;                                                                  \
+    default: CALL(9); break;                                                                 \
+    }
+
+template <typename T, bool MAXOP, bool AL>
+__device__ __forceinline__ void wave_body(const TileJob &J, int unit, uint32_t flip)
+{
+    const int lane = threadIdx.x & 63;
+    const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
+    const uint32_t id = MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16));
+    const RowLoader<T, AL> L(J.src, J.pitch, J.H, J.W, id, flip);
+    const int co = ((AL ? L.mis : 0) - J.ax) & 3;
+    const int Q = sx * WQ + lane;
+    const int gx = -J.ax - co + 4 * Q;
+    const int y0 = sy * J.TB;
+    const int y1 = min(y0 + J.TB, J.H);
+    uint32_t r01[RING], r23[RING];
+#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, gx, r01, r23)
+    MORPH_WY_SWITCH(J.wy, MORPH_FIRST)
+#undef MORPH_FIRST
+    for (int y = y0; y < y1; y += KR) {
+        uint32_t v01[KR], v23[KR];
+        const bool more = y + KR < y1;
+#define MORPH_VERT(W) wv_vertical<W, MAXOP>(L, y + KR - J.ay + W - 1, gx, more, r01, r23, v01, v23)
+        MORPH_WY_SWITCH(J.wy, MORPH_VERT)
+#undef MORPH_VERT
+        wv_horizontal_any<MAXOP>(J.wx, co, v01, v23); // every lane takes part in the shifts
+        if (lane < WQ) {
+            const int x = 4 * Q;
+#pragma unroll
+            for (int m = 0; m < KR; m++)
+                if (y + m < y1)
+                    Px<T>::store(J.dst + (int64_t)(y + m) * J.dpitch, x, J.W, v01[m] ^ flip,
+                                 v23[m] ^ flip);
+        }
+    }
+}
+#undef MORPH_WY_SWITCH
 
 // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  Give each
 // XCD a contiguous run of tiles so that neighbouring tiles, whose halos overlap,
@@ -755,8 +970,34 @@ static TileKernelFn pick_kernel(const TileJob &j)
     return al ? tile_kernel<uint16_t, false, true> : tile_kernel<uint16_t, false, false>;
 }
 
+template <typename T, bool MAXOP, bool AL>
+__global__ __launch_bounds__(NT) void wave_kernel(TileJob J)
+{
+    const int units = J.tiles_x * J.tiles_y;
+    const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
+                                                 (int)(threadIdx.x >> 6));
+    if (u >= units) return; // the whole wave leaves
+    wave_body<T, MAXOP, AL>(J, u, 0u);
+}
+
+static TileKernelFn pick_wave_kernel(const TileJob &j)
+{
+    const bool al = rows_aligned(j);
+    if (j.dtype == 0) {
+        if (j.op) return al ? wave_kernel<uint8_t, true, true> : wave_kernel<uint8_t, true, false>;
+        return al ? wave_kernel<uint8_t, false, true> : wave_kernel<uint8_t, false, false>;
+    }
+    if (j.op) return al ? wave_kernel<uint16_t, true, true> : wave_kernel<uint16_t, true, false>;
+    return al ? wave_kernel<uint16_t, false, true> : wave_kernel<uint16_t, false, false>;
+}
+
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
 {
+    if (job.kind == KIND_WAVE) {
+        const int units = job.tiles_x * job.tiles_y;
+        hipLaunchKernelGGL(pick_wave_kernel(job), dim3((units + 3) / 4), dim3(NT), 0, stream, job);
+        return hipGetLastError();
+    }
     TileKernelFn fn = pick_kernel(job);
     const int lds = lds_bytes(job);
     if (lds > 64 * 1024) {
@@ -782,21 +1023,18 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchTables bt)
     extern __shared__ uint32_t lds[];
     __shared__ long long next_tile;
     constexpr uint32_t all_ones = Px<T>::maxv | (Px<T>::maxv << 16);
-    for (;;) {
+    if (threadIdx.x == 0) next_tile = (long long)atomicAdd(bt.counter, 1ull);
+    __syncthreads();
+    long long t = next_tile;
+    while (t < bt.n_tiles) {
+        __syncthreads(); // everyone has read next_tile
+        // claim the following tile now, so the atomic's round trip overlaps this tile
         if (threadIdx.x == 0) next_tile = (long long)atomicAdd(bt.counter, 1ull);
-        __syncthreads();
-        const long long t = next_tile;
-        __syncthreads(); // everyone has read next_tile before thread 0 overwrites it
-        if (t >= bt.n_tiles) break;
-        int lo = 0, hi = bt.n_jobs - 1; // last job with tile_start <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (bt.tile_start[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const TileJob J = bt.jobs[lo];
-        tile_body<T, false, AL>(J, (int)(t - bt.tile_start[lo]), lds, J.op ? all_ones : 0u);
-        __syncthreads(); // LDS is reused by the next tile
+        const int jb = bt.tile_job[t];
+        const TileJob J = bt.jobs[jb];
+        tile_body<T, false, AL>(J, (int)(t - bt.tile_start[jb]), lds, J.op ? all_ones : 0u);
+        __syncthreads(); // LDS is reused by the next tile; next_tile is visible
+        t = next_tile;
     }
     // The last workgroup to finish puts both counters back to zero for the next
     // launch (every other workgroup has left the loop by then), so a replayed graph
@@ -811,14 +1049,35 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchTables bt)
 }
 
 
-// Batches are launched per group of jobs with the same element type and row
-// alignment (dtype 0/1, aligned or not).
-hipError_t launch_batch(const BatchTables &t, int dtype, bool aligned, int grid, int lds,
+// The batch form of the wave kernel: one wave per unit of the group's tile table (four
+// per workgroup), no persistence and no shared counter: units cost about the same,
+// so the hardware's workgroup dispatch balances them, and a hundred thousand small
+// units would serialise on one counter.
+template <typename T, bool AL>
+__global__ __launch_bounds__(NT) void batch_wave_kernel(BatchTables bt)
+{
+    constexpr uint32_t all_ones = Px<T>::maxv | (Px<T>::maxv << 16);
+    const int t = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
+                                                 (int)(threadIdx.x >> 6));
+    if (t >= bt.n_tiles) return; // the whole wave leaves
+    const int jb = bt.tile_job[t];
+    const TileJob J = bt.jobs[jb];
+    wave_body<T, false, AL>(J, (int)(t - bt.tile_start[jb]), J.op ? all_ones : 0u);
+}
+
+// Batches are launched per group of jobs with the same kernel kind, element type and
+// row alignment.
+hipError_t launch_batch(const BatchTables &t, int kind, int dtype, bool aligned, int grid, int lds,
                         hipStream_t stream)
 {
     typedef void (*BatchFn)(BatchTables);
-    BatchFn fn = dtype == 0 ? (aligned ? batch_kernel<uint8_t, true> : batch_kernel<uint8_t, false>)
-                            : (aligned ? batch_kernel<uint16_t, true> : batch_kernel<uint16_t, false>);
+    BatchFn fn;
+    if (kind == KIND_WAVE)
+        fn = dtype == 0 ? (aligned ? batch_wave_kernel<uint8_t, true> : batch_wave_kernel<uint8_t, false>)
+                        : (aligned ? batch_wave_kernel<uint16_t, true> : batch_wave_kernel<uint16_t, false>);
+    else
+        fn = dtype == 0 ? (aligned ? batch_kernel<uint8_t, true> : batch_kernel<uint8_t, false>)
+                        : (aligned ? batch_kernel<uint16_t, true> : batch_kernel<uint16_t, false>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)fn,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);

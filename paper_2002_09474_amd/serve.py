@@ -183,8 +183,8 @@ class GpuExecutor:
         self.slots = []
         for _ in range(n_streams):
             self.slots.append({"stream": torch.cuda.Stream(device=self.dev),
-                               "b1": morph.Batch(max_images, 1 << 24),
-                               "b2": morph.Batch(max_images, 1 << 24),
+                               "b1": morph.Batch(max_images, 1 << 20),
+                               "b2": morph.Batch(max_images, 1 << 20),
                                "busy": None})
 
     @staticmethod

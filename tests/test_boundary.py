@@ -99,6 +99,8 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert p["method_x"] == "direct" and p["method_y"] == "vhgw"
         p = morph.resolve_plan("u8", 1080, 1920, 7, 7)
         assert p["method_x"] == "direct" and p["method_y"] == "direct"
+        # both passes direct: one wave per strip of 60 quads x 8 rows
+        assert (p["tile_w"], p["tile_h"]) == (240, 8)
         # a window of 1 skips the pass
         assert morph.resolve_plan("u8", 100, 100, 1, 31)["method_x"] is None
         # windows are clipped to the image: 255x1 on a 4-wide image is a 7-wide window

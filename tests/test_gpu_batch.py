@@ -116,3 +116,24 @@ def test_batch_of_document_images_like_the_benchmark():
     for it in items:
         assert np.array_equal(to_host(it["dst"]), _want(it))
     b.close()
+
+
+def test_batch_with_many_wave_units():
+    """A batch whose direct-window images give far more wave units than the chip
+    holds waves at once (24 images of 1000x1000 with 3x3 and 9x9 windows: 15000
+    units), mixed with vHGW images: every unit is done."""
+    items = []
+    for i in range(24):
+        img = synth.uniform(1000, 1000 - 3 * i, np.uint8, seed=4000 + i)
+        src, _ = to_dev(img, pitch_elems=1024)
+        dst, _ = to_dev(np.zeros_like(img), pitch_elems=1024)
+        w = (3, 9, 31)[i % 3]
+        items.append(dict(img=img, src=src, dst=dst, wx=w, wy=w, ax=-1, ay=-1,
+                          op="erode" if i % 2 else "dilate"))
+    b = morph.Batch(32, 1 << 20)
+    assert b.set(items) > 10000
+    b.enqueue()
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        assert np.array_equal(to_host(it["dst"]), _want(it)), k
+    b.close()

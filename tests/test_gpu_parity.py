@@ -109,6 +109,31 @@ def test_tile_shapes_do_not_change_results(tile):
             _check(img, op, wx, wy, tile=tile)
 
 
+@pytest.mark.parametrize("rows", [16, 24, 64])
+def test_wave_units_of_several_row_chunks(rows, tmp_path):
+    """Both passes direct run one wave per strip unit of `rows` output rows, taken
+    8 at a time with the shared input rows carried in registers: every unit height
+    gives the oracle's result, with ragged last units and any anchor."""
+    import json
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps({"u8": {"wave_rows": rows}, "u16": {"wave_rows": rows}}))
+    morph.load_tuning(str(f))
+    try:
+        rng = np.random.default_rng(rows)
+        for dtype in (np.uint8, np.uint16):
+            for i, (H, W) in enumerate([(1, 1), (7, 300), (63, 65), (129, 257), (517, 1000)]):
+                img = synth.uniform(H, W, dtype, seed=900 + i)
+                assert morph.resolve_plan("u8" if dtype == np.uint8 else "u16", H, W, 3, 3)[
+                    "tile_h"] == min(rows, (H + 7) // 8 * 8)
+                for wx, wy in ((3, 3), (9, 9), (1, 5), (5, 1), (2, 8), (8, 2)):
+                    ax = int(rng.integers(-1, wx))
+                    ay = int(rng.integers(-1, wy))
+                    for op in ("erode", "dilate"):
+                        _check(img, op, wx, wy, ax, ay)
+    finally:
+        morph.load_tuning(None)
+
+
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 def test_pitch_offset_and_guard_bytes(dtype):
     """Strided rows, a base pointer off by one element, and sentinel bytes around
