@@ -73,12 +73,23 @@ extern "C" {
 #define MORPH_METHOD_AUTO 0
 #define MORPH_METHOD_DIRECT 1 /* sliding min/max, O(w) per pixel (§5.1.2, §5.2.2) */
 #define MORPH_METHOD_VHGW 2   /* van Herk/Gil-Werman, O(1) per pixel (§5.1.1, §5.2.1) */
+#define MORPH_METHOD_DOUBLING 3 /* horizontal only, not in the paper: log-step doubling
+                                 * min/max across a wave's lanes, O(log w) per pixel */
 
 /* Optional launch plan.  Fields left 0 are filled from the tuning table.
  * method_x / method_y force the horizontal / vertical pass algorithm (a window of
  * 1 always skips its pass); tile_w / tile_h set the output tile of one workgroup
  * (tile_w a multiple of 4, tile_h a multiple of 2).  A plan never changes the
- * result, only how it is computed. */
+ * result, only how it is computed.
+ * Kernels: both passes direct run one wave per strip in registers; with both
+ * methods AUTO and no tile, larger windows (wx <= 128, wy <= 64) run one wave per
+ * strip that streams down the rows (vertical vHGW through LDS, horizontal direct
+ * or doubling); anything else -- a forced vHGW pass, a tile, larger windows --
+ * runs the workgroup-tile kernel, which implements exactly the paper's two
+ * methods.  method_x = DOUBLING selects the streaming kernel (method_y must be
+ * AUTO or VHGW); DOUBLING for method_y, or with a tile, is MORPH_EINVAL.
+ * morph_resolve_plan reports the kernel's passes and its unit (tile_w x tile_h
+ * output pixels). */
 typedef struct morph_plan {
     int32_t method_x;
     int32_t method_y;
@@ -179,9 +190,9 @@ int morph_batch_destroy(morph_batch_t b);
 /* ---- misc ------------------------------------------------------------------ */
 /* Load a tuning table (JSON written by the autotuner) replacing the current one:
  * per-dtype direct/vHGW thresholds, tile shapes per window bucket (tq = input
- * quads of a tile row, tb = output rows) and the output rows of a wave unit
- * (a multiple of 8, at most 64), e.g.
- *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16,
+ * quads of a tile row, tb = output rows), the output rows of a direct wave unit
+ * (a multiple of 8, at most 64) and of a streaming unit (1 .. 4096), e.g.
+ *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 128,
  *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
  * A dtype missing from the file keeps its table; a key missing keeps its value.  NULL restores the built-in
  * defaults.  A malformed file returns MORPH_EINVAL and changes nothing. */

@@ -206,7 +206,7 @@ def resolve_plan(dtype_name: str, H: int, W: int, wx: int, wy: int, method_x=Non
     p = _plan(method_x, method_y, tile) or Plan(0, 0, 0, 0)
     _lib.check(_lib.lib().morph_resolve_plan(_lib.U8 if dtype_name == "u8" else _lib.U16,
                                              H, W, wx, wy, ctypes.byref(p)), "resolve_plan")
-    names = {0: None, 1: "direct", 2: "vhgw"}
+    names = {0: None, 1: "direct", 2: "vhgw", 3: "doubling"}
     return dict(method_x=names[p.method_x], method_y=names[p.method_y], tile_w=p.tile_w,
                 tile_h=p.tile_h)
 

@@ -25,7 +25,7 @@ OP_ERODE, OP_DILATE, OP_OPEN, OP_CLOSE = 0, 1, 2, 3
 OP_CODES = {"erode": OP_ERODE, "dilate": OP_DILATE, "open": OP_OPEN, "close": OP_CLOSE}
 U8, U16 = 0, 1
 METHOD_AUTO, METHOD_DIRECT, METHOD_VHGW = 0, 1, 2
-METHOD_CODES = {None: 0, "auto": 0, "direct": 1, "vhgw": 2}
+METHOD_CODES = {None: 0, "auto": 0, "direct": 1, "vhgw": 2, "doubling": 3}
 
 # every symbol include/morph.h declares
 EXPORTS = (

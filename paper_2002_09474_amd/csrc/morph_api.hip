@@ -39,13 +39,14 @@ struct TileRule {
 struct DtypeTuning {
     int t_x, t_y; // direct when w <= t (per pass)
     std::vector<TileRule> tiles;
-    int wave_rows; // output rows of a wave unit (both passes direct), multiple of kWaveRows
+    int wave_rows;   // output rows of a wave unit (both passes direct), multiple of kWaveRows
+    int stream_rows; // output rows of a streaming-kernel unit
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 128},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 128},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -148,6 +149,13 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
         t.wave_rows = r;
     }
+    it = o.obj.find("stream_rows");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r < 1 || r > 4096) return false;
+        t.stream_rows = r;
+    }
     it = o.obj.find("tiles");
     if (it != o.obj.end()) {
         if (it->second.k != JVal::ARR) return false;
@@ -229,11 +237,18 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     const DtypeTuning tu = tuning_for(dtype);
     const int mx = plan ? plan->method_x : MORPH_METHOD_AUTO;
     const int my = plan ? plan->method_y : MORPH_METHOD_AUTO;
-    if (mx < 0 || mx > 2 || my < 0 || my > 2) return MORPH_EINVAL;
+    const bool user_tile = plan && (plan->tile_w > 0 || plan->tile_h > 0);
+    if (mx < 0 || mx > 3 || my < 0 || my > 2) return MORPH_EINVAL;
+    if (mx == MORPH_METHOD_DOUBLING && (user_tile || my == MORPH_METHOD_DIRECT))
+        return MORPH_EINVAL;
+    const bool auto_both = mx == MORPH_METHOD_AUTO && my == MORPH_METHOD_AUTO;
+    const bool stream_fits = j.wx <= kStreamMaxWx && j.wy <= kStreamMaxWy;
+    if (mx == MORPH_METHOD_DOUBLING && !stream_fits) return MORPH_EUNSUPPORTED;
     // horizontal pass
     if (j.wx == 1) j.hm = PASS_NONE;
     else if (mx == MORPH_METHOD_DIRECT) j.hm = PASS_DIRECT;
     else if (mx == MORPH_METHOD_VHGW) j.hm = PASS_VHGW;
+    else if (mx == MORPH_METHOD_DOUBLING) j.hm = PASS_DOUBLING;
     else j.hm = (j.wx <= std::min(tu.t_x, kDirectMax)) ? PASS_DIRECT : PASS_VHGW;
     // vertical pass (a window of 1 is the direct pass's plain load)
     if (j.wy == 1) j.vm = PASS_DIRECT;
@@ -244,15 +259,30 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         return MORPH_EUNSUPPORTED;
     j.vcode = (j.vm == PASS_DIRECT) ? j.wy : 0;
     j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
+    j.SA = j.SB = 0;
+    j.vrun = j.vtt = 0;
 
     // both passes direct and no tile asked for: the register-only wave kernel
     j.kind = KIND_TILE;
-    if (j.vm == PASS_DIRECT && j.hm != PASS_VHGW && !(plan && (plan->tile_w > 0 || plan->tile_h > 0))) {
+    if (j.vm == PASS_DIRECT && (j.hm == PASS_DIRECT || j.hm == PASS_NONE) && !user_tile) {
         j.kind = KIND_WAVE;
         j.TW = 4 * kWaveQuads;
         j.TB = std::min(tu.wave_rows, (H + kWaveRows - 1) / kWaveRows * kWaveRows);
-        j.SA = j.SB = 0;
-        j.vrun = j.vtt = 0;
+        j.tiles_x = (W + j.TW - 1) / j.TW;
+        j.tiles_y = (H + j.TB - 1) / j.TB;
+        if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
+        return MORPH_OK;
+    }
+    // doubling asked for, or everything automatic and the windows fit: the streaming
+    // kernel (its vertical pass is vHGW through the LDS ring whatever wy is)
+    if (j.hm == PASS_DOUBLING || (auto_both && !user_tile && stream_fits)) {
+        j.kind = KIND_STREAM;
+        if (j.hm == PASS_VHGW) j.hm = PASS_DOUBLING;
+        j.vm = PASS_VHGW;
+        j.vcode = 0;
+        j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
+        j.TW = 4 * stream_quads(j.wx);
+        j.TB = std::min(tu.stream_rows, H);
         j.tiles_x = (W + j.TW - 1) / j.TW;
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
@@ -281,7 +311,6 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     const int w4 = (W + 3) & ~3;
     tw = std::min(tw, std::max(4, w4));
     tb = std::min(tb, std::max(2, (H + 1) & ~1));
-    const bool user_tile = plan && (plan->tile_w > 0 || plan->tile_h > 0);
     for (;;) {
         j.TW = tw;
         j.TB = tb;
@@ -472,8 +501,10 @@ int morph_resolve_plan(int dtype, int H, int W, int wx, int wy, morph_plan *plan
     int rc = plan_job(MORPH_OP_ERODE, dtype, (const void *)16, (void *)16, H, W, p, p, wx, wy, -1,
                       -1, &in, j);
     if (rc != MORPH_OK) return rc;
-    plan->method_x = j.hm == PASS_NONE ? MORPH_METHOD_AUTO
-                                       : (j.hm == PASS_DIRECT ? MORPH_METHOD_DIRECT : MORPH_METHOD_VHGW);
+    plan->method_x = j.hm == PASS_NONE        ? MORPH_METHOD_AUTO
+                     : j.hm == PASS_DIRECT   ? MORPH_METHOD_DIRECT
+                     : j.hm == PASS_DOUBLING ? MORPH_METHOD_DOUBLING
+                                             : MORPH_METHOD_VHGW;
     plan->method_y = (j.wy == 1) ? MORPH_METHOD_AUTO
                                  : (j.vm == PASS_DIRECT ? MORPH_METHOD_DIRECT : MORPH_METHOD_VHGW);
     plan->tile_w = j.TW;
@@ -531,7 +562,7 @@ struct morph_batch {
     bool staged_pending = false;
 };
 
-static constexpr int kBatchGroups = 8; // kernel kind x element type x row alignment
+static constexpr int kBatchGroups = 4 * kKinds; // kernel kind x element type x row alignment
 
 static int device_cus()
 {
@@ -633,6 +664,9 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         if (G.kind == KIND_WAVE) {
             // one wave per unit, four per workgroup: the grid covers every unit
             G.grid = (int)std::max<int64_t>((t + 3) / 4, 1);
+        } else if (G.kind == KIND_STREAM) {
+            // one single-wave workgroup per unit
+            G.grid = (int)std::max<int64_t>(t, 1);
         } else {
             const int per_cu = std::max(1, std::min(8, kMaxLdsBytes / std::max(G.lds + 64, 1)));
             G.grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(t, 1));

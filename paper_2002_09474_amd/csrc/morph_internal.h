@@ -12,11 +12,17 @@ constexpr int kDirectChunkX = 8; // output columns per direct horizontal work un
 constexpr int kVhgwBatch = 8;    // rows the vertical vHGW pass loads at a time
 constexpr int kMaxLdsBytes = 160 * 1024;
 
-enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2 };
+enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3 };
 // KIND_TILE: a workgroup per tile through LDS (any windows).  KIND_WAVE: both passes
 // direct, a wave per strip of kWaveQuads output quads and TB rows (a multiple of
-// kWaveRows, done kWaveRows at a time), in registers.
-enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1 };
+// kWaveRows, done kWaveRows at a time), in registers.  KIND_STREAM: a wave per strip
+// of TW / 4 output quads and TB rows, walking down the rows once: vertical vHGW
+// through a ring of wy rows in LDS, horizontal direct or log-step doubling across
+// the lanes.
+enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2 };
+constexpr int kKinds = 3;
+constexpr int kStreamMaxWx = 128; // wider windows leave a 64-quad strip too few outputs
+constexpr int kStreamMaxWy = 64;  // the ring takes 512 bytes of LDS per row
 constexpr int kWaveQuads = 60;
 constexpr int kWaveRows = 8;
 
@@ -47,6 +53,8 @@ struct TileJob {
 
 inline int lds_bytes(const TileJob &j)
 {
+    if (j.kind == KIND_WAVE) return 0;
+    if (j.kind == KIND_STREAM) return j.wy * 64 * 8; // per single-wave workgroup
     const int b = (j.TB / 2) * j.SB;
     return (j.TB * j.SA + (b > j.vtt ? b : j.vtt)) * 4;
 }
@@ -66,6 +74,9 @@ struct BatchTables {
 };
 hipError_t launch_batch(const BatchTables &t, int kind, int dtype, bool aligned, int grid, int lds,
                         hipStream_t stream);
+// output quads of a stream-kernel strip for a horizontal window wx (worst-case
+// origin offset 3): the last one's input, 4Q + 3 + wx + 2, must lie in 64 quads
+inline int stream_quads(int wx) { return (250 - wx) / 4 + 1; }
 bool job_rows_aligned(const TileJob &j);
 
 } // namespace morph

@@ -32,6 +32,8 @@
 // combines it in place.  Per pixel that is three min/max ops whatever w is.
 #include "morph_internal.h"
 
+#include <type_traits>
+
 namespace morph {
 
 constexpr int NT = kThreads;
@@ -779,32 +781,112 @@ __device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *
 // ======================= both passes direct: one wave per strip ==================
 // When both windows are at most kDirectMax, a wave works alone on a strip of 64
 // column quads and J.TB output rows, KR rows at a time: the vertical pass in
-// registers (as above), then the horizontal pass in registers too, taking the
-// columns right of its own quad from the next lanes with wave-wide DPP shifts
-// (v_mov_b32_dpp wave_shl:1).  No LDS, no barrier.  The last lanes of the wave only
-// supply those columns: a wave stores WQ = 60 quads.  Input quad Q starts at image
-// column cxa + 4Q, where cxa = -ax - co puts the quad grid on multiples of the load
-// size; output quad Q (columns 4Q .. 4Q + 3) reads input pixels 4Q + co ..
-// 4Q + co + 3 + wx - 1.  The wy - 1 input rows that two chunks of KR rows share stay
-// in registers: a ring of KR + wy - 1 rows moves down KR rows per chunk.
+// registers, then the horizontal pass in registers too, taking the columns right
+// of its own quad from the next lanes with wave-wide DPP shifts (v_mov_b32_dpp
+// wave_shl:1).  No LDS, no barrier.  The last lanes of the wave only supply those
+// columns: a wave stores WQ = 60 quads.  Input quad Q starts at image column
+// gxa + 4Q, gxa = 4 WQ sx - ax - co, where co puts the quad grid on multiples of
+// the load size; output quad Q (columns 4Q .. 4Q + 3 of the strip) reads input
+// pixels 4Q + co .. 4Q + co + 3 + wx - 1.  The wy - 1 input rows that two chunks
+// of KR rows share stay in registers: a ring of KR + wy - 1 rows moves down KR
+// rows per chunk.
+//
+// Pixels outside the image are not replaced by the identity here but by the
+// nearest image pixel (rows and columns clamped into the image).  For a flat
+// window the two give the same result: the output pixel itself lies in its window
+// and windows are contiguous, so every clamped-to row or column is already in the
+// window, and a repeated value changes no minimum or maximum.  Clamping costs no
+// per-pixel work: rows are clamped on the scalar unit, and a lane whose quad
+// reaches outside loads the nearest quad inside and picks its pixels with the
+// byte selectors of the widening v_perm (uint8) or of one v_perm per output row
+// (uint16).
 constexpr int WQ = kWaveQuads;
 constexpr int KR = kWaveRows;
 constexpr int RING = KR + kDirectMax - 1;
 
-template <int WY, typename T, bool AL>
-__device__ __forceinline__ void wv_first(const RowLoader<T, AL> &L, int gy0, int gx,
-                                         uint32_t *r01, uint32_t *r23)
+// Rows with 4-aligned (uint8) / 8-aligned (uint16) pitch: lane set-up for a unit.
+template <typename T> struct WaveLoader {
+    const uint8_t *abase; // src rounded down to the quad size
+    uint32_t pitch;       // bytes (the image spans < 4 GiB)
+    int H;
+    uint32_t voff;        // byte offset of the lane's (clamped) quad within a row
+    uint32_t s01, s23;    // v_perm selectors that pick the lane's four pixels
+
+    __device__ __forceinline__ WaveLoader(const TileJob &J, int mis, int gx)
+    {
+        abase = J.src - mis * (int)sizeof(T);
+        pitch = (uint32_t)J.pitch;
+        H = J.H;
+        // the lane's quad covers image columns gx .. gx + 3 (gx + mis a multiple of
+        // 4); outside the image, take the quad holding column 0 or W - 1
+        int gq = gx;
+        if (gx + 3 < 0) gq = -mis;
+        else if (gx > J.W - 1) gq = ((J.W - 1 + mis) & ~3) - mis;
+        voff = (uint32_t)(gq + mis) * (uint32_t)sizeof(T);
+        int b[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) b[j] = min(max(gx + j, 0), J.W - 1) - gq;
+        if constexpr (sizeof(T) == 1) {
+            // widen bytes b0, b1 (b2, b3) into the two u16 halves; 0x0c gives 0
+            s01 = (uint32_t)b[0] | 0x0c00u | ((uint32_t)b[1] << 16) | 0x0c000000u;
+            s23 = (uint32_t)b[2] | 0x0c00u | ((uint32_t)b[3] << 16) | 0x0c000000u;
+        } else {
+            // u16 halves of {p23, p01}: pixel b is bytes 2b, 2b + 1
+            s01 = (uint32_t)(2 * b[0]) | (uint32_t)(2 * b[0] + 1) << 8 |
+                  (uint32_t)(2 * b[1]) << 16 | (uint32_t)(2 * b[1] + 1) << 24;
+            s23 = (uint32_t)(2 * b[2]) | (uint32_t)(2 * b[2] + 1) << 8 |
+                  (uint32_t)(2 * b[3]) << 16 | (uint32_t)(2 * b[3] + 1) << 24;
+        }
+    }
+    // input row gy (clamped into the image; gy is the same in every lane): the load,
+    // then the lane's four pixels as two pair dwords
+    using Raw = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
+    __device__ __forceinline__ Raw issue(int gy) const
+    {
+        const uint8_t *r = abase + (uint32_t)min(max(gy, 0), H - 1) * pitch;
+        return *(const GLOBAL Raw *)(r + voff);
+    }
+    __device__ __forceinline__ void widen(Raw d, uint32_t &v01, uint32_t &v23) const
+    {
+        if constexpr (sizeof(T) == 1) {
+            v01 = perm(0u, d, s01);
+            v23 = perm(0u, d, s23);
+        } else {
+            v01 = (uint32_t)d;
+            v23 = (uint32_t)(d >> 32);
+        }
+    }
+    __device__ __forceinline__ void row(int gy, uint32_t &v01, uint32_t &v23) const
+    {
+        widen(issue(gy), v01, v23);
+    }
+    template <int N>
+    __device__ __forceinline__ void rows(int gy0, uint32_t *v01, uint32_t *v23) const
+    {
+#pragma unroll
+        for (int k = 0; k < N; k++) row(gy0 + k, v01[k], v23[k]);
+    }
+    // uint16: pick the lane's pixels from an output row computed on the raw quad
+    __device__ __forceinline__ void fix(uint32_t &v01, uint32_t &v23) const
+    {
+        const uint32_t a = perm(v23, v01, s01), b = perm(v23, v01, s23);
+        v01 = a;
+        v23 = b;
+    }
+};
+
+template <int WY, typename Ld>
+__device__ __forceinline__ void wv_first(const Ld &L, int gy0, uint32_t *r01, uint32_t *r23)
 {
-    load_rows<KR + WY - 1>(L, gy0, 1, gx, KR + WY - 1, r01, r23);
+    L.template rows<KR + WY - 1>(gy0, r01, r23);
 }
 
 // Output rows of this chunk from the ring; then, if another chunk follows, move the
 // ring down and issue the loads of its KR new rows (input row gnext onwards), which
 // complete while this chunk's horizontal pass and stores run.
-template <int WY, bool MAXOP, typename T, bool AL>
-__device__ __forceinline__ void wv_vertical(const RowLoader<T, AL> &L, int gnext, int gx, bool more,
-                                            uint32_t *r01, uint32_t *r23, uint32_t *o01,
-                                            uint32_t *o23)
+template <int WY, bool MAXOP, typename Ld>
+__device__ __forceinline__ void wv_vertical(const Ld &L, int gnext, bool more, uint32_t *r01,
+                                            uint32_t *r23, uint32_t *o01, uint32_t *o23)
 {
 #pragma unroll
     for (int m = 0; m < KR; m += 2) {
@@ -817,9 +899,38 @@ __device__ __forceinline__ void wv_vertical(const RowLoader<T, AL> &L, int gnext
             r01[k] = r01[k + KR];
             r23[k] = r23[k + KR];
         }
-        load_rows<KR>(L, gnext, 1, gx, KR, r01 + WY - 1, r23 + WY - 1);
+        L.template rows<KR>(gnext, r01 + WY - 1, r23 + WY - 1);
     }
 }
+
+// Rows of any pitch: the general loader (identity outside the image).
+template <typename T> struct WaveLoaderAny {
+    RowLoader<T, false> L;
+    int gx;
+    __device__ __forceinline__ WaveLoaderAny(const TileJob &J, uint32_t id, int gx_)
+        : L(J.src, J.pitch, J.H, J.W, id, 0u), gx(gx_)
+    {
+    }
+    template <int N>
+    __device__ __forceinline__ void rows(int gy0, uint32_t *v01, uint32_t *v23) const
+    {
+        load_rows<N>(L, gy0, 1, gx, N, v01, v23);
+    }
+    struct Raw {
+        uint32_t a, b;
+    };
+    __device__ __forceinline__ Raw issue(int gy) const
+    {
+        Raw r;
+        L.load_any(gy, gx, true, r.a, r.b);
+        return r;
+    }
+    __device__ __forceinline__ void widen(Raw d, uint32_t &v01, uint32_t &v23) const
+    {
+        v01 = d.a;
+        v23 = d.b;
+    }
+};
 
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
 {
@@ -827,43 +938,43 @@ __device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
 }
 
 template <int WX, int CO, bool MAXOP>
-__device__ __forceinline__ void wv_horizontal(uint32_t *v01, uint32_t *v23)
+__device__ __forceinline__ void wv_horizontal_row(uint32_t &v01, uint32_t &v23)
 {
     constexpr int NPX = CO + WX + 3; // pixels 0 .. CO + WX + 2 of the span
     constexpr int NQ = (NPX + 3) / 4;
+    uint32_t d[2 * NQ]; // d[k] = pixels (2k, 2k + 1)
+    d[0] = v01;
+    d[1] = v23;
 #pragma unroll
-    for (int m = 0; m < KR; m++) {
-        uint32_t d[2 * NQ]; // d[k] = pixels (2k, 2k + 1)
-        d[0] = v01[m];
-        d[1] = v23[m];
-#pragma unroll
-        for (int q = 1; q < NQ; q++) {
-            d[2 * q] = from_next_lane(d[2 * q - 2]);
-            d[2 * q + 1] = from_next_lane(d[2 * q - 1]);
-        }
-        uint32_t p[NPX - 1]; // p[k] = pixels (k, k + 1)
-#pragma unroll
-        for (int k = 0; k < NPX - 1; k++)
-            p[k] = (k & 1) ? __builtin_amdgcn_alignbit(d[(k + 1) / 2], d[(k - 1) / 2], 16)
-                           : d[k / 2];
-        uint32_t o01, o23;
-        if constexpr (WX == 1) {
-            o01 = p[CO];
-            o23 = p[CO + 2];
-        } else if constexpr (WX == 2) {
-            o01 = pk<MAXOP>(p[CO], p[CO + 1]);
-            o23 = pk<MAXOP>(p[CO + 2], p[CO + 3]);
-        } else {
-            // the two output pairs share the window starts CO + 2 .. CO + WX - 1
-            uint32_t core = p[CO + 2];
-#pragma unroll
-            for (int t = CO + 3; t < CO + WX; t++) core = pk<MAXOP>(core, p[t]);
-            o01 = pk<MAXOP>(pk<MAXOP>(core, p[CO]), p[CO + 1]);
-            o23 = pk<MAXOP>(pk<MAXOP>(core, p[CO + WX]), p[CO + WX + 1]);
-        }
-        v01[m] = o01;
-        v23[m] = o23;
+    for (int q = 1; q < NQ; q++) {
+        d[2 * q] = from_next_lane(d[2 * q - 2]);
+        d[2 * q + 1] = from_next_lane(d[2 * q - 1]);
     }
+    uint32_t p[NPX - 1]; // p[k] = pixels (k, k + 1)
+#pragma unroll
+    for (int k = 0; k < NPX - 1; k++)
+        p[k] = (k & 1) ? __builtin_amdgcn_alignbit(d[(k + 1) / 2], d[(k - 1) / 2], 16) : d[k / 2];
+    if constexpr (WX == 1) {
+        v01 = p[CO];
+        v23 = p[CO + 2];
+    } else if constexpr (WX == 2) {
+        v01 = pk<MAXOP>(p[CO], p[CO + 1]);
+        v23 = pk<MAXOP>(p[CO + 2], p[CO + 3]);
+    } else {
+        // the two output pairs share the window starts CO + 2 .. CO + WX - 1
+        uint32_t core = p[CO + 2];
+#pragma unroll
+        for (int t = CO + 3; t < CO + WX; t++) core = pk<MAXOP>(core, p[t]);
+        v01 = pk<MAXOP>(pk<MAXOP>(core, p[CO]), p[CO + 1]);
+        v23 = pk<MAXOP>(pk<MAXOP>(core, p[CO + WX]), p[CO + WX + 1]);
+    }
+}
+
+template <int WX, int CO, bool MAXOP>
+__device__ __forceinline__ void wv_horizontal(uint32_t *v01, uint32_t *v23)
+{
+#pragma unroll
+    for (int m = 0; m < KR; m++) wv_horizontal_row<WX, CO, MAXOP>(v01[m], v23[m]);
 }
 
 template <bool MAXOP>
@@ -896,39 +1007,327 @@ __device__ __forceinline__ void wv_horizontal_any(int wx, int co, uint32_t *v01,
     }
 
 template <typename T, bool MAXOP, bool AL>
-__device__ __forceinline__ void wave_body(const TileJob &J, int unit, uint32_t flip)
+__device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 {
     const int lane = threadIdx.x & 63;
     const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
-    const uint32_t id = MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16));
-    const RowLoader<T, AL> L(J.src, J.pitch, J.H, J.W, id, flip);
-    const int co = ((AL ? L.mis : 0) - J.ax) & 3;
-    const int Q = sx * WQ + lane;
-    const int gx = -J.ax - co + 4 * Q;
+    const int mis = AL ? (int)(((uintptr_t)J.src & (4 * sizeof(T) - 1)) / sizeof(T)) : 0;
+    const int co = (mis - J.ax) & 3;
+    const int gxa = 4 * WQ * sx - J.ax - co; // lane 0's first input column
+    const int gx = gxa + 4 * lane;
     const int y0 = sy * J.TB;
     const int y1 = min(y0 + J.TB, J.H);
+    // uint16 lanes whose quad reaches outside the image pick their pixels per row
+    const bool edge = gxa < 0 || gxa + 4 * 64 > J.W;
+    using Ld = typename std::conditional<AL, WaveLoader<T>, WaveLoaderAny<T>>::type;
+    const Ld L = [&]() {
+        if constexpr (AL) return WaveLoader<T>(J, mis, gx);
+        else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)), gx);
+    }();
     uint32_t r01[RING], r23[RING];
-#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, gx, r01, r23)
+#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, r01, r23)
     MORPH_WY_SWITCH(J.wy, MORPH_FIRST)
 #undef MORPH_FIRST
+    // destination: 4-byte aligned rows and a strip wholly inside the image take
+    // one plain store per row and lane
+    const int Q = WQ * sx + lane;
+    const bool fast_store = (((uintptr_t)J.dst | (uintptr_t)J.dpitch) & 3) == 0 &&
+                            4 * (WQ * sx + WQ) <= J.W;
     for (int y = y0; y < y1; y += KR) {
         uint32_t v01[KR], v23[KR];
         const bool more = y + KR < y1;
-#define MORPH_VERT(W) wv_vertical<W, MAXOP>(L, y + KR - J.ay + W - 1, gx, more, r01, r23, v01, v23)
+#define MORPH_VERT(W) wv_vertical<W, MAXOP>(L, y + KR - J.ay + W - 1, more, r01, r23, v01, v23)
         MORPH_WY_SWITCH(J.wy, MORPH_VERT)
 #undef MORPH_VERT
+        if constexpr (AL && sizeof(T) == 2) {
+            if (edge) {
+#pragma unroll
+                for (int m = 0; m < KR; m++) L.fix(v01[m], v23[m]);
+            }
+        }
         wv_horizontal_any<MAXOP>(J.wx, co, v01, v23); // every lane takes part in the shifts
         if (lane < WQ) {
-            const int x = 4 * Q;
+            uint8_t *drow = J.dst + (int64_t)y * J.dpitch;
+            if (fast_store) {
+                const uint32_t o = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
 #pragma unroll
-            for (int m = 0; m < KR; m++)
-                if (y + m < y1)
-                    Px<T>::store(J.dst + (int64_t)(y + m) * J.dpitch, x, J.W, v01[m] ^ flip,
-                                 v23[m] ^ flip);
+                for (int m = 0; m < KR; m++) {
+                    if (y + m < y1) {
+                        if constexpr (sizeof(T) == 1) {
+                            store_u32((uintptr_t)(drow + o), perm(v23[m], v01[m], SEL_NARROW));
+                        } else {
+                            store_u32((uintptr_t)(drow + o), v01[m]);
+                            store_u32((uintptr_t)(drow + o + 4), v23[m]);
+                        }
+                    }
+                    drow += J.dpitch;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < KR; m++) {
+                    if (y + m < y1) Px<T>::store(drow, 4 * Q, J.W, v01[m], v23[m]);
+                    drow += J.dpitch;
+                }
+            }
         }
     }
 }
 #undef MORPH_WY_SWITCH
+
+// ======================= larger windows: one wave per strip, streaming down =======
+// One wave per strip of 64 column quads and J.TB output rows, walking down the
+// input rows once (no LDS shared between waves, no barrier):
+//  - vertical pass, van Herk/Gil-Werman over blocks of wy input rows (the paper's
+//    vHGW, Section 3.2) with a ring of wy rows in LDS per wave: while block b + 1
+//    streams in, its prefix g runs in registers and output row s = b wy + j is
+//    min(h_b[j], g over the first j rows of block b + 1), h_b read from the ring,
+//    where the incoming row then takes its place; at the end of a block a backward
+//    walk over the ring turns it into that block's suffixes h.
+//  - horizontal pass on each output row as it is produced, across the lanes: the
+//    direct pass (wx <= kDirectMax) or, for wider windows, a log-step doubling
+//    (m_2L[k] = min(m_L[k], m_L[k + L]), then m_w[k] = min(m_L[k], m_L[k + w - L])
+//    for the largest L <= w), whose shifts are lane moves (DPP, ds_bpermute).
+// The wave stores the output quads whose input lies inside its 64 quads: J.TW / 4 of
+// them.  Pixels outside the image are the nearest image pixels, as in the direct
+// wave kernel.
+constexpr int SD = 8; // input rows per chunk (and rows in flight) per wave
+
+__device__ __forceinline__ uint32_t lane_fetch(uint32_t v, uint32_t byte_addr)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_addr, (int)v);
+}
+
+// Per-unit constants of the doubling pass.
+struct Doubling {
+    int wx;
+    bool hiq0, hiq1;   // pair lookup at offsets co (resp. co + wx - L) starts in dword 1
+    uint32_t sh0, sh1; // 16 when that offset is odd
+    uint32_t ad0, ad1; // ds_bpermute addresses of lanes + q1 and + q1 + 1, q1 = (co + wx - L) / 4
+
+    __device__ __forceinline__ Doubling(int wx_, int co)
+    {
+        wx = wx_;
+        int L = 1;
+        while (2 * L <= wx) L *= 2;
+        const int d1 = co + wx - L;
+        hiq0 = co >= 2;
+        sh0 = (co & 1) ? 16u : 0u;
+        hiq1 = (d1 & 3) >= 2;
+        sh1 = (d1 & 1) ? 16u : 0u;
+        const int lane = threadIdx.x & 63;
+        ad0 = (uint32_t)(lane + (d1 >> 2)) << 2;
+        ad1 = (uint32_t)(lane + (d1 >> 2) + 1) << 2;
+    }
+};
+
+// The horizontal passes below work on G rows at once, level by level, so that the
+// rows' chains of lane moves and min/max interleave.
+template <int G, bool MAXOP>
+__device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, uint32_t *e1)
+{
+    // a0 = (m_L[0], m_L[1]), a1 = (m_L[2], m_L[3]) for the lane's quad
+    const int lane = threadIdx.x & 63;
+    if (S.wx >= 2) { // L = 1 -> 2: shift by one pixel
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = from_next_lane(e0[r]);
+            const uint32_t s1 = __builtin_amdgcn_alignbit(e1[r], e0[r], 16);
+            const uint32_t s3 = __builtin_amdgcn_alignbit(n0, e1[r], 16);
+            e0[r] = pk<MAXOP>(e0[r], s1);
+            e1[r] = pk<MAXOP>(e1[r], s3);
+        }
+    }
+    if (S.wx >= 4) { // 2 -> 4: two pixels
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = from_next_lane(e0[r]);
+            e0[r] = pk<MAXOP>(e0[r], e1[r]);
+            e1[r] = pk<MAXOP>(e1[r], n0);
+        }
+    }
+    if (S.wx >= 8) { // 4 -> 8: one lane
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = from_next_lane(e0[r]), n1 = from_next_lane(e1[r]);
+            e0[r] = pk<MAXOP>(e0[r], n0);
+            e1[r] = pk<MAXOP>(e1[r], n1);
+        }
+    }
+    for (int q = 2; 8 * q <= S.wx; q *= 2) { // 4q -> 8q: q lanes
+        const uint32_t ad = (uint32_t)(lane + q) << 2;
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = lane_fetch(e0[r], ad), n1 = lane_fetch(e1[r], ad);
+            e0[r] = pk<MAXOP>(e0[r], n0);
+            e1[r] = pk<MAXOP>(e1[r], n1);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < G; r++) {
+        const uint32_t a0 = e0[r], a1 = e1[r];
+        // pairs at offsets co, co + 2 from [a0 a1 | next lane's a0 a1] ...
+        const uint32_t n0 = from_next_lane(a0), n1 = from_next_lane(a1);
+        const uint32_t l0 = S.hiq0 ? a1 : a0, m0 = S.hiq0 ? n0 : a1, h0 = S.hiq0 ? n1 : n0;
+        const uint32_t p0 = __builtin_amdgcn_alignbit(m0, l0, S.sh0);
+        const uint32_t p2 = __builtin_amdgcn_alignbit(h0, m0, S.sh0);
+        // ... and at co + wx - L, co + wx - L + 2 from lanes + q1, + q1 + 1
+        const uint32_t f0 = lane_fetch(a0, S.ad0), f1 = lane_fetch(a1, S.ad0);
+        const uint32_t f2 = lane_fetch(a0, S.ad1), f3 = lane_fetch(a1, S.ad1);
+        const uint32_t l1 = S.hiq1 ? f1 : f0, m1 = S.hiq1 ? f2 : f1, h1 = S.hiq1 ? f3 : f2;
+        const uint32_t r0 = __builtin_amdgcn_alignbit(m1, l1, S.sh1);
+        const uint32_t r2 = __builtin_amdgcn_alignbit(h1, m1, S.sh1);
+        e0[r] = pk<MAXOP>(p0, r0);
+        e1[r] = pk<MAXOP>(p2, r2);
+    }
+}
+
+template <int G, bool MAXOP>
+__device__ __forceinline__ void direct_rows_any(int wx, int co, uint32_t *v01, uint32_t *v23)
+{
+#define MORPH_WH1(W, C)                                                                      \
+    case W * 4 + C:                                                                          \
+        _Pragma("unroll") for (int r = 0; r < G; r++)                                        \
+            wv_horizontal_row<W, C, MAXOP>(v01[r], v23[r]);                                  \
+        break;
+#define MORPH_WH(W) MORPH_WH1(W, 0) MORPH_WH1(W, 1) MORPH_WH1(W, 2) MORPH_WH1(W, 3)
+    switch (wx * 4 + co) {
+        MORPH_WH(1) MORPH_WH(2) MORPH_WH(3) MORPH_WH(4) MORPH_WH(5) MORPH_WH(6) MORPH_WH(7)
+        MORPH_WH(8) MORPH_WH(9)
+    default: break;
+    }
+#undef MORPH_WH
+#undef MORPH_WH1
+}
+
+// Backward walk over the ring (entries wy - 1 .. 0): each becomes the suffix min.
+template <bool MAXOP>
+__device__ __forceinline__ void ring_suffixes(uint2 *ring, int wy)
+{
+    uint32_t h01 = MAXOP ? 0u : 0xffffffffu, h23 = h01;
+    for (int j = wy - 1; j >= 0; j -= 8) {
+        uint2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (j - k >= 0) v[k] = ring[64 * (j - k)];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (j - k >= 0) {
+                h01 = pk<MAXOP>(h01, v[k].x);
+                h23 = pk<MAXOP>(h23, v[k].y);
+                ring[64 * (j - k)] = make_uint2(h01, h23);
+            }
+    }
+}
+
+template <typename T, bool MAXOP, bool AL>
+__device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t *lds)
+{
+    const int lane = threadIdx.x & 63;
+    const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
+    const int mis = AL ? (int)(((uintptr_t)J.src & (4 * sizeof(T) - 1)) / sizeof(T)) : 0;
+    const int co = (mis - J.ax) & 3;
+    const int gxa = J.TW * sx - J.ax - co; // lane 0's first input column
+    const int gx = gxa + 4 * lane;
+    const int y0 = sy * J.TB;
+    const int rows = min(J.TB, J.H - y0);
+    const int wy = J.wy;
+    // input rows 0 .. last - 1 feed the outputs; input row t >= wy emits output row
+    // t - wy, so steps run up to t = last
+    const int last = rows + wy - 1;
+    const int gy0 = y0 - J.ay;
+    const bool edge = gxa < 0 || gxa + 4 * 64 > J.W;
+    using Ld = typename std::conditional<AL, WaveLoader<T>, WaveLoaderAny<T>>::type;
+    const Ld L = [&]() {
+        if constexpr (AL) return WaveLoader<T>(J, mis, gx);
+        else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)), gx);
+    }();
+    const Doubling S(J.wx, co);
+    const bool hdirect = J.wx <= kDirectMax;
+    uint2 *ring = (uint2 *)lds + lane; // entry j of the lane at ring[64 j]
+    // destination
+    const int Q = (J.TW >> 2) * sx + lane;
+    const bool store_lane = lane < (J.TW >> 2);
+    const bool fast_store = (((uintptr_t)J.dst | (uintptr_t)J.dpitch) & 3) == 0 &&
+                            J.TW * (sx + 1) <= J.W;
+    const uint32_t id = MAXOP ? 0u : 0xffffffffu;
+
+    // Rows are taken in chunks of up to SD that stay inside one block: block 0 fills
+    // the ring, every later chunk emits outputs.  The next chunk's rows are loaded
+    // while the current one is worked on.
+    typename Ld::Raw cur[SD], nxt[SD];
+#pragma unroll
+    for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + k);
+    uint32_t g01 = id, g23 = id;
+    int t = 0, j = 0;
+    bool fill = true;
+    while (t <= last) {
+        const int cnt = min(min(SD, wy - j), last - t + 1);
+#pragma unroll
+        for (int k = 0; k < SD; k++) nxt[k] = L.issue(gy0 + t + cnt + k);
+        uint32_t x01[SD], x23[SD];
+#pragma unroll
+        for (int k = 0; k < SD; k++) L.widen(cur[k], x01[k], x23[k]);
+        if (fill) {
+#pragma unroll
+            for (int k = 0; k < SD; k++)
+                if (k < cnt) ring[64 * (j + k)] = make_uint2(x01[k], x23[k]);
+        } else {
+            uint2 h[SD];
+#pragma unroll
+            for (int k = 0; k < SD; k++) h[k] = ring[64 * min(j + k, wy - 1)];
+            uint32_t o01[SD], o23[SD];
+#pragma unroll
+            for (int k = 0; k < SD; k++) {
+                // h_b[j + k] against the prefix of this block's first j + k rows
+                o01[k] = pk<MAXOP>(h[k].x, g01);
+                o23[k] = pk<MAXOP>(h[k].y, g23);
+                g01 = pk<MAXOP>(g01, x01[k]);
+                g23 = pk<MAXOP>(g23, x23[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < SD; k++)
+                if (k < cnt) ring[64 * (j + k)] = make_uint2(x01[k], x23[k]);
+            // output rows t - wy .. t - wy + cnt - 1: horizontal pass, then store
+            if constexpr (AL && sizeof(T) == 2)
+                if (edge) {
+#pragma unroll
+                    for (int k = 0; k < SD; k++) L.fix(o01[k], o23[k]);
+                }
+            if (hdirect) direct_rows_any<SD, MAXOP>(J.wx, co, o01, o23);
+            else doubling_rows<SD, MAXOP>(S, o01, o23);
+            if (store_lane) {
+                uint8_t *drow = J.dst + (int64_t)(y0 + t - wy) * J.dpitch;
+                const uint32_t o = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int k = 0; k < SD; k++) {
+                    if (k < cnt) {
+                        if (fast_store) {
+                            if constexpr (sizeof(T) == 1) {
+                                store_u32((uintptr_t)(drow + o), perm(o23[k], o01[k], SEL_NARROW));
+                            } else {
+                                store_u32((uintptr_t)(drow + o), o01[k]);
+                                store_u32((uintptr_t)(drow + o + 4), o23[k]);
+                            }
+                        } else {
+                            Px<T>::store(drow, 4 * Q, J.W, o01[k], o23[k]);
+                        }
+                    }
+                    drow += J.dpitch;
+                }
+            }
+        }
+        t += cnt;
+        j += cnt;
+        if (j == wy) { // block complete: its suffixes replace it in the ring
+            ring_suffixes<MAXOP>(ring, wy);
+            j = 0;
+            fill = false;
+            g01 = g23 = id;
+        }
+#pragma unroll
+        for (int k = 0; k < SD; k++) cur[k] = nxt[k];
+    }
+}
 
 // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  Give each
 // XCD a contiguous run of tiles so that neighbouring tiles, whose halos overlap,
@@ -977,7 +1376,7 @@ __global__ __launch_bounds__(NT) void wave_kernel(TileJob J)
     const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
                                                  (int)(threadIdx.x >> 6));
     if (u >= units) return; // the whole wave leaves
-    wave_body<T, MAXOP, AL>(J, u, 0u);
+    wave_body<T, MAXOP, AL>(J, u);
 }
 
 static TileKernelFn pick_wave_kernel(const TileJob &j)
@@ -991,8 +1390,40 @@ static TileKernelFn pick_wave_kernel(const TileJob &j)
     return al ? wave_kernel<uint16_t, false, true> : wave_kernel<uint16_t, false, false>;
 }
 
+template <typename T, bool MAXOP, bool AL>
+__global__ __launch_bounds__(64) void stream_kernel(TileJob J)
+{
+    extern __shared__ uint32_t lds[];
+    stream_body<T, MAXOP, AL>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+static TileKernelFn pick_stream_kernel(const TileJob &j)
+{
+    const bool al = rows_aligned(j);
+    if (j.dtype == 0) {
+        if (j.op) return al ? stream_kernel<uint8_t, true, true> : stream_kernel<uint8_t, true, false>;
+        return al ? stream_kernel<uint8_t, false, true> : stream_kernel<uint8_t, false, false>;
+    }
+    if (j.op) return al ? stream_kernel<uint16_t, true, true> : stream_kernel<uint16_t, true, false>;
+    return al ? stream_kernel<uint16_t, false, true> : stream_kernel<uint16_t, false, false>;
+}
+
+static hipError_t set_lds_limit(const void *fn, int lds)
+{
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
 {
+    if (job.kind == KIND_STREAM) {
+        TileKernelFn fn = pick_stream_kernel(job);
+        const int lds = lds_bytes(job);
+        hipError_t e = set_lds_limit((const void *)fn, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3(job.tiles_x * job.tiles_y), dim3(64), lds, stream, job);
+        return hipGetLastError();
+    }
     if (job.kind == KIND_WAVE) {
         const int units = job.tiles_x * job.tiles_y;
         hipLaunchKernelGGL(pick_wave_kernel(job), dim3((units + 3) / 4), dim3(NT), 0, stream, job);
@@ -1000,11 +1431,8 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
     }
     TileKernelFn fn = pick_kernel(job);
     const int lds = lds_bytes(job);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = set_lds_limit((const void *)fn, lds);
+    if (e != hipSuccess) return e;
     const int grid = job.tiles_x * job.tiles_y;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, stream, job);
     return hipGetLastError();
@@ -1056,13 +1484,28 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchTables bt)
 template <typename T, bool AL>
 __global__ __launch_bounds__(NT) void batch_wave_kernel(BatchTables bt)
 {
-    constexpr uint32_t all_ones = Px<T>::maxv | (Px<T>::maxv << 16);
     const int t = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
                                                  (int)(threadIdx.x >> 6));
     if (t >= bt.n_tiles) return; // the whole wave leaves
     const int jb = bt.tile_job[t];
     const TileJob J = bt.jobs[jb];
-    wave_body<T, false, AL>(J, (int)(t - bt.tile_start[jb]), J.op ? all_ones : 0u);
+    const int u = (int)(t - bt.tile_start[jb]);
+    if (J.op) wave_body<T, true, AL>(J, u);
+    else wave_body<T, false, AL>(J, u);
+}
+
+// The batch form of the stream kernel: one single-wave workgroup per unit.
+template <typename T, bool AL>
+__global__ __launch_bounds__(64) void batch_stream_kernel(BatchTables bt)
+{
+    extern __shared__ uint32_t lds[];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= bt.n_tiles) return;
+    const int jb = bt.tile_job[t];
+    const TileJob J = bt.jobs[jb];
+    const int u = (int)(t - bt.tile_start[jb]);
+    if (J.op) stream_body<T, true, AL>(J, u, lds);
+    else stream_body<T, false, AL>(J, u, lds);
 }
 
 // Batches are launched per group of jobs with the same kernel kind, element type and
@@ -1072,18 +1515,21 @@ hipError_t launch_batch(const BatchTables &t, int kind, int dtype, bool aligned,
 {
     typedef void (*BatchFn)(BatchTables);
     BatchFn fn;
+    int block = NT;
     if (kind == KIND_WAVE)
         fn = dtype == 0 ? (aligned ? batch_wave_kernel<uint8_t, true> : batch_wave_kernel<uint8_t, false>)
                         : (aligned ? batch_wave_kernel<uint16_t, true> : batch_wave_kernel<uint16_t, false>);
+    else if (kind == KIND_STREAM) {
+        fn = dtype == 0 ? (aligned ? batch_stream_kernel<uint8_t, true> : batch_stream_kernel<uint8_t, false>)
+                        : (aligned ? batch_stream_kernel<uint16_t, true> : batch_stream_kernel<uint16_t, false>);
+        block = 64;
+    }
     else
         fn = dtype == 0 ? (aligned ? batch_kernel<uint8_t, true> : batch_kernel<uint8_t, false>)
                         : (aligned ? batch_kernel<uint16_t, true> : batch_kernel<uint16_t, false>);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, stream, t);
+    hipError_t e = set_lds_limit((const void *)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, stream, t);
     return hipGetLastError();
 }
 

@@ -103,6 +103,20 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert (p["tile_w"], p["tile_h"]) == (240, 8)
         # a window of 1 skips the pass
         assert morph.resolve_plan("u8", 100, 100, 1, 31)["method_x"] is None
+        # larger windows: the streaming kernel (vertical vHGW, horizontal doubling)
+        # up to 128 x 64, the tile kernel beyond
+        p = morph.resolve_plan("u8", 1080, 1920, 31, 31)
+        assert (p["method_x"], p["method_y"]) == ("doubling", "vhgw")
+        assert (p["tile_w"], p["tile_h"]) == (4 * 55, 128)
+        p = morph.resolve_plan("u8", 1080, 1920, 7, 63)
+        assert (p["method_x"], p["method_y"]) == ("direct", "vhgw")
+        assert morph.resolve_plan("u8", 100, 90, 3, 3, method_x="doubling")["tile_h"] == 100
+        p = morph.resolve_plan("u8", 1080, 1920, 101, 101)
+        assert (p["method_x"], p["method_y"]) == ("vhgw", "vhgw")
+        for bad_kw in (dict(method_y="doubling"), dict(method_x="doubling", tile=(64, 32)),
+                       dict(method_x="doubling", method_y="direct")):
+            with pytest.raises(morph.MorphError):
+                morph.resolve_plan("u8", 100, 100, 15, 5, **bad_kw)
         # windows are clipped to the image: 255x1 on a 4-wide image is a 7-wide window
         p = morph.resolve_plan("u8", 4, 4, 255, 1, method_x="direct")
         assert p["method_x"] == "direct"
@@ -112,11 +126,18 @@ def test_plan_resolution_and_thresholds(tmp_path):
             {"wmax": 8, "tq": 16, "tb": 32}, {"wmax": 1000000, "tq": 40, "tb": 16}]}}))
         morph.load_tuning(str(f))
         assert morph.get_thresholds("u8") == (3, 4)
-        # the input row of a tile fills tq quads: tw + wx - 1 + 3 <= 4 tq
-        p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
+        # forced vHGW runs the workgroup-tile kernel, whose input row fills tq quads:
+        # tw + wx - 1 + 3 <= 4 tq
+        v = dict(method_x="vhgw", method_y="vhgw")
+        p = morph.resolve_plan("u8", 1000, 1000, 5, 5, **v)
         assert (p["tile_w"], p["tile_h"]) == (64 - 8, 32)
-        p = morph.resolve_plan("u8", 1000, 1000, 30, 30)
+        p = morph.resolve_plan("u8", 1000, 1000, 30, 30, **v)
         assert (p["tile_w"], p["tile_h"]) == (160 - 32, 16)
+        # automatic methods beyond the thresholds: the streaming kernel, whose strip
+        # stores the quads whose input fits in 64: (250 - wx) // 4 + 1 of them
+        p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
+        assert (p["method_x"], p["method_y"]) == ("doubling", "vhgw")
+        assert (p["tile_w"], p["tile_h"]) == (4 * 62, 128)
         bad = tmp_path / "bad.json"
         bad.write_text('{"u8": {"t_x": 3, "tiles": [{"wmax": 8, "tq": 1, "tb": 32}]}}')
         with pytest.raises(morph.MorphError):

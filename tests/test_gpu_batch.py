@@ -120,8 +120,9 @@ def test_batch_of_document_images_like_the_benchmark():
 
 def test_batch_with_many_wave_units():
     """A batch whose direct-window images give far more wave units than the chip
-    holds waves at once (24 images of 1000x1000 with 3x3 and 9x9 windows: 15000
-    units), mixed with vHGW images: every unit is done."""
+    holds waves at once (16 images of about 1000x1000 with 3x3 and 9x9 windows:
+    over 9000 units), mixed with 31x31 images on the streaming kernel: every unit
+    is done."""
     items = []
     for i in range(24):
         img = synth.uniform(1000, 1000 - 3 * i, np.uint8, seed=4000 + i)
@@ -131,7 +132,7 @@ def test_batch_with_many_wave_units():
         items.append(dict(img=img, src=src, dst=dst, wx=w, wy=w, ax=-1, ay=-1,
                           op="erode" if i % 2 else "dilate"))
     b = morph.Batch(32, 1 << 20)
-    assert b.set(items) > 10000
+    assert b.set(items) > 9000  # wave units alone: more than 8192
     b.enqueue()
     torch.cuda.synchronize()
     for k, it in enumerate(items):

@@ -135,6 +135,57 @@ def test_wave_units_of_several_row_chunks(rows, tmp_path):
 
 
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_streaming_kernel_every_window(dtype):
+    """The streaming kernel (vertical vHGW through the per-wave ring, horizontal
+    direct or doubling across lanes) for every horizontal window 1..128 (doubling
+    forced, so small windows take it too) and vertical windows up to 64, random
+    anchors, on an image of two strips and two row bands with ragged edges."""
+    rng = np.random.default_rng(31)
+    img = synth.document(181, 333, seed=41, n_rect=50).astype(dtype)
+    if dtype == np.uint16:
+        img = img * 257 - rng.integers(0, 200, img.shape).astype(np.uint16)
+    for wx in range(1, 129):
+        wy = int(rng.integers(1, 65))
+        ax = int(rng.integers(-1, wx))
+        ay = int(rng.integers(-1, wy))
+        op = ("erode", "dilate")[wx % 2]
+        _check(img, op, wx, wy, ax, ay, method_x="doubling")
+        if wx <= 64:
+            _check(img, op, wy, wx, ay, ax)  # automatic: wave or streaming kernel
+
+
+@pytest.mark.parametrize("rows", [1, 5, 16, 40])
+def test_streaming_units_of_any_height(rows, tmp_path):
+    """Streaming units of `rows` output rows, shorter and longer than the vertical
+    window (the vHGW blocks then span several units or one unit holds several
+    blocks), for both element types, aligned and unaligned rows, and images a
+    fraction of a strip wide."""
+    import json
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps({"u8": {"stream_rows": rows}, "u16": {"stream_rows": rows}}))
+    morph.load_tuning(str(f))
+    try:
+        rng = np.random.default_rng(rows)
+        for dtype in (np.uint8, np.uint16):
+            for i, (H, W) in enumerate([(1, 1), (3, 70), (64, 65), (97, 500)]):
+                img = synth.uniform(H, W, dtype, seed=950 + i)
+                for wx, wy in ((15, 15), (31, 3), (4, 63), (64, 64), (2, 17)):
+                    ax = int(rng.integers(-1, wx))
+                    ay = int(rng.integers(-1, wy))
+                    for op in ("erode", "dilate"):
+                        _check(img, op, wx, wy, ax, ay)
+                # unaligned rows and a source that is not quad-aligned
+                pitch = W + 3
+                d, _ = to_dev(img, pitch_elems=pitch, offset_elems=1)
+                out = empty_like_dev(d)[0]
+                morph.apply("erode", d, 33, 21, out=out)
+                torch.cuda.synchronize()
+                assert np.array_equal(to_host(out), _ref(img, "erode", 33, 21))
+    finally:
+        morph.load_tuning(None)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 def test_pitch_offset_and_guard_bytes(dtype):
     """Strided rows, a base pointer off by one element, and sentinel bytes around
     the image and in the pitch gap that must stay untouched."""
@@ -192,9 +243,9 @@ def test_config_1920x1080_document_sweep():
     img = synth.document(1080, 1920, seed=2)
     for w in (3, 5, 7, 9, 15, 21, 31, 45, 63):
         for op in ("erode", "dilate"):
-            _check(img, op, w, w)
+            _check(img, op, w, w)  # wave kernel up to 9, streaming kernel beyond
+            _check(img, op, w, w, method_x="vhgw", method_y="vhgw")  # tile kernel
             if w <= DMAX:
-                _check(img, op, w, w, method_x="vhgw", method_y="vhgw")
                 _check(img, op, w, w, method_x="direct", method_y="direct")
 
 
