@@ -5,7 +5,7 @@ Workload (one "step"): the mixed-size batch -- 512 uint8 document-like images,
 H and W each log-uniform in [64, 2048], a square window per image drawn from
 {3, 5, 9, 15, 31, 63}, erosion or dilation at random (seed 5) -- run as one
 graph-replayed batch: a wave-kernel launch for the images whose two passes are
-direct and a persistent tile-kernel launch for the others.  Images are resident
+direct and a streaming-kernel launch for the others.  Images are resident
 in HBM before timing; rows are padded to a 64-byte pitch.  The roofline figure
 is that of the slower of the two kernels, timed alone on its images.  Reported
 beside it: the same 512 images as 512 separate launches (eager and captured in
@@ -171,15 +171,18 @@ def c3_lines(torch, morph, dev, steps):
 
 
 def kernel_groups(morph, items):
-    """Split the batch by the kernel its images run on: both passes direct -> the
-    wave kernel, any vHGW pass -> the tile kernel."""
-    groups = {"wave": [], "tile": []}
+    """Split the batch by the kernel its images run on (the library's plan)."""
+    groups = {}
     for it in items:
         H, W = it["src"].shape
-        p = morph.resolve_plan("u8", H, W, it["wx"], it["wy"])
-        vhgw = "vhgw" in (p["method_x"], p["method_y"])
-        groups["tile" if vhgw else "wave"].append(it)
+        k = morph.resolve_plan("u8", H, W, it["wx"], it["wy"])["kernel"]
+        groups.setdefault(k, []).append(it)
     return groups
+
+
+KERNEL_LABELS = {"wave": "batch_wave_kernel<u8, aligned rows>",
+                 "stream": "batch_stream_kernel<u8, aligned rows>",
+                 "tile": "batch_kernel<u8, aligned rows>"}
 
 
 def main():
@@ -233,8 +236,8 @@ def main():
     sp = sorted(per)
 
     # The step launches one kernel per group of images (wave kernel: both passes
-    # direct; tile kernel: a vHGW pass).  Each group alone, as its own batch, times
-    # that kernel's launch; the roofline is taken on the dominant one.
+    # direct; streaming kernel: larger windows).  Each group alone, as its own batch,
+    # times that kernel's launch; the roofline is taken on the dominant one.
     _log("timing each kernel of the step")
     kernels = []
     for name, its in kernel_groups(morph, items).items():
@@ -246,8 +249,7 @@ def main():
         kms = sum(kp) / len(kp)
         kpx = sum(it["src"].shape[0] * it["src"].shape[1] for it in its)
         gbs = 2 * kpx / (kms * 1e-3) / 1e9  # one read and one write of every uint8 pixel
-        kernels.append({"kernel": {"wave": "batch_wave_kernel<u8, aligned rows>",
-                                   "tile": "batch_kernel<u8, aligned rows>"}[name],
+        kernels.append({"kernel": KERNEL_LABELS[name],
                         "images": len(its), "pixels": kpx, "ms_per_launch": round(kms, 5),
                         "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)})
         sub.close()
@@ -272,7 +274,7 @@ def main():
                    "windows": "square, from 3,5,9,15,31,63", "ops": "erode or dilate",
                    "content": "document-like: white page, black rectangles, noise sigma 12",
                    "pixels_per_step": npx, "tiles": ntiles, "row_pitch": "64-byte aligned",
-                   "launch": "one kernel per group (wave / tile), hipGraph replay"},
+                   "launch": "one kernel per group (wave / stream), hipGraph replay"},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["gbs"],
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": dom["frac"],
                      "traffic": traffic,

@@ -95,7 +95,13 @@ typedef struct morph_plan {
     int32_t method_y;
     int32_t tile_w;
     int32_t tile_h;
+    int32_t kernel; /* out (morph_resolve_plan): MORPH_KERNEL_*; ignored on input */
 } morph_plan;
+
+/* kernels (morph_plan.kernel) */
+#define MORPH_KERNEL_TILE 0   /* workgroup tile through LDS, the paper's two methods */
+#define MORPH_KERNEL_WAVE 1   /* both passes direct, one wave per strip, registers only */
+#define MORPH_KERNEL_STREAM 2 /* one wave per strip streaming down the rows */
 
 /* Erosion, uint8 (§2 Eq. (1)).  See the conventions above for every argument. */
 int morph_erode(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,

@@ -61,7 +61,7 @@ def _plan(method_x, method_y, tile):
     if method_x is None and method_y is None and tile is None:
         return None
     tw, th = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
-    return Plan(_lib.METHOD_CODES[method_x], _lib.METHOD_CODES[method_y], tw, th)
+    return Plan(_lib.METHOD_CODES[method_x], _lib.METHOD_CODES[method_y], tw, th, 0)
 
 
 def workspace_bytes(H: int, W: int, pitch: int, elem_bytes: int) -> int:
@@ -73,8 +73,9 @@ def apply(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = 
           tile=None, stream=None):
     """Run ``op`` in {"erode", "dilate", "open", "close"} on ``src``; returns ``out``.
 
-    ``method_x`` / ``method_y`` force "direct" or "vhgw" for a pass and ``tile``
-    = (tile_w, tile_h) sets the workgroup tile; neither changes the result.
+    ``method_x`` / ``method_y`` force "direct" or "vhgw" for a pass (and
+    ``method_x="doubling"`` the streaming kernel's lane doubling) and ``tile`` =
+    (tile_w, tile_h) sets the workgroup tile; neither changes the result.
     ``out`` must have the same shape, dtype and row pitch as ``src``.
     """
     torch = _torch()
@@ -203,12 +204,12 @@ def set_thresholds(dtype_name: str, t_x: int, t_y: int) -> None:
 
 def resolve_plan(dtype_name: str, H: int, W: int, wx: int, wy: int, method_x=None,
                  method_y=None, tile=None):
-    p = _plan(method_x, method_y, tile) or Plan(0, 0, 0, 0)
+    p = _plan(method_x, method_y, tile) or Plan(0, 0, 0, 0, 0)
     _lib.check(_lib.lib().morph_resolve_plan(_lib.U8 if dtype_name == "u8" else _lib.U16,
                                              H, W, wx, wy, ctypes.byref(p)), "resolve_plan")
     names = {0: None, 1: "direct", 2: "vhgw", 3: "doubling"}
     return dict(method_x=names[p.method_x], method_y=names[p.method_y], tile_w=p.tile_w,
-                tile_h=p.tile_h)
+                tile_h=p.tile_h, kernel=_lib.KERNEL_NAMES[p.kernel])
 
 
 def version() -> str:

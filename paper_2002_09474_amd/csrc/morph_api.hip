@@ -40,13 +40,13 @@ struct DtypeTuning {
     int t_x, t_y; // direct when w <= t (per pass)
     std::vector<TileRule> tiles;
     int wave_rows;   // output rows of a wave unit (both passes direct), multiple of kWaveRows
-    int stream_rows; // output rows of a streaming-kernel unit
+    int stream_rows; // output rows of a streaming-kernel unit, 0: automatic
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 128},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 128},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 0},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 0},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -153,8 +153,8 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
     if (it != o.obj.end()) {
         if (it->second.k != JVal::NUM) return false;
         const int r = (int)it->second.num;
-        if (r < 1 || r > 4096) return false;
-        t.stream_rows = r;
+        if (r < 0 || r > 4096) return false;
+        t.stream_rows = r; // 0: automatic
     }
     it = o.obj.find("tiles");
     if (it != o.obj.end()) {
@@ -215,7 +215,8 @@ int default_anchor(int w) { return w - 1 - w / 2; }
 // anchor a and right extent r = w - 1 - a, only min(a, W-1) columns to the left and
 // min(r, W-1) to the right can ever be inside the image.
 int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
-             size_t dpitch, int wx, int wy, int ax, int ay, const morph_plan *plan, TileJob &j)
+             size_t dpitch, int wx, int wy, int ax, int ay, const morph_plan *plan, TileJob &j,
+             bool in_batch = false)
 {
     if (ax < 0) ax = default_anchor(wx);
     if (ay < 0) ay = default_anchor(wy);
@@ -282,8 +283,19 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         j.vcode = 0;
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
         j.TW = 4 * stream_quads(j.wx);
-        j.TB = std::min(tu.stream_rows, H);
         j.tiles_x = (W + j.TW - 1) / j.TW;
+        if (tu.stream_rows > 0) {
+            j.TB = std::min(tu.stream_rows, H);
+        } else {
+            // about four vertical windows per unit (the wy - 1 halo rows a unit reads
+            // twice stay a small part of it), 32 .. 256 rows; a single image is cut
+            // finer until it gives the chip a few waves per SIMD
+            // (in a batch at most 128: long units would trail the end of the launch)
+            int tb = std::min(in_batch ? 128 : 256, std::max(32, (4 * j.wy + 7) & ~7));
+            if (!in_batch)
+                while (tb > 32 && (int64_t)j.tiles_x * ((H + tb - 1) / tb) < kStreamMinUnits) tb /= 2;
+            j.TB = std::min(tb, H);
+        }
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
         return MORPH_OK;
@@ -509,6 +521,7 @@ int morph_resolve_plan(int dtype, int H, int W, int wx, int wy, morph_plan *plan
                                  : (j.vm == PASS_DIRECT ? MORPH_METHOD_DIRECT : MORPH_METHOD_VHGW);
     plan->tile_w = j.TW;
     plan->tile_h = j.TB;
+    plan->kernel = j.kind; // KernelKind values are the MORPH_KERNEL_* codes
     return MORPH_OK;
 }
 
@@ -539,6 +552,13 @@ struct BatchGroup {
     bool aligned = true;
 };
 
+// groups: kernel kind x element type x row alignment, and for the streaming kernel
+// three ring sizes (wy <= 16, 32, 64) so that small windows are not given the LDS
+// of large ones
+static constexpr int kRingClasses = 3;
+static constexpr int kBatchGroups = 4 * (kKinds + kRingClasses - 1);
+static constexpr int kSide = 4;                  // group launches in flight at once
+
 struct morph_batch {
     int max_images = 0;
     int64_t max_tiles = 0;
@@ -560,9 +580,12 @@ struct morph_batch {
     // previous copy before it overwrites them
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
+    // the group kernels run side by side: group g on the caller's stream (g % kSide
+    // == 0) or on aux[g % kSide - 1], forked from and joined back to the caller's
+    hipStream_t aux[kSide - 1] = {};
+    hipEvent_t fork = nullptr, join[kSide - 1] = {};
 };
 
-static constexpr int kBatchGroups = 4 * kKinds; // kernel kind x element type x row alignment
 
 static int device_cus()
 {
@@ -603,12 +626,38 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
         (e = hipMemset(b->d_counter, 0, sizeof(unsigned long long) * ncount)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) {
         morph_batch_destroy(b);
         return hip_fail(e);
     }
+    for (int i = 0; i < kSide - 1; i++)
+        if ((e = hipStreamCreateWithFlags(&b->aux[i], hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming)) != hipSuccess) {
+            morph_batch_destroy(b);
+            return hip_fail(e);
+        }
     *out = b;
     return MORPH_OK;
+}
+
+// Group index of a job: (dtype, alignment) in the low two bits; above them the
+// kernel kind, the streaming kernel split by ring size.
+static int group_of(const TileJob &j)
+{
+    int k = j.kind;
+    if (j.kind == KIND_STREAM) k += (j.wy > 16) + (j.wy > 32);
+    return 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
+}
+
+// Launch order of the groups: streaming groups from the largest ring down (their
+// units are the longest), then the tile and wave groups.
+static int group_order(int gi)
+{
+    constexpr int ns = 4 * kRingClasses;
+    if (gi < ns) return 4 * (KIND_STREAM + kRingClasses - 1 - gi / 4) + gi % 4;
+    gi -= ns;
+    return gi < 4 ? 4 * KIND_TILE + gi : 4 * KIND_WAVE + (gi - 4);
 }
 
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream)
@@ -636,22 +685,24 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
             return MORPH_EALIAS;
         TileJob j;
         rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, dp, d.wx, d.wy, d.ax,
-                      d.ay, nullptr, j);
+                      d.ay, nullptr, j, true);
         if (rc != MORPH_OK) return rc;
-        jobs[4 * j.kind + 2 * d.dtype + (job_rows_aligned(j) ? 0 : 1)].push_back(j);
+        jobs[group_of(j)].push_back(j);
     }
     std::vector<BatchGroup> groups;
     int64_t tiles = 0;
     int m = 0, starts = 0;
     const int cus = device_cus();
-    for (int g = 0; g < kBatchGroups; g++) {
+    for (int gi = 0; gi < kBatchGroups; gi++) {
+        // heaviest first: the streaming groups from the largest ring down, then the rest
+        const int g = group_order(gi);
         if (jobs[g].empty()) continue;
         BatchGroup G;
         G.job0 = m;
         G.njobs = (int)jobs[g].size();
-        G.kind = g / 4;
-        G.dtype = (g / 2) % 2;
-        G.aligned = (g % 2) == 0;
+        G.kind = jobs[g][0].kind;
+        G.dtype = jobs[g][0].dtype;
+        G.aligned = job_rows_aligned(jobs[g][0]);
         int64_t t = 0;
         for (const TileJob &j : jobs[g]) {
             b->h_tile_start[starts++] = t;
@@ -713,16 +764,31 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
 
 static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
 {
+    // side streams only for a real stream with more than one group (the legacy null
+    // stream keeps its implicit ordering)
+    const int ng = (int)b->groups.size();
+    const int side = (stream == nullptr) ? 1 : std::min(kSide, ng);
+    hipError_t e;
+    if (side > 1) {
+        if ((e = hipEventRecord(b->fork, stream)) != hipSuccess) return e;
+        for (int i = 0; i < side - 1; i++)
+            if ((e = hipStreamWaitEvent(b->aux[i], b->fork, 0)) != hipSuccess) return e;
+    }
     int start = 0;
     int64_t tstart = 0;
-    for (size_t g = 0; g < b->groups.size(); g++) {
+    for (int g = 0; g < ng; g++) {
         const BatchGroup &G = b->groups[g];
         BatchTables t{b->d_jobs + G.job0, b->d_tile_start + start, b->d_tile_job + tstart,
                       G.njobs, G.tiles, b->d_counter + 2 * g};
         start += G.njobs + 1;
         tstart += G.tiles;
-        hipError_t e = launch_batch(t, G.kind, G.dtype, G.aligned, G.grid, G.lds, stream);
+        const int k = g % side;
+        e = launch_batch(t, G.kind, G.dtype, G.aligned, G.grid, G.lds, k ? b->aux[k - 1] : stream);
         if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < side - 1; i++) {
+        if ((e = hipEventRecord(b->join[i], b->aux[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(stream, b->join[i], 0)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -779,6 +845,11 @@ int morph_batch_destroy(morph_batch_t b)
     if (!b) return MORPH_EINVAL;
     drop_graph(b);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (int i = 0; i < kSide - 1; i++) {
+        if (b->aux[i]) (void)hipStreamDestroy(b->aux[i]);
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_tile_start) (void)hipFree(b->d_tile_start);
     if (b->d_tile_job) (void)hipFree(b->d_tile_job);

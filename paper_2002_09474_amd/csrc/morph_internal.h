@@ -22,7 +22,12 @@ enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3
 enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2 };
 constexpr int kKinds = 3;
 constexpr int kStreamMaxWx = 128; // wider windows leave a 64-quad strip too few outputs
-constexpr int kStreamMaxWy = 64;  // the ring takes 512 bytes of LDS per row
+constexpr int kStreamMaxWy = 64;  // the ring takes 256 (u8) or 512 (u16) bytes of LDS per row
+constexpr int kStreamMinUnits = 2048; // a single image's streaming units: a few per SIMD
+constexpr int kStreamChunk = 8;       // rows a streaming wave takes at a time
+// ring entries of the streaming kernel's vertical pass: wy, plus slack so that a
+// chunk may read kStreamChunk entries from any position
+inline int stream_ring_entries(int wy) { return wy + kStreamChunk - 1; }
 constexpr int kWaveQuads = 60;
 constexpr int kWaveRows = 8;
 
@@ -54,7 +59,8 @@ struct TileJob {
 inline int lds_bytes(const TileJob &j)
 {
     if (j.kind == KIND_WAVE) return 0;
-    if (j.kind == KIND_STREAM) return j.wy * 64 * 8; // per single-wave workgroup
+    if (j.kind == KIND_STREAM) // per single-wave workgroup: 64 lanes x 4 (u8) / 8 (u16) bytes
+        return stream_ring_entries(j.wy) * 64 * (j.dtype ? 8 : 4);
     const int b = (j.TB / 2) * j.SB;
     return (j.TB * j.SA + (b > j.vtt ? b : j.vtt)) * 4;
 }

@@ -68,6 +68,8 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
 // compiler emits global_* rather than flat_* accesses also where the pointer comes
 // from a table in memory (the batch kernels).
 #define GLOBAL __attribute__((address_space(1)))
+// Word 3 of a raw (untyped, unswizzled) buffer resource on gfx9-family GPUs.
+constexpr int kBufferWord3 = 0x00020000;
 __device__ __forceinline__ uint32_t load_u32(uintptr_t a) { return *(const GLOBAL uint32_t *)a; }
 __device__ __forceinline__ void store_u32(uintptr_t a, uint32_t v) { *(GLOBAL uint32_t *)a = v; }
 __device__ __forceinline__ void store_u8(uintptr_t a, uint8_t v) { *(GLOBAL uint8_t *)a = v; }
@@ -805,18 +807,25 @@ constexpr int KR = kWaveRows;
 constexpr int RING = KR + kDirectMax - 1;
 
 // Rows with 4-aligned (uint8) / 8-aligned (uint16) pitch: lane set-up for a unit.
+// Loads go through a buffer resource on the image (it spans < 4 GiB): the row
+// offset is a scalar operand and the lane's column offset a fixed vector operand,
+// so a row costs no vector instruction to address.
 template <typename T> struct WaveLoader {
-    const uint8_t *abase; // src rounded down to the quad size
-    uint32_t pitch;       // bytes (the image spans < 4 GiB)
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t pitch;       // bytes
     int H;
     uint32_t voff;        // byte offset of the lane's (clamped) quad within a row
     uint32_t s01, s23;    // v_perm selectors that pick the lane's four pixels
 
     __device__ __forceinline__ WaveLoader(const TileJob &J, int mis, int gx)
     {
-        abase = J.src - mis * (int)sizeof(T);
+        const uint8_t *abase = J.src - mis * (int)sizeof(T);
         pitch = (uint32_t)J.pitch;
         H = J.H;
+        const uint64_t span = (uint64_t)(J.H - 1) * J.pitch + (uint64_t)(J.W + mis + 3) * sizeof(T);
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)abase, (short)0,
+                                                 (int)(uint32_t)min(span, (uint64_t)0xffffffffu),
+                                                 kBufferWord3);
         // the lane's quad covers image columns gx .. gx + 3 (gx + mis a multiple of
         // 4); outside the image, take the quad holding column 0 or W - 1
         int gq = gx;
@@ -843,8 +852,13 @@ template <typename T> struct WaveLoader {
     using Raw = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
     __device__ __forceinline__ Raw issue(int gy) const
     {
-        const uint8_t *r = abase + (uint32_t)min(max(gy, 0), H - 1) * pitch;
-        return *(const GLOBAL Raw *)(r + voff);
+        const int soff = (int)((uint32_t)min(max(gy, 0), H - 1) * pitch);
+        if constexpr (sizeof(T) == 1) {
+            return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, soff, 0);
+        } else {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)voff, soff, 0);
+            return (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+        }
     }
     __device__ __forceinline__ void widen(Raw d, uint32_t &v01, uint32_t &v23) const
     {
@@ -932,9 +946,11 @@ template <typename T> struct WaveLoaderAny {
     }
 };
 
+// Lane i gets x of lane i + 1 (DPP wave_shl:1; lane 63 gets 0 through bound_ctrl,
+// which also spares the move that would give the destination an old value).
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
 {
-    return __builtin_amdgcn_update_dpp(0u, x, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
 }
 
 template <int WX, int CO, bool MAXOP>
@@ -1090,7 +1106,7 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 // The wave stores the output quads whose input lies inside its 64 quads: J.TW / 4 of
 // them.  Pixels outside the image are the nearest image pixels, as in the direct
 // wave kernel.
-constexpr int SD = 8; // input rows per chunk (and rows in flight) per wave
+constexpr int SD = kStreamChunk; // input rows per chunk (and rows in flight) per wave
 
 __device__ __forceinline__ uint32_t lane_fetch(uint32_t v, uint32_t byte_addr)
 {
@@ -1100,8 +1116,7 @@ __device__ __forceinline__ uint32_t lane_fetch(uint32_t v, uint32_t byte_addr)
 // Per-unit constants of the doubling pass.
 struct Doubling {
     int wx;
-    bool hiq0, hiq1;   // pair lookup at offsets co (resp. co + wx - L) starts in dword 1
-    uint32_t sh0, sh1; // 16 when that offset is odd
+    int c0, c1;        // pixel offsets co and co + wx - L within their first quad (0..3)
     uint32_t ad0, ad1; // ds_bpermute addresses of lanes + q1 and + q1 + 1, q1 = (co + wx - L) / 4
 
     __device__ __forceinline__ Doubling(int wx_, int co)
@@ -1110,22 +1125,49 @@ struct Doubling {
         int L = 1;
         while (2 * L <= wx) L *= 2;
         const int d1 = co + wx - L;
-        hiq0 = co >= 2;
-        sh0 = (co & 1) ? 16u : 0u;
-        hiq1 = (d1 & 3) >= 2;
-        sh1 = (d1 & 1) ? 16u : 0u;
+        c0 = co;
+        c1 = d1 & 3;
         const int lane = threadIdx.x & 63;
         ad0 = (uint32_t)(lane + (d1 >> 2)) << 2;
         ad1 = (uint32_t)(lane + (d1 >> 2) + 1) << 2;
     }
 };
 
+// The pixel pairs at offsets c and c + 2 from four consecutive pair dwords F
+// (offsets 0, 2, 4, 6).
+template <int C>
+__device__ __forceinline__ void pairs_at(uint32_t f0, uint32_t f1, uint32_t f2, uint32_t f3,
+                                         uint32_t &p, uint32_t &p2)
+{
+    const uint32_t lo = (C >> 1) ? f1 : f0, mid = (C >> 1) ? f2 : f1, hi = (C >> 1) ? f3 : f2;
+    p = (C & 1) ? __builtin_amdgcn_alignbit(mid, lo, 16) : lo;
+    p2 = (C & 1) ? __builtin_amdgcn_alignbit(hi, mid, 16) : mid;
+}
+
+// m_wx[k] = min(m_L[k], m_L[k + wx - L]) at k = co .. co + 3, from the level-L pairs.
+template <int C0, int C1, int G, bool MAXOP>
+__device__ __forceinline__ void doubling_final(const Doubling &S, uint32_t *e0, uint32_t *e1)
+{
+#pragma unroll
+    for (int r = 0; r < G; r++) {
+        const uint32_t a0 = e0[r], a1 = e1[r];
+        const uint32_t n0 = from_next_lane(a0), n1 = (C0 >> 1) ? from_next_lane(a1) : 0u;
+        uint32_t p0, p2, r0, r2;
+        pairs_at<C0>(a0, a1, n0, n1, p0, p2);
+        const uint32_t f0 = (C1 >> 1) ? 0u : lane_fetch(a0, S.ad0), f1 = lane_fetch(a1, S.ad0);
+        const uint32_t f2 = lane_fetch(a0, S.ad1), f3 = (C1 >> 1) ? lane_fetch(a1, S.ad1) : 0u;
+        pairs_at<C1>(f0, f1, f2, f3, r0, r2);
+        e0[r] = pk<MAXOP>(p0, r0);
+        e1[r] = pk<MAXOP>(p2, r2);
+    }
+}
+
 // The horizontal passes below work on G rows at once, level by level, so that the
 // rows' chains of lane moves and min/max interleave.
 template <int G, bool MAXOP>
 __device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, uint32_t *e1)
 {
-    // a0 = (m_L[0], m_L[1]), a1 = (m_L[2], m_L[3]) for the lane's quad
+    // e0 = (m_L[0], m_L[1]), e1 = (m_L[2], m_L[3]) for the lane's quad
     const int lane = threadIdx.x & 63;
     if (S.wx >= 2) { // L = 1 -> 2: shift by one pixel
 #pragma unroll
@@ -1162,23 +1204,15 @@ __device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, u
             e1[r] = pk<MAXOP>(e1[r], n1);
         }
     }
-#pragma unroll
-    for (int r = 0; r < G; r++) {
-        const uint32_t a0 = e0[r], a1 = e1[r];
-        // pairs at offsets co, co + 2 from [a0 a1 | next lane's a0 a1] ...
-        const uint32_t n0 = from_next_lane(a0), n1 = from_next_lane(a1);
-        const uint32_t l0 = S.hiq0 ? a1 : a0, m0 = S.hiq0 ? n0 : a1, h0 = S.hiq0 ? n1 : n0;
-        const uint32_t p0 = __builtin_amdgcn_alignbit(m0, l0, S.sh0);
-        const uint32_t p2 = __builtin_amdgcn_alignbit(h0, m0, S.sh0);
-        // ... and at co + wx - L, co + wx - L + 2 from lanes + q1, + q1 + 1
-        const uint32_t f0 = lane_fetch(a0, S.ad0), f1 = lane_fetch(a1, S.ad0);
-        const uint32_t f2 = lane_fetch(a0, S.ad1), f3 = lane_fetch(a1, S.ad1);
-        const uint32_t l1 = S.hiq1 ? f1 : f0, m1 = S.hiq1 ? f2 : f1, h1 = S.hiq1 ? f3 : f2;
-        const uint32_t r0 = __builtin_amdgcn_alignbit(m1, l1, S.sh1);
-        const uint32_t r2 = __builtin_amdgcn_alignbit(h1, m1, S.sh1);
-        e0[r] = pk<MAXOP>(p0, r0);
-        e1[r] = pk<MAXOP>(p2, r2);
+#define MORPH_FIN1(A, B)                                                                     \
+    case A * 4 + B: doubling_final<A, B, G, MAXOP>(S, e0, e1); break;
+#define MORPH_FIN(A) MORPH_FIN1(A, 0) MORPH_FIN1(A, 1) MORPH_FIN1(A, 2) MORPH_FIN1(A, 3)
+    switch (S.c0 * 4 + S.c1) {
+        MORPH_FIN(0) MORPH_FIN(1) MORPH_FIN(2) MORPH_FIN(3)
+    default: break;
     }
+#undef MORPH_FIN
+#undef MORPH_FIN1
 }
 
 template <int G, bool MAXOP>
@@ -1199,25 +1233,80 @@ __device__ __forceinline__ void direct_rows_any(int wx, int co, uint32_t *v01, u
 #undef MORPH_WH1
 }
 
-// Backward walk over the ring (entries wy - 1 .. 0): each becomes the suffix min.
-template <bool MAXOP>
-__device__ __forceinline__ void ring_suffixes(uint2 *ring, int wy)
-{
-    uint32_t h01 = MAXOP ? 0u : 0xffffffffu, h23 = h01;
-    for (int j = wy - 1; j >= 0; j -= 8) {
-        uint2 v[8];
-#pragma unroll
-        for (int k = 0; k < 8; k++)
-            if (j - k >= 0) v[k] = ring[64 * (j - k)];
-#pragma unroll
-        for (int k = 0; k < 8; k++)
-            if (j - k >= 0) {
-                h01 = pk<MAXOP>(h01, v[k].x);
-                h23 = pk<MAXOP>(h23, v[k].y);
-                ring[64 * (j - k)] = make_uint2(h01, h23);
-            }
+// The per-wave ring of the vertical vHGW pass in LDS: stream_ring_entries(wy) entries
+// (wy of them used; the rest let a chunk read SD entries from any position) of 64
+// lanes.  uint8: an entry is a lane's raw quad (4 bytes), written as loaded and,
+// once a block's suffixes replace it, as the narrowed suffix; uint16: the two pair
+// dwords.
+template <typename T> struct Ring;
+template <> struct Ring<uint8_t> {
+    uint32_t *e; // lane's entry 0; entry j at e[64 j]
+    __device__ __forceinline__ explicit Ring(uint32_t *lds) : e(lds + (threadIdx.x & 63)) {}
+    template <typename R>
+    __device__ __forceinline__ void put(int j, R raw, uint32_t x01, uint32_t x23) const
+    {
+        // a raw quad as loaded, or (rows of any pitch, loaded widened) narrowed back
+        if constexpr (std::is_same<R, uint32_t>::value) e[64 * j] = raw;
+        else e[64 * j] = perm(x23, x01, SEL_NARROW);
     }
-}
+    __device__ __forceinline__ void get(int j, uint32_t &h01, uint32_t &h23) const
+    {
+        const uint32_t d = e[64 * j];
+        h01 = perm(0u, d, SEL_U8_01);
+        h23 = perm(0u, d, SEL_U8_23);
+    }
+    // entries wy - 1 .. 0 become suffix minima (raw quads widened with the lane's
+    // selectors s01 / s23)
+    template <bool MAXOP>
+    __device__ __forceinline__ void suffixes(int wy, uint32_t s01, uint32_t s23) const
+    {
+        uint32_t h01 = MAXOP ? 0u : 0xffffffffu, h23 = h01;
+        for (int j = wy - 1; j >= 0; j -= 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) v[k] = e[64 * max(j - k, 0)];
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (j - k >= 0) {
+                    h01 = pk<MAXOP>(h01, perm(0u, v[k], s01));
+                    h23 = pk<MAXOP>(h23, perm(0u, v[k], s23));
+                    e[64 * (j - k)] = perm(h23, h01, SEL_NARROW);
+                }
+        }
+    }
+};
+template <> struct Ring<uint16_t> {
+    uint2 *e;
+    __device__ __forceinline__ explicit Ring(uint32_t *lds) : e((uint2 *)lds + (threadIdx.x & 63)) {}
+    template <typename R>
+    __device__ __forceinline__ void put(int j, R, uint32_t x01, uint32_t x23) const
+    {
+        e[64 * j] = make_uint2(x01, x23);
+    }
+    __device__ __forceinline__ void get(int j, uint32_t &h01, uint32_t &h23) const
+    {
+        const uint2 d = e[64 * j];
+        h01 = d.x;
+        h23 = d.y;
+    }
+    template <bool MAXOP>
+    __device__ __forceinline__ void suffixes(int wy, uint32_t, uint32_t) const
+    {
+        uint32_t h01 = MAXOP ? 0u : 0xffffffffu, h23 = h01;
+        for (int j = wy - 1; j >= 0; j -= 8) {
+            uint2 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) v[k] = e[64 * max(j - k, 0)];
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (j - k >= 0) {
+                    h01 = pk<MAXOP>(h01, v[k].x);
+                    h23 = pk<MAXOP>(h23, v[k].y);
+                    e[64 * (j - k)] = make_uint2(h01, h23);
+                }
+        }
+    }
+};
 
 template <typename T, bool MAXOP, bool AL>
 __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t *lds)
@@ -1241,20 +1330,32 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
         if constexpr (AL) return WaveLoader<T>(J, mis, gx);
         else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)), gx);
     }();
+    // uint8 rings hold raw quads widened with the loader's selectors (identity ones
+    // for rows of any pitch, which the loader returns widened already)
+    uint32_t rs01 = SEL_U8_01, rs23 = SEL_U8_23;
+    if constexpr (AL) {
+        rs01 = L.s01;
+        rs23 = L.s23;
+    }
     const Doubling S(J.wx, co);
     const bool hdirect = J.wx <= kDirectMax;
-    uint2 *ring = (uint2 *)lds + lane; // entry j of the lane at ring[64 j]
-    // destination
+    const Ring<T> ring(lds);
+    // destination: rows 4-byte aligned, the strip wholly inside the image and the
+    // image spanning < 4 GiB take buffer stores (row offset scalar)
     const int Q = (J.TW >> 2) * sx + lane;
     const bool store_lane = lane < (J.TW >> 2);
+    const uint64_t dspan = (uint64_t)(J.H - 1) * J.dpitch + (uint64_t)J.W * sizeof(T);
     const bool fast_store = (((uintptr_t)J.dst | (uintptr_t)J.dpitch) & 3) == 0 &&
-                            J.TW * (sx + 1) <= J.W;
+                            J.TW * (sx + 1) <= J.W && dspan < 0xffffffffull;
+    const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)J.dst, (short)0, (int)(uint32_t)min(dspan, (uint64_t)0xffffffffu), kBufferWord3);
+    const uint32_t dvoff = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
     const uint32_t id = MAXOP ? 0u : 0xffffffffu;
 
     // Rows are taken in chunks of up to SD that stay inside one block: block 0 fills
-    // the ring, every later chunk emits outputs.  The next chunk's rows are loaded
-    // while the current one is worked on.
-    typename Ld::Raw cur[SD], nxt[SD];
+    // the ring, every later chunk emits outputs.  As soon as a chunk's rows are
+    // widened, the next chunk's loads are issued into the same registers.
+    typename Ld::Raw cur[SD];
 #pragma unroll
     for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + k);
     uint32_t g01 = id, g23 = id;
@@ -1262,31 +1363,34 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
     bool fill = true;
     while (t <= last) {
         const int cnt = min(min(SD, wy - j), last - t + 1);
-#pragma unroll
-        for (int k = 0; k < SD; k++) nxt[k] = L.issue(gy0 + t + cnt + k);
+        typename Ld::Raw raw[SD];
         uint32_t x01[SD], x23[SD];
 #pragma unroll
-        for (int k = 0; k < SD; k++) L.widen(cur[k], x01[k], x23[k]);
+        for (int k = 0; k < SD; k++) {
+            raw[k] = cur[k];
+            L.widen(raw[k], x01[k], x23[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + t + cnt + k);
         if (fill) {
 #pragma unroll
             for (int k = 0; k < SD; k++)
-                if (k < cnt) ring[64 * (j + k)] = make_uint2(x01[k], x23[k]);
+                if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
         } else {
-            uint2 h[SD];
-#pragma unroll
-            for (int k = 0; k < SD; k++) h[k] = ring[64 * min(j + k, wy - 1)];
             uint32_t o01[SD], o23[SD];
+#pragma unroll
+            for (int k = 0; k < SD; k++) ring.get(j + k, o01[k], o23[k]);
 #pragma unroll
             for (int k = 0; k < SD; k++) {
                 // h_b[j + k] against the prefix of this block's first j + k rows
-                o01[k] = pk<MAXOP>(h[k].x, g01);
-                o23[k] = pk<MAXOP>(h[k].y, g23);
+                o01[k] = pk<MAXOP>(o01[k], g01);
+                o23[k] = pk<MAXOP>(o23[k], g23);
                 g01 = pk<MAXOP>(g01, x01[k]);
                 g23 = pk<MAXOP>(g23, x23[k]);
             }
 #pragma unroll
             for (int k = 0; k < SD; k++)
-                if (k < cnt) ring[64 * (j + k)] = make_uint2(x01[k], x23[k]);
+                if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
             // output rows t - wy .. t - wy + cnt - 1: horizontal pass, then store
             if constexpr (AL && sizeof(T) == 2)
                 if (edge) {
@@ -1296,36 +1400,36 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
             if (hdirect) direct_rows_any<SD, MAXOP>(J.wx, co, o01, o23);
             else doubling_rows<SD, MAXOP>(S, o01, o23);
             if (store_lane) {
-                uint8_t *drow = J.dst + (int64_t)(y0 + t - wy) * J.dpitch;
-                const uint32_t o = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
+                const int y = y0 + t - wy;
 #pragma unroll
                 for (int k = 0; k < SD; k++) {
                     if (k < cnt) {
                         if (fast_store) {
+                            const int so = (int)((uint32_t)(y + k) * (uint32_t)J.dpitch);
                             if constexpr (sizeof(T) == 1) {
-                                store_u32((uintptr_t)(drow + o), perm(o23[k], o01[k], SEL_NARROW));
+                                __builtin_amdgcn_raw_buffer_store_b32(
+                                    perm(o23[k], o01[k], SEL_NARROW), drs, (int)dvoff, so, 0);
                             } else {
-                                store_u32((uintptr_t)(drow + o), o01[k]);
-                                store_u32((uintptr_t)(drow + o + 4), o23[k]);
+                                __builtin_amdgcn_raw_buffer_store_b32(o01[k], drs, (int)dvoff, so, 0);
+                                __builtin_amdgcn_raw_buffer_store_b32(o23[k], drs, (int)dvoff + 4,
+                                                                      so, 0);
                             }
                         } else {
-                            Px<T>::store(drow, 4 * Q, J.W, o01[k], o23[k]);
+                            Px<T>::store(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W,
+                                         o01[k], o23[k]);
                         }
                     }
-                    drow += J.dpitch;
                 }
             }
         }
         t += cnt;
         j += cnt;
         if (j == wy) { // block complete: its suffixes replace it in the ring
-            ring_suffixes<MAXOP>(ring, wy);
+            ring.template suffixes<MAXOP>(wy, rs01, rs23);
             j = 0;
             fill = false;
             g01 = g23 = id;
         }
-#pragma unroll
-        for (int k = 0; k < SD; k++) cur[k] = nxt[k];
     }
 }
 
