@@ -4,14 +4,14 @@
 Workload (one "step"): the mixed-size batch -- 512 uint8 document-like images,
 H and W each log-uniform in [64, 2048], a square window per image drawn from
 {3, 5, 9, 15, 31, 63}, erosion or dilation at random (seed 5) -- run as one
-graph-replayed batch: a wave-kernel launch for the images whose two passes are
-direct and a streaming-kernel launch for the others.  Images are resident
-in HBM before timing; rows are padded to a 64-byte pitch.  The roofline figure
-is that of the slower of the two kernels, timed alone on its images.  Reported
-beside it: the same 512 images as 512 separate launches (eager and captured in
-one graph), the 4096x4096 uint8 and uint16 erosion/dilation kernels at the four
-large windows and at 3x3, and the CPU oracle timed on a bounded sample of the
-batch on the host's cores.
+graph-replayed batch: one kernel dispatch per launch group (the wave kernel for the
+images whose two passes are direct, the streaming kernel per ring size for the
+others).  Images are resident in HBM before timing; rows are padded to a 64-byte
+pitch.  The roofline figure is that of the slowest dispatch of the step, timed
+alone on its images.  Reported beside it: the same 512 images as 512 separate
+launches (eager and captured in one graph), the 4096x4096 uint8 and uint16
+erosion/dilation kernels at the four large windows and at 3x3, and the CPU oracle
+timed on a bounded sample of the batch on the host's cores.
 
 Prints ONE JSON line.  ``--gpus`` other than 1 exits with a message: this build
 runs on one GPU.
@@ -46,9 +46,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, kernel: str):
-    """HBM traffic per launch of `kernel` from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources (else None)."""
+def load_traffic(workload: str, group: str):
+    """HBM traffic per dispatch of the launch group `group` from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources (else
+    None)."""
     path = os.path.join(ROOT, "profiles", "batch512_traffic.json")
     try:
         with open(path) as f:
@@ -57,7 +58,7 @@ def load_traffic(workload: str, kernel: str):
         return None
     if t.get("workload") != workload or t.get("kernel_digest") != kernel_source_digest():
         return None
-    return t.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+    return t.get("groups", {}).get(group, {}).get("hbm_bytes_per_launch")
 
 
 def build_batch(torch, morph, synth, dev):
@@ -170,19 +171,34 @@ def c3_lines(torch, morph, dev, steps):
     return out
 
 
+def _effective(w, extent):
+    """A window clipped to the image (default anchor), as the library plans it."""
+    a = w - 1 - w // 2
+    return min(a, extent - 1) + min(w - 1 - a, extent - 1) + 1
+
+
 def kernel_groups(morph, items):
-    """Split the batch by the kernel its images run on (the library's plan)."""
+    """Split the batch into the library's launch groups (one kernel dispatch each):
+    by kernel, and for the streaming kernel by ring size (effective wy <= 16, 32, 64)."""
     groups = {}
     for it in items:
         H, W = it["src"].shape
         k = morph.resolve_plan("u8", H, W, it["wx"], it["wy"])["kernel"]
+        if k == "stream":
+            wy = _effective(it["wy"], H)
+            k = "stream_wy%d" % (16 if wy <= 16 else 32 if wy <= 32 else 64)
         groups.setdefault(k, []).append(it)
     return groups
 
 
 KERNEL_LABELS = {"wave": "batch_wave_kernel<u8, aligned rows>",
-                 "stream": "batch_stream_kernel<u8, aligned rows>",
                  "tile": "batch_kernel<u8, aligned rows>"}
+
+
+def kernel_label(group):
+    if group.startswith("stream_wy"):
+        return "batch_stream_kernel<u8, aligned rows>, ring wy <= %s" % group[len("stream_wy"):]
+    return KERNEL_LABELS[group]
 
 
 def main():
@@ -235,27 +251,26 @@ def main():
     value = npx / (ms_per_step * 1e-3) / 1e9
     sp = sorted(per)
 
-    # The step launches one kernel per group of images (wave kernel: both passes
-    # direct; streaming kernel: larger windows).  Each group alone, as its own batch,
-    # times that kernel's launch; the roofline is taken on the dominant one.
-    _log("timing each kernel of the step")
+    # The step launches one kernel dispatch per group of images (wave kernel: both
+    # passes direct; streaming kernel, per ring size: larger windows).  Each group
+    # alone, as its own batch (one dispatch), times that dispatch; the roofline is
+    # taken on the dominant one.
+    _log("timing each kernel dispatch of the step")
     kernels = []
-    for name, its in kernel_groups(morph, items).items():
-        if not its:
-            continue
+    for name, its in sorted(kernel_groups(morph, items).items()):
         sub = morph.Batch(len(its), 1 << 22)
-        sub.set(its)
+        units = sub.set(its)
         kp, _ = time_launches(torch, lambda: sub.enqueue(), args.steps, args.warmup, stream)
         kms = sum(kp) / len(kp)
         kpx = sum(it["src"].shape[0] * it["src"].shape[1] for it in its)
         gbs = 2 * kpx / (kms * 1e-3) / 1e9  # one read and one write of every uint8 pixel
-        kernels.append({"kernel": KERNEL_LABELS[name],
-                        "images": len(its), "pixels": kpx, "ms_per_launch": round(kms, 5),
+        kernels.append({"kernel": kernel_label(name), "group": name, "images": len(its),
+                        "units": units, "pixels": kpx, "ms_per_launch": round(kms, 5),
                         "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)})
         sub.close()
     dom = max(kernels, key=lambda k: k["ms_per_launch"])
     workload = "batch512_mixed_u8"
-    traffic = load_traffic(workload, dom["kernel"])
+    traffic = load_traffic(workload, dom["group"])
     res = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -279,6 +294,7 @@ def main():
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": dom["frac"],
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": 2 * dom["pixels"],
+                     "units_per_launch": dom["units"],
                      "ms_per_launch": dom["ms_per_launch"]},
         "kernels": kernels,
         "step_gbs": round(2 * npx / (ms_per_step * 1e-3) / 1e9, 1),

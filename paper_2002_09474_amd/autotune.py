@@ -1,17 +1,22 @@
-"""Autotuner: measures, on the GPU it runs on, where the direct pass stops beating
-van Herk/Gil-Werman (per pass and element type) and which tile shape is fastest
-for each window bucket, and writes the tuning table the library loads
+"""Autotuner: measures, on the GPU it runs on, where the direct passes stop beating
+the large-window passes (per pass and element type), how many rows the wave and
+streaming kernels' units should hold, and which tile shapes the workgroup-tile
+kernel should use, and writes the tuning table the library loads
 (``morph_load_tuning``; the Python package loads ``tuning_gfx950.json`` next to
 this file at start-up when it exists).
 
 The paper chose its switch-over windows by timing both implementations of each
 pass over a range of windows (§5.1.3, §5.2.3, §5.3); this does the same with the
-GPU kernels: single-pass sweeps along x (w x 1) and along y (1 x w) on the
-1920x1080 document page, both methods forced.  The threshold of a pass is the
-largest window up to which the direct pass is never slower than vHGW by more than
-the timing noise.  Tile shapes (input quads per tile row ``tq`` and output rows
-``tb``) are then timed per window bucket on 4096x4096 images with the chosen
-thresholds.  Run ``python -m paper_2002_09474_amd.autotune``.
+GPU kernels the automatic plan picks between: for a pass of window w, the direct
+pass (the register-only wave kernel when both passes are direct) against the
+large-window pass (the streaming kernel: vHGW through an LDS ring vertically,
+doubling across lanes horizontally), as single-pass sweeps along x (w x 1) and
+along y (1 x w) on the 1920x1080 document page.  The threshold of a pass is the
+largest window up to which direct is never slower by more than the timing noise.
+Unit heights are then chosen on the 512-image batch of the benchmark (the wave
+kernel's on its direct-window images, the streaming kernel's on the others), and
+tile shapes of the tile kernel per window bucket on 4096x4096 images.  Run
+``python -m paper_2002_09474_amd.autotune``.
 """
 from __future__ import annotations
 
@@ -19,6 +24,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning_gfx950.json")
@@ -26,6 +32,8 @@ DIRECT_MAX = 9
 BUCKETS = ((9, 9), (16, 15), (32, 31), (64, 63), (1 << 30, 101))  # (wmax, representative w)
 TQ = (16, 32, 48, 64, 96)
 TB = (16, 32, 64, 128)
+WAVE_ROWS = (8, 16, 24, 32, 48)
+STREAM_ROWS = (0, 32, 64, 96, 128)  # 0: the library's automatic choice
 
 
 def _timer(torch, fn, iters, warmup=5):
@@ -47,48 +55,84 @@ def _bufs(torch, img, n):
     return srcs, [torch.empty_like(s) for s in srcs]
 
 
-def pass_sweep(torch, morph, srcs, dsts, iters=40):
-    """Time each single pass, direct vs vHGW, for w = 2 .. DIRECT_MAX."""
-    rows = []
-    for axis in ("x", "y"):
-        for w in range(2, DIRECT_MAX + 1):
-            wx, wy = (w, 1) if axis == "x" else (1, w)
-            t = {}
-            for m in ("direct", "vhgw"):
-                k = [0]
-                kw = {"method_x": m} if axis == "x" else {"method_y": m}
+def _with_table(morph, table):
+    """Load a tuning table given as a dict (through a temporary file)."""
+    fd, path = tempfile.mkstemp(suffix=".json")
+    try:
+        with os.fdopen(fd, "w") as f:
+            json.dump(table, f)
+        morph.load_tuning(path)
+    finally:
+        os.unlink(path)
 
-                def fn():
-                    i = k[0] % len(srcs)
-                    k[0] += 1
-                    morph.apply("erode", srcs[i], wx, wy, out=dsts[i], **kw)
-                t[m] = _timer(torch, fn, iters)
-            rows.append({"axis": axis, "w": w, "direct_us": round(t["direct"], 3),
-                         "vhgw_us": round(t["vhgw"], 3)})
+
+def pass_sweep(torch, morph, dname, srcs, dsts, iters=40):
+    """Time each single pass for w = 2 .. DIRECT_MAX, direct (threshold >= w) against
+    the large-window pass (threshold w - 1), with automatic methods."""
+    rows = []
+    t0 = morph.get_thresholds(dname)
+    try:
+        for axis in ("x", "y"):
+            for w in range(2, DIRECT_MAX + 1):
+                wx, wy = (w, 1) if axis == "x" else (1, w)
+                t = {}
+                for name, thr in (("direct", w), ("large", w - 1)):
+                    morph.set_thresholds(dname, thr if axis == "x" else t0[0],
+                                         thr if axis == "y" else t0[1])
+                    k = [0]
+
+                    def fn():
+                        i = k[0] % len(srcs)
+                        k[0] += 1
+                        morph.apply("erode", srcs[i], wx, wy, out=dsts[i])
+                    t[name] = _timer(torch, fn, iters)
+                rows.append({"axis": axis, "w": w, "direct_us": round(t["direct"], 3),
+                             "large_us": round(t["large"], 3)})
+    finally:
+        morph.set_thresholds(dname, *t0)
     return rows
 
 
 def threshold(rows, axis, tol=0.03):
-    """Largest w such that direct <= vHGW * (1 + tol) for every w' <= w (1 if none)."""
+    """Largest w such that direct <= large * (1 + tol) for every w' <= w (1 if none)."""
     t = 1
     for r in sorted((r for r in rows if r["axis"] == axis), key=lambda r: r["w"]):
-        if r["direct_us"] <= r["vhgw_us"] * (1 + tol):
+        if r["direct_us"] <= r["large_us"] * (1 + tol):
             t = r["w"]
         else:
             break
     return t
 
 
+def best_rows(torch, morph, dname, items, key, choices, base, iters=10):
+    """The `key` (wave_rows or stream_rows) among `choices` that runs `items` as one
+    batch fastest, the rest of the table being `base`."""
+    res = []
+    for c in choices:
+        _with_table(morph, {dname: dict(base, **{key: c})})
+        b = morph.Batch(len(items), 1 << 22)
+        try:
+            b.set(items)
+            us = _timer(torch, lambda: b.enqueue(), iters, warmup=3)
+        finally:
+            b.close()
+        res.append({key: c, "us": round(us, 2)})
+    best = min(res, key=lambda r: r["us"])[key]
+    return best, res
+
+
 def tile_sweep(torch, morph, srcs, dsts, dname, iters=20):
+    """Tile shapes of the workgroup-tile kernel (forced vHGW passes) per window bucket."""
     rules, table = [], []
     H, W = srcs[0].shape
+    v = dict(method_x="vhgw", method_y="vhgw")
     for wmax, w in BUCKETS:
         best = None
         for tq in TQ:
             for tb in TB:
                 tw = max(4 * tq - ((w + 2 + 3) // 4 * 4), (2 * w + 3) // 4 * 4)
                 try:
-                    plan = morph.resolve_plan(dname, H, W, w, w, tile=(tw, tb))
+                    plan = morph.resolve_plan(dname, H, W, w, w, tile=(tw, tb), **v)
                 except morph.MorphError:
                     continue
                 k = [0]
@@ -96,7 +140,7 @@ def tile_sweep(torch, morph, srcs, dsts, dname, iters=20):
                 def fn():
                     i = k[0] % len(srcs)
                     k[0] += 1
-                    morph.apply("erode", srcs[i], w, w, out=dsts[i], tile=(tw, tb))
+                    morph.apply("erode", srcs[i], w, w, out=dsts[i], tile=(tw, tb), **v)
                 try:
                     us = _timer(torch, fn, iters)
                 except morph.MorphError:
@@ -108,6 +152,22 @@ def tile_sweep(torch, morph, srcs, dsts, dname, iters=20):
         if best is not None:
             rules.append({"wmax": wmax, "tq": best[1], "tb": best[2]})
     return rules, table
+
+
+def _batch_items(torch, morph, dev, dname):
+    """The benchmark's 512-image batch (uint8, or the same images scaled to uint16),
+    split by kernel: direct-window images and the others."""
+    from . import synth
+    specs = synth.batch_specs(512, seed=5)
+    imgs = synth.batch_images(specs, seed=5)
+    direct, large = [], []
+    for s, im in zip(specs, imgs):
+        t = torch.from_numpy(im).to(dev)
+        if dname == "u16":
+            t = (t.to(torch.int32) * 257).to(torch.int16).view(torch.uint16)
+        it = dict(src=t, dst=torch.empty_like(t), wx=s["w"], wy=s["w"], op=s["op"])
+        (direct if s["w"] <= DIRECT_MAX else large).append(it)
+    return direct, large
 
 
 def tune(out_path=DEFAULT_OUT, quick=False):
@@ -122,10 +182,19 @@ def tune(out_path=DEFAULT_OUT, quick=False):
     for dname in ("u8", "u16"):
         img = doc if dname == "u8" else (doc.to(torch.int32) * 257).to(torch.int16).view(torch.uint16)
         srcs, dsts = _bufs(torch, img, 8)
-        rows = pass_sweep(torch, morph, srcs, dsts, iters=20 if quick else 40)
+        rows = pass_sweep(torch, morph, dname, srcs, dsts, iters=20 if quick else 40)
         tx, ty = threshold(rows, "x"), threshold(rows, "y")
-        morph.set_thresholds(dname, tx, ty)
         del srcs, dsts
+        base = {"t_x": tx, "t_y": ty}
+        direct, large = _batch_items(torch, morph, dev, dname)
+        wr, wr_table = best_rows(torch, morph, dname, direct, "wave_rows", WAVE_ROWS, base,
+                                 iters=5 if quick else 10)
+        base["wave_rows"] = wr
+        sr, sr_table = best_rows(torch, morph, dname, large, "stream_rows", STREAM_ROWS, base,
+                                 iters=5 if quick else 10)
+        base["stream_rows"] = sr
+        del direct, large
+        _with_table(morph, {dname: base})
         g = torch.Generator(device=dev).manual_seed(3)
         big = torch.randint(0, 256 if dname == "u8" else 65536, (4096, 4096), generator=g,
                             dtype=torch.int32, device=dev)
@@ -133,11 +202,12 @@ def tune(out_path=DEFAULT_OUT, quick=False):
         srcs, dsts = _bufs(torch, big, 6)
         rules, table = tile_sweep(torch, morph, srcs, dsts, dname, iters=8 if quick else 20)
         del srcs, dsts, big
-        result[dname] = {"t_x": tx, "t_y": ty, "tiles": rules}
+        result[dname] = dict(base, tiles=rules)
         result[dname + "_pass_sweep"] = rows
+        result[dname + "_wave_rows_sweep"] = wr_table
+        result[dname + "_stream_rows_sweep"] = sr_table
         result[dname + "_tile_sweep"] = table
-        print("[autotune] %s: t_x=%d t_y=%d tiles=%s" % (dname, tx, ty, rules), file=sys.stderr,
-              flush=True)
+        print("[autotune] %s: %s" % (dname, result[dname]), file=sys.stderr, flush=True)
     with open(out_path, "w") as f:
         json.dump(result, f, indent=1)
     morph.load_tuning(out_path)

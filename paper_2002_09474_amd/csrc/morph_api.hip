@@ -557,7 +557,10 @@ struct BatchGroup {
 // of large ones
 static constexpr int kRingClasses = 3;
 static constexpr int kBatchGroups = 4 * (kKinds + kRingClasses - 1);
-static constexpr int kSide = 4;                  // group launches in flight at once
+#ifndef MORPH_SIDE_STREAMS
+#define MORPH_SIDE_STREAMS 4
+#endif
+static constexpr int kSide = MORPH_SIDE_STREAMS; // group launches in flight at once
 
 struct morph_batch {
     int max_images = 0;

@@ -852,7 +852,12 @@ template <typename T> struct WaveLoader {
     using Raw = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
     __device__ __forceinline__ Raw issue(int gy) const
     {
-        const int soff = (int)((uint32_t)min(max(gy, 0), H - 1) * pitch);
+        return issue_at((uint32_t)min(max(gy, 0), H - 1) * pitch);
+    }
+    // the row at byte offset soff (a row inside the image)
+    __device__ __forceinline__ Raw issue_at(uint32_t soff_) const
+    {
+        const int soff = (int)soff_;
         if constexpr (sizeof(T) == 1) {
             return __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, soff, 0);
         } else {
@@ -1261,17 +1266,23 @@ template <> struct Ring<uint8_t> {
     __device__ __forceinline__ void suffixes(int wy, uint32_t s01, uint32_t s23) const
     {
         uint32_t h01 = MAXOP ? 0u : 0xffffffffu, h23 = h01;
-        for (int j = wy - 1; j >= 0; j -= 8) {
+        int j = wy - 1;
+        for (; j >= 7; j -= 8) { // whole batches of 8 entries
             uint32_t v[8];
 #pragma unroll
-            for (int k = 0; k < 8; k++) v[k] = e[64 * max(j - k, 0)];
+            for (int k = 0; k < 8; k++) v[k] = e[64 * (j - k)];
 #pragma unroll
-            for (int k = 0; k < 8; k++)
-                if (j - k >= 0) {
-                    h01 = pk<MAXOP>(h01, perm(0u, v[k], s01));
-                    h23 = pk<MAXOP>(h23, perm(0u, v[k], s23));
-                    e[64 * (j - k)] = perm(h23, h01, SEL_NARROW);
-                }
+            for (int k = 0; k < 8; k++) {
+                h01 = pk<MAXOP>(h01, perm(0u, v[k], s01));
+                h23 = pk<MAXOP>(h23, perm(0u, v[k], s23));
+                e[64 * (j - k)] = perm(h23, h01, SEL_NARROW);
+            }
+        }
+        for (; j >= 0; j--) {
+            const uint32_t v = e[64 * j];
+            h01 = pk<MAXOP>(h01, perm(0u, v, s01));
+            h23 = pk<MAXOP>(h23, perm(0u, v, s23));
+            e[64 * j] = perm(h23, h01, SEL_NARROW);
         }
     }
 };
@@ -1293,17 +1304,23 @@ template <> struct Ring<uint16_t> {
     __device__ __forceinline__ void suffixes(int wy, uint32_t, uint32_t) const
     {
         uint32_t h01 = MAXOP ? 0u : 0xffffffffu, h23 = h01;
-        for (int j = wy - 1; j >= 0; j -= 8) {
+        int j = wy - 1;
+        for (; j >= 7; j -= 8) { // whole batches of 8 entries
             uint2 v[8];
 #pragma unroll
-            for (int k = 0; k < 8; k++) v[k] = e[64 * max(j - k, 0)];
+            for (int k = 0; k < 8; k++) v[k] = e[64 * (j - k)];
 #pragma unroll
-            for (int k = 0; k < 8; k++)
-                if (j - k >= 0) {
-                    h01 = pk<MAXOP>(h01, v[k].x);
-                    h23 = pk<MAXOP>(h23, v[k].y);
-                    e[64 * (j - k)] = make_uint2(h01, h23);
-                }
+            for (int k = 0; k < 8; k++) {
+                h01 = pk<MAXOP>(h01, v[k].x);
+                h23 = pk<MAXOP>(h23, v[k].y);
+                e[64 * (j - k)] = make_uint2(h01, h23);
+            }
+        }
+        for (; j >= 0; j--) {
+            const uint2 v = e[64 * j];
+            h01 = pk<MAXOP>(h01, v.x);
+            h23 = pk<MAXOP>(h23, v.y);
+            e[64 * j] = make_uint2(h01, h23);
         }
     }
 };
@@ -1338,7 +1355,7 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
         rs23 = L.s23;
     }
     const Doubling S(J.wx, co);
-    const bool hdirect = J.wx <= kDirectMax;
+    const bool hdirect = J.hm != PASS_DOUBLING; // direct (wx <= kDirectMax) or none
     const Ring<T> ring(lds);
     // destination: rows 4-byte aligned, the strip wholly inside the image and the
     // image spanning < 4 GiB take buffer stores (row offset scalar)
@@ -1355,6 +1372,10 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
     // Rows are taken in chunks of up to SD that stay inside one block: block 0 fills
     // the ring, every later chunk emits outputs.  As soon as a chunk's rows are
     // widened, the next chunk's loads are issued into the same registers.
+    // units clear of the image's top and bottom rows load without clamping, at row
+    // offsets stepped by the pitch
+    const bool rows_in = AL && gy0 >= 0 && gy0 + last + 2 * SD <= J.H;
+    const uint32_t pitch = (uint32_t)J.pitch;
     typename Ld::Raw cur[SD];
 #pragma unroll
     for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + k);
@@ -1363,6 +1384,7 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
     bool fill = true;
     while (t <= last) {
         const int cnt = min(min(SD, wy - j), last - t + 1);
+        const bool full = cnt == SD;
         typename Ld::Raw raw[SD];
         uint32_t x01[SD], x23[SD];
 #pragma unroll
@@ -1370,12 +1392,28 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
             raw[k] = cur[k];
             L.widen(raw[k], x01[k], x23[k]);
         }
+        if constexpr (AL) {
+            if (rows_in) {
+                uint32_t so = (uint32_t)(gy0 + t + cnt) * pitch;
 #pragma unroll
-        for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + t + cnt + k);
+                for (int k = 0; k < SD; k++, so += pitch) cur[k] = L.issue_at(so);
+            } else {
+#pragma unroll
+                for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + t + cnt + k);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + t + cnt + k);
+        }
         if (fill) {
+            if (full) {
 #pragma unroll
-            for (int k = 0; k < SD; k++)
-                if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
+                for (int k = 0; k < SD; k++) ring.put(j + k, raw[k], x01[k], x23[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < SD; k++)
+                    if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
+            }
         } else {
             uint32_t o01[SD], o23[SD];
 #pragma unroll
@@ -1388,9 +1426,14 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
                 g01 = pk<MAXOP>(g01, x01[k]);
                 g23 = pk<MAXOP>(g23, x23[k]);
             }
+            if (full) {
 #pragma unroll
-            for (int k = 0; k < SD; k++)
-                if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
+                for (int k = 0; k < SD; k++) ring.put(j + k, raw[k], x01[k], x23[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < SD; k++)
+                    if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
+            }
             // output rows t - wy .. t - wy + cnt - 1: horizontal pass, then store
             if constexpr (AL && sizeof(T) == 2)
                 if (edge) {
@@ -1401,24 +1444,28 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
             else doubling_rows<SD, MAXOP>(S, o01, o23);
             if (store_lane) {
                 const int y = y0 + t - wy;
+                if (fast_store) {
+                    uint32_t so = (uint32_t)y * (uint32_t)J.dpitch;
 #pragma unroll
-                for (int k = 0; k < SD; k++) {
-                    if (k < cnt) {
-                        if (fast_store) {
-                            const int so = (int)((uint32_t)(y + k) * (uint32_t)J.dpitch);
+                    for (int k = 0; k < SD; k++, so += (uint32_t)J.dpitch) {
+                        if (full || k < cnt) {
                             if constexpr (sizeof(T) == 1) {
                                 __builtin_amdgcn_raw_buffer_store_b32(
-                                    perm(o23[k], o01[k], SEL_NARROW), drs, (int)dvoff, so, 0);
+                                    perm(o23[k], o01[k], SEL_NARROW), drs, (int)dvoff, (int)so, 0);
                             } else {
-                                __builtin_amdgcn_raw_buffer_store_b32(o01[k], drs, (int)dvoff, so, 0);
+                                __builtin_amdgcn_raw_buffer_store_b32(o01[k], drs, (int)dvoff,
+                                                                      (int)so, 0);
                                 __builtin_amdgcn_raw_buffer_store_b32(o23[k], drs, (int)dvoff + 4,
-                                                                      so, 0);
+                                                                      (int)so, 0);
                             }
-                        } else {
-                            Px<T>::store(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W,
-                                         o01[k], o23[k]);
                         }
                     }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < SD; k++)
+                        if (k < cnt)
+                            Px<T>::store(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W, o01[k],
+                                         o23[k]);
                 }
             }
         }
