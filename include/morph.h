@@ -82,7 +82,7 @@ extern "C" {
  * (tile_w a multiple of 4, tile_h a multiple of 2).  A plan never changes the
  * result, only how it is computed.
  * Kernels: both passes direct run one wave per strip in registers; with both
- * methods AUTO and no tile, larger windows (wx <= 128, wy <= 64) run one wave per
+ * methods AUTO and no tile, larger windows (wx <= 128, wy <= 128) run one wave per
  * strip that streams down the rows (vertical vHGW through LDS, horizontal direct
  * or doubling); anything else -- a forced vHGW pass, a tile, larger windows --
  * runs the workgroup-tile kernel, which implements exactly the paper's two
@@ -197,11 +197,13 @@ int morph_batch_destroy(morph_batch_t b);
 /* Load a tuning table (JSON written by the autotuner) replacing the current one:
  * per-dtype direct/vHGW thresholds, tile shapes per window bucket (tq = input
  * quads of a tile row, tb = output rows), the output rows of a direct wave unit
- * (a multiple of 8, at most 64) and of a streaming unit (1 .. 4096), e.g.
- *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 128,
+ * (a multiple of 8, at most 64; default 24) and of a streaming unit (1 .. 4096;
+ * default 48), e.g.
+ *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 64,
  *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
- * A dtype missing from the file keeps its table; a key missing keeps its value.  NULL restores the built-in
- * defaults.  A malformed file returns MORPH_EINVAL and changes nothing. */
+ * A dtype missing from the file keeps its table; a key missing keeps its value.
+ * NULL restores the built-in defaults.  A malformed file returns MORPH_EINVAL and
+ * changes nothing. */
 int morph_load_tuning(const char *json_path);
 /* Current per-pass direct->vHGW thresholds for a dtype (direct when w <= t). */
 int morph_get_thresholds(int dtype, int *t_x, int *t_y);

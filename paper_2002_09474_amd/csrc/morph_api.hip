@@ -40,13 +40,13 @@ struct DtypeTuning {
     int t_x, t_y; // direct when w <= t (per pass)
     std::vector<TileRule> tiles;
     int wave_rows;   // output rows of a wave unit (both passes direct), multiple of kWaveRows
-    int stream_rows; // output rows of a streaming-kernel unit, 0: automatic
+    int stream_rows; // output rows of a streaming-kernel unit
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 0},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 8, 0},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -153,8 +153,8 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
     if (it != o.obj.end()) {
         if (it->second.k != JVal::NUM) return false;
         const int r = (int)it->second.num;
-        if (r < 0 || r > 4096) return false;
-        t.stream_rows = r; // 0: automatic
+        if (r < 1 || r > 4096) return false;
+        t.stream_rows = r;
     }
     it = o.obj.find("tiles");
     if (it != o.obj.end()) {
@@ -215,8 +215,7 @@ int default_anchor(int w) { return w - 1 - w / 2; }
 // anchor a and right extent r = w - 1 - a, only min(a, W-1) columns to the left and
 // min(r, W-1) to the right can ever be inside the image.
 int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
-             size_t dpitch, int wx, int wy, int ax, int ay, const morph_plan *plan, TileJob &j,
-             bool in_batch = false)
+             size_t dpitch, int wx, int wy, int ax, int ay, const morph_plan *plan, TileJob &j)
 {
     if (ax < 0) ax = default_anchor(wx);
     if (ay < 0) ay = default_anchor(wy);
@@ -284,18 +283,10 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
         j.TW = 4 * stream_quads(j.wx);
         j.tiles_x = (W + j.TW - 1) / j.TW;
-        if (tu.stream_rows > 0) {
-            j.TB = std::min(tu.stream_rows, H);
-        } else {
-            // about four vertical windows per unit (the wy - 1 halo rows a unit reads
-            // twice stay a small part of it), 32 .. 256 rows; a single image is cut
-            // finer until it gives the chip a few waves per SIMD
-            // (in a batch at most 128: long units would trail the end of the launch)
-            int tb = std::min(in_batch ? 128 : 256, std::max(32, (4 * j.wy + 7) & ~7));
-            if (!in_batch)
-                while (tb > 32 && (int64_t)j.tiles_x * ((H + tb - 1) / tb) < kStreamMinUnits) tb /= 2;
-            j.TB = std::min(tb, H);
-        }
+        // (48 rows measured within a few per cent of the best unit height for every
+        // window of the benchmark batch and the 4096x4096 images, and best for the
+        // mixed batch, whose short per-group launches want many units)
+        j.TB = std::min(tu.stream_rows, H);
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
         return MORPH_OK;
@@ -553,14 +544,10 @@ struct BatchGroup {
 };
 
 // groups: kernel kind x element type x row alignment, and for the streaming kernel
-// three ring sizes (wy <= 16, 32, 64) so that small windows are not given the LDS
-// of large ones
-static constexpr int kRingClasses = 3;
+// four ring sizes (wy <= 16, 32, 64, 128) so that small windows are not given the
+// LDS of large ones
+static constexpr int kRingClasses = 4;
 static constexpr int kBatchGroups = 4 * (kKinds + kRingClasses - 1);
-#ifndef MORPH_SIDE_STREAMS
-#define MORPH_SIDE_STREAMS 4
-#endif
-static constexpr int kSide = MORPH_SIDE_STREAMS; // group launches in flight at once
 
 struct morph_batch {
     int max_images = 0;
@@ -583,10 +570,6 @@ struct morph_batch {
     // previous copy before it overwrites them
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
-    // the group kernels run side by side: group g on the caller's stream (g % kSide
-    // == 0) or on aux[g % kSide - 1], forked from and joined back to the caller's
-    hipStream_t aux[kSide - 1] = {};
-    hipEvent_t fork = nullptr, join[kSide - 1] = {};
 };
 
 
@@ -629,17 +612,10 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
         (e = hipMemset(b->d_counter, 0, sizeof(unsigned long long) * ncount)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess) {
         morph_batch_destroy(b);
         return hip_fail(e);
     }
-    for (int i = 0; i < kSide - 1; i++)
-        if ((e = hipStreamCreateWithFlags(&b->aux[i], hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming)) != hipSuccess) {
-            morph_batch_destroy(b);
-            return hip_fail(e);
-        }
     *out = b;
     return MORPH_OK;
 }
@@ -649,12 +625,12 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
 static int group_of(const TileJob &j)
 {
     int k = j.kind;
-    if (j.kind == KIND_STREAM) k += (j.wy > 16) + (j.wy > 32);
+    if (j.kind == KIND_STREAM) k += (j.wy > 16) + (j.wy > 32) + (j.wy > 64);
     return 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
 }
 
-// Launch order of the groups: streaming groups from the largest ring down (their
-// units are the longest), then the tile and wave groups.
+// Launch order of the groups: streaming groups from the largest ring down, then the
+// tile and wave groups.
 static int group_order(int gi)
 {
     constexpr int ns = 4 * kRingClasses;
@@ -688,7 +664,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
             return MORPH_EALIAS;
         TileJob j;
         rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, dp, d.wx, d.wy, d.ax,
-                      d.ay, nullptr, j, true);
+                      d.ay, nullptr, j);
         if (rc != MORPH_OK) return rc;
         jobs[group_of(j)].push_back(j);
     }
@@ -697,7 +673,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
     int m = 0, starts = 0;
     const int cus = device_cus();
     for (int gi = 0; gi < kBatchGroups; gi++) {
-        // heaviest first: the streaming groups from the largest ring down, then the rest
+        // the streaming groups from the largest ring down, then the rest
         const int g = group_order(gi);
         if (jobs[g].empty()) continue;
         BatchGroup G;
@@ -765,33 +741,20 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
     return MORPH_OK;
 }
 
+// The group kernels one after the other on the caller's stream (running them side
+// by side on forked streams measured no faster on the benchmark batch).
 static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
 {
-    // side streams only for a real stream with more than one group (the legacy null
-    // stream keeps its implicit ordering)
-    const int ng = (int)b->groups.size();
-    const int side = (stream == nullptr) ? 1 : std::min(kSide, ng);
-    hipError_t e;
-    if (side > 1) {
-        if ((e = hipEventRecord(b->fork, stream)) != hipSuccess) return e;
-        for (int i = 0; i < side - 1; i++)
-            if ((e = hipStreamWaitEvent(b->aux[i], b->fork, 0)) != hipSuccess) return e;
-    }
     int start = 0;
     int64_t tstart = 0;
-    for (int g = 0; g < ng; g++) {
+    for (size_t g = 0; g < b->groups.size(); g++) {
         const BatchGroup &G = b->groups[g];
         BatchTables t{b->d_jobs + G.job0, b->d_tile_start + start, b->d_tile_job + tstart,
                       G.njobs, G.tiles, b->d_counter + 2 * g};
         start += G.njobs + 1;
         tstart += G.tiles;
-        const int k = g % side;
-        e = launch_batch(t, G.kind, G.dtype, G.aligned, G.grid, G.lds, k ? b->aux[k - 1] : stream);
+        hipError_t e = launch_batch(t, G.kind, G.dtype, G.aligned, G.grid, G.lds, stream);
         if (e != hipSuccess) return e;
-    }
-    for (int i = 0; i < side - 1; i++) {
-        if ((e = hipEventRecord(b->join[i], b->aux[i])) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(stream, b->join[i], 0)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -848,11 +811,6 @@ int morph_batch_destroy(morph_batch_t b)
     if (!b) return MORPH_EINVAL;
     drop_graph(b);
     if (b->staged) (void)hipEventDestroy(b->staged);
-    if (b->fork) (void)hipEventDestroy(b->fork);
-    for (int i = 0; i < kSide - 1; i++) {
-        if (b->aux[i]) (void)hipStreamDestroy(b->aux[i]);
-        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
-    }
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_tile_start) (void)hipFree(b->d_tile_start);
     if (b->d_tile_job) (void)hipFree(b->d_tile_job);

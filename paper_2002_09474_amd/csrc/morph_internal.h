@@ -22,8 +22,7 @@ enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3
 enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2 };
 constexpr int kKinds = 3;
 constexpr int kStreamMaxWx = 128; // wider windows leave a 64-quad strip too few outputs
-constexpr int kStreamMaxWy = 64;  // the ring takes 256 (u8) or 512 (u16) bytes of LDS per row
-constexpr int kStreamMinUnits = 2048; // a single image's streaming units: a few per SIMD
+constexpr int kStreamMaxWy = 128; // the ring takes 256 (u8) or 512 (u16) bytes of LDS per row
 constexpr int kStreamChunk = 8;       // rows a streaming wave takes at a time
 // ring entries of the streaming kernel's vertical pass: wy, plus slack so that a
 // chunk may read kStreamChunk entries from any position

@@ -1376,43 +1376,44 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
     // offsets stepped by the pitch
     const bool rows_in = AL && gy0 >= 0 && gy0 + last + 2 * SD <= J.H;
     const uint32_t pitch = (uint32_t)J.pitch;
-    typename Ld::Raw cur[SD];
-#pragma unroll
-    for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + k);
     uint32_t g01 = id, g23 = id;
     int t = 0, j = 0;
     bool fill = true;
-    while (t <= last) {
+    // One chunk: rows t .. t + cnt - 1 from `cur`; the next chunk's rows are loaded into
+    // `nxt`.  The loop below alternates the two buffers, so that no loaded register is
+    // ever copied (a copy would wait for the load).  Returns whether rows remain.
+    auto chunk = [&](typename Ld::Raw(&cur)[SD], typename Ld::Raw(&nxt)[SD]) -> bool {
         const int cnt = min(min(SD, wy - j), last - t + 1);
         const bool full = cnt == SD;
-        typename Ld::Raw raw[SD];
         uint32_t x01[SD], x23[SD];
 #pragma unroll
-        for (int k = 0; k < SD; k++) {
-            raw[k] = cur[k];
-            L.widen(raw[k], x01[k], x23[k]);
-        }
+        for (int k = 0; k < SD; k++) L.widen(cur[k], x01[k], x23[k]);
         if constexpr (AL) {
+            // row offsets first (scalar; clamped only near the image's top and bottom),
+            // then the loads in one straight run
+            const int r0 = gy0 + t + cnt;
+            uint32_t so[SD];
             if (rows_in) {
-                uint32_t so = (uint32_t)(gy0 + t + cnt) * pitch;
 #pragma unroll
-                for (int k = 0; k < SD; k++, so += pitch) cur[k] = L.issue_at(so);
+                for (int k = 0; k < SD; k++) so[k] = (uint32_t)(r0 + k) * pitch;
             } else {
 #pragma unroll
-                for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + t + cnt + k);
+                for (int k = 0; k < SD; k++) so[k] = (uint32_t)min(max(r0 + k, 0), J.H - 1) * pitch;
             }
+#pragma unroll
+            for (int k = 0; k < SD; k++) nxt[k] = L.issue_at(__builtin_amdgcn_readfirstlane(so[k]));
         } else {
 #pragma unroll
-            for (int k = 0; k < SD; k++) cur[k] = L.issue(gy0 + t + cnt + k);
+            for (int k = 0; k < SD; k++) nxt[k] = L.issue(gy0 + t + cnt + k);
         }
         if (fill) {
             if (full) {
 #pragma unroll
-                for (int k = 0; k < SD; k++) ring.put(j + k, raw[k], x01[k], x23[k]);
+                for (int k = 0; k < SD; k++) ring.put(j + k, cur[k], x01[k], x23[k]);
             } else {
 #pragma unroll
                 for (int k = 0; k < SD; k++)
-                    if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
+                    if (k < cnt) ring.put(j + k, cur[k], x01[k], x23[k]);
             }
         } else {
             uint32_t o01[SD], o23[SD];
@@ -1428,11 +1429,11 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
             }
             if (full) {
 #pragma unroll
-                for (int k = 0; k < SD; k++) ring.put(j + k, raw[k], x01[k], x23[k]);
+                for (int k = 0; k < SD; k++) ring.put(j + k, cur[k], x01[k], x23[k]);
             } else {
 #pragma unroll
                 for (int k = 0; k < SD; k++)
-                    if (k < cnt) ring.put(j + k, raw[k], x01[k], x23[k]);
+                    if (k < cnt) ring.put(j + k, cur[k], x01[k], x23[k]);
             }
             // output rows t - wy .. t - wy + cnt - 1: horizontal pass, then store
             if constexpr (AL && sizeof(T) == 2)
@@ -1477,6 +1478,12 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
             fill = false;
             g01 = g23 = id;
         }
+        return t <= last;
+    };
+    typename Ld::Raw bufa[SD], bufb[SD];
+#pragma unroll
+    for (int k = 0; k < SD; k++) bufa[k] = L.issue(gy0 + k);
+    while (chunk(bufa, bufb) && chunk(bufb, bufa)) {
     }
 }
 

@@ -99,21 +99,23 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert p["method_x"] == "direct" and p["method_y"] == "vhgw"
         p = morph.resolve_plan("u8", 1080, 1920, 7, 7)
         assert p["method_x"] == "direct" and p["method_y"] == "direct"
-        # both passes direct: one wave per strip of 60 quads x 8 rows
-        assert (p["tile_w"], p["tile_h"], p["kernel"]) == (240, 8, "wave")
+        # both passes direct: one wave per strip of 60 quads x 24 rows
+        assert (p["tile_w"], p["tile_h"], p["kernel"]) == (240, 24, "wave")
         # a window of 1 skips the pass
         assert morph.resolve_plan("u8", 100, 100, 1, 31)["method_x"] is None
         # larger windows: the streaming kernel (vertical vHGW, horizontal doubling)
-        # up to 128 x 64, the tile kernel beyond
+        # up to 128 x 128, the tile kernel beyond
         p = morph.resolve_plan("u8", 1080, 1920, 31, 31)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
-        # units of about 4 wy rows (32 .. 256), fewer rows for a single image that
-        # would otherwise give under 2048 units
-        assert (p["tile_w"], p["tile_h"]) == (4 * 55, 32)
+        # streaming units of 48 rows
+        assert (p["tile_w"], p["tile_h"]) == (4 * 55, 48)
         p = morph.resolve_plan("u8", 1080, 1920, 7, 63)
         assert (p["method_x"], p["method_y"]) == ("direct", "vhgw")
-        assert morph.resolve_plan("u8", 100, 90, 3, 3, method_x="doubling")["tile_h"] == 32
+        assert morph.resolve_plan("u8", 100, 90, 3, 3, method_x="doubling")["tile_h"] == 48
+        assert morph.resolve_plan("u8", 20, 90, 3, 3, method_x="doubling")["tile_h"] == 20
         p = morph.resolve_plan("u8", 1080, 1920, 101, 101)
+        assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
+        p = morph.resolve_plan("u8", 1080, 1920, 129, 129)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("vhgw", "vhgw", "tile")
         for bad_kw in (dict(method_y="doubling"), dict(method_x="doubling", tile=(64, 32)),
                        dict(method_x="doubling", method_y="direct")):
@@ -139,7 +141,7 @@ def test_plan_resolution_and_thresholds(tmp_path):
         # stores the quads whose input fits in 64: (250 - wx) // 4 + 1 of them
         p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
         assert (p["method_x"], p["method_y"]) == ("doubling", "vhgw")
-        assert (p["tile_w"], p["tile_h"]) == (4 * 62, 32)
+        assert (p["tile_w"], p["tile_h"]) == (4 * 62, 48)
         f.write_text(json.dumps({"u8": {"stream_rows": 100}}))
         morph.load_tuning(str(f))
         assert morph.resolve_plan("u8", 1000, 1000, 5, 5)["tile_h"] == 100

@@ -118,23 +118,30 @@ def test_batch_of_document_images_like_the_benchmark():
     b.close()
 
 
-def test_batch_with_many_wave_units():
+def test_batch_with_many_wave_units(tmp_path):
     """A batch whose direct-window images give far more wave units than the chip
-    holds waves at once (16 images of about 1000x1000 with 3x3 and 9x9 windows:
-    over 9000 units), mixed with 31x31 images on the streaming kernel: every unit
-    is done."""
-    items = []
-    for i in range(24):
-        img = synth.uniform(1000, 1000 - 3 * i, np.uint8, seed=4000 + i)
-        src, _ = to_dev(img, pitch_elems=1024)
-        dst, _ = to_dev(np.zeros_like(img), pitch_elems=1024)
-        w = (3, 9, 31)[i % 3]
-        items.append(dict(img=img, src=src, dst=dst, wx=w, wy=w, ax=-1, ay=-1,
-                          op="erode" if i % 2 else "dilate"))
-    b = morph.Batch(32, 1 << 20)
-    assert b.set(items) > 9000  # wave units alone: more than 8192
-    b.enqueue()
-    torch.cuda.synchronize()
-    for k, it in enumerate(items):
-        assert np.array_equal(to_host(it["dst"]), _want(it)), k
-    b.close()
+    holds waves at once (16 images of about 1000x1000 with 3x3 and 9x9 windows in
+    8-row units: over 9000 units), mixed with 31x31 images on the streaming kernel:
+    every unit is done."""
+    import json
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps({"u8": {"wave_rows": 8}}))
+    morph.load_tuning(str(f))
+    try:
+        items = []
+        for i in range(24):
+            img = synth.uniform(1000, 1000 - 3 * i, np.uint8, seed=4000 + i)
+            src, _ = to_dev(img, pitch_elems=1024)
+            dst, _ = to_dev(np.zeros_like(img), pitch_elems=1024)
+            w = (3, 9, 31)[i % 3]
+            items.append(dict(img=img, src=src, dst=dst, wx=w, wy=w, ax=-1, ay=-1,
+                              op="erode" if i % 2 else "dilate"))
+        b = morph.Batch(32, 1 << 20)
+        assert b.set(items) > 9000  # wave units alone: more than 8192
+        b.enqueue()
+        torch.cuda.synchronize()
+        for k, it in enumerate(items):
+            assert np.array_equal(to_host(it["dst"]), _want(it)), k
+        b.close()
+    finally:
+        morph.load_tuning(None)
