@@ -5,8 +5,8 @@ Workload (one "step"): the mixed-size batch -- 512 uint8 document-like images,
 H and W each log-uniform in [64, 2048], a square window per image drawn from
 {3, 5, 9, 15, 31, 63}, erosion or dilation at random (seed 5) -- run as one
 graph-replayed batch: one kernel dispatch per launch group (the wave kernel for the
-images whose two passes are direct, the streaming kernel per ring size for the
-others).  Images are resident in HBM before timing; rows are padded to a 64-byte
+images whose two passes are direct, the streaming kernel in its two vertical forms
+for the others).  Images are resident in HBM before timing; rows are padded to a 64-byte
 pitch.  The roofline figure is that of the slowest dispatch of the step, timed
 alone on its images.  Reported beside it: the same 512 images as 512 separate
 launches (eager and captured in one graph), the 4096x4096 uint8 and uint16
@@ -178,15 +178,14 @@ def _effective(w, extent):
 
 def kernel_groups(morph, items):
     """Split the batch into the library's launch groups (one kernel dispatch each):
-    by kernel, and for the streaming kernel by ring size (effective wy <= 16, 32, 64,
-    128)."""
+    by kernel, and for the streaming kernel by vertical form (LDS ring for an
+    effective wy <= 16, run totals above)."""
     groups = {}
     for it in items:
         H, W = it["src"].shape
         k = morph.resolve_plan("u8", H, W, it["wx"], it["wy"])["kernel"]
         if k == "stream":
-            wy = _effective(it["wy"], H)
-            k = "stream_wy%d" % (16 if wy <= 16 else 32 if wy <= 32 else 64 if wy <= 64 else 128)
+            k = "stream_ring" if _effective(it["wy"], H) <= 16 else "stream_runs"
         groups.setdefault(k, []).append(it)
     return groups
 
@@ -196,8 +195,10 @@ KERNEL_LABELS = {"wave": "batch_wave_kernel<u8, aligned rows>",
 
 
 def kernel_label(group):
-    if group.startswith("stream_wy"):
-        return "batch_stream_kernel<u8, aligned rows>, ring wy <= %s" % group[len("stream_wy"):]
+    if group == "stream_ring":
+        return "batch_stream_kernel<u8, aligned rows, LDS ring>"
+    if group == "stream_runs":
+        return "batch_stream_kernel<u8, aligned rows, run totals>"
     return KERNEL_LABELS[group]
 
 
@@ -252,7 +253,7 @@ def main():
     sp = sorted(per)
 
     # The step launches one kernel dispatch per group of images (wave kernel: both
-    # passes direct; streaming kernel, per ring size: larger windows).  Each group
+    # passes direct; streaming kernel, per vertical form: larger windows).  Each group
     # alone, as its own batch (one dispatch), times that dispatch; the roofline is
     # taken on the dominant one.
     _log("timing each kernel dispatch of the step")

@@ -198,7 +198,8 @@ int morph_batch_destroy(morph_batch_t b);
  * per-dtype direct/vHGW thresholds, tile shapes per window bucket (tq = input
  * quads of a tile row, tb = output rows), the output rows of a direct wave unit
  * (a multiple of 8, at most 64; default 24) and of a streaming unit (1 .. 4096;
- * default 48), e.g.
+ * stream_rows for vertical windows up to 16, default 48, stream_rows_runs above,
+ * default 32), e.g.
  *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 64,
  *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
  * A dtype missing from the file keeps its table; a key missing keeps its value.

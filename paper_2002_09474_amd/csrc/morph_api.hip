@@ -40,13 +40,14 @@ struct DtypeTuning {
     int t_x, t_y; // direct when w <= t (per pass)
     std::vector<TileRule> tiles;
     int wave_rows;   // output rows of a wave unit (both passes direct), multiple of kWaveRows
-    int stream_rows; // output rows of a streaming-kernel unit
+    int stream_rows;      // output rows of a streaming-kernel unit (LDS-ring form)
+    int stream_rows_runs; // the same for the run-total form (wy > kStreamRingMaxWy)
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -149,12 +150,13 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
         t.wave_rows = r;
     }
-    it = o.obj.find("stream_rows");
-    if (it != o.obj.end()) {
+    for (const char *key : {"stream_rows", "stream_rows_runs"}) {
+        it = o.obj.find(key);
+        if (it == o.obj.end()) continue;
         if (it->second.k != JVal::NUM) return false;
         const int r = (int)it->second.num;
         if (r < 1 || r > 4096) return false;
-        t.stream_rows = r;
+        (key[sizeof("stream_rows") - 1] ? t.stream_rows_runs : t.stream_rows) = r;
     }
     it = o.obj.find("tiles");
     if (it != o.obj.end()) {
@@ -283,10 +285,11 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
         j.TW = 4 * stream_quads(j.wx);
         j.tiles_x = (W + j.TW - 1) / j.TW;
-        // (48 rows measured within a few per cent of the best unit height for every
-        // window of the benchmark batch and the 4096x4096 images, and best for the
-        // mixed batch, whose short per-group launches want many units)
-        j.TB = std::min(tu.stream_rows, H);
+        // (by measurement: 48 rows for the LDS-ring form, 32 for the run-total form,
+        // near the best for every window of the benchmark batch and the 4096x4096
+        // images, and best for the mixed batch, whose per-group launches want many
+        // units)
+        j.TB = std::min(stream_two_level(j.wy) ? tu.stream_rows_runs : tu.stream_rows, H);
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
         return MORPH_OK;
@@ -539,14 +542,13 @@ const char *morph_version(void) { return "morph-gfx950 0.1"; }
 struct BatchGroup {
     int job0 = 0, njobs = 0; // jobs [job0, job0 + njobs) of the (group-sorted) table
     int64_t tiles = 0;
-    int lds = 0, grid = 0, dtype = 0, kind = 0;
+    int lds = 0, grid = 0, dtype = 0, kind = 0, variant = 0;
     bool aligned = true;
 };
 
 // groups: kernel kind x element type x row alignment, and for the streaming kernel
-// four ring sizes (wy <= 16, 32, 64, 128) so that small windows are not given the
-// LDS of large ones
-static constexpr int kRingClasses = 4;
+// its two vertical forms (LDS ring for wy <= kStreamRingMaxWy, run totals above)
+static constexpr int kRingClasses = 2;
 static constexpr int kBatchGroups = 4 * (kKinds + kRingClasses - 1);
 
 struct morph_batch {
@@ -625,11 +627,11 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
 static int group_of(const TileJob &j)
 {
     int k = j.kind;
-    if (j.kind == KIND_STREAM) k += (j.wy > 16) + (j.wy > 32) + (j.wy > 64);
+    if (j.kind == KIND_STREAM) k += stream_two_level(j.wy) ? 1 : 0;
     return 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
 }
 
-// Launch order of the groups: streaming groups from the largest ring down, then the
+// Launch order of the groups: streaming groups (run totals, then ring), then the
 // tile and wave groups.
 static int group_order(int gi)
 {
@@ -673,7 +675,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
     int m = 0, starts = 0;
     const int cus = device_cus();
     for (int gi = 0; gi < kBatchGroups; gi++) {
-        // the streaming groups from the largest ring down, then the rest
+        // the streaming groups first, then the rest
         const int g = group_order(gi);
         if (jobs[g].empty()) continue;
         BatchGroup G;
@@ -682,6 +684,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         G.kind = jobs[g][0].kind;
         G.dtype = jobs[g][0].dtype;
         G.aligned = job_rows_aligned(jobs[g][0]);
+        G.variant = (G.kind == KIND_STREAM && stream_two_level(jobs[g][0].wy)) ? 1 : 0;
         int64_t t = 0;
         for (const TileJob &j : jobs[g]) {
             b->h_tile_start[starts++] = t;
@@ -719,7 +722,8 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
                    [](const BatchGroup &x, const BatchGroup &y) {
                        return x.job0 == y.job0 && x.njobs == y.njobs && x.tiles == y.tiles &&
                               x.lds == y.lds && x.grid == y.grid && x.dtype == y.dtype &&
-                              x.aligned == y.aligned && x.kind == y.kind;
+                              x.aligned == y.aligned && x.kind == y.kind &&
+                              x.variant == y.variant;
                    });
     if (!same_layout) drop_graph(b);
     b->groups = groups;
@@ -753,7 +757,7 @@ static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
                       G.njobs, G.tiles, b->d_counter + 2 * g};
         start += G.njobs + 1;
         tstart += G.tiles;
-        hipError_t e = launch_batch(t, G.kind, G.dtype, G.aligned, G.grid, G.lds, stream);
+        hipError_t e = launch_batch(t, G.kind, G.variant, G.dtype, G.aligned, G.grid, G.lds, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -22,11 +22,17 @@ enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3
 enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2 };
 constexpr int kKinds = 3;
 constexpr int kStreamMaxWx = 128; // wider windows leave a 64-quad strip too few outputs
-constexpr int kStreamMaxWy = 128; // the ring takes 256 (u8) or 512 (u16) bytes of LDS per row
-constexpr int kStreamChunk = 8;       // rows a streaming wave takes at a time
-// ring entries of the streaming kernel's vertical pass: wy, plus slack so that a
-// chunk may read kStreamChunk entries from any position
-inline int stream_ring_entries(int wy) { return wy + kStreamChunk - 1; }
+constexpr int kStreamMaxWy = 128; // run tables grow with wy / 8
+constexpr int kStreamChunk = 8; // rows a streaming wave takes at a time (one run of a block)
+// runs of kStreamChunk rows in a block of wy rows (the last may be shorter)
+__host__ __device__ inline int stream_runs(int wy) { return (wy + kStreamChunk - 1) / kStreamChunk; }
+// vertical vHGW form of the streaming kernel: a ring of the block's wy suffixes in LDS
+// up to kStreamRingMaxWy, above it run totals in LDS and a second read of the rows
+constexpr int kStreamRingMaxWy = 16;
+__host__ __device__ inline bool stream_two_level(int wy) { return wy > kStreamRingMaxWy; }
+// ring entries: wy, plus slack so that a chunk may read kStreamChunk entries from any
+// position
+__host__ __device__ inline int stream_ring_entries(int wy) { return wy + kStreamChunk - 1; }
 constexpr int kWaveQuads = 60;
 constexpr int kWaveRows = 8;
 
@@ -58,8 +64,10 @@ struct TileJob {
 inline int lds_bytes(const TileJob &j)
 {
     if (j.kind == KIND_WAVE) return 0;
-    if (j.kind == KIND_STREAM) // per single-wave workgroup: 64 lanes x 4 (u8) / 8 (u16) bytes
-        return stream_ring_entries(j.wy) * 64 * (j.dtype ? 8 : 4);
+    if (j.kind == KIND_STREAM) // per single-wave workgroup, 64 lanes x 4 (u8) / 8 (u16)
+                               // bytes per entry: run totals and suffixes, or the ring
+        return (stream_two_level(j.wy) ? 2 * stream_runs(j.wy) + 1 : stream_ring_entries(j.wy)) *
+               64 * (j.dtype ? 8 : 4);
     const int b = (j.TB / 2) * j.SB;
     return (j.TB * j.SA + (b > j.vtt ? b : j.vtt)) * 4;
 }
@@ -77,8 +85,8 @@ struct BatchTables {
     unsigned long long *counter; // device: [0] next tile, [1] workgroups finished (both 0
                                  // between launches); not used by wave groups
 };
-hipError_t launch_batch(const BatchTables &t, int kind, int dtype, bool aligned, int grid, int lds,
-                        hipStream_t stream);
+hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, bool aligned, int grid,
+                        int lds, hipStream_t stream);
 // output quads of a stream-kernel strip for a horizontal window wx (worst-case
 // origin offset 3): the last one's input, 4Q + 3 + wx + 2, must lie in 64 quads
 inline int stream_quads(int wx) { return (250 - wx) / 4 + 1; }

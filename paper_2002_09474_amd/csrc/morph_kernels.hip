@@ -1325,7 +1325,60 @@ template <> struct Ring<uint16_t> {
     }
 };
 
-template <typename T, bool MAXOP, bool AL>
+// Per-wave LDS of the vertical pass: the run totals of the block being streamed (T,
+// stream_runs(wy) entries) and the suffix minima over the runs of the previous
+// block (S, one more entry, the last the identity), 64 lanes each.  uint8: an entry
+// is a lane's four pixels narrowed to bytes; uint16: the two pair dwords.
+template <typename T> struct RunTable;
+template <> struct RunTable<uint8_t> {
+    uint32_t *e;
+    __device__ __forceinline__ explicit RunTable(uint32_t *lds) : e(lds + (threadIdx.x & 63)) {}
+    __device__ __forceinline__ void put(int i, uint32_t v01, uint32_t v23) const
+    {
+        e[64 * i] = perm(v23, v01, SEL_NARROW);
+    }
+    __device__ __forceinline__ void get(int i, uint32_t &v01, uint32_t &v23) const
+    {
+        const uint32_t d = e[64 * i];
+        v01 = perm(0u, d, SEL_U8_01);
+        v23 = perm(0u, d, SEL_U8_23);
+    }
+};
+template <> struct RunTable<uint16_t> {
+    uint2 *e;
+    __device__ __forceinline__ explicit RunTable(uint32_t *lds)
+        : e((uint2 *)lds + (threadIdx.x & 63)) {}
+    __device__ __forceinline__ void put(int i, uint32_t v01, uint32_t v23) const
+    {
+        e[64 * i] = make_uint2(v01, v23);
+    }
+    __device__ __forceinline__ void get(int i, uint32_t &v01, uint32_t &v23) const
+    {
+        const uint2 d = e[64 * i];
+        v01 = d.x;
+        v23 = d.y;
+    }
+};
+
+// The vertical pass is vHGW over blocks of wy input rows (§5.1.1), in one of two
+// forms (RUNS, chosen by stream_two_level(wy)):
+//  - ring (small wy): block b's suffixes h_b sit in a per-wave LDS ring of wy rows;
+//    while block b + 1 streams in, output row b wy + j is op(h_b[j], prefix of block
+//    b + 1 over its first j rows) and the incoming row takes h_b[j]'s slot; at the
+//    end of a block a backward walk over the ring turns it into that block's h.
+//  - runs (larger wy): each block is split into runs of SD rows: output row
+//    s = b wy + j (j in run r of block b) is
+//     op( suffix of run r of block b from row s,  S_b[r + 1],  prefix of block b + 1
+//         over its first j rows )
+// where S_b[r + 1] is the extremum of block b's runs after r.  Streaming down, the
+// chunk of block b + 1 that emits rows s .. s + SD - 1 also re-reads block b's rows
+// at the same offsets (from cache: they streamed past wy rows earlier) and forms the
+// in-run suffixes in registers; the run totals of each block go to LDS as the block
+// streams past, and at its end a backward walk over them gives S.  Per wave this
+// keeps 2 stream_runs(wy) + 1 small LDS entries instead of a ring of wy rows, at the
+// price of a second (cached) load of every row: a win where the ring's LDS would
+// limit the waves resident per CU.
+template <typename T, bool MAXOP, bool AL, bool RUNS>
 __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t *lds)
 {
     const int lane = threadIdx.x & 63;
@@ -1347,16 +1400,19 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
         if constexpr (AL) return WaveLoader<T>(J, mis, gx);
         else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)), gx);
     }();
-    // uint8 rings hold raw quads widened with the loader's selectors (identity ones
+    const Doubling S(J.wx, co);
+    const bool hdirect = J.hm != PASS_DOUBLING; // direct (wx <= kDirectMax) or none
+    const int nruns = stream_runs(wy);
+    const RunTable<T> tot(lds);                  // runs: T, entries 0 .. nruns - 1
+    const RunTable<T> suf(lds + nruns * 64 * (sizeof(T) == 1 ? 1 : 2)); // S: 0 .. nruns
+    const Ring<T> ring(lds);                     // ring: wy (+ SD - 1) entries
+    // uint8 rings hold raw quads, widened with the loader's selectors (identity ones
     // for rows of any pitch, which the loader returns widened already)
     uint32_t rs01 = SEL_U8_01, rs23 = SEL_U8_23;
     if constexpr (AL) {
         rs01 = L.s01;
         rs23 = L.s23;
     }
-    const Doubling S(J.wx, co);
-    const bool hdirect = J.hm != PASS_DOUBLING; // direct (wx <= kDirectMax) or none
-    const Ring<T> ring(lds);
     // destination: rows 4-byte aligned, the strip wholly inside the image and the
     // image spanning < 4 GiB take buffer stores (row offset scalar)
     const int Q = (J.TW >> 2) * sx + lane;
@@ -1369,44 +1425,57 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
     const uint32_t dvoff = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
     const uint32_t id = MAXOP ? 0u : 0xffffffffu;
 
-    // Rows are taken in chunks of up to SD that stay inside one block: block 0 fills
-    // the ring, every later chunk emits outputs.  As soon as a chunk's rows are
-    // widened, the next chunk's loads are issued into the same registers.
-    // units clear of the image's top and bottom rows load without clamping, at row
-    // offsets stepped by the pitch
+    // units clear of the image's top and bottom rows load without clamping
     const bool rows_in = AL && gy0 >= 0 && gy0 + last + 2 * SD <= J.H;
     const uint32_t pitch = (uint32_t)J.pitch;
-    uint32_t g01 = id, g23 = id;
-    int t = 0, j = 0;
-    bool fill = true;
-    // One chunk: rows t .. t + cnt - 1 from `cur`; the next chunk's rows are loaded into
-    // `nxt`.  The loop below alternates the two buffers, so that no loaded register is
-    // ever copied (a copy would wait for the load).  Returns whether rows remain.
-    auto chunk = [&](typename Ld::Raw(&cur)[SD], typename Ld::Raw(&nxt)[SD]) -> bool {
-        const int cnt = min(min(SD, wy - j), last - t + 1);
-        const bool full = cnt == SD;
-        uint32_t x01[SD], x23[SD];
-#pragma unroll
-        for (int k = 0; k < SD; k++) L.widen(cur[k], x01[k], x23[k]);
+    auto issue8 = [&](typename Ld::Raw(&buf)[SD], int r0) {
         if constexpr (AL) {
-            // row offsets first (scalar; clamped only near the image's top and bottom),
-            // then the loads in one straight run
-            const int r0 = gy0 + t + cnt;
+            // row offsets first (scalar), then the loads in one straight run
             uint32_t so[SD];
             if (rows_in) {
 #pragma unroll
                 for (int k = 0; k < SD; k++) so[k] = (uint32_t)(r0 + k) * pitch;
             } else {
 #pragma unroll
-                for (int k = 0; k < SD; k++) so[k] = (uint32_t)min(max(r0 + k, 0), J.H - 1) * pitch;
+                for (int k = 0; k < SD; k++)
+                    so[k] = (uint32_t)min(max(r0 + k, 0), J.H - 1) * pitch;
             }
 #pragma unroll
-            for (int k = 0; k < SD; k++) nxt[k] = L.issue_at(__builtin_amdgcn_readfirstlane(so[k]));
+            for (int k = 0; k < SD; k++) buf[k] = L.issue_at(__builtin_amdgcn_readfirstlane(so[k]));
         } else {
 #pragma unroll
-            for (int k = 0; k < SD; k++) nxt[k] = L.issue(gy0 + t + cnt + k);
+            for (int k = 0; k < SD; k++) buf[k] = L.issue(r0 + k);
         }
-        if (fill) {
+    };
+
+    uint32_t g01 = id, g23 = id;
+    int t = 0, j = 0;
+    bool fill = true;
+    // One chunk: rows t .. t + cnt - 1 of the current block from `cur` and, once
+    // outputs are due, the previous block's rows at the same offsets from `hcur`; the
+    // next chunk's rows are loaded into `nxt` / `hnxt`.  The loop alternates the
+    // buffers so that no loaded register is copied (a copy would wait for its load).
+    auto chunk = [&](typename Ld::Raw(&cur)[SD], typename Ld::Raw(&nxt)[SD],
+                     typename Ld::Raw(&hcur)[SD], typename Ld::Raw(&hnxt)[SD]) -> bool {
+        const int runlen = min(SD, wy - j);       // rows of this run of the block
+        const int cnt = min(runlen, last - t + 1); // of which this unit still needs
+        const bool full = cnt == SD;
+        uint32_t x01[SD], x23[SD];
+#pragma unroll
+        for (int k = 0; k < SD; k++) L.widen(cur[k], x01[k], x23[k]);
+        issue8(nxt, gy0 + t + cnt);
+        if constexpr (RUNS) {
+            if (t + cnt >= wy) issue8(hnxt, gy0 + t + cnt - wy);
+            // this run's total, for the block's S
+            uint32_t r01 = x01[0], r23 = x23[0];
+#pragma unroll
+            for (int k = 1; k < SD; k++)
+                if (full || k < cnt) {
+                    r01 = pk<MAXOP>(r01, x01[k]);
+                    r23 = pk<MAXOP>(r23, x23[k]);
+                }
+            tot.put(j / SD, r01, r23);
+        } else if (fill) {
             if (full) {
 #pragma unroll
                 for (int k = 0; k < SD; k++) ring.put(j + k, cur[k], x01[k], x23[k]);
@@ -1415,10 +1484,30 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
                 for (int k = 0; k < SD; k++)
                     if (k < cnt) ring.put(j + k, cur[k], x01[k], x23[k]);
             }
-        } else {
+        }
+        if (!fill) {
             uint32_t o01[SD], o23[SD];
+            if constexpr (RUNS) {
+                // previous block's rows at these offsets: suffixes over the whole run
+                // (even where this unit stops early), then the later runs' extremum
+                // S_b[r + 1]
+                uint32_t s01, s23;
+                suf.get(j / SD + 1, s01, s23);
 #pragma unroll
-            for (int k = 0; k < SD; k++) ring.get(j + k, o01[k], o23[k]);
+                for (int k = 0; k < SD; k++) L.widen(hcur[k], o01[k], o23[k]);
+#pragma unroll
+                for (int k = SD - 1; k >= 0; k--) {
+                    if (k < runlen) {
+                        s01 = pk<MAXOP>(s01, o01[k]);
+                        s23 = pk<MAXOP>(s23, o23[k]);
+                    }
+                    o01[k] = s01;
+                    o23[k] = s23;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < SD; k++) ring.get(j + k, o01[k], o23[k]);
+            }
 #pragma unroll
             for (int k = 0; k < SD; k++) {
                 // h_b[j + k] against the prefix of this block's first j + k rows
@@ -1427,13 +1516,15 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
                 g01 = pk<MAXOP>(g01, x01[k]);
                 g23 = pk<MAXOP>(g23, x23[k]);
             }
-            if (full) {
+            if constexpr (!RUNS) {
+                if (full) {
 #pragma unroll
-                for (int k = 0; k < SD; k++) ring.put(j + k, cur[k], x01[k], x23[k]);
-            } else {
+                    for (int k = 0; k < SD; k++) ring.put(j + k, cur[k], x01[k], x23[k]);
+                } else {
 #pragma unroll
-                for (int k = 0; k < SD; k++)
-                    if (k < cnt) ring.put(j + k, cur[k], x01[k], x23[k]);
+                    for (int k = 0; k < SD; k++)
+                        if (k < cnt) ring.put(j + k, cur[k], x01[k], x23[k]);
+                }
             }
             // output rows t - wy .. t - wy + cnt - 1: horizontal pass, then store
             if constexpr (AL && sizeof(T) == 2)
@@ -1472,18 +1563,29 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
         }
         t += cnt;
         j += cnt;
-        if (j == wy) { // block complete: its suffixes replace it in the ring
-            ring.template suffixes<MAXOP>(wy, rs01, rs23);
+        if (j == wy) { // block complete
+            if constexpr (RUNS) { // S over its runs, from the last one back
+                uint32_t a01 = id, a23 = id;
+                suf.put(nruns, id, id);
+                for (int r = nruns - 1; r >= 0; r--) {
+                    uint32_t v01, v23;
+                    tot.get(r, v01, v23);
+                    a01 = pk<MAXOP>(a01, v01);
+                    a23 = pk<MAXOP>(a23, v23);
+                    suf.put(r, a01, a23);
+                }
+            } else { // its suffixes replace it in the ring
+                ring.template suffixes<MAXOP>(wy, rs01, rs23);
+            }
             j = 0;
             fill = false;
             g01 = g23 = id;
         }
         return t <= last;
     };
-    typename Ld::Raw bufa[SD], bufb[SD];
-#pragma unroll
-    for (int k = 0; k < SD; k++) bufa[k] = L.issue(gy0 + k);
-    while (chunk(bufa, bufb) && chunk(bufb, bufa)) {
+    typename Ld::Raw bufa[SD], bufb[SD], hbufa[SD], hbufb[SD];
+    issue8(bufa, gy0);
+    while (chunk(bufa, bufb, hbufa, hbufb) && chunk(bufb, bufa, hbufb, hbufa)) {
     }
 }
 
@@ -1548,22 +1650,28 @@ static TileKernelFn pick_wave_kernel(const TileJob &j)
     return al ? wave_kernel<uint16_t, false, true> : wave_kernel<uint16_t, false, false>;
 }
 
-template <typename T, bool MAXOP, bool AL>
+template <typename T, bool MAXOP, bool AL, bool RUNS>
 __global__ __launch_bounds__(64) void stream_kernel(TileJob J)
 {
     extern __shared__ uint32_t lds[];
-    stream_body<T, MAXOP, AL>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+    stream_body<T, MAXOP, AL, RUNS>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+template <bool RUNS>
+static TileKernelFn pick_stream_kernel_v(const TileJob &j)
+{
+    const bool al = rows_aligned(j);
+    if (j.dtype == 0) {
+        if (j.op) return al ? stream_kernel<uint8_t, true, true, RUNS> : stream_kernel<uint8_t, true, false, RUNS>;
+        return al ? stream_kernel<uint8_t, false, true, RUNS> : stream_kernel<uint8_t, false, false, RUNS>;
+    }
+    if (j.op) return al ? stream_kernel<uint16_t, true, true, RUNS> : stream_kernel<uint16_t, true, false, RUNS>;
+    return al ? stream_kernel<uint16_t, false, true, RUNS> : stream_kernel<uint16_t, false, false, RUNS>;
 }
 
 static TileKernelFn pick_stream_kernel(const TileJob &j)
 {
-    const bool al = rows_aligned(j);
-    if (j.dtype == 0) {
-        if (j.op) return al ? stream_kernel<uint8_t, true, true> : stream_kernel<uint8_t, true, false>;
-        return al ? stream_kernel<uint8_t, false, true> : stream_kernel<uint8_t, false, false>;
-    }
-    if (j.op) return al ? stream_kernel<uint16_t, true, true> : stream_kernel<uint16_t, true, false>;
-    return al ? stream_kernel<uint16_t, false, true> : stream_kernel<uint16_t, false, false>;
+    return stream_two_level(j.wy) ? pick_stream_kernel_v<true>(j) : pick_stream_kernel_v<false>(j);
 }
 
 static hipError_t set_lds_limit(const void *fn, int lds)
@@ -1653,7 +1761,7 @@ __global__ __launch_bounds__(NT) void batch_wave_kernel(BatchTables bt)
 }
 
 // The batch form of the stream kernel: one single-wave workgroup per unit.
-template <typename T, bool AL>
+template <typename T, bool AL, bool RUNS>
 __global__ __launch_bounds__(64) void batch_stream_kernel(BatchTables bt)
 {
     extern __shared__ uint32_t lds[];
@@ -1662,14 +1770,14 @@ __global__ __launch_bounds__(64) void batch_stream_kernel(BatchTables bt)
     const int jb = bt.tile_job[t];
     const TileJob J = bt.jobs[jb];
     const int u = (int)(t - bt.tile_start[jb]);
-    if (J.op) stream_body<T, true, AL>(J, u, lds);
-    else stream_body<T, false, AL>(J, u, lds);
+    if (J.op) stream_body<T, true, AL, RUNS>(J, u, lds);
+    else stream_body<T, false, AL, RUNS>(J, u, lds);
 }
 
 // Batches are launched per group of jobs with the same kernel kind, element type and
 // row alignment.
-hipError_t launch_batch(const BatchTables &t, int kind, int dtype, bool aligned, int grid, int lds,
-                        hipStream_t stream)
+hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, bool aligned, int grid,
+                        int lds, hipStream_t stream)
 {
     typedef void (*BatchFn)(BatchTables);
     BatchFn fn;
@@ -1678,8 +1786,12 @@ hipError_t launch_batch(const BatchTables &t, int kind, int dtype, bool aligned,
         fn = dtype == 0 ? (aligned ? batch_wave_kernel<uint8_t, true> : batch_wave_kernel<uint8_t, false>)
                         : (aligned ? batch_wave_kernel<uint16_t, true> : batch_wave_kernel<uint16_t, false>);
     else if (kind == KIND_STREAM) {
-        fn = dtype == 0 ? (aligned ? batch_stream_kernel<uint8_t, true> : batch_stream_kernel<uint8_t, false>)
-                        : (aligned ? batch_stream_kernel<uint16_t, true> : batch_stream_kernel<uint16_t, false>);
+        if (variant)
+            fn = dtype == 0 ? (aligned ? batch_stream_kernel<uint8_t, true, true> : batch_stream_kernel<uint8_t, false, true>)
+                            : (aligned ? batch_stream_kernel<uint16_t, true, true> : batch_stream_kernel<uint16_t, false, true>);
+        else
+            fn = dtype == 0 ? (aligned ? batch_stream_kernel<uint8_t, true, false> : batch_stream_kernel<uint8_t, false, false>)
+                            : (aligned ? batch_stream_kernel<uint16_t, true, false> : batch_stream_kernel<uint16_t, false, false>);
         block = 64;
     }
     else

@@ -107,8 +107,9 @@ def test_plan_resolution_and_thresholds(tmp_path):
         # up to 128 x 128, the tile kernel beyond
         p = morph.resolve_plan("u8", 1080, 1920, 31, 31)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
-        # streaming units of 48 rows
-        assert (p["tile_w"], p["tile_h"]) == (4 * 55, 48)
+        # streaming units of 32 rows for wy > 16 (run-total form), 48 below (LDS ring)
+        assert (p["tile_w"], p["tile_h"]) == (4 * 55, 32)
+        assert morph.resolve_plan("u8", 1080, 1920, 31, 15)["tile_h"] == 48
         p = morph.resolve_plan("u8", 1080, 1920, 7, 63)
         assert (p["method_x"], p["method_y"]) == ("direct", "vhgw")
         assert morph.resolve_plan("u8", 100, 90, 3, 3, method_x="doubling")["tile_h"] == 48
@@ -142,9 +143,10 @@ def test_plan_resolution_and_thresholds(tmp_path):
         p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
         assert (p["method_x"], p["method_y"]) == ("doubling", "vhgw")
         assert (p["tile_w"], p["tile_h"]) == (4 * 62, 48)
-        f.write_text(json.dumps({"u8": {"stream_rows": 100}}))
+        f.write_text(json.dumps({"u8": {"stream_rows": 100, "stream_rows_runs": 40}}))
         morph.load_tuning(str(f))
         assert morph.resolve_plan("u8", 1000, 1000, 5, 5)["tile_h"] == 100
+        assert morph.resolve_plan("u8", 1000, 1000, 5, 17)["tile_h"] == 40
         bad = tmp_path / "bad.json"
         bad.write_text('{"u8": {"t_x": 3, "tiles": [{"wmax": 8, "tq": 1, "tb": 32}]}}')
         with pytest.raises(morph.MorphError):

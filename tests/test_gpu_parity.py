@@ -158,11 +158,13 @@ def test_streaming_kernel_every_window(dtype):
 def test_streaming_units_of_any_height(rows, tmp_path):
     """Streaming units of `rows` output rows, shorter and longer than the vertical
     window (the vHGW blocks then span several units or one unit holds several
-    blocks), for both element types, aligned and unaligned rows, and images a
-    fraction of a strip wide."""
+    blocks), in both vertical forms (LDS ring for wy <= 16, run totals above), for
+    both element types, aligned and unaligned rows, and images a fraction of a strip
+    wide."""
     import json
     f = tmp_path / "t.json"
-    f.write_text(json.dumps({"u8": {"stream_rows": rows}, "u16": {"stream_rows": rows}}))
+    t = {"stream_rows": rows, "stream_rows_runs": rows}
+    f.write_text(json.dumps({"u8": t, "u16": t}))
     morph.load_tuning(str(f))
     try:
         rng = np.random.default_rng(rows)
