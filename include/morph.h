@@ -82,7 +82,7 @@ extern "C" {
  * (tile_w a multiple of 4, tile_h a multiple of 2).  A plan never changes the
  * result, only how it is computed.
  * Kernels: both passes direct run one wave per strip in registers; with both
- * methods AUTO and no tile, larger windows (wx <= 128, wy <= 128) run one wave per
+ * methods AUTO and no tile, larger windows (wx <= 128, wy <= 256) run one wave per
  * strip that streams down the rows (vertical vHGW through LDS, horizontal direct
  * or doubling); anything else -- a forced vHGW pass, a tile, larger windows --
  * runs the workgroup-tile kernel, which implements exactly the paper's two

@@ -22,7 +22,7 @@ enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3
 enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2 };
 constexpr int kKinds = 3;
 constexpr int kStreamMaxWx = 128; // wider windows leave a 64-quad strip too few outputs
-constexpr int kStreamMaxWy = 128; // run tables grow with wy / 8
+constexpr int kStreamMaxWy = 256; // run tables grow with wy / 8
 constexpr int kStreamChunk = 8; // rows a streaming wave takes at a time (one run of a block)
 // runs of kStreamChunk rows in a block of wy rows (the last may be shorter)
 __host__ __device__ inline int stream_runs(int wy) { return (wy + kStreamChunk - 1) / kStreamChunk; }

@@ -104,7 +104,7 @@ def test_plan_resolution_and_thresholds(tmp_path):
         # a window of 1 skips the pass
         assert morph.resolve_plan("u8", 100, 100, 1, 31)["method_x"] is None
         # larger windows: the streaming kernel (vertical vHGW, horizontal doubling)
-        # up to 128 x 128, the tile kernel beyond
+        # up to 128 x 256, the tile kernel beyond
         p = morph.resolve_plan("u8", 1080, 1920, 31, 31)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
         # streaming units of 32 rows for wy > 16 (run-total form), 48 below (LDS ring)
@@ -118,6 +118,8 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
         p = morph.resolve_plan("u8", 1080, 1920, 129, 129)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("vhgw", "vhgw", "tile")
+        assert morph.resolve_plan("u8", 4096, 4096, 1, 255)["kernel"] == "stream"
+        assert morph.resolve_plan("u8", 4096, 4096, 1, 257)["kernel"] == "tile"
         for bad_kw in (dict(method_y="doubling"), dict(method_x="doubling", tile=(64, 32)),
                        dict(method_x="doubling", method_y="direct")):
             with pytest.raises(morph.MorphError):

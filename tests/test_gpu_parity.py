@@ -138,14 +138,14 @@ def test_wave_units_of_several_row_chunks(rows, tmp_path):
 def test_streaming_kernel_every_window(dtype):
     """The streaming kernel (vertical vHGW through the per-wave ring, horizontal
     direct or doubling across lanes) for every horizontal window 1..128 (doubling
-    forced, so small windows take it too) and vertical windows up to 128, random
+    forced, so small windows take it too) and vertical windows up to 256, random
     anchors, on an image of two strips and two row bands with ragged edges."""
     rng = np.random.default_rng(31)
     img = synth.document(181, 333, seed=41, n_rect=50).astype(dtype)
     if dtype == np.uint16:
         img = img * 257 - rng.integers(0, 200, img.shape).astype(np.uint16)
     for wx in range(1, 129):
-        wy = int(rng.integers(1, 129))
+        wy = int(rng.integers(1, 257))
         ax = int(rng.integers(-1, wx))
         ay = int(rng.integers(-1, wy))
         op = ("erode", "dilate")[wx % 2]
