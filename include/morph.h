@@ -81,13 +81,14 @@ extern "C" {
  * 1 always skips its pass); tile_w / tile_h set the output tile of one workgroup
  * (tile_w a multiple of 4, tile_h a multiple of 2).  A plan never changes the
  * result, only how it is computed.
- * Kernels: both passes direct run one wave per strip in registers; with both
- * methods AUTO and no tile, larger windows (wx <= 128, wy <= 256) run one wave per
- * strip that streams down the rows (vertical vHGW through LDS, horizontal direct
- * or doubling); anything else -- a forced vHGW pass, a tile, larger windows --
- * runs the workgroup-tile kernel, which implements exactly the paper's two
- * methods.  method_x = DOUBLING selects the streaming kernel (method_y must be
- * AUTO or VHGW); DOUBLING for method_y, or with a tile, is MORPH_EINVAL.
+ * Kernels: a direct vertical pass (wy <= 9) runs one wave per strip in registers,
+ * its horizontal pass direct or (wider windows, up to 128) doubling; with both
+ * methods AUTO and no tile, larger vertical windows (wx <= 128, wy <= 256) run one
+ * wave per strip that streams down the rows (vertical vHGW through LDS,
+ * horizontal direct or doubling); anything else -- a forced vHGW pass, a tile,
+ * larger windows -- runs the workgroup-tile kernel, which implements exactly the
+ * paper's two methods.  method_x = DOUBLING takes the wave or streaming kernel
+ * by the vertical pass; DOUBLING for method_y, or with a tile, is MORPH_EINVAL.
  * morph_resolve_plan reports the kernel's passes and its unit (tile_w x tile_h
  * output pixels). */
 typedef struct morph_plan {

@@ -33,7 +33,8 @@ BUCKETS = ((9, 9), (16, 15), (32, 31), (64, 63), (1 << 30, 101))  # (wmax, repre
 TQ = (16, 32, 48, 64, 96)
 TB = (16, 32, 64, 128)
 WAVE_ROWS = (8, 16, 24, 32, 48)
-STREAM_ROWS = (0, 32, 64, 96, 128)  # 0: the library's automatic choice
+STREAM_ROWS = (32, 48, 64, 96)      # streaming units, LDS-ring form (wy <= 16)
+STREAM_ROWS_RUNS = (24, 32, 48, 64)  # streaming units, run-total form (wy > 16)
 
 
 def _timer(torch, fn, iters, warmup=5):
@@ -156,18 +157,19 @@ def tile_sweep(torch, morph, srcs, dsts, dname, iters=20):
 
 def _batch_items(torch, morph, dev, dname):
     """The benchmark's 512-image batch (uint8, or the same images scaled to uint16),
-    split by kernel: direct-window images and the others."""
+    split by kernel: direct-window images, streaming images with wy <= 16 (LDS-ring
+    form) and the others (run-total form)."""
     from . import synth
     specs = synth.batch_specs(512, seed=5)
     imgs = synth.batch_images(specs, seed=5)
-    direct, large = [], []
+    direct, ring, runs = [], [], []
     for s, im in zip(specs, imgs):
         t = torch.from_numpy(im).to(dev)
         if dname == "u16":
             t = (t.to(torch.int32) * 257).to(torch.int16).view(torch.uint16)
         it = dict(src=t, dst=torch.empty_like(t), wx=s["w"], wy=s["w"], op=s["op"])
-        (direct if s["w"] <= DIRECT_MAX else large).append(it)
-    return direct, large
+        (direct if s["w"] <= DIRECT_MAX else ring if s["w"] <= 16 else runs).append(it)
+    return direct, ring, runs
 
 
 def tune(out_path=DEFAULT_OUT, quick=False):
@@ -186,14 +188,16 @@ def tune(out_path=DEFAULT_OUT, quick=False):
         tx, ty = threshold(rows, "x"), threshold(rows, "y")
         del srcs, dsts
         base = {"t_x": tx, "t_y": ty}
-        direct, large = _batch_items(torch, morph, dev, dname)
-        wr, wr_table = best_rows(torch, morph, dname, direct, "wave_rows", WAVE_ROWS, base,
-                                 iters=5 if quick else 10)
+        direct, ring, runs = _batch_items(torch, morph, dev, dname)
+        it = 5 if quick else 10
+        wr, wr_table = best_rows(torch, morph, dname, direct, "wave_rows", WAVE_ROWS, base, it)
         base["wave_rows"] = wr
-        sr, sr_table = best_rows(torch, morph, dname, large, "stream_rows", STREAM_ROWS, base,
-                                 iters=5 if quick else 10)
+        sr, sr_table = best_rows(torch, morph, dname, ring, "stream_rows", STREAM_ROWS, base, it)
         base["stream_rows"] = sr
-        del direct, large
+        sq, sq_table = best_rows(torch, morph, dname, runs, "stream_rows_runs", STREAM_ROWS_RUNS,
+                                 base, it)
+        base["stream_rows_runs"] = sq
+        del direct, ring, runs
         _with_table(morph, {dname: base})
         g = torch.Generator(device=dev).manual_seed(3)
         big = torch.randint(0, 256 if dname == "u8" else 65536, (4096, 4096), generator=g,
@@ -206,6 +210,7 @@ def tune(out_path=DEFAULT_OUT, quick=False):
         result[dname + "_pass_sweep"] = rows
         result[dname + "_wave_rows_sweep"] = wr_table
         result[dname + "_stream_rows_sweep"] = sr_table
+        result[dname + "_stream_rows_runs_sweep"] = sq_table
         result[dname + "_tile_sweep"] = table
         print("[autotune] %s: %s" % (dname, result[dname]), file=sys.stderr, flush=True)
     with open(out_path, "w") as f:

@@ -241,8 +241,7 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     const int my = plan ? plan->method_y : MORPH_METHOD_AUTO;
     const bool user_tile = plan && (plan->tile_w > 0 || plan->tile_h > 0);
     if (mx < 0 || mx > 3 || my < 0 || my > 2) return MORPH_EINVAL;
-    if (mx == MORPH_METHOD_DOUBLING && (user_tile || my == MORPH_METHOD_DIRECT))
-        return MORPH_EINVAL;
+    if (mx == MORPH_METHOD_DOUBLING && user_tile) return MORPH_EINVAL;
     const bool auto_both = mx == MORPH_METHOD_AUTO && my == MORPH_METHOD_AUTO;
     const bool stream_fits = j.wx <= kStreamMaxWx && j.wy <= kStreamMaxWy;
     if (mx == MORPH_METHOD_DOUBLING && !stream_fits) return MORPH_EUNSUPPORTED;
@@ -264,11 +263,16 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     j.SA = j.SB = 0;
     j.vrun = j.vtt = 0;
 
-    // both passes direct and no tile asked for: the register-only wave kernel
+    // vertical pass direct and no tile asked for: the register-only wave kernel, with
+    // the horizontal pass direct or (wider windows, automatic or asked for) doubling
     j.kind = KIND_TILE;
-    if (j.vm == PASS_DIRECT && (j.hm == PASS_DIRECT || j.hm == PASS_NONE) && !user_tile) {
+    const bool h_wave = j.hm == PASS_DIRECT || j.hm == PASS_NONE || j.hm == PASS_DOUBLING ||
+                        (j.hm == PASS_VHGW && mx == MORPH_METHOD_AUTO && j.wx <= kStreamMaxWx);
+    if (j.vm == PASS_DIRECT && h_wave && !user_tile && (my != MORPH_METHOD_VHGW)) {
         j.kind = KIND_WAVE;
-        j.TW = 4 * kWaveQuads;
+        if (j.hm == PASS_VHGW) j.hm = PASS_DOUBLING;
+        j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
+        j.TW = j.hm == PASS_DOUBLING ? 4 * stream_quads(j.wx) : 4 * kWaveQuads;
         j.TB = std::min(tu.wave_rows, (H + kWaveRows - 1) / kWaveRows * kWaveRows);
         j.tiles_x = (W + j.TW - 1) / j.TW;
         j.tiles_y = (H + j.TB - 1) / j.TB;

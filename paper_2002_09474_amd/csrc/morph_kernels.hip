@@ -780,18 +780,140 @@ __device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *
     store_pairs(c, J);
 }
 
-// ======================= both passes direct: one wave per strip ==================
-// When both windows are at most kDirectMax, a wave works alone on a strip of 64
-// column quads and J.TB output rows, KR rows at a time: the vertical pass in
+// ======================= lane moves and the doubling pass ==========================
+// Used by the wave and streaming kernels for windows wider than the direct pass
+// takes: min/max over a row held across the wave's lanes (a lane holds four
+// consecutive pixels as two pair dwords) by log-step doubling,
+// m_2L[k] = min(m_L[k], m_L[k + L]), then m_w[k] = min(m_L[k], m_L[k + w - L]) for the
+// largest L <= w; shifts by one or two pixels are in-lane (alignbit) plus one DPP
+// move, by one lane DPP, by more lanes ds_bpermute.
+// Lane i gets x of lane i + 1 (DPP wave_shl:1; lane 63 gets 0 through bound_ctrl,
+// which also spares the move that would give the destination an old value).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+}
+
+__device__ __forceinline__ uint32_t lane_fetch(uint32_t v, uint32_t byte_addr)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_addr, (int)v);
+}
+
+// Per-unit constants of the doubling pass.
+struct Doubling {
+    int wx;
+    int c0, c1;        // pixel offsets co and co + wx - L within their first quad (0..3)
+    uint32_t ad0, ad1; // ds_bpermute addresses of lanes + q1 and + q1 + 1, q1 = (co + wx - L) / 4
+
+    __device__ __forceinline__ Doubling(int wx_, int co)
+    {
+        wx = wx_;
+        int L = 1;
+        while (2 * L <= wx) L *= 2;
+        const int d1 = co + wx - L;
+        c0 = co;
+        c1 = d1 & 3;
+        const int lane = threadIdx.x & 63;
+        ad0 = (uint32_t)(lane + (d1 >> 2)) << 2;
+        ad1 = (uint32_t)(lane + (d1 >> 2) + 1) << 2;
+    }
+};
+
+// The pixel pairs at offsets c and c + 2 from four consecutive pair dwords F
+// (offsets 0, 2, 4, 6).
+template <int C>
+__device__ __forceinline__ void pairs_at(uint32_t f0, uint32_t f1, uint32_t f2, uint32_t f3,
+                                         uint32_t &p, uint32_t &p2)
+{
+    const uint32_t lo = (C >> 1) ? f1 : f0, mid = (C >> 1) ? f2 : f1, hi = (C >> 1) ? f3 : f2;
+    p = (C & 1) ? __builtin_amdgcn_alignbit(mid, lo, 16) : lo;
+    p2 = (C & 1) ? __builtin_amdgcn_alignbit(hi, mid, 16) : mid;
+}
+
+// m_wx[k] = min(m_L[k], m_L[k + wx - L]) at k = co .. co + 3, from the level-L pairs.
+template <int C0, int C1, int G, bool MAXOP>
+__device__ __forceinline__ void doubling_final(const Doubling &S, uint32_t *e0, uint32_t *e1)
+{
+#pragma unroll
+    for (int r = 0; r < G; r++) {
+        const uint32_t a0 = e0[r], a1 = e1[r];
+        const uint32_t n0 = from_next_lane(a0), n1 = (C0 >> 1) ? from_next_lane(a1) : 0u;
+        uint32_t p0, p2, r0, r2;
+        pairs_at<C0>(a0, a1, n0, n1, p0, p2);
+        const uint32_t f0 = (C1 >> 1) ? 0u : lane_fetch(a0, S.ad0), f1 = lane_fetch(a1, S.ad0);
+        const uint32_t f2 = lane_fetch(a0, S.ad1), f3 = (C1 >> 1) ? lane_fetch(a1, S.ad1) : 0u;
+        pairs_at<C1>(f0, f1, f2, f3, r0, r2);
+        e0[r] = pk<MAXOP>(p0, r0);
+        e1[r] = pk<MAXOP>(p2, r2);
+    }
+}
+
+// The horizontal passes below work on G rows at once, level by level, so that the
+// rows' chains of lane moves and min/max interleave.
+template <int G, bool MAXOP>
+__device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, uint32_t *e1)
+{
+    // e0 = (m_L[0], m_L[1]), e1 = (m_L[2], m_L[3]) for the lane's quad
+    const int lane = threadIdx.x & 63;
+    if (S.wx >= 2) { // L = 1 -> 2: shift by one pixel
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = from_next_lane(e0[r]);
+            const uint32_t s1 = __builtin_amdgcn_alignbit(e1[r], e0[r], 16);
+            const uint32_t s3 = __builtin_amdgcn_alignbit(n0, e1[r], 16);
+            e0[r] = pk<MAXOP>(e0[r], s1);
+            e1[r] = pk<MAXOP>(e1[r], s3);
+        }
+    }
+    if (S.wx >= 4) { // 2 -> 4: two pixels
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = from_next_lane(e0[r]);
+            e0[r] = pk<MAXOP>(e0[r], e1[r]);
+            e1[r] = pk<MAXOP>(e1[r], n0);
+        }
+    }
+    if (S.wx >= 8) { // 4 -> 8: one lane
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = from_next_lane(e0[r]), n1 = from_next_lane(e1[r]);
+            e0[r] = pk<MAXOP>(e0[r], n0);
+            e1[r] = pk<MAXOP>(e1[r], n1);
+        }
+    }
+    for (int q = 2; 8 * q <= S.wx; q *= 2) { // 4q -> 8q: q lanes
+        const uint32_t ad = (uint32_t)(lane + q) << 2;
+#pragma unroll
+        for (int r = 0; r < G; r++) {
+            const uint32_t n0 = lane_fetch(e0[r], ad), n1 = lane_fetch(e1[r], ad);
+            e0[r] = pk<MAXOP>(e0[r], n0);
+            e1[r] = pk<MAXOP>(e1[r], n1);
+        }
+    }
+#define MORPH_FIN1(A, B)                                                                     \
+    case A * 4 + B: doubling_final<A, B, G, MAXOP>(S, e0, e1); break;
+#define MORPH_FIN(A) MORPH_FIN1(A, 0) MORPH_FIN1(A, 1) MORPH_FIN1(A, 2) MORPH_FIN1(A, 3)
+    switch (S.c0 * 4 + S.c1) {
+        MORPH_FIN(0) MORPH_FIN(1) MORPH_FIN(2) MORPH_FIN(3)
+    default: break;
+    }
+#undef MORPH_FIN
+#undef MORPH_FIN1
+}
+
+// ======================= direct vertical pass: one wave per strip ==================
+// When the vertical window is at most kDirectMax, a wave works alone on a strip of
+// 64 column quads and J.TB output rows, KR rows at a time: the vertical pass in
 // registers, then the horizontal pass in registers too, taking the columns right
 // of its own quad from the next lanes with wave-wide DPP shifts (v_mov_b32_dpp
-// wave_shl:1).  No LDS, no barrier.  The last lanes of the wave only supply those
-// columns: a wave stores WQ = 60 quads.  Input quad Q starts at image column
-// gxa + 4Q, gxa = 4 WQ sx - ax - co, where co puts the quad grid on multiples of
-// the load size; output quad Q (columns 4Q .. 4Q + 3 of the strip) reads input
-// pixels 4Q + co .. 4Q + co + 3 + wx - 1.  The wy - 1 input rows that two chunks
-// of KR rows share stay in registers: a ring of KR + wy - 1 rows moves down KR
-// rows per chunk.
+// wave_shl:1): the direct pass, or for wider windows the doubling pass.  No LDS,
+// no barrier.  The last lanes of the wave only supply those columns: a wave stores
+// wq = J.TW / 4 quads (60 for the direct pass, stream_quads(wx) for doubling).
+// Input quad Q starts at image column gxa + 4Q, gxa = 4 wq sx - ax - co, where co
+// puts the quad grid on multiples of the load size; output quad Q (columns 4Q ..
+// 4Q + 3 of the strip) reads input pixels 4Q + co .. 4Q + co + 3 + wx - 1.  The
+// wy - 1 input rows that two chunks of KR rows share stay in registers: a ring of
+// KR + wy - 1 rows moves down KR rows per chunk.
 //
 // Pixels outside the image are not replaced by the identity here but by the
 // nearest image pixel (rows and columns clamped into the image).  For a flat
@@ -802,7 +924,6 @@ __device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *
 // reaches outside loads the nearest quad inside and picks its pixels with the
 // byte selectors of the widening v_perm (uint8) or of one v_perm per output row
 // (uint16).
-constexpr int WQ = kWaveQuads;
 constexpr int KR = kWaveRows;
 constexpr int RING = KR + kDirectMax - 1;
 
@@ -951,13 +1072,6 @@ template <typename T> struct WaveLoaderAny {
     }
 };
 
-// Lane i gets x of lane i + 1 (DPP wave_shl:1; lane 63 gets 0 through bound_ctrl,
-// which also spares the move that would give the destination an old value).
-__device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
-}
-
 template <int WX, int CO, bool MAXOP>
 __device__ __forceinline__ void wv_horizontal_row(uint32_t &v01, uint32_t &v23)
 {
@@ -1034,7 +1148,8 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
     const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
     const int mis = AL ? (int)(((uintptr_t)J.src & (4 * sizeof(T) - 1)) / sizeof(T)) : 0;
     const int co = (mis - J.ax) & 3;
-    const int gxa = 4 * WQ * sx - J.ax - co; // lane 0's first input column
+    const int wq = J.TW >> 2; // output quads per strip
+    const int gxa = 4 * wq * sx - J.ax - co; // lane 0's first input column
     const int gx = gxa + 4 * lane;
     const int y0 = sy * J.TB;
     const int y1 = min(y0 + J.TB, J.H);
@@ -1051,9 +1166,11 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 #undef MORPH_FIRST
     // destination: 4-byte aligned rows and a strip wholly inside the image take
     // one plain store per row and lane
-    const int Q = WQ * sx + lane;
+    const int Q = wq * sx + lane;
     const bool fast_store = (((uintptr_t)J.dst | (uintptr_t)J.dpitch) & 3) == 0 &&
-                            4 * (WQ * sx + WQ) <= J.W;
+                            4 * (wq * sx + wq) <= J.W;
+    const bool doubling = J.hm == PASS_DOUBLING;
+    const Doubling S(J.wx, co);
     for (int y = y0; y < y1; y += KR) {
         uint32_t v01[KR], v23[KR];
         const bool more = y + KR < y1;
@@ -1066,8 +1183,10 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
                 for (int m = 0; m < KR; m++) L.fix(v01[m], v23[m]);
             }
         }
-        wv_horizontal_any<MAXOP>(J.wx, co, v01, v23); // every lane takes part in the shifts
-        if (lane < WQ) {
+        // every lane takes part in the shifts
+        if (doubling) doubling_rows<KR, MAXOP>(S, v01, v23);
+        else wv_horizontal_any<MAXOP>(J.wx, co, v01, v23);
+        if (lane < wq) {
             uint8_t *drow = J.dst + (int64_t)y * J.dpitch;
             if (fast_store) {
                 const uint32_t o = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
@@ -1112,113 +1231,6 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 // them.  Pixels outside the image are the nearest image pixels, as in the direct
 // wave kernel.
 constexpr int SD = kStreamChunk; // input rows per chunk (and rows in flight) per wave
-
-__device__ __forceinline__ uint32_t lane_fetch(uint32_t v, uint32_t byte_addr)
-{
-    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_addr, (int)v);
-}
-
-// Per-unit constants of the doubling pass.
-struct Doubling {
-    int wx;
-    int c0, c1;        // pixel offsets co and co + wx - L within their first quad (0..3)
-    uint32_t ad0, ad1; // ds_bpermute addresses of lanes + q1 and + q1 + 1, q1 = (co + wx - L) / 4
-
-    __device__ __forceinline__ Doubling(int wx_, int co)
-    {
-        wx = wx_;
-        int L = 1;
-        while (2 * L <= wx) L *= 2;
-        const int d1 = co + wx - L;
-        c0 = co;
-        c1 = d1 & 3;
-        const int lane = threadIdx.x & 63;
-        ad0 = (uint32_t)(lane + (d1 >> 2)) << 2;
-        ad1 = (uint32_t)(lane + (d1 >> 2) + 1) << 2;
-    }
-};
-
-// The pixel pairs at offsets c and c + 2 from four consecutive pair dwords F
-// (offsets 0, 2, 4, 6).
-template <int C>
-__device__ __forceinline__ void pairs_at(uint32_t f0, uint32_t f1, uint32_t f2, uint32_t f3,
-                                         uint32_t &p, uint32_t &p2)
-{
-    const uint32_t lo = (C >> 1) ? f1 : f0, mid = (C >> 1) ? f2 : f1, hi = (C >> 1) ? f3 : f2;
-    p = (C & 1) ? __builtin_amdgcn_alignbit(mid, lo, 16) : lo;
-    p2 = (C & 1) ? __builtin_amdgcn_alignbit(hi, mid, 16) : mid;
-}
-
-// m_wx[k] = min(m_L[k], m_L[k + wx - L]) at k = co .. co + 3, from the level-L pairs.
-template <int C0, int C1, int G, bool MAXOP>
-__device__ __forceinline__ void doubling_final(const Doubling &S, uint32_t *e0, uint32_t *e1)
-{
-#pragma unroll
-    for (int r = 0; r < G; r++) {
-        const uint32_t a0 = e0[r], a1 = e1[r];
-        const uint32_t n0 = from_next_lane(a0), n1 = (C0 >> 1) ? from_next_lane(a1) : 0u;
-        uint32_t p0, p2, r0, r2;
-        pairs_at<C0>(a0, a1, n0, n1, p0, p2);
-        const uint32_t f0 = (C1 >> 1) ? 0u : lane_fetch(a0, S.ad0), f1 = lane_fetch(a1, S.ad0);
-        const uint32_t f2 = lane_fetch(a0, S.ad1), f3 = (C1 >> 1) ? lane_fetch(a1, S.ad1) : 0u;
-        pairs_at<C1>(f0, f1, f2, f3, r0, r2);
-        e0[r] = pk<MAXOP>(p0, r0);
-        e1[r] = pk<MAXOP>(p2, r2);
-    }
-}
-
-// The horizontal passes below work on G rows at once, level by level, so that the
-// rows' chains of lane moves and min/max interleave.
-template <int G, bool MAXOP>
-__device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, uint32_t *e1)
-{
-    // e0 = (m_L[0], m_L[1]), e1 = (m_L[2], m_L[3]) for the lane's quad
-    const int lane = threadIdx.x & 63;
-    if (S.wx >= 2) { // L = 1 -> 2: shift by one pixel
-#pragma unroll
-        for (int r = 0; r < G; r++) {
-            const uint32_t n0 = from_next_lane(e0[r]);
-            const uint32_t s1 = __builtin_amdgcn_alignbit(e1[r], e0[r], 16);
-            const uint32_t s3 = __builtin_amdgcn_alignbit(n0, e1[r], 16);
-            e0[r] = pk<MAXOP>(e0[r], s1);
-            e1[r] = pk<MAXOP>(e1[r], s3);
-        }
-    }
-    if (S.wx >= 4) { // 2 -> 4: two pixels
-#pragma unroll
-        for (int r = 0; r < G; r++) {
-            const uint32_t n0 = from_next_lane(e0[r]);
-            e0[r] = pk<MAXOP>(e0[r], e1[r]);
-            e1[r] = pk<MAXOP>(e1[r], n0);
-        }
-    }
-    if (S.wx >= 8) { // 4 -> 8: one lane
-#pragma unroll
-        for (int r = 0; r < G; r++) {
-            const uint32_t n0 = from_next_lane(e0[r]), n1 = from_next_lane(e1[r]);
-            e0[r] = pk<MAXOP>(e0[r], n0);
-            e1[r] = pk<MAXOP>(e1[r], n1);
-        }
-    }
-    for (int q = 2; 8 * q <= S.wx; q *= 2) { // 4q -> 8q: q lanes
-        const uint32_t ad = (uint32_t)(lane + q) << 2;
-#pragma unroll
-        for (int r = 0; r < G; r++) {
-            const uint32_t n0 = lane_fetch(e0[r], ad), n1 = lane_fetch(e1[r], ad);
-            e0[r] = pk<MAXOP>(e0[r], n0);
-            e1[r] = pk<MAXOP>(e1[r], n1);
-        }
-    }
-#define MORPH_FIN1(A, B)                                                                     \
-    case A * 4 + B: doubling_final<A, B, G, MAXOP>(S, e0, e1); break;
-#define MORPH_FIN(A) MORPH_FIN1(A, 0) MORPH_FIN1(A, 1) MORPH_FIN1(A, 2) MORPH_FIN1(A, 3)
-    switch (S.c0 * 4 + S.c1) {
-        MORPH_FIN(0) MORPH_FIN(1) MORPH_FIN(2) MORPH_FIN(3)
-    default: break;
-    }
-#undef MORPH_FIN
-#undef MORPH_FIN1
-}
 
 template <int G, bool MAXOP>
 __device__ __forceinline__ void direct_rows_any(int wx, int co, uint32_t *v01, uint32_t *v23)

@@ -112,16 +112,22 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert morph.resolve_plan("u8", 1080, 1920, 31, 15)["tile_h"] == 48
         p = morph.resolve_plan("u8", 1080, 1920, 7, 63)
         assert (p["method_x"], p["method_y"]) == ("direct", "vhgw")
-        assert morph.resolve_plan("u8", 100, 90, 3, 3, method_x="doubling")["tile_h"] == 48
-        assert morph.resolve_plan("u8", 20, 90, 3, 3, method_x="doubling")["tile_h"] == 20
+        # doubling with a direct-size vertical window: the wave kernel, 24-row units
+        # (rounded up to 8 rows for short images), strips of stream_quads(wx) quads
+        p = morph.resolve_plan("u8", 100, 90, 3, 3, method_x="doubling")
+        assert (p["kernel"], p["tile_w"], p["tile_h"]) == ("wave", 4 * 62, 24)
+        assert morph.resolve_plan("u8", 20, 90, 3, 3, method_x="doubling")["tile_h"] == 24
+        assert morph.resolve_plan("u8", 12, 90, 3, 3, method_x="doubling")["tile_h"] == 16
+        # automatic: wide and short windows stay on the wave kernel with doubling
+        p = morph.resolve_plan("u8", 1080, 1920, 63, 1)
+        assert (p["method_x"], p["kernel"], p["tile_w"]) == ("doubling", "wave", 4 * 47)
         p = morph.resolve_plan("u8", 1080, 1920, 101, 101)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
         p = morph.resolve_plan("u8", 1080, 1920, 129, 129)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("vhgw", "vhgw", "tile")
         assert morph.resolve_plan("u8", 4096, 4096, 1, 255)["kernel"] == "stream"
         assert morph.resolve_plan("u8", 4096, 4096, 1, 257)["kernel"] == "tile"
-        for bad_kw in (dict(method_y="doubling"), dict(method_x="doubling", tile=(64, 32)),
-                       dict(method_x="doubling", method_y="direct")):
+        for bad_kw in (dict(method_y="doubling"), dict(method_x="doubling", tile=(64, 32))):
             with pytest.raises(morph.MorphError):
                 morph.resolve_plan("u8", 100, 100, 15, 5, **bad_kw)
         # windows are clipped to the image: 255x1 on a 4-wide image is a 7-wide window

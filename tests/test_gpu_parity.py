@@ -154,6 +154,28 @@ def test_streaming_kernel_every_window(dtype):
             _check(img, op, wy, wx, ay, ax)  # automatic: wave or streaming kernel
 
 
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_wide_short_windows_on_the_wave_kernel(dtype):
+    """Horizontal windows wider than the direct pass with a direct-size vertical
+    window run the wave kernel's doubling pass: strips of stream_quads(wx) quads,
+    ragged edges, any anchor, aligned and unaligned rows, both ops."""
+    rng = np.random.default_rng(77)
+    for i, (H, W) in enumerate([(5, 700), (61, 333), (130, 1000)]):
+        img = synth.uniform(H, W, dtype, seed=1300 + i)
+        for wx, wy in ((10, 1), (63, 1), (31, 3), (128, 9), (17, 2), (100, 5)):
+            ax = int(rng.integers(-1, wx))
+            ay = int(rng.integers(-1, wy))
+            assert morph.resolve_plan("u8" if dtype == np.uint8 else "u16", H, W, wx, wy)[
+                "kernel"] == "wave"
+            for op in ("erode", "dilate"):
+                _check(img, op, wx, wy, ax, ay)
+        d, _ = to_dev(img, pitch_elems=W + 5, offset_elems=3)
+        out = empty_like_dev(d)[0]
+        morph.apply("dilate", d, 45, 7, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out), _ref(img, "dilate", 45, 7))
+
+
 @pytest.mark.parametrize("rows", [1, 5, 16, 40])
 def test_streaming_units_of_any_height(rows, tmp_path):
     """Streaming units of `rows` output rows, shorter and longer than the vertical
