@@ -191,7 +191,8 @@ def kernel_groups(morph, items):
 
 
 KERNEL_LABELS = {"wave": "batch_wave_kernel<u8, aligned rows>",
-                 "tile": "batch_kernel<u8, aligned rows>"}
+                 "tile": "batch_kernel<u8, aligned rows>",
+                 "rows": "batch_rows_kernel<aligned rows>"}
 
 
 def kernel_label(group):

@@ -85,10 +85,13 @@ extern "C" {
  * its horizontal pass direct or (wider windows, up to 128) doubling; with both
  * methods AUTO and no tile, larger vertical windows (wx <= 128, wy <= 256) run one
  * wave per strip that streams down the rows (vertical vHGW through LDS,
- * horizontal direct or doubling); anything else -- a forced vHGW pass, a tile,
- * larger windows -- runs the workgroup-tile kernel, which implements exactly the
- * paper's two methods.  method_x = DOUBLING takes the wave or streaming kernel
- * by the vertical pass; DOUBLING for method_y, or with a tile, is MORPH_EINVAL.
+ * horizontal direct or doubling); uint8 with wy = 1 and 128 < wx <= 1000 runs
+ * one wave per strip of rows with 16 pixels a lane (horizontal doubling);
+ * anything else -- a forced vHGW pass, a tile, larger windows -- runs the
+ * workgroup-tile kernel, which implements exactly the paper's two methods.
+ * method_x = DOUBLING takes the wave, streaming or wide-row kernel by the
+ * windows (MORPH_EUNSUPPORTED where none fits); DOUBLING for method_y, or with a
+ * tile, is MORPH_EINVAL.
  * morph_resolve_plan reports the kernel's passes and its unit (tile_w x tile_h
  * output pixels). */
 typedef struct morph_plan {
@@ -103,6 +106,7 @@ typedef struct morph_plan {
 #define MORPH_KERNEL_TILE 0   /* workgroup tile through LDS, the paper's two methods */
 #define MORPH_KERNEL_WAVE 1   /* both passes direct, one wave per strip, registers only */
 #define MORPH_KERNEL_STREAM 2 /* one wave per strip streaming down the rows */
+#define MORPH_KERNEL_ROWS 3   /* uint8, wy = 1, wide wx: one wave per strip, 16 pixels a lane */
 
 /* Erosion, uint8 (§2 Eq. (1)).  See the conventions above for every argument. */
 int morph_erode(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
@@ -200,7 +204,7 @@ int morph_batch_destroy(morph_batch_t b);
  * quads of a tile row, tb = output rows), the output rows of a direct wave unit
  * (a multiple of 8, at most 64; default 24) and of a streaming unit (1 .. 4096;
  * stream_rows for vertical windows up to 16, default 48, stream_rows_runs above,
- * default 32), e.g.
+ * default 32) and of a wide-row unit (wide_rows, 1 .. 4096, default 4), e.g.
  *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 64,
  *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
  * A dtype missing from the file keeps its table; a key missing keeps its value.

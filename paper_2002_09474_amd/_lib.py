@@ -57,7 +57,7 @@ class Plan(ctypes.Structure):
                 ("kernel", ctypes.c_int32)]
 
 
-KERNEL_NAMES = {0: "tile", 1: "wave", 2: "stream"}
+KERNEL_NAMES = {0: "tile", 1: "wave", 2: "stream", 3: "rows"}
 
 
 class Desc(ctypes.Structure):

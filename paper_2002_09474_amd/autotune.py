@@ -15,7 +15,9 @@ along y (1 x w) on the 1920x1080 document page.  The threshold of a pass is the
 largest window up to which direct is never slower by more than the timing noise.
 Unit heights are then chosen on the 512-image batch of the benchmark (the wave
 kernel's on its direct-window images, the streaming kernel's on the others), and
-tile shapes of the tile kernel per window bucket on 4096x4096 images.  Run
+tile shapes of the tile kernel per window bucket on 4096x4096 images, and the unit
+height of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same
+images.  Run
 ``python -m paper_2002_09474_amd.autotune``.
 """
 from __future__ import annotations
@@ -35,6 +37,8 @@ TB = (16, 32, 64, 128)
 WAVE_ROWS = (8, 16, 24, 32, 48)
 STREAM_ROWS = (32, 48, 64, 96)      # streaming units, LDS-ring form (wy <= 16)
 STREAM_ROWS_RUNS = (24, 32, 48, 64)  # streaming units, run-total form (wy > 16)
+WIDE_ROWS = (2, 4, 8, 16)            # wide-row units (uint8, wy = 1, wx > 128)
+WIDE_WINDOWS = (200, 255, 511)
 
 
 def _timer(torch, fn, iters, warmup=5):
@@ -155,6 +159,25 @@ def tile_sweep(torch, morph, srcs, dsts, dname, iters=20):
     return rules, table
 
 
+def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20):
+    """Rows of a wide-row unit: the sum over WIDE_WINDOWS (w x 1) on uint8 4096x4096
+    images, per choice; the fastest."""
+    res = []
+    for c in WIDE_ROWS:
+        _with_table(morph, {"u8": dict(base, wide_rows=c)})
+        us = 0.0
+        for w in WIDE_WINDOWS:
+            k = [0]
+
+            def fn():
+                i = k[0] % len(srcs)
+                k[0] += 1
+                morph.apply("erode", srcs[i], w, 1, out=dsts[i])
+            us += _timer(torch, fn, iters)
+        res.append({"wide_rows": c, "us": round(us, 2)})
+    return min(res, key=lambda r: r["us"])["wide_rows"], res
+
+
 def _batch_items(torch, morph, dev, dname):
     """The benchmark's 512-image batch (uint8, or the same images scaled to uint16),
     split by kernel: direct-window images, streaming images with wy <= 16 (LDS-ring
@@ -204,6 +227,11 @@ def tune(out_path=DEFAULT_OUT, quick=False):
                             dtype=torch.int32, device=dev)
         big = big.to(torch.uint8) if dname == "u8" else big.to(torch.int16).view(torch.uint16)
         srcs, dsts = _bufs(torch, big, 6)
+        if dname == "u8":
+            wr2, wr2_table = wide_rows_sweep(torch, morph, srcs, dsts, base, 8 if quick else 20)
+            base["wide_rows"] = wr2
+            result["u8_wide_rows_sweep"] = wr2_table
+            _with_table(morph, {dname: base})
         rules, table = tile_sweep(torch, morph, srcs, dsts, dname, iters=8 if quick else 20)
         del srcs, dsts, big
         result[dname] = dict(base, tiles=rules)

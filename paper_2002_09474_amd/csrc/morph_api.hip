@@ -42,12 +42,13 @@ struct DtypeTuning {
     int wave_rows;   // output rows of a wave unit (both passes direct), multiple of kWaveRows
     int stream_rows;      // output rows of a streaming-kernel unit (LDS-ring form)
     int stream_rows_runs; // the same for the run-total form (wy > kStreamRingMaxWy)
+    int wide_rows;        // output rows of a wide-row unit (uint8, wy 1, wx > kStreamMaxWx)
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -150,6 +151,13 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
         t.wave_rows = r;
     }
+    it = o.obj.find("wide_rows");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r < 1 || r > 4096) return false;
+        t.wide_rows = r;
+    }
     for (const char *key : {"stream_rows", "stream_rows_runs"}) {
         it = o.obj.find(key);
         if (it == o.obj.end()) continue;
@@ -244,7 +252,10 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     if (mx == MORPH_METHOD_DOUBLING && user_tile) return MORPH_EINVAL;
     const bool auto_both = mx == MORPH_METHOD_AUTO && my == MORPH_METHOD_AUTO;
     const bool stream_fits = j.wx <= kStreamMaxWx && j.wy <= kStreamMaxWy;
-    if (mx == MORPH_METHOD_DOUBLING && !stream_fits) return MORPH_EUNSUPPORTED;
+    // uint8 rows with a window too wide for the other kernels' strips (vertical window 1)
+    const bool rows_fit = dtype == MORPH_U8 && j.wy == 1 && j.wx > kStreamMaxWx &&
+                          j.wx <= kRowsMaxWx;
+    if (mx == MORPH_METHOD_DOUBLING && !stream_fits && !rows_fit) return MORPH_EUNSUPPORTED;
     // horizontal pass
     if (j.wx == 1) j.hm = PASS_NONE;
     else if (mx == MORPH_METHOD_DIRECT) j.hm = PASS_DIRECT;
@@ -262,6 +273,21 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
     j.SA = j.SB = 0;
     j.vrun = j.vtt = 0;
+
+    // wide windows along rows: the wide-row kernel (horizontal doubling, 16 pixels a
+    // lane), unless a tile or the vHGW passes are asked for
+    if (rows_fit && !user_tile && (mx == MORPH_METHOD_AUTO || mx == MORPH_METHOD_DOUBLING) &&
+        my != MORPH_METHOD_VHGW) {
+        j.kind = KIND_ROWS;
+        j.hm = PASS_DOUBLING;
+        j.hcode = 0;
+        j.TW = 16 * rows_lanes(j.wx);
+        j.TB = std::min(tu.wide_rows, H);
+        j.tiles_x = (W + j.TW - 1) / j.TW;
+        j.tiles_y = (H + j.TB - 1) / j.TB;
+        if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
+        return MORPH_OK;
+    }
 
     // vertical pass direct and no tile asked for: the register-only wave kernel, with
     // the horizontal pass direct or (wider windows, automatic or asked for) doubling
@@ -553,7 +579,9 @@ struct BatchGroup {
 // groups: kernel kind x element type x row alignment, and for the streaming kernel
 // its two vertical forms (LDS ring for wy <= kStreamRingMaxWy, run totals above)
 static constexpr int kRingClasses = 2;
-static constexpr int kBatchGroups = 4 * (kKinds + kRingClasses - 1);
+// group classes: tile, wave, streaming (ring), streaming (run totals), wide rows
+static constexpr int kGroupClasses = kKinds + kRingClasses - 1;
+static constexpr int kBatchGroups = 4 * kGroupClasses;
 
 struct morph_batch {
     int max_images = 0;
@@ -631,18 +659,18 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
 static int group_of(const TileJob &j)
 {
     int k = j.kind;
-    if (j.kind == KIND_STREAM) k += stream_two_level(j.wy) ? 1 : 0;
+    if (j.kind == KIND_STREAM && stream_two_level(j.wy)) k = KIND_STREAM + 1;
+    else if (j.kind == KIND_ROWS) k = kGroupClasses - 1;
     return 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
 }
 
 // Launch order of the groups: streaming groups (run totals, then ring), then the
-// tile and wave groups.
+// tile, wave and wide-row groups.
 static int group_order(int gi)
 {
-    constexpr int ns = 4 * kRingClasses;
-    if (gi < ns) return 4 * (KIND_STREAM + kRingClasses - 1 - gi / 4) + gi % 4;
-    gi -= ns;
-    return gi < 4 ? 4 * KIND_TILE + gi : 4 * KIND_WAVE + (gi - 4);
+    static const int order[kGroupClasses] = {KIND_STREAM + 1, KIND_STREAM, KIND_TILE, KIND_WAVE,
+                                             kGroupClasses - 1};
+    return 4 * order[gi / 4] + gi % 4;
 }
 
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream)
@@ -698,7 +726,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         }
         b->h_tile_start[starts++] = t;
         G.tiles = t;
-        if (G.kind == KIND_WAVE) {
+        if (G.kind == KIND_WAVE || G.kind == KIND_ROWS) {
             // one wave per unit, four per workgroup: the grid covers every unit
             G.grid = (int)std::max<int64_t>((t + 3) / 4, 1);
         } else if (G.kind == KIND_STREAM) {

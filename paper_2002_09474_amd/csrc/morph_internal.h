@@ -19,8 +19,14 @@ enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3
 // of TW / 4 output quads and TB rows, walking down the rows once: vertical vHGW
 // through a ring of wy rows in LDS, horizontal direct or log-step doubling across
 // the lanes.
-enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2 };
-constexpr int kKinds = 3;
+enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2, KIND_ROWS = 3 };
+constexpr int kKinds = 4;
+// KIND_ROWS: uint8, vertical window 1, horizontal window kStreamMaxWx < wx <=
+// kRowsMaxWx: a wave per strip of rows_lanes(wx) lanes x 16 pixels and kWaveRows rows.
+constexpr int kRowsMaxWx = 1000;
+// lanes of a wide-row strip that store: the last one's input, 16 l + 3 + wx + 14,
+// must lie in the 1024 pixels of 64 lanes
+inline int rows_lanes(int wx) { return (1006 - wx) / 16 + 1; }
 constexpr int kStreamMaxWx = 128; // wider windows leave a 64-quad strip too few outputs
 constexpr int kStreamMaxWy = 256; // run tables grow with wy / 8
 constexpr int kStreamChunk = 8; // rows a streaming wave takes at a time (one run of a block)
@@ -63,7 +69,7 @@ struct TileJob {
 
 inline int lds_bytes(const TileJob &j)
 {
-    if (j.kind == KIND_WAVE) return 0;
+    if (j.kind == KIND_WAVE || j.kind == KIND_ROWS) return 0;
     if (j.kind == KIND_STREAM) // per single-wave workgroup, 64 lanes x 4 (u8) / 8 (u16)
                                // bytes per entry: run totals and suffixes, or the ring
         return (stream_two_level(j.wy) ? 2 * stream_runs(j.wy) + 1 : stream_ring_entries(j.wy)) *

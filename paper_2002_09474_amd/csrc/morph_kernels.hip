@@ -33,6 +33,7 @@
 #include "morph_internal.h"
 
 #include <type_traits>
+#include <utility>
 
 namespace morph {
 
@@ -1214,6 +1215,195 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 }
 #undef MORPH_WY_SWITCH
 
+// ======================= wide rows: vertical window 1, 16 pixels per lane ===========
+// A horizontal window too wide for a 64-quad strip (wx > 128) with a vertical window
+// of 1 (uint8): a lane holds four quads of a row (16 pixels as eight pair dwords), so
+// a wave covers 1024 pixels and stores rows_lanes(wx) lanes' worth of them.  The
+// doubling pass as above: shifts of up to 16 pixels take the lane and the next one
+// (DPP), shifts of whole lanes ds_bpermute.  The final step, op(m_L[k],
+// m_L[k + wx - L]) at k = co .. co + 15, reads m_L back as bytes: the first operand
+// from the lane's own quads and the next lane's first, the second from a copy of
+// the row in LDS at a byte offset the same in every lane; byte shifts (alignbyte)
+// take the offsets at run time, so every row takes the same straight-line code and
+// the rows of a group go through each step together.
+constexpr int NP16 = 8; // pair dwords per lane
+constexpr int RG = 4;   // rows of a group
+// LDS per row of a group: the 1024 bytes of m_L, and reads of lanes that store
+// nothing run on to byte 16 * 63 + 3 + (1000 - 512) + 20 < 1536
+constexpr int kRowsLdsDwords = 384;
+static_assert(kRowsMaxWx <= 1000 && 16 * 63 + 3 + (1000 - 512) + 20 <= 4 * kRowsLdsDwords,
+              "wide-row LDS reads must stay inside a row's region");
+
+// Pixel pair (D, D + 1) of the lane's 16 pixels followed by 16 more (n).
+template <int D>
+__device__ __forceinline__ uint32_t pair16(const uint32_t *e, const uint32_t *n)
+{
+    constexpr int i = D / 2;
+    uint32_t lo, hi = 0;
+    if constexpr (i < NP16) lo = e[i];
+    else lo = n[i - NP16];
+    if constexpr (D % 2 == 0) {
+        return lo;
+    } else {
+        if constexpr (i + 1 < NP16) hi = e[i + 1];
+        else hi = n[i + 1 - NP16];
+        return __builtin_amdgcn_alignbit(hi, lo, 16);
+    }
+}
+
+// e[i] = op(e[i], pair at 2i + S) for all eight pairs, S pixels (S <= 16) to the right.
+template <int S, bool MAXOP, int... I>
+__device__ __forceinline__ void level16_in(uint32_t *e, const uint32_t *n,
+                                          std::integer_sequence<int, I...>)
+{
+    const uint32_t out[NP16] = {pk<MAXOP>(e[I], pair16<2 * I + S>(e, n))...};
+    ((e[I] = out[I]), ...);
+}
+
+template <int S, bool MAXOP>
+__device__ __forceinline__ void level16(uint32_t (&e)[RG][NP16])
+{
+    // next-lane pairs the shift reaches: pairs up to index (14 + S + 1) / 2
+    constexpr int NN = (15 + S) / 2 + 1 - NP16;
+#pragma unroll
+    for (int m = 0; m < RG; m++) {
+        uint32_t n[NP16];
+#pragma unroll
+        for (int k = 0; k < NP16; k++) n[k] = k < NN ? from_next_lane(e[m][k]) : 0u;
+        level16_in<S, MAXOP>(e[m], n, std::make_integer_sequence<int, NP16>{});
+    }
+}
+
+// Doubling across lanes: wx > 128, so L reaches 128 at least.
+template <bool MAXOP>
+__device__ __forceinline__ void doubling16(int wx, uint32_t (&e)[RG][NP16])
+{
+    const int lane = threadIdx.x & 63;
+    level16<1, MAXOP>(e);
+    level16<2, MAXOP>(e);
+    level16<4, MAXOP>(e);
+    level16<8, MAXOP>(e);
+    level16<16, MAXOP>(e);
+    for (int q = 2; 32 * q <= wx; q *= 2) { // 16q -> 32q pixels: q lanes
+        const uint32_t ad = (uint32_t)(lane + q) << 2;
+#pragma unroll
+        for (int m = 0; m < RG; m++)
+#pragma unroll
+            for (int i = 0; i < NP16; i++) e[m][i] = pk<MAXOP>(e[m][i], lane_fetch(e[m][i], ad));
+    }
+}
+
+// The lane's 16 output pixels of one row, as four dwords of bytes: op of the pixels
+// at byte offsets sh0 (0..3) and k1 (>= 0) past the lane's first, row = the row's
+// LDS copy (its m_L bytes are written here).
+template <bool MAXOP>
+__device__ __forceinline__ void final16(const uint32_t *e, uint32_t *row, uint32_t sh0,
+                                        uint32_t k1, uint4 &out)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t w[5];
+#pragma unroll
+    for (int j = 0; j < 4; j++) w[j] = perm(e[2 * j + 1], e[2 * j], SEL_NARROW);
+    w[4] = from_next_lane(w[0]);
+    *(uint4 *)(row + 4 * lane) = uint4{w[0], w[1], w[2], w[3]};
+    const uint32_t *r1 = row + 4 * lane + (k1 >> 2);
+    uint32_t v[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) v[j] = r1[j];
+    const uint32_t sh1 = k1 & 3;
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t a = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh0);
+        const uint32_t b = __builtin_amdgcn_alignbyte(v[j + 1], v[j], sh1);
+        const uint32_t lo = pk<MAXOP>(perm(0u, a, SEL_U8_01), perm(0u, b, SEL_U8_01));
+        const uint32_t hi = pk<MAXOP>(perm(0u, a, SEL_U8_23), perm(0u, b, SEL_U8_23));
+        o[j] = perm(hi, lo, SEL_NARROW);
+    }
+    out = uint4{o[0], o[1], o[2], o[3]};
+}
+
+template <bool MAXOP, bool AL>
+__device__ __forceinline__ void rows_body(const TileJob &J, int unit, uint32_t *lds)
+{
+    using T = uint8_t;
+    const int lane = threadIdx.x & 63;
+    const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
+    const int mis = AL ? (int)((uintptr_t)J.src & 3) : 0;
+    const int co = (mis - J.ax) & 3;
+    const int nl = J.TW >> 4;              // lanes that store
+    const int gx = J.TW * sx - J.ax - co + 16 * lane; // the lane's first input column
+    const int y0 = sy * J.TB;
+    const int y1 = min(y0 + J.TB, J.H);
+    using Ld = typename std::conditional<AL, WaveLoader<T>, WaveLoaderAny<T>>::type;
+    auto mk = [&](int q) {
+        if constexpr (AL) return WaveLoader<T>(J, mis, gx + 4 * q);
+        else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)),
+                                     gx + 4 * q);
+    };
+    const Ld L0 = mk(0), L1 = mk(1), L2 = mk(2), L3 = mk(3);
+    int L = 1;
+    while (2 * L <= J.wx) L *= 2;
+    const uint32_t k1 = (uint32_t)(co + J.wx - L); // byte offset of the second operand
+    const int xo = J.TW * sx + 16 * lane;          // the lane's first output column
+    const bool store_lane = lane < nl && xo < J.W;
+    const bool fast_store = ((uintptr_t)J.dst & 3) == 0 && (J.dpitch & 3) == 0 && xo + 16 <= J.W;
+    using Raw = typename Ld::Raw;
+    auto issue = [&](Raw (&r)[RG][4], int y) {
+#pragma unroll
+        for (int m = 0; m < RG; m++) {
+            const int gy = min(y + m, y1 - 1);
+            r[m][0] = L0.issue(gy);
+            r[m][1] = L1.issue(gy);
+            r[m][2] = L2.issue(gy);
+            r[m][3] = L3.issue(gy);
+        }
+    };
+    int y = y0;
+    // rows y .. y + RG - 1 (those past the unit repeat its last row and store
+    // nothing) from cur, with the next group's loads in flight in nxt
+    auto group = [&](Raw (&cur)[RG][4], Raw (&nxt)[RG][4]) -> bool {
+        const bool more = y + RG < y1;
+        if (more) issue(nxt, y + RG);
+        uint32_t e[RG][NP16];
+#pragma unroll
+        for (int m = 0; m < RG; m++) {
+            L0.widen(cur[m][0], e[m][0], e[m][1]);
+            L1.widen(cur[m][1], e[m][2], e[m][3]);
+            L2.widen(cur[m][2], e[m][4], e[m][5]);
+            L3.widen(cur[m][3], e[m][6], e[m][7]);
+        }
+        doubling16<MAXOP>(J.wx, e); // every lane takes part in the lane moves
+#pragma unroll
+        for (int m = 0; m < RG; m++) {
+            uint4 o;
+            final16<MAXOP>(e[m], lds + m * kRowsLdsDwords, (uint32_t)co, k1, o);
+            if (store_lane && y + m < y1) {
+                uint8_t *drow = J.dst + (int64_t)(y + m) * J.dpitch;
+                if (fast_store) {
+                    const uintptr_t a = (uintptr_t)(drow + xo);
+                    store_u32(a, o.x);
+                    store_u32(a + 4, o.y);
+                    store_u32(a + 8, o.z);
+                    store_u32(a + 12, o.w);
+                } else {
+                    const uint32_t d[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                    for (int j = 0; j < 16; j++)
+                        if (xo + j < J.W)
+                            store_u8((uintptr_t)(drow + xo + j), (uint8_t)(d[j >> 2] >> (8 * (j & 3))));
+                }
+            }
+        }
+        y += RG;
+        return more;
+    };
+    Raw ra[RG][4], rb[RG][4];
+    issue(ra, y0);
+    while (group(ra, rb) && group(rb, ra)) {
+    }
+}
+
 // ======================= larger windows: one wave per strip, streaming down =======
 // One wave per strip of 64 column quads and J.TB output rows, walking down the
 // input rows once (no LDS shared between waves, no barrier):
@@ -1686,6 +1876,24 @@ static TileKernelFn pick_stream_kernel(const TileJob &j)
     return stream_two_level(j.wy) ? pick_stream_kernel_v<true>(j) : pick_stream_kernel_v<false>(j);
 }
 
+template <bool MAXOP, bool AL>
+__global__ __launch_bounds__(NT) void rows_kernel(TileJob J)
+{
+    const int units = J.tiles_x * J.tiles_y;
+    const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
+                                                 (int)(threadIdx.x >> 6));
+    if (u >= units) return; // the whole wave leaves
+    __shared__ __align__(16) uint32_t lds[4 * RG * kRowsLdsDwords];
+    rows_body<MAXOP, AL>(J, u, lds + (threadIdx.x >> 6) * RG * kRowsLdsDwords);
+}
+
+static TileKernelFn pick_rows_kernel(const TileJob &j)
+{
+    const bool al = rows_aligned(j);
+    if (j.op) return al ? rows_kernel<true, true> : rows_kernel<true, false>;
+    return al ? rows_kernel<false, true> : rows_kernel<false, false>;
+}
+
 static hipError_t set_lds_limit(const void *fn, int lds)
 {
     if (lds <= 64 * 1024) return hipSuccess;
@@ -1694,6 +1902,11 @@ static hipError_t set_lds_limit(const void *fn, int lds)
 
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
 {
+    if (job.kind == KIND_ROWS) {
+        const int units = job.tiles_x * job.tiles_y;
+        hipLaunchKernelGGL(pick_rows_kernel(job), dim3((units + 3) / 4), dim3(NT), 0, stream, job);
+        return hipGetLastError();
+    }
     if (job.kind == KIND_STREAM) {
         TileKernelFn fn = pick_stream_kernel(job);
         const int lds = lds_bytes(job);
@@ -1772,6 +1985,22 @@ __global__ __launch_bounds__(NT) void batch_wave_kernel(BatchTables bt)
     else wave_body<T, false, AL>(J, u);
 }
 
+// The batch form of the wide-row kernel: one wave per unit, four per workgroup.
+template <bool AL>
+__global__ __launch_bounds__(NT) void batch_rows_kernel(BatchTables bt)
+{
+    const int t = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
+                                                 (int)(threadIdx.x >> 6));
+    if (t >= bt.n_tiles) return; // the whole wave leaves
+    const int jb = bt.tile_job[t];
+    const TileJob J = bt.jobs[jb];
+    const int u = (int)(t - bt.tile_start[jb]);
+    __shared__ __align__(16) uint32_t lds[4 * RG * kRowsLdsDwords];
+    uint32_t *wl = lds + (threadIdx.x >> 6) * RG * kRowsLdsDwords;
+    if (J.op) rows_body<true, AL>(J, u, wl);
+    else rows_body<false, AL>(J, u, wl);
+}
+
 // The batch form of the stream kernel: one single-wave workgroup per unit.
 template <typename T, bool AL, bool RUNS>
 __global__ __launch_bounds__(64) void batch_stream_kernel(BatchTables bt)
@@ -1794,7 +2023,9 @@ hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, 
     typedef void (*BatchFn)(BatchTables);
     BatchFn fn;
     int block = NT;
-    if (kind == KIND_WAVE)
+    if (kind == KIND_ROWS)
+        fn = aligned ? batch_rows_kernel<true> : batch_rows_kernel<false>;
+    else if (kind == KIND_WAVE)
         fn = dtype == 0 ? (aligned ? batch_wave_kernel<uint8_t, true> : batch_wave_kernel<uint8_t, false>)
                         : (aligned ? batch_wave_kernel<uint16_t, true> : batch_wave_kernel<uint16_t, false>);
     else if (kind == KIND_STREAM) {

@@ -127,6 +127,20 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("vhgw", "vhgw", "tile")
         assert morph.resolve_plan("u8", 4096, 4096, 1, 255)["kernel"] == "stream"
         assert morph.resolve_plan("u8", 4096, 4096, 1, 257)["kernel"] == "tile"
+        # uint8, vertical window 1, 128 < wx <= 1000: the wide-row kernel, whose strip
+        # stores the 16-pixel lanes whose input fits in 1024: (1006 - wx) // 16 + 1
+        p = morph.resolve_plan("u8", 4096, 4096, 255, 1)
+        assert (p["method_x"], p["kernel"], p["tile_w"], p["tile_h"]) == \
+            ("doubling", "rows", 16 * 47, 4)
+        assert morph.resolve_plan("u8", 4096, 4096, 1000, 1)["tile_w"] == 16
+        assert morph.resolve_plan("u8", 4096, 4096, 129, 1, method_x="doubling")["kernel"] == "rows"
+        for kw in (dict(dtype_name="u16"), dict(wx=1001), dict(wy=2), dict(method_x="vhgw"),
+                   dict(tile=(256, 16))):
+            a = dict(dtype_name="u8", H=4096, W=4096, wx=255, wy=1)
+            a.update(kw)
+            assert morph.resolve_plan(**a)["kernel"] == "tile", kw
+        with pytest.raises(morph.MorphError):
+            morph.resolve_plan("u8", 4096, 4096, 300, 3, method_x="doubling")
         for bad_kw in (dict(method_y="doubling"), dict(method_x="doubling", tile=(64, 32))):
             with pytest.raises(morph.MorphError):
                 morph.resolve_plan("u8", 100, 100, 15, 5, **bad_kw)
@@ -151,9 +165,11 @@ def test_plan_resolution_and_thresholds(tmp_path):
         p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
         assert (p["method_x"], p["method_y"]) == ("doubling", "vhgw")
         assert (p["tile_w"], p["tile_h"]) == (4 * 62, 48)
-        f.write_text(json.dumps({"u8": {"stream_rows": 100, "stream_rows_runs": 40}}))
+        f.write_text(json.dumps({"u8": {"stream_rows": 100, "stream_rows_runs": 40,
+                                        "wide_rows": 7}}))
         morph.load_tuning(str(f))
         assert morph.resolve_plan("u8", 1000, 1000, 5, 5)["tile_h"] == 100
+        assert morph.resolve_plan("u8", 1000, 1000, 200, 1)["tile_h"] == 7
         assert morph.resolve_plan("u8", 1000, 1000, 5, 17)["tile_h"] == 40
         bad = tmp_path / "bad.json"
         bad.write_text('{"u8": {"t_x": 3, "tiles": [{"wmax": 8, "tq": 1, "tb": 32}]}}')

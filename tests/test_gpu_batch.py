@@ -25,8 +25,9 @@ def _items(n, seed, dtype_mix=True):
         W = int(rng.integers(1, 300))
         dt = np.uint16 if (dtype_mix and i % 3 == 2) else np.uint8
         img = synth.uniform(H, W, dt, seed=seed * 1000 + i)
-        w = int(rng.choice([1, 2, 3, 5, 9, 15, 31, 63]))
-        wy = int(rng.choice([w, 1, 3]))
+        w = int(rng.choice([1, 2, 3, 5, 9, 15, 31, 63, 200, 400]))
+        # (wide windows along rows: the wide-row kernel for uint8)
+        wy = 1 if w > 128 else int(rng.choice([w, 1, 3]))
         ax = int(rng.integers(-1, w))
         ay = int(rng.integers(-1, wy))
         op = "erode" if rng.integers(0, 2) else "dilate"
