@@ -182,7 +182,9 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out);
  * on the same stream read the old tables.  Too many images or tiles ->
  * MORPH_ENOMEM. */
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream);
-/* Enqueue the whole batch on `stream`: launch the group kernels (the last
+/* Enqueue the whole batch on `stream`: one kernel dispatch for the wave and
+ * streaming units of each element type and row alignment (long streaming units
+ * dealt out first), then the tile and wide-row groups' kernels (the last
  * workgroup of a persistent one leaves its queue counter at zero for the next
  * launch).  The first call
  * on a stream captures the launch into a hipGraph that later calls replay; the
@@ -204,7 +206,11 @@ int morph_batch_destroy(morph_batch_t b);
  * quads of a tile row, tb = output rows), the output rows of a direct wave unit
  * (a multiple of 8, at most 64; default 24) and of a streaming unit (1 .. 4096;
  * stream_rows for vertical windows up to 16, default 48, stream_rows_runs above,
- * default 32) and of a wide-row unit (wide_rows, 1 .. 4096, default 4), e.g.
+ * default 32) and of a wide-row unit (wide_rows, 1 .. 4096, default 4); for the
+ * images of a batch, batch_wave_rows (default 32), batch_stream_rows (48) and
+ * batch_stream_rows_runs (48) in place of the first three; and fuse (0 or 1,
+ * default 1): a batch runs its wave and streaming units of one element type and
+ * row alignment as one kernel dispatch, e.g.
  *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 64,
  *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
  * A dtype missing from the file keeps its table; a key missing keeps its value.

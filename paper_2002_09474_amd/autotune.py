@@ -13,11 +13,11 @@ large-window pass (the streaming kernel: vHGW through an LDS ring vertically,
 doubling across lanes horizontally), as single-pass sweeps along x (w x 1) and
 along y (1 x w) on the 1920x1080 document page.  The threshold of a pass is the
 largest window up to which direct is never slower by more than the timing noise.
-Unit heights are then chosen on the 512-image batch of the benchmark (the wave
-kernel's on its direct-window images, the streaming kernel's on the others), and
-tile shapes of the tile kernel per window bucket on 4096x4096 images, and the unit
-height of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same
-images.  Run
+Unit heights of batched images are then chosen on the whole 512-image batch of the
+benchmark (one key at a time), those of single images on 4096x4096 images (the
+wave kernel's at 3x3, the streaming kernel's at 15x15 and 31x31), the unit height
+of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same images,
+and tile shapes of the tile kernel per window bucket.  Run
 ``python -m paper_2002_09474_amd.autotune``.
 """
 from __future__ import annotations
@@ -37,6 +37,12 @@ TB = (16, 32, 64, 128)
 WAVE_ROWS = (8, 16, 24, 32, 48)
 STREAM_ROWS = (32, 48, 64, 96)      # streaming units, LDS-ring form (wy <= 16)
 STREAM_ROWS_RUNS = (24, 32, 48, 64)  # streaming units, run-total form (wy > 16)
+# unit heights of single images, each timed on 4096x4096 images at one window
+SINGLE_KEYS = (("wave_rows", WAVE_ROWS, 3), ("stream_rows", STREAM_ROWS, 15),
+               ("stream_rows_runs", STREAM_ROWS_RUNS, 31))
+# unit heights of batched images, timed on the whole benchmark batch
+BATCH_KEYS = (("batch_wave_rows", (16, 24, 32, 48)), ("batch_stream_rows", (32, 48, 64, 96)),
+              ("batch_stream_rows_runs", (32, 48, 64)))
 WIDE_ROWS = (2, 4, 8, 16)            # wide-row units (uint8, wy = 1, wx > 128)
 WIDE_WINDOWS = (200, 255, 511)
 
@@ -110,8 +116,8 @@ def threshold(rows, axis, tol=0.03):
 
 
 def best_rows(torch, morph, dname, items, key, choices, base, iters=10):
-    """The `key` (wave_rows or stream_rows) among `choices` that runs `items` as one
-    batch fastest, the rest of the table being `base`."""
+    """The `key` (a batch unit height) among `choices` that runs `items` as one batch
+    fastest, the rest of the table being `base`."""
     res = []
     for c in choices:
         _with_table(morph, {dname: dict(base, **{key: c})})
@@ -159,6 +165,22 @@ def tile_sweep(torch, morph, srcs, dsts, dname, iters=20):
     return rules, table
 
 
+def best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w, iters=20):
+    """The `key` (a single-image unit height) among `choices` that runs a w x w
+    erosion of the images `srcs` fastest, the rest of the table being `base`."""
+    res = []
+    for c in choices:
+        _with_table(morph, {dname: dict(base, **{key: c})})
+        k = [0]
+
+        def fn():
+            i = k[0] % len(srcs)
+            k[0] += 1
+            morph.apply("erode", srcs[i], w, w, out=dsts[i])
+        res.append({key: c, "us": round(_timer(torch, fn, iters), 3)})
+    return min(res, key=lambda r: r["us"])[key], res
+
+
 def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20):
     """Rows of a wide-row unit: the sum over WIDE_WINDOWS (w x 1) on uint8 4096x4096
     images, per choice; the fastest."""
@@ -179,20 +201,17 @@ def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20):
 
 
 def _batch_items(torch, morph, dev, dname):
-    """The benchmark's 512-image batch (uint8, or the same images scaled to uint16),
-    split by kernel: direct-window images, streaming images with wy <= 16 (LDS-ring
-    form) and the others (run-total form)."""
+    """The benchmark's 512-image batch (uint8, or the same images scaled to uint16)."""
     from . import synth
     specs = synth.batch_specs(512, seed=5)
     imgs = synth.batch_images(specs, seed=5)
-    direct, ring, runs = [], [], []
+    items = []
     for s, im in zip(specs, imgs):
         t = torch.from_numpy(im).to(dev)
         if dname == "u16":
             t = (t.to(torch.int32) * 257).to(torch.int16).view(torch.uint16)
-        it = dict(src=t, dst=torch.empty_like(t), wx=s["w"], wy=s["w"], op=s["op"])
-        (direct if s["w"] <= DIRECT_MAX else ring if s["w"] <= 16 else runs).append(it)
-    return direct, ring, runs
+        items.append(dict(src=t, dst=torch.empty_like(t), wx=s["w"], wy=s["w"], op=s["op"]))
+    return items
 
 
 def tune(out_path=DEFAULT_OUT, quick=False):
@@ -211,22 +230,25 @@ def tune(out_path=DEFAULT_OUT, quick=False):
         tx, ty = threshold(rows, "x"), threshold(rows, "y")
         del srcs, dsts
         base = {"t_x": tx, "t_y": ty}
-        direct, ring, runs = _batch_items(torch, morph, dev, dname)
+        items = _batch_items(torch, morph, dev, dname)
         it = 5 if quick else 10
-        wr, wr_table = best_rows(torch, morph, dname, direct, "wave_rows", WAVE_ROWS, base, it)
-        base["wave_rows"] = wr
-        sr, sr_table = best_rows(torch, morph, dname, ring, "stream_rows", STREAM_ROWS, base, it)
-        base["stream_rows"] = sr
-        sq, sq_table = best_rows(torch, morph, dname, runs, "stream_rows_runs", STREAM_ROWS_RUNS,
-                                 base, it)
-        base["stream_rows_runs"] = sq
-        del direct, ring, runs
+        for key, choices in BATCH_KEYS:
+            best, table = best_rows(torch, morph, dname, items, key, choices, base, it)
+            base[key] = best
+            result[dname + "_" + key + "_sweep"] = table
+        del items
         _with_table(morph, {dname: base})
         g = torch.Generator(device=dev).manual_seed(3)
         big = torch.randint(0, 256 if dname == "u8" else 65536, (4096, 4096), generator=g,
                             dtype=torch.int32, device=dev)
         big = big.to(torch.uint8) if dname == "u8" else big.to(torch.int16).view(torch.uint16)
         srcs, dsts = _bufs(torch, big, 6)
+        for key, choices, w in SINGLE_KEYS:
+            best, table = best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w,
+                                           8 if quick else 20)
+            base[key] = best
+            result[dname + "_" + key + "_sweep"] = table
+        _with_table(morph, {dname: base})
         if dname == "u8":
             wr2, wr2_table = wide_rows_sweep(torch, morph, srcs, dsts, base, 8 if quick else 20)
             base["wide_rows"] = wr2
@@ -236,9 +258,6 @@ def tune(out_path=DEFAULT_OUT, quick=False):
         del srcs, dsts, big
         result[dname] = dict(base, tiles=rules)
         result[dname + "_pass_sweep"] = rows
-        result[dname + "_wave_rows_sweep"] = wr_table
-        result[dname + "_stream_rows_sweep"] = sr_table
-        result[dname + "_stream_rows_runs_sweep"] = sq_table
         result[dname + "_tile_sweep"] = table
         print("[autotune] %s: %s" % (dname, result[dname]), file=sys.stderr, flush=True)
     with open(out_path, "w") as f:

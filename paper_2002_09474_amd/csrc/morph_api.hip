@@ -43,12 +43,16 @@ struct DtypeTuning {
     int stream_rows;      // output rows of a streaming-kernel unit (LDS-ring form)
     int stream_rows_runs; // the same for the run-total form (wy > kStreamRingMaxWy)
     int wide_rows;        // output rows of a wide-row unit (uint8, wy 1, wx > kStreamMaxWx)
+    int fuse;             // batches: wave and streaming groups in one dispatch (0 / 1)
+    // the unit heights above for images of a batch, whose many units fill the GPU
+    // whatever their height, so that longer units (less vertical warm-up) pay
+    int batch_wave_rows, batch_stream_rows, batch_stream_rows_runs;
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -144,12 +148,20 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_x = (int)it->second.num;
     it = o.obj.find("t_y");
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_y = (int)it->second.num;
-    it = o.obj.find("wave_rows");
-    if (it != o.obj.end()) {
+    for (const char *key : {"wave_rows", "batch_wave_rows"}) {
+        it = o.obj.find(key);
+        if (it == o.obj.end()) continue;
         if (it->second.k != JVal::NUM) return false;
         const int r = (int)it->second.num;
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
-        t.wave_rows = r;
+        (key[0] == 'b' ? t.batch_wave_rows : t.wave_rows) = r;
+    }
+    it = o.obj.find("fuse");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r != 0 && r != 1) return false;
+        t.fuse = r;
     }
     it = o.obj.find("wide_rows");
     if (it != o.obj.end()) {
@@ -158,13 +170,20 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         if (r < 1 || r > 4096) return false;
         t.wide_rows = r;
     }
-    for (const char *key : {"stream_rows", "stream_rows_runs"}) {
-        it = o.obj.find(key);
+    const struct {
+        const char *key;
+        int DtypeTuning::*field;
+    } rows_keys[] = {{"stream_rows", &DtypeTuning::stream_rows},
+                     {"stream_rows_runs", &DtypeTuning::stream_rows_runs},
+                     {"batch_stream_rows", &DtypeTuning::batch_stream_rows},
+                     {"batch_stream_rows_runs", &DtypeTuning::batch_stream_rows_runs}};
+    for (const auto &rk : rows_keys) {
+        it = o.obj.find(rk.key);
         if (it == o.obj.end()) continue;
         if (it->second.k != JVal::NUM) return false;
         const int r = (int)it->second.num;
         if (r < 1 || r > 4096) return false;
-        (key[sizeof("stream_rows") - 1] ? t.stream_rows_runs : t.stream_rows) = r;
+        t.*rk.field = r;
     }
     it = o.obj.find("tiles");
     if (it != o.obj.end()) {
@@ -225,7 +244,8 @@ int default_anchor(int w) { return w - 1 - w / 2; }
 // anchor a and right extent r = w - 1 - a, only min(a, W-1) columns to the left and
 // min(r, W-1) to the right can ever be inside the image.
 int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
-             size_t dpitch, int wx, int wy, int ax, int ay, const morph_plan *plan, TileJob &j)
+             size_t dpitch, int wx, int wy, int ax, int ay, const morph_plan *plan, TileJob &j,
+             bool batch = false)
 {
     if (ax < 0) ax = default_anchor(wx);
     if (ay < 0) ay = default_anchor(wy);
@@ -299,7 +319,8 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         if (j.hm == PASS_VHGW) j.hm = PASS_DOUBLING;
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
         j.TW = j.hm == PASS_DOUBLING ? 4 * stream_quads(j.wx) : 4 * kWaveQuads;
-        j.TB = std::min(tu.wave_rows, (H + kWaveRows - 1) / kWaveRows * kWaveRows);
+        j.TB = std::min(batch ? tu.batch_wave_rows : tu.wave_rows,
+                        (H + kWaveRows - 1) / kWaveRows * kWaveRows);
         j.tiles_x = (W + j.TW - 1) / j.TW;
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
@@ -315,11 +336,13 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
         j.TW = 4 * stream_quads(j.wx);
         j.tiles_x = (W + j.TW - 1) / j.TW;
-        // (by measurement: 48 rows for the LDS-ring form, 32 for the run-total form,
-        // near the best for every window of the benchmark batch and the 4096x4096
-        // images, and best for the mixed batch, whose per-group launches want many
-        // units)
-        j.TB = std::min(stream_two_level(j.wy) ? tu.stream_rows_runs : tu.stream_rows, H);
+        // (by measurement: single images, 48 rows for the LDS-ring form and 32 for
+        // the run-total form, which give a 4096x4096 image units enough to fill the
+        // GPU; in a batch, whose units fill it anyway, 48 for both, which spends less
+        // on each unit's vertical warm-up)
+        j.TB = std::min(stream_two_level(j.wy) ? (batch ? tu.batch_stream_rows_runs : tu.stream_rows_runs)
+                                               : (batch ? tu.batch_stream_rows : tu.stream_rows),
+                        H);
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
         return MORPH_OK;
@@ -698,7 +721,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
             return MORPH_EALIAS;
         TileJob j;
         rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, dp, d.wx, d.wy, d.ax,
-                      d.ay, nullptr, j);
+                      d.ay, nullptr, j, true);
         if (rc != MORPH_OK) return rc;
         jobs[group_of(j)].push_back(j);
     }
@@ -777,19 +800,57 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
     return MORPH_OK;
 }
 
-// The group kernels one after the other on the caller's stream (running them side
-// by side on forked streams measured no faster on the benchmark batch).
+// Class of a group in a fused dispatch (-1: launched on its own).
+static int fused_class(const BatchGroup &G)
+{
+    if (!tuning_for(G.dtype).fuse) return -1;
+    if (G.kind == KIND_STREAM) return G.variant ? 0 : 1;
+    return G.kind == KIND_WAVE ? 2 : -1;
+}
+
+// The wave and streaming groups of each element type and row alignment as one
+// fused dispatch (see launch_fused), then the other groups' kernels, one after the
+// other on the caller's stream (running the groups side by side on forked streams
+// measured no faster on the benchmark batch; fusing them does).
 static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
 {
     int start = 0;
     int64_t tstart = 0;
+    std::vector<BatchTables> tabs(b->groups.size());
     for (size_t g = 0; g < b->groups.size(); g++) {
         const BatchGroup &G = b->groups[g];
-        BatchTables t{b->d_jobs + G.job0, b->d_tile_start + start, b->d_tile_job + tstart,
-                      G.njobs, G.tiles, b->d_counter + 2 * g};
+        tabs[g] = BatchTables{b->d_jobs + G.job0, b->d_tile_start + start, b->d_tile_job + tstart,
+                              G.njobs, G.tiles, b->d_counter + 2 * g};
         start += G.njobs + 1;
         tstart += G.tiles;
-        hipError_t e = launch_batch(t, G.kind, G.variant, G.dtype, G.aligned, G.grid, G.lds, stream);
+    }
+    for (int dt = 0; dt < 2; dt++)
+        for (int al = 0; al < 2; al++) {
+            FusedTables ft{};
+            int64_t n[kFusedClasses] = {0, 0, 0};
+            int lds = 0;
+            for (size_t g = 0; g < b->groups.size(); g++) {
+                const BatchGroup &G = b->groups[g];
+                const int c = fused_class(G);
+                if (c < 0 || G.dtype != dt || G.aligned != (al == 0)) continue;
+                ft.g[c] = tabs[g];
+                n[c] = G.tiles;
+                lds = std::max(lds, G.lds);
+            }
+            if (n[0] + n[1] + n[2] == 0) continue;
+            ft.b0[0] = 0;
+            for (int c = 0; c < kFusedClasses; c++) {
+                const int64_t nb = ft.b0[c] + (n[c] + 7) / 8 * 8;
+                if (nb > INT32_MAX) return hipErrorInvalidValue;
+                ft.b0[c + 1] = (int32_t)nb;
+            }
+            hipError_t e = launch_fused(ft, dt, al == 0, lds, stream);
+            if (e != hipSuccess) return e;
+        }
+    for (size_t g = 0; g < b->groups.size(); g++) {
+        const BatchGroup &G = b->groups[g];
+        if (fused_class(G) >= 0) continue;
+        hipError_t e = launch_batch(tabs[g], G.kind, G.variant, G.dtype, G.aligned, G.grid, G.lds, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -93,6 +93,17 @@ struct BatchTables {
 };
 hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, bool aligned, int grid,
                         int lds, hipStream_t stream);
+// One dispatch for the wave and streaming groups of one element type and row
+// alignment: classes 0 (streaming, run totals), 1 (streaming, LDS ring) and 2
+// (wave), one single-wave workgroup per unit, class c taking blocks
+// [b0[c], b0[c + 1]) (b0[c] a multiple of 8, so each class keeps its units
+// contiguous per XCD).
+struct FusedTables {
+    BatchTables g[3];
+    int32_t b0[4];
+};
+constexpr int kFusedClasses = 3;
+hipError_t launch_fused(const FusedTables &t, int dtype, bool aligned, int lds, hipStream_t stream);
 // output quads of a stream-kernel strip for a horizontal window wx (worst-case
 // origin offset 3): the last one's input, 4Q + 3 + wx + 2, must lie in 64 quads
 inline int stream_quads(int wx) { return (250 - wx) / 4 + 1; }

@@ -2017,6 +2017,45 @@ __global__ __launch_bounds__(64) void batch_stream_kernel(BatchTables bt)
 
 // Batches are launched per group of jobs with the same kernel kind, element type and
 // row alignment.
+// The wave and streaming groups of a batch in one dispatch: the dispatcher deals the
+// run-total streaming units out first, then the ring ones, then the wave units, so
+// the short units fill in behind the long ones instead of each group filling and
+// draining the GPU on its own.
+template <typename T, bool AL>
+__global__ __launch_bounds__(64) void batch_fused_kernel(FusedTables ft)
+{
+    extern __shared__ uint32_t lds[];
+    const int b = blockIdx.x;
+    const int c = b < ft.b0[1] ? 0 : (b < ft.b0[2] ? 1 : 2);
+    const BatchTables &bt = c == 0 ? ft.g[0] : (c == 1 ? ft.g[1] : ft.g[2]);
+    const int t = xcd_tile(b - ft.b0[c], ft.b0[c + 1] - ft.b0[c]);
+    if (t >= bt.n_tiles) return;
+    const int jb = bt.tile_job[t];
+    const TileJob J = bt.jobs[jb];
+    const int u = (int)(t - bt.tile_start[jb]);
+    if (c == 0) {
+        if (J.op) stream_body<T, true, AL, true>(J, u, lds);
+        else stream_body<T, false, AL, true>(J, u, lds);
+    } else if (c == 1) {
+        if (J.op) stream_body<T, true, AL, false>(J, u, lds);
+        else stream_body<T, false, AL, false>(J, u, lds);
+    } else {
+        if (J.op) wave_body<T, true, AL>(J, u);
+        else wave_body<T, false, AL>(J, u);
+    }
+}
+
+hipError_t launch_fused(const FusedTables &t, int dtype, bool aligned, int lds, hipStream_t stream)
+{
+    typedef void (*FusedFn)(FusedTables);
+    const FusedFn fn = dtype == 0 ? (aligned ? batch_fused_kernel<uint8_t, true> : batch_fused_kernel<uint8_t, false>)
+                                  : (aligned ? batch_fused_kernel<uint16_t, true> : batch_fused_kernel<uint16_t, false>);
+    hipError_t e = set_lds_limit((const void *)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(t.b0[kFusedClasses]), dim3(64), lds, stream, t);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, bool aligned, int grid,
                         int lds, hipStream_t stream)
 {

@@ -171,6 +171,14 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert morph.resolve_plan("u8", 1000, 1000, 5, 5)["tile_h"] == 100
         assert morph.resolve_plan("u8", 1000, 1000, 200, 1)["tile_h"] == 7
         assert morph.resolve_plan("u8", 1000, 1000, 5, 17)["tile_h"] == 40
+        # batch unit heights and the fused batch dispatch are keys of their own
+        f.write_text(json.dumps({"u8": {"batch_wave_rows": 16, "batch_stream_rows": 20,
+                                        "batch_stream_rows_runs": 30, "fuse": 0}}))
+        morph.load_tuning(str(f))
+        for bad_t in ({"batch_wave_rows": 12}, {"fuse": 2}, {"batch_stream_rows": 0}):
+            f.write_text(json.dumps({"u8": bad_t}))
+            with pytest.raises(morph.MorphError):
+                morph.load_tuning(str(f))
         bad = tmp_path / "bad.json"
         bad.write_text('{"u8": {"t_x": 3, "tiles": [{"wmax": 8, "tq": 1, "tb": 32}]}}')
         with pytest.raises(morph.MorphError):

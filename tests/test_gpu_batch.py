@@ -46,7 +46,21 @@ def _want(it):
                         it["ax"], it["ay"], method="direct")
 
 
-def test_batch_matches_oracle_and_single_calls():
+@pytest.mark.parametrize("fuse", [1, 0])
+def test_batch_matches_oracle_and_single_calls(fuse, tmp_path):
+    """With the wave and streaming groups fused into one dispatch per element type
+    and row alignment (the default) and launched one group at a time."""
+    import json
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps({"u8": {"fuse": fuse}, "u16": {"fuse": fuse}}))
+    morph.load_tuning(str(f))
+    try:
+        _batch_matches_oracle_and_single_calls()
+    finally:
+        morph.load_tuning(None)
+
+
+def _batch_matches_oracle_and_single_calls():
     items = _items(40, seed=1)
     b = morph.Batch(64, 1 << 20)
     ntiles = b.set(items)
@@ -126,7 +140,7 @@ def test_batch_with_many_wave_units(tmp_path):
     every unit is done."""
     import json
     f = tmp_path / "t.json"
-    f.write_text(json.dumps({"u8": {"wave_rows": 8}}))
+    f.write_text(json.dumps({"u8": {"batch_wave_rows": 8}}))
     morph.load_tuning(str(f))
     try:
         items = []
