@@ -1016,31 +1016,36 @@ template <typename T> struct WaveLoader {
     }
 };
 
+// The unit's first WY - 1 input rows into the ring, and the loads of the first
+// chunk's KR new rows (input row gy0 + WY - 1 onwards) into raw.
 template <int WY, typename Ld>
-__device__ __forceinline__ void wv_first(const Ld &L, int gy0, uint32_t *r01, uint32_t *r23)
+__device__ __forceinline__ void wv_first(const Ld &L, int gy0, uint32_t *r01, uint32_t *r23,
+                                         typename Ld::Raw *raw)
 {
-    L.template rows<KR + WY - 1>(gy0, r01, r23);
+    L.template rows<WY - 1>(gy0, r01, r23);
+#pragma unroll
+    for (int m = 0; m < KR; m++) raw[m] = L.issue(gy0 + WY - 1 + m);
 }
 
-// Output rows of this chunk from the ring; then, if another chunk follows, move the
-// ring down and issue the loads of its KR new rows (input row gnext onwards), which
-// complete while this chunk's horizontal pass and stores run.
+// One chunk's vertical pass: its KR new rows (the loads in cur, issued during the
+// previous chunk) into the ring, its output rows, and the ring moved down for the
+// next chunk.
 template <int WY, bool MAXOP, typename Ld>
-__device__ __forceinline__ void wv_vertical(const Ld &L, int gnext, bool more, uint32_t *r01,
-                                            uint32_t *r23, uint32_t *o01, uint32_t *o23)
+__device__ __forceinline__ void wv_vertical(const Ld &L, const typename Ld::Raw *cur,
+                                            uint32_t *r01, uint32_t *r23, uint32_t *o01,
+                                            uint32_t *o23)
 {
+#pragma unroll
+    for (int m = 0; m < KR; m++) L.widen(cur[m], r01[WY - 1 + m], r23[WY - 1 + m]);
 #pragma unroll
     for (int m = 0; m < KR; m += 2) {
         pair_window<WY, MAXOP>(r01 + m, o01[m], o01[m + 1]);
         pair_window<WY, MAXOP>(r23 + m, o23[m], o23[m + 1]);
     }
-    if (more) {
 #pragma unroll
-        for (int k = 0; k < WY - 1; k++) {
-            r01[k] = r01[k + KR];
-            r23[k] = r23[k + KR];
-        }
-        L.template rows<KR>(gnext, r01 + WY - 1, r23 + WY - 1);
+    for (int k = 0; k < WY - 1; k++) {
+        r01[k] = r01[k + KR];
+        r23[k] = r23[k + KR];
     }
 }
 
@@ -1162,7 +1167,9 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
         else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)), gx);
     }();
     uint32_t r01[RING], r23[RING];
-#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, r01, r23)
+    using Raw = typename Ld::Raw;
+    Raw ra[KR], rb[KR];
+#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, r01, r23, ra)
     MORPH_WY_SWITCH(J.wy, MORPH_FIRST)
 #undef MORPH_FIRST
     // destination: 4-byte aligned rows and a strip wholly inside the image take
@@ -1172,10 +1179,20 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
                             4 * (wq * sx + wq) <= J.W;
     const bool doubling = J.hm == PASS_DOUBLING;
     const Doubling S(J.wx, co);
-    for (int y = y0; y < y1; y += KR) {
+    int y = y0;
+    // rows y .. y + KR - 1 from the loads in cur, the next chunk's issued into nxt
+    // (two buffers taking turns, so no load in flight is ever copied)
+    auto chunk = [&](Raw (&cur)[KR], Raw (&nxt)[KR]) __attribute__((always_inline)) -> bool {
         uint32_t v01[KR], v23[KR];
         const bool more = y + KR < y1;
-#define MORPH_VERT(W) wv_vertical<W, MAXOP>(L, y + KR - J.ay + W - 1, more, r01, r23, v01, v23)
+        // the next chunk's KR new rows (input row gn onwards) complete while this
+        // chunk's passes and stores run; they are widened only by the next chunk
+        if (more) {
+            const int gn = y + KR - J.ay + J.wy - 1;
+#pragma unroll
+            for (int m = 0; m < KR; m++) nxt[m] = L.issue(gn + m);
+        }
+#define MORPH_VERT(W) wv_vertical<W, MAXOP>(L, cur, r01, r23, v01, v23)
         MORPH_WY_SWITCH(J.wy, MORPH_VERT)
 #undef MORPH_VERT
         if constexpr (AL && sizeof(T) == 2) {
@@ -1211,6 +1228,10 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
                 }
             }
         }
+        y += KR;
+        return more;
+    };
+    while (chunk(ra, rb) && chunk(rb, ra)) {
     }
 }
 #undef MORPH_WY_SWITCH
