@@ -85,8 +85,8 @@ extern "C" {
  * its horizontal pass direct or (wider windows, up to 128) doubling; with both
  * methods AUTO and no tile, larger vertical windows (wx <= 128, wy <= 256) run one
  * wave per strip that streams down the rows (vertical vHGW through LDS,
- * horizontal direct or doubling); uint8 with wy = 1 and 128 < wx <= 1000 runs
- * one wave per strip of rows with 16 pixels a lane (horizontal doubling);
+ * horizontal direct or doubling); wy = 1 with 128 < wx <= 1000 runs one wave
+ * per strip of rows with 16 pixels a lane (horizontal doubling);
  * anything else -- a forced vHGW pass, a tile, larger windows -- runs the
  * workgroup-tile kernel, which implements exactly the paper's two methods.
  * method_x = DOUBLING takes the wave, streaming or wide-row kernel by the
@@ -106,7 +106,7 @@ typedef struct morph_plan {
 #define MORPH_KERNEL_TILE 0   /* workgroup tile through LDS, the paper's two methods */
 #define MORPH_KERNEL_WAVE 1   /* both passes direct, one wave per strip, registers only */
 #define MORPH_KERNEL_STREAM 2 /* one wave per strip streaming down the rows */
-#define MORPH_KERNEL_ROWS 3   /* uint8, wy = 1, wide wx: one wave per strip, 16 pixels a lane */
+#define MORPH_KERNEL_ROWS 3   /* wy = 1, wide wx: one wave per strip, 16 pixels a lane */
 
 /* Erosion, uint8 (§2 Eq. (1)).  See the conventions above for every argument. */
 int morph_erode(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
@@ -206,7 +206,8 @@ int morph_batch_destroy(morph_batch_t b);
  * quads of a tile row, tb = output rows), the output rows of a direct wave unit
  * (a multiple of 8, at most 64; default 24) and of a streaming unit (1 .. 4096;
  * stream_rows for vertical windows up to 16, default 48, stream_rows_runs above,
- * default 32) and of a wide-row unit (wide_rows, 1 .. 4096, default 4); for the
+ * default 32) and of a wide-row unit (wide_rows, 1 .. 4096, default 4; the
+ * kernel takes rows in groups of 4 for uint8, 2 for uint16); for the
  * images of a batch, batch_wave_rows (default 32), batch_stream_rows (48) and
  * batch_stream_rows_runs (48) in place of the first three; and fuse (0 or 1,
  * default 1): a batch runs its wave and streaming units of one element type and

@@ -42,7 +42,7 @@ struct DtypeTuning {
     int wave_rows;   // output rows of a wave unit (both passes direct), multiple of kWaveRows
     int stream_rows;      // output rows of a streaming-kernel unit (LDS-ring form)
     int stream_rows_runs; // the same for the run-total form (wy > kStreamRingMaxWy)
-    int wide_rows;        // output rows of a wide-row unit (uint8, wy 1, wx > kStreamMaxWx)
+    int wide_rows;        // output rows of a wide-row unit (wy 1, wx > kStreamMaxWx)
     int fuse;             // batches: wave and streaming groups in one dispatch (0 / 1)
     // the unit heights above for images of a batch, whose many units fill the GPU
     // whatever their height, so that longer units (less vertical warm-up) pay
@@ -272,9 +272,8 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     if (mx == MORPH_METHOD_DOUBLING && user_tile) return MORPH_EINVAL;
     const bool auto_both = mx == MORPH_METHOD_AUTO && my == MORPH_METHOD_AUTO;
     const bool stream_fits = j.wx <= kStreamMaxWx && j.wy <= kStreamMaxWy;
-    // uint8 rows with a window too wide for the other kernels' strips (vertical window 1)
-    const bool rows_fit = dtype == MORPH_U8 && j.wy == 1 && j.wx > kStreamMaxWx &&
-                          j.wx <= kRowsMaxWx;
+    // rows with a window too wide for the other kernels' strips (vertical window 1)
+    const bool rows_fit = j.wy == 1 && j.wx > kStreamMaxWx && j.wx <= kRowsMaxWx;
     if (mx == MORPH_METHOD_DOUBLING && !stream_fits && !rows_fit) return MORPH_EUNSUPPORTED;
     // horizontal pass
     if (j.wx == 1) j.hm = PASS_NONE;

@@ -21,7 +21,7 @@ enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3
 // the lanes.
 enum KernelKind { KIND_TILE = 0, KIND_WAVE = 1, KIND_STREAM = 2, KIND_ROWS = 3 };
 constexpr int kKinds = 4;
-// KIND_ROWS: uint8, vertical window 1, horizontal window kStreamMaxWx < wx <=
+// KIND_ROWS: vertical window 1, horizontal window kStreamMaxWx < wx <=
 // kRowsMaxWx: a wave per strip of rows_lanes(wx) lanes x 16 pixels and kWaveRows rows.
 constexpr int kRowsMaxWx = 1000;
 // lanes of a wide-row strip that store: the last one's input, 16 l + 3 + wx + 14,

@@ -1238,22 +1238,28 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 
 // ======================= wide rows: vertical window 1, 16 pixels per lane ===========
 // A horizontal window too wide for a 64-quad strip (wx > 128) with a vertical window
-// of 1 (uint8): a lane holds four quads of a row (16 pixels as eight pair dwords), so
-// a wave covers 1024 pixels and stores rows_lanes(wx) lanes' worth of them.  The
-// doubling pass as above: shifts of up to 16 pixels take the lane and the next one
-// (DPP), shifts of whole lanes ds_bpermute.  The final step, op(m_L[k],
-// m_L[k + wx - L]) at k = co .. co + 15, reads m_L back as bytes: the first operand
-// from the lane's own quads and the next lane's first, the second from a copy of
-// the row in LDS at a byte offset the same in every lane; byte shifts (alignbyte)
-// take the offsets at run time, so every row takes the same straight-line code and
-// the rows of a group go through each step together.
+// of 1: a lane holds four quads of a row (16 pixels as eight pair dwords), so a wave
+// covers 1024 pixels and stores rows_lanes(wx) lanes' worth of them.  The doubling
+// pass as above: shifts of up to 16 pixels take the lane and the next one (DPP),
+// shifts of whole lanes ds_bpermute.  The final step, op(m_L[k], m_L[k + wx - L]) at
+// k = co .. co + 15, reads m_L back from a copy of the row in LDS at offsets that are
+// the same in every lane (uint8: as bytes, the first operand from the lane's own
+// quads and the next lane's first; uint16: as pixel pairs, both operands from LDS);
+// byte or half-dword shifts (alignbyte, alignbit) take the offsets at run time, so
+// every row takes the same straight-line code and the rows of a group go through
+// each step together.
 constexpr int NP16 = 8; // pair dwords per lane
-constexpr int RG = 4;   // rows of a group
-// LDS per row of a group: the 1024 bytes of m_L, and reads of lanes that store
-// nothing run on to byte 16 * 63 + 3 + (1000 - 512) + 20 < 1536
-constexpr int kRowsLdsDwords = 384;
-static_assert(kRowsMaxWx <= 1000 && 16 * 63 + 3 + (1000 - 512) + 20 <= 4 * kRowsLdsDwords,
+// rows of a group: 4 (uint8) or 2 (uint16), so that a wave's LDS is 6 KB either way
+template <typename T> constexpr int rows_group() { return sizeof(T) == 1 ? 4 : 2; }
+// LDS per row of a group: m_L (1024 bytes for uint8, 2048 for uint16), and reads of
+// lanes that store nothing run on to byte 16 * 63 + 3 + (1000 - 512) + 20 < 1536
+// (uint8) or dword 8 * 63 + (3 + 1000 - 512) / 2 + 9 <= 768 (uint16)
+template <typename T> constexpr int rows_lds_dwords() { return sizeof(T) == 1 ? 384 : 768; }
+constexpr int kRowsWaveLdsDwords = 1536; // per wave: rows_group<T>() * rows_lds_dwords<T>()
+static_assert(kRowsMaxWx <= 1000 && 16 * 63 + 3 + (1000 - 512) + 20 <= 4 * 384 &&
+                  8 * 63 + (3 + 1000 - 512) / 2 + 9 <= 768,
               "wide-row LDS reads must stay inside a row's region");
+static_assert(4 * 384 == kRowsWaveLdsDwords && 2 * 768 == kRowsWaveLdsDwords, "");
 
 // Pixel pair (D, D + 1) of the lane's 16 pixels followed by 16 more (n).
 template <int D>
@@ -1281,7 +1287,7 @@ __device__ __forceinline__ void level16_in(uint32_t *e, const uint32_t *n,
     ((e[I] = out[I]), ...);
 }
 
-template <int S, bool MAXOP>
+template <int S, bool MAXOP, int RG>
 __device__ __forceinline__ void level16(uint32_t (&e)[RG][NP16])
 {
     // next-lane pairs the shift reaches: pairs up to index (14 + S + 1) / 2
@@ -1296,15 +1302,15 @@ __device__ __forceinline__ void level16(uint32_t (&e)[RG][NP16])
 }
 
 // Doubling across lanes: wx > 128, so L reaches 128 at least.
-template <bool MAXOP>
+template <bool MAXOP, int RG>
 __device__ __forceinline__ void doubling16(int wx, uint32_t (&e)[RG][NP16])
 {
     const int lane = threadIdx.x & 63;
-    level16<1, MAXOP>(e);
-    level16<2, MAXOP>(e);
-    level16<4, MAXOP>(e);
-    level16<8, MAXOP>(e);
-    level16<16, MAXOP>(e);
+    level16<1, MAXOP, RG>(e);
+    level16<2, MAXOP, RG>(e);
+    level16<4, MAXOP, RG>(e);
+    level16<8, MAXOP, RG>(e);
+    level16<16, MAXOP, RG>(e);
     for (int q = 2; 32 * q <= wx; q *= 2) { // 16q -> 32q pixels: q lanes
         const uint32_t ad = (uint32_t)(lane + q) << 2;
 #pragma unroll
@@ -1344,13 +1350,40 @@ __device__ __forceinline__ void final16(const uint32_t *e, uint32_t *row, uint32
     out = uint4{o[0], o[1], o[2], o[3]};
 }
 
-template <bool MAXOP, bool AL>
+// uint16: the lane's 16 output pixels as eight pair dwords, op of the pixels at
+// offsets co (0..3) and k1 (>= 0) past the lane's first, both read back from the
+// row's LDS copy (its m_L pairs are written here) and shifted by half a dword when
+// the offset is odd.
+template <bool MAXOP>
+__device__ __forceinline__ void final16_u16(const uint32_t *e, uint32_t *row, uint32_t co,
+                                            uint32_t k1, uint32_t *out)
+{
+    const int lane = threadIdx.x & 63;
+    *(uint4 *)(row + 8 * lane) = uint4{e[0], e[1], e[2], e[3]};
+    *(uint4 *)(row + 8 * lane + 4) = uint4{e[4], e[5], e[6], e[7]};
+    const uint32_t *r0 = row + 8 * lane + (co >> 1);
+    const uint32_t *r1 = row + 8 * lane + (k1 >> 1);
+    uint32_t a[NP16 + 1], b[NP16 + 1];
+#pragma unroll
+    for (int j = 0; j <= NP16; j++) {
+        a[j] = r0[j];
+        b[j] = r1[j];
+    }
+    const uint32_t sh0 = (co & 1) * 16, sh1 = (k1 & 1) * 16;
+#pragma unroll
+    for (int j = 0; j < NP16; j++)
+        out[j] = pk<MAXOP>(__builtin_amdgcn_alignbit(a[j + 1], a[j], sh0),
+                           __builtin_amdgcn_alignbit(b[j + 1], b[j], sh1));
+}
+
+template <typename T, bool MAXOP, bool AL>
 __device__ __forceinline__ void rows_body(const TileJob &J, int unit, uint32_t *lds)
 {
-    using T = uint8_t;
+    constexpr int RG = rows_group<T>();
+    constexpr int LD = rows_lds_dwords<T>();
     const int lane = threadIdx.x & 63;
     const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
-    const int mis = AL ? (int)((uintptr_t)J.src & 3) : 0;
+    const int mis = AL ? (int)(((uintptr_t)J.src & (4 * sizeof(T) - 1)) / sizeof(T)) : 0;
     const int co = (mis - J.ax) & 3;
     const int nl = J.TW >> 4;              // lanes that store
     const int gx = J.TW * sx - J.ax - co + 16 * lane; // the lane's first input column
@@ -1363,12 +1396,15 @@ __device__ __forceinline__ void rows_body(const TileJob &J, int unit, uint32_t *
                                      gx + 4 * q);
     };
     const Ld L0 = mk(0), L1 = mk(1), L2 = mk(2), L3 = mk(3);
+    // uint16 lanes whose quads reach outside the image pick their pixels per row
+    const bool edge = gx - 16 * lane < 0 || gx - 16 * lane + 1024 > J.W;
     int L = 1;
     while (2 * L <= J.wx) L *= 2;
     const uint32_t k1 = (uint32_t)(co + J.wx - L); // byte offset of the second operand
     const int xo = J.TW * sx + 16 * lane;          // the lane's first output column
     const bool store_lane = lane < nl && xo < J.W;
     const bool fast_store = ((uintptr_t)J.dst & 3) == 0 && (J.dpitch & 3) == 0 && xo + 16 <= J.W;
+    constexpr int ES = (int)sizeof(T);
     using Raw = typename Ld::Raw;
     auto issue = [&](Raw (&r)[RG][4], int y) {
 #pragma unroll
@@ -1393,26 +1429,47 @@ __device__ __forceinline__ void rows_body(const TileJob &J, int unit, uint32_t *
             L1.widen(cur[m][1], e[m][2], e[m][3]);
             L2.widen(cur[m][2], e[m][4], e[m][5]);
             L3.widen(cur[m][3], e[m][6], e[m][7]);
+            if constexpr (AL && sizeof(T) == 2) {
+                if (edge) {
+                    L0.fix(e[m][0], e[m][1]);
+                    L1.fix(e[m][2], e[m][3]);
+                    L2.fix(e[m][4], e[m][5]);
+                    L3.fix(e[m][6], e[m][7]);
+                }
+            }
         }
-        doubling16<MAXOP>(J.wx, e); // every lane takes part in the lane moves
+        doubling16<MAXOP, RG>(J.wx, e); // every lane takes part in the lane moves
 #pragma unroll
         for (int m = 0; m < RG; m++) {
-            uint4 o;
-            final16<MAXOP>(e[m], lds + m * kRowsLdsDwords, (uint32_t)co, k1, o);
+            // the lane's 16 output pixels: four dwords of bytes (uint8) or eight
+            // pair dwords (uint16)
+            uint32_t o[4 * ES];
+            if constexpr (sizeof(T) == 1) {
+                uint4 q;
+                final16<MAXOP>(e[m], lds + m * LD, (uint32_t)co, k1, q);
+                o[0] = q.x;
+                o[1] = q.y;
+                o[2] = q.z;
+                o[3] = q.w;
+            } else {
+                final16_u16<MAXOP>(e[m], lds + m * LD, (uint32_t)co, k1, o);
+            }
             if (store_lane && y + m < y1) {
                 uint8_t *drow = J.dst + (int64_t)(y + m) * J.dpitch;
                 if (fast_store) {
-                    const uintptr_t a = (uintptr_t)(drow + xo);
-                    store_u32(a, o.x);
-                    store_u32(a + 4, o.y);
-                    store_u32(a + 8, o.z);
-                    store_u32(a + 12, o.w);
-                } else {
-                    const uint32_t d[4] = {o.x, o.y, o.z, o.w};
+                    const uintptr_t a = (uintptr_t)(drow + ES * xo);
+#pragma unroll
+                    for (int j = 0; j < 4 * ES; j++) store_u32(a + 4 * j, o[j]);
+                } else if constexpr (sizeof(T) == 1) {
 #pragma unroll
                     for (int j = 0; j < 16; j++)
                         if (xo + j < J.W)
-                            store_u8((uintptr_t)(drow + xo + j), (uint8_t)(d[j >> 2] >> (8 * (j & 3))));
+                            store_u8((uintptr_t)(drow + xo + j), (uint8_t)(o[j >> 2] >> (8 * (j & 3))));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (xo + 4 * q < J.W)
+                            Px<T>::store(drow, xo + 4 * q, J.W, o[2 * q], o[2 * q + 1]);
                 }
             }
         }
@@ -1897,22 +1954,26 @@ static TileKernelFn pick_stream_kernel(const TileJob &j)
     return stream_two_level(j.wy) ? pick_stream_kernel_v<true>(j) : pick_stream_kernel_v<false>(j);
 }
 
-template <bool MAXOP, bool AL>
+template <typename T, bool MAXOP, bool AL>
 __global__ __launch_bounds__(NT) void rows_kernel(TileJob J)
 {
     const int units = J.tiles_x * J.tiles_y;
     const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
                                                  (int)(threadIdx.x >> 6));
     if (u >= units) return; // the whole wave leaves
-    __shared__ __align__(16) uint32_t lds[4 * RG * kRowsLdsDwords];
-    rows_body<MAXOP, AL>(J, u, lds + (threadIdx.x >> 6) * RG * kRowsLdsDwords);
+    __shared__ __align__(16) uint32_t lds[4 * kRowsWaveLdsDwords];
+    rows_body<T, MAXOP, AL>(J, u, lds + (threadIdx.x >> 6) * kRowsWaveLdsDwords);
 }
 
 static TileKernelFn pick_rows_kernel(const TileJob &j)
 {
     const bool al = rows_aligned(j);
-    if (j.op) return al ? rows_kernel<true, true> : rows_kernel<true, false>;
-    return al ? rows_kernel<false, true> : rows_kernel<false, false>;
+    if (j.dtype == 0) {
+        if (j.op) return al ? rows_kernel<uint8_t, true, true> : rows_kernel<uint8_t, true, false>;
+        return al ? rows_kernel<uint8_t, false, true> : rows_kernel<uint8_t, false, false>;
+    }
+    if (j.op) return al ? rows_kernel<uint16_t, true, true> : rows_kernel<uint16_t, true, false>;
+    return al ? rows_kernel<uint16_t, false, true> : rows_kernel<uint16_t, false, false>;
 }
 
 static hipError_t set_lds_limit(const void *fn, int lds)
@@ -2007,7 +2068,7 @@ __global__ __launch_bounds__(NT) void batch_wave_kernel(BatchTables bt)
 }
 
 // The batch form of the wide-row kernel: one wave per unit, four per workgroup.
-template <bool AL>
+template <typename T, bool AL>
 __global__ __launch_bounds__(NT) void batch_rows_kernel(BatchTables bt)
 {
     const int t = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
@@ -2016,10 +2077,10 @@ __global__ __launch_bounds__(NT) void batch_rows_kernel(BatchTables bt)
     const int jb = bt.tile_job[t];
     const TileJob J = bt.jobs[jb];
     const int u = (int)(t - bt.tile_start[jb]);
-    __shared__ __align__(16) uint32_t lds[4 * RG * kRowsLdsDwords];
-    uint32_t *wl = lds + (threadIdx.x >> 6) * RG * kRowsLdsDwords;
-    if (J.op) rows_body<true, AL>(J, u, wl);
-    else rows_body<false, AL>(J, u, wl);
+    __shared__ __align__(16) uint32_t lds[4 * kRowsWaveLdsDwords];
+    uint32_t *wl = lds + (threadIdx.x >> 6) * kRowsWaveLdsDwords;
+    if (J.op) rows_body<T, true, AL>(J, u, wl);
+    else rows_body<T, false, AL>(J, u, wl);
 }
 
 // The batch form of the stream kernel: one single-wave workgroup per unit.
@@ -2084,7 +2145,8 @@ hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, 
     BatchFn fn;
     int block = NT;
     if (kind == KIND_ROWS)
-        fn = aligned ? batch_rows_kernel<true> : batch_rows_kernel<false>;
+        fn = dtype == 0 ? (aligned ? batch_rows_kernel<uint8_t, true> : batch_rows_kernel<uint8_t, false>)
+                        : (aligned ? batch_rows_kernel<uint16_t, true> : batch_rows_kernel<uint16_t, false>);
     else if (kind == KIND_WAVE)
         fn = dtype == 0 ? (aligned ? batch_wave_kernel<uint8_t, true> : batch_wave_kernel<uint8_t, false>)
                         : (aligned ? batch_wave_kernel<uint16_t, true> : batch_wave_kernel<uint16_t, false>);

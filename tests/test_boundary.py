@@ -134,8 +134,8 @@ def test_plan_resolution_and_thresholds(tmp_path):
             ("doubling", "rows", 16 * 47, 4)
         assert morph.resolve_plan("u8", 4096, 4096, 1000, 1)["tile_w"] == 16
         assert morph.resolve_plan("u8", 4096, 4096, 129, 1, method_x="doubling")["kernel"] == "rows"
-        for kw in (dict(dtype_name="u16"), dict(wx=1001), dict(wy=2), dict(method_x="vhgw"),
-                   dict(tile=(256, 16))):
+        assert morph.resolve_plan("u16", 4096, 4096, 255, 1)["kernel"] == "rows"
+        for kw in (dict(wx=1001), dict(wy=2), dict(method_x="vhgw"), dict(tile=(256, 16))):
             a = dict(dtype_name="u8", H=4096, W=4096, wx=255, wy=1)
             a.update(kw)
             assert morph.resolve_plan(**a)["kernel"] == "tile", kw

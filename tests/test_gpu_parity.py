@@ -176,26 +176,29 @@ def test_wide_short_windows_on_the_wave_kernel(dtype):
         assert np.array_equal(to_host(out), _ref(img, "dilate", 45, 7))
 
 
-@pytest.mark.parametrize("rows", [1, 3, 16, 64])
-def test_wide_row_kernel(rows, tmp_path):
-    """uint8 rows with a vertical window of 1 and a horizontal window of 129 .. 1000
-    run the wide-row kernel (16 pixels a lane, doubling across lanes): windows on
-    both sides of every power of two up to 512 and the largest, any anchor, images
-    narrower than a strip and several strips wide with a ragged right edge, units of
-    `rows` rows (shorter and longer than a load group of 4), aligned and unaligned
-    rows."""
+@pytest.mark.parametrize("dtype,rows", [(np.uint8, 1), (np.uint8, 3), (np.uint8, 16),
+                                        (np.uint8, 64), (np.uint16, 1), (np.uint16, 5),
+                                        (np.uint16, 16)])
+def test_wide_row_kernel(dtype, rows, tmp_path):
+    """Rows with a vertical window of 1 and a horizontal window of 129 .. 1000 run the
+    wide-row kernel (16 pixels a lane, doubling across lanes): windows on both sides
+    of every power of two up to 512 and the largest, any anchor, images narrower than
+    a strip and several strips wide with a ragged right edge, units of `rows` rows
+    (shorter and longer than a row group: 4 for uint8, 2 for uint16), aligned and
+    unaligned rows."""
     import json
+    dn = "u8" if dtype == np.uint8 else "u16"
     f = tmp_path / "t.json"
-    f.write_text(json.dumps({"u8": {"wide_rows": rows}}))
+    f.write_text(json.dumps({dn: {"wide_rows": rows}}))
     morph.load_tuning(str(f))
     try:
         rng = np.random.default_rng(500 + rows)
         for i, (H, W) in enumerate([(1, 130), (3, 1023), (37, 1500), (9, 4097), (6, 200)]):
-            img = synth.uniform(H, W, np.uint8, seed=1400 + i)
+            img = synth.uniform(H, W, dtype, seed=1400 + i)
             for wx in (129, 130, 200, 255, 256, 257, 383, 511, 512, 777, 1000):
                 ax = int(rng.integers(-1, wx))
                 if W >= wx:  # (a window clipped to a narrow image may take another kernel)
-                    assert morph.resolve_plan("u8", H, W, wx, 1)["kernel"] == "rows"
+                    assert morph.resolve_plan(dn, H, W, wx, 1)["kernel"] == "rows"
                 for op in ("erode", "dilate"):
                     _check(img, op, wx, 1, ax, -1)
             pitch = W + 3
