@@ -14,7 +14,8 @@ first column is ``x - ax`` and first row ``y - ay``.  ``ax = -1`` (the default)
 means the Eq. (1) placement ``ax = wx - 1 - wx // 2`` (likewise for y).  Pixels
 outside the image count as the identity of the operation (the type's largest
 value for erosion, 0 for dilation).  Opening is dilation after erosion and
-closing erosion after dilation, with the same rectangle (§2).
+closing erosion after dilation, with the same rectangle (§2); the morphological
+gradient is dilation minus erosion, again with the same rectangle.
 """
 from __future__ import annotations
 
@@ -150,7 +151,18 @@ def closing(img, wx, wy, ax=-1, ay=-1, **kw):
     return erode(dilate(img, wx, wy, ax, ay, **kw), wx, wy, ax, ay, **kw)
 
 
-OPS = {"erode": erode, "dilate": dilate, "open": opening, "close": closing}
+def gradient(img, wx, wy, ax=-1, ay=-1, **kw):
+    """Morphological gradient: dilation minus erosion with the same rectangle and
+    anchor, one of the arithmetic combinations of erosion and dilation §2 names.
+    Never negative (a window's maximum is at least its minimum), so it keeps the
+    input's type."""
+    d = dilate(img, wx, wy, ax, ay, **kw).astype(np.int64)
+    e = erode(img, wx, wy, ax, ay, **kw).astype(np.int64)
+    return (d - e).astype(img.dtype)
+
+
+OPS = {"erode": erode, "dilate": dilate, "open": opening, "close": closing,
+       "gradient": gradient}
 
 
 def apply(op_name: str, img, wx, wy, ax=-1, ay=-1, **kw):

@@ -244,6 +244,51 @@ def test_open_close_properties():
         assert np.array_equal(oracle.closing(c, w, w, method="direct"), c)
 
 
+def _gradient_by_hand(img, wx, wy, ax, ay):
+    """max - min over the window clipped to the image, pixel by pixel (pure Python;
+    the definition of the gradient written out, not the oracle's code)."""
+    H, W = img.shape
+    out = np.zeros_like(img)
+    for y in range(H):
+        for x in range(W):
+            vals = [int(img[yy, xx])
+                    for yy in range(max(0, y - ay), min(H, y - ay + wy))
+                    for xx in range(max(0, x - ax), min(W, x - ax + wx))]
+            out[y, x] = max(vals) - min(vals)
+    return out
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_gradient_pins(dtype):
+    """The morphological gradient (dilation minus erosion, §2) against its
+    definition by brute force on tiny images for every anchor, a step edge in closed
+    form, and its invariants: zero on a constant image and for a 1x1 window,
+    unchanged by taking the complement."""
+    rng = np.random.default_rng(41)
+    maxv = np.iinfo(dtype).max
+    for H, W in ((1, 1), (3, 5), (6, 4)):
+        img = rng.integers(0, maxv + 1, size=(H, W)).astype(dtype)
+        for wx, wy in ((1, 1), (2, 3), (3, 2), (5, 4)):
+            for ax, ay in itertools.product(range(wx), range(wy)):
+                want = _gradient_by_hand(img, wx, wy, ax, ay)
+                for m in ("direct", "vhgw"):
+                    assert np.array_equal(oracle.gradient(img, wx, wy, ax, ay, method=m), want)
+    # step edge: 0 left of column 10, v from it on; a w x 1 window straddles the edge
+    # exactly at columns 10 - (w - 1 - a) .. 9 + a
+    v = 200 if dtype == np.uint8 else 50000
+    img = np.zeros((3, 24), dtype)
+    img[:, 10:] = v
+    for w, a in ((5, 2), (4, 0), (7, 6)):
+        want = np.zeros_like(img)
+        want[:, 10 - (w - 1 - a):10 + a] = v
+        assert np.array_equal(oracle.gradient(img, w, 1, a, 0), want), (w, a)
+    img = synth.uniform(20, 30, dtype, seed=7)
+    assert not oracle.gradient(img, 1, 1).any()
+    assert not oracle.gradient(np.full((9, 11), 77, dtype), 5, 3).any()
+    g = oracle.gradient(img, 7, 3, method="vhgw")
+    assert np.array_equal(oracle.gradient((maxv - img).astype(dtype), 7, 3), g)
+
+
 def test_u8_u16_consistency_scaled_by_257():
     img = synth.uniform(19, 23, np.uint8, seed=14)
     img16 = img.astype(np.uint16) * 257
