@@ -170,6 +170,35 @@ def c3_lines(torch, morph, dev, steps):
     return out
 
 
+def gradient_lines(torch, morph, dev, steps):
+    """4096x4096 morphological gradients (dilation - erosion), uint8 and uint16: one
+    pass at 3x3 and 9x9 (both extrema from one read), composed at 15x15 (dilation,
+    erosion to a workspace, subtraction); GB/s over the gradient's own 2 sizeof(T)
+    bytes a pixel, 10 launches over 10 buffer sets in one graph."""
+    out = []
+    stream = torch.cuda.current_stream()
+    for dt, es in (("u8", 1), ("u16", 2)):
+        nbuf = 10
+        g = torch.Generator(device=dev).manual_seed(5 if dt == "u8" else 6)
+        srcs = [torch.randint(0, 256 if dt == "u8" else 65536, (4096, 4096), generator=g,
+                              dtype=torch.int32, device=dev).to(torch.uint8 if dt == "u8"
+                                                                else torch.int16)
+                for _ in range(nbuf)]
+        if dt == "u16":
+            srcs = [s.view(torch.uint16) for s in srcs]
+        dsts = [torch.empty_like(s) for s in srcs]
+        wss = [torch.empty(4096 * 4096 * es, dtype=torch.uint8, device=dev) for _ in srcs]
+        for w, form in ((3, "one pass"), (9, "one pass"), (15, "composed")):
+            fns = [(lambda i=i: morph.gradient(srcs[i], w, w, out=dsts[i], workspace=wss[i]))
+                   for i in range(nbuf)]
+            us = graph_time(torch, fns, max(5, steps // 2), stream) * 1e3
+            gbs = 2 * es * 4096 * 4096 / (us * 1e-6) / 1e9
+            out.append(dict(dtype=dt, w="%dx%d" % (w, w), form=form, us=round(us, 2),
+                            gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4)))
+        del srcs, dsts, wss
+    return out
+
+
 def _effective(w, extent):
     """A window clipped to the image (default anchor), as the library plans it."""
     a = w - 1 - w // 2
@@ -339,6 +368,8 @@ def main():
         }
         _log("4096x4096 kernels")
         res["c3_4096"] = c3_lines(torch, morph, dev, max(10, args.steps))
+        _log("4096x4096 gradients")
+        res["gradient_4096"] = gradient_lines(torch, morph, dev, max(10, args.steps))
 
     if not args.no_cpu_baseline:
         _log("CPU oracle baseline")

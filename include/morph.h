@@ -64,6 +64,7 @@ extern "C" {
 #define MORPH_OP_DILATE 1
 #define MORPH_OP_OPEN 2  /* dilate(erode(src)), same rectangle and anchor (§2) */
 #define MORPH_OP_CLOSE 3 /* erode(dilate(src)), same rectangle and anchor (§2) */
+#define MORPH_OP_GRADIENT 4 /* dilate(src) - erode(src), same rectangle and anchor (§2) */
 
 /* element types */
 #define MORPH_U8 0
@@ -141,9 +142,26 @@ int morph_close_u16(const void *src, void *dst, int H, int W, size_t pitch, int 
                     int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
                     hipStream_t stream);
 
+/* Morphological gradient (§2 names the arithmetic combinations of erosion and
+ * dilation): dst = dilation - erosion with the same rectangle and anchor, never
+ * negative.  Where the wave kernel takes the job (vertical window <= 9, horizontal
+ * <= 128, automatic or direct methods) and the rows are aligned (pitch a multiple
+ * of 4 bytes for uint8, 8 for uint16), one pass computes both extrema from a single
+ * read and workspace may be NULL; otherwise dilation goes to dst, erosion to
+ * `workspace` (at least morph_workspace_bytes(), else MORPH_ENOMEM; it must not
+ * overlap src or dst, MORPH_EALIAS) and a third launch subtracts. */
+int morph_gradient(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                   int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                   hipStream_t stream);
+int morph_gradient_u16(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                       int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* General entry: any op (MORPH_OP_*) and dtype (MORPH_U8 / MORPH_U16) with an
  * optional plan (NULL = tuned defaults).  workspace is needed only for OPEN and
- * CLOSE.  The named entry points above are this call with plan = NULL. */
+ * CLOSE, and for GRADIENT where its one-pass form does not apply (see
+ * morph_gradient).  The named entry points above are this call with plan = NULL.
+ * Batch descriptors take ERODE and DILATE only. */
 int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
                 int wx, int wy, int anchor_x, int anchor_y, int border,
                 const morph_plan *plan, void *workspace, size_t ws_bytes, hipStream_t stream);

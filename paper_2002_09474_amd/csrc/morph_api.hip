@@ -438,11 +438,41 @@ int run_single(int op, int dtype, const void *src, void *dst, int H, int W, size
 // ---------------- C ABI ----------------
 extern "C" {
 
+// Morphological gradient: both extrema from one read where the wave kernel runs the
+// job on aligned rows, else dilation into dst, erosion into the workspace and dst
+// minus the workspace.
+static int run_gradient(int dtype, const void *src, void *dst, int H, int W, size_t pitch,
+                        int wx, int wy, int ax, int ay, const morph_plan *plan, void *workspace,
+                        size_t ws_bytes, hipStream_t stream)
+{
+    TileJob j;
+    int rc = plan_job(MORPH_OP_ERODE, dtype, src, dst, H, W, pitch, pitch, wx, wy, ax, ay, plan, j);
+    if (rc != MORPH_OK) return rc;
+    hipError_t e;
+    if (j.kind == KIND_WAVE && job_rows_aligned(j)) {
+        if ((e = launch_gradient_job(j, stream)) != hipSuccess) return hip_fail(e);
+        return MORPH_OK;
+    }
+    const size_t span = image_span(H, W, pitch, dtype);
+    if (!workspace || ws_bytes < morph_workspace_bytes(H, W, pitch, (int)elem_bytes(dtype)))
+        return MORPH_ENOMEM;
+    if (ranges_overlap(workspace, span, src, span) || ranges_overlap(workspace, span, dst, span))
+        return MORPH_EALIAS;
+    rc = run_single(MORPH_OP_DILATE, dtype, src, dst, H, W, pitch, wx, wy, ax, ay, plan, stream);
+    if (rc != MORPH_OK) return rc;
+    rc = run_single(MORPH_OP_ERODE, dtype, src, workspace, H, W, pitch, wx, wy, ax, ay, plan,
+                    stream);
+    if (rc != MORPH_OK) return rc;
+    if ((e = launch_subtract(workspace, dst, H, W, pitch, dtype, stream)) != hipSuccess)
+        return hip_fail(e);
+    return MORPH_OK;
+}
+
 int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
                 int wx, int wy, int anchor_x, int anchor_y, int border, const morph_plan *plan,
                 void *workspace, size_t ws_bytes, hipStream_t stream)
 {
-    if (op < MORPH_OP_ERODE || op > MORPH_OP_CLOSE) return MORPH_EINVAL;
+    if (op < MORPH_OP_ERODE || op > MORPH_OP_GRADIENT) return MORPH_EINVAL;
     int rc = check_image(dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, border);
     if (rc != MORPH_OK || H == 0 || W == 0) return rc;
     const size_t span = image_span(H, W, pitch, dtype);
@@ -450,6 +480,9 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
     if (op == MORPH_OP_ERODE || op == MORPH_OP_DILATE)
         return run_single(op, dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
                           stream);
+    if (op == MORPH_OP_GRADIENT)
+        return run_gradient(dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
+                            workspace, ws_bytes, stream);
     // opening = dilate(erode(src)), closing = erode(dilate(src)) (§2)
     if (!workspace || ws_bytes < morph_workspace_bytes(H, W, pitch, (int)elem_bytes(dtype)))
         return MORPH_ENOMEM;
@@ -487,6 +520,8 @@ MORPH_COMPOSED(morph_open, MORPH_OP_OPEN, MORPH_U8)
 MORPH_COMPOSED(morph_close, MORPH_OP_CLOSE, MORPH_U8)
 MORPH_COMPOSED(morph_open_u16, MORPH_OP_OPEN, MORPH_U16)
 MORPH_COMPOSED(morph_close_u16, MORPH_OP_CLOSE, MORPH_U16)
+MORPH_COMPOSED(morph_gradient, MORPH_OP_GRADIENT, MORPH_U8)
+MORPH_COMPOSED(morph_gradient_u16, MORPH_OP_GRADIENT, MORPH_U16)
 #undef MORPH_COMPOSED
 
 size_t morph_workspace_bytes(int H, int W, size_t pitch, int elem_bytes_)

@@ -1234,6 +1234,125 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
     while (chunk(ra, rb) && chunk(rb, ra)) {
     }
 }
+
+// ======================= morphological gradient: both extrema from one read ========
+// Dilation minus erosion with the same rectangle (one of §2's combinations of the
+// two), on the wave kernel's path: a direct vertical window and rows of aligned
+// pitch, whose loads clamp to the image, so that one loaded row serves the minimum
+// and the maximum alike (with the identity border the two would need different
+// fill values).  The vertical and horizontal passes run twice on the same
+// registers, once per extremum, and the difference is stored: 2 sizeof(T) bytes a
+// pixel instead of the 6 of erosion, dilation and a subtraction through memory.
+template <int WY, typename Ld>
+__device__ __forceinline__ void wv_vertical2(const Ld &L, const typename Ld::Raw *cur,
+                                             uint32_t *r01, uint32_t *r23, uint32_t *lo01,
+                                             uint32_t *lo23, uint32_t *hi01, uint32_t *hi23)
+{
+#pragma unroll
+    for (int m = 0; m < KR; m++) L.widen(cur[m], r01[WY - 1 + m], r23[WY - 1 + m]);
+#pragma unroll
+    for (int m = 0; m < KR; m += 2) {
+        pair_window<WY, false>(r01 + m, lo01[m], lo01[m + 1]);
+        pair_window<WY, false>(r23 + m, lo23[m], lo23[m + 1]);
+        pair_window<WY, true>(r01 + m, hi01[m], hi01[m + 1]);
+        pair_window<WY, true>(r23 + m, hi23[m], hi23[m + 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < WY - 1; k++) {
+        r01[k] = r01[k + KR];
+        r23[k] = r23[k + KR];
+    }
+}
+
+// a - b in each 16-bit half (b <= a in both)
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b)
+{
+    const u16x2 x = __builtin_bit_cast(u16x2, a), y = __builtin_bit_cast(u16x2, b);
+    return __builtin_bit_cast(uint32_t, (u16x2)(x - y));
+}
+
+template <typename T>
+__device__ __forceinline__ void grad_body(const TileJob &J, int unit)
+{
+    const int lane = threadIdx.x & 63;
+    const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
+    const int mis = (int)(((uintptr_t)J.src & (4 * sizeof(T) - 1)) / sizeof(T));
+    const int co = (mis - J.ax) & 3;
+    const int wq = J.TW >> 2; // output quads per strip
+    const int gxa = 4 * wq * sx - J.ax - co; // lane 0's first input column
+    const int gx = gxa + 4 * lane;
+    const int y0 = sy * J.TB;
+    const int y1 = min(y0 + J.TB, J.H);
+    const bool edge = gxa < 0 || gxa + 4 * 64 > J.W;
+    using Ld = WaveLoader<T>;
+    const Ld L(J, mis, gx);
+    uint32_t r01[RING], r23[RING];
+    using Raw = typename Ld::Raw;
+    Raw ra[KR], rb[KR];
+#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, r01, r23, ra)
+    MORPH_WY_SWITCH(J.wy, MORPH_FIRST)
+#undef MORPH_FIRST
+    const int Q = wq * sx + lane;
+    const bool fast_store = (((uintptr_t)J.dst | (uintptr_t)J.dpitch) & 3) == 0 &&
+                            4 * (wq * sx + wq) <= J.W;
+    const bool doubling = J.hm == PASS_DOUBLING;
+    const Doubling S(J.wx, co);
+    int y = y0;
+    auto chunk = [&](Raw (&cur)[KR], Raw (&nxt)[KR]) __attribute__((always_inline)) -> bool {
+        uint32_t lo01[KR], lo23[KR], hi01[KR], hi23[KR];
+        const bool more = y + KR < y1;
+        if (more) {
+            const int gn = y + KR - J.ay + J.wy - 1;
+#pragma unroll
+            for (int m = 0; m < KR; m++) nxt[m] = L.issue(gn + m);
+        }
+#define MORPH_VERT2(W) wv_vertical2<W>(L, cur, r01, r23, lo01, lo23, hi01, hi23)
+        MORPH_WY_SWITCH(J.wy, MORPH_VERT2)
+#undef MORPH_VERT2
+        if constexpr (sizeof(T) == 2) {
+            if (edge) {
+#pragma unroll
+                for (int m = 0; m < KR; m++) {
+                    L.fix(lo01[m], lo23[m]);
+                    L.fix(hi01[m], hi23[m]);
+                }
+            }
+        }
+        // every lane takes part in the shifts
+        if (doubling) {
+            doubling_rows<KR, false>(S, lo01, lo23);
+            doubling_rows<KR, true>(S, hi01, hi23);
+        } else {
+            wv_horizontal_any<false>(J.wx, co, lo01, lo23);
+            wv_horizontal_any<true>(J.wx, co, hi01, hi23);
+        }
+        if (lane < wq) {
+            uint8_t *drow = J.dst + (int64_t)y * J.dpitch;
+#pragma unroll
+            for (int m = 0; m < KR; m++) {
+                const uint32_t v01 = pk_sub(hi01[m], lo01[m]), v23 = pk_sub(hi23[m], lo23[m]);
+                if (y + m < y1) {
+                    if (fast_store) {
+                        const uintptr_t o = (uintptr_t)(drow + (uint32_t)Q * 4u * (uint32_t)sizeof(T));
+                        if constexpr (sizeof(T) == 1) {
+                            store_u32(o, perm(v23, v01, SEL_NARROW));
+                        } else {
+                            store_u32(o, v01);
+                            store_u32(o + 4, v23);
+                        }
+                    } else {
+                        Px<T>::store(drow, 4 * Q, J.W, v01, v23);
+                    }
+                }
+                drow += J.dpitch;
+            }
+        }
+        y += KR;
+        return more;
+    };
+    while (chunk(ra, rb) && chunk(rb, ra)) {
+    }
+}
 #undef MORPH_WY_SWITCH
 
 // ======================= wide rows: vertical window 1, 16 pixels per lane ===========
@@ -1976,10 +2095,53 @@ static TileKernelFn pick_rows_kernel(const TileJob &j)
     return al ? rows_kernel<uint16_t, false, true> : rows_kernel<uint16_t, false, false>;
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT) void grad_kernel(TileJob J)
+{
+    const int units = J.tiles_x * J.tiles_y;
+    const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
+                                                 (int)(threadIdx.x >> 6));
+    if (u >= units) return; // the whole wave leaves
+    grad_body<T>(J, u);
+}
+
+// dst -= lo, pixel by pixel (the gradient composed from two separate passes):
+// block b covers 256 pixels of row b / nseg
+template <typename T>
+__global__ __launch_bounds__(256) void sub_kernel(const uint8_t *lo, uint8_t *dst, int W,
+                                                  int64_t pitch, int nseg)
+{
+    const int y = blockIdx.x / nseg;
+    const int x = (blockIdx.x - y * nseg) * 256 + (int)threadIdx.x;
+    if (x >= W) return;
+    const T a = *((const GLOBAL T *)(lo + (int64_t)y * pitch) + x);
+    GLOBAL T *d = (GLOBAL T *)(dst + (int64_t)y * pitch) + x;
+    *d = (T)(*d - a);
+}
+
 static hipError_t set_lds_limit(const void *fn, int lds)
 {
     if (lds <= 64 * 1024) return hipSuccess;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+hipError_t launch_gradient_job(const TileJob &job, hipStream_t stream)
+{
+    const int units = job.tiles_x * job.tiles_y;
+    hipLaunchKernelGGL(job.dtype == 0 ? grad_kernel<uint8_t> : grad_kernel<uint16_t>,
+                       dim3((units + 3) / 4), dim3(NT), 0, stream, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_subtract(const void *lo, void *dst, int H, int W, size_t pitch, int dtype,
+                           hipStream_t stream)
+{
+    const int nseg = (W + 255) / 256;
+    if ((int64_t)nseg * H > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(dtype == 0 ? sub_kernel<uint8_t> : sub_kernel<uint16_t>,
+                       dim3(nseg * H), dim3(256), 0, stream, (const uint8_t *)lo,
+                       (uint8_t *)dst, W, (int64_t)pitch, nseg);
+    return hipGetLastError();
 }
 
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)

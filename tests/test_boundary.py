@@ -76,6 +76,16 @@ def test_open_close_workspace_checks():
                         None) == E.MORPH_EALIAS
     assert L.morph_close_u16(FAKE_SRC, FAKE_DST, 8, 8, 16, 3, 3, -1, -1, 0, FAKE_DST - 16, 128,
                              None) == E.MORPH_EALIAS
+    # the gradient needs the workspace where its one-pass form does not apply: a
+    # vertical window over 9 (the streaming kernel) or rows of unaligned pitch
+    assert L.morph_gradient(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 15, -1, -1, 0, None, 0,
+                            None) == E.MORPH_ENOMEM
+    assert L.morph_gradient(FAKE_SRC, FAKE_DST, 8, 7, 7, 3, 3, -1, -1, 0, ws, 55,
+                            None) == E.MORPH_ENOMEM
+    assert L.morph_gradient_u16(FAKE_SRC, FAKE_DST, 8, 8, 16, 31, 31, -1, -1, 0, FAKE_SRC + 8,
+                                128, None) == E.MORPH_EALIAS
+    assert L.morph_apply(5, 0, FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, None, 0,
+                         None) == E.MORPH_EINVAL
 
 
 def test_forced_direct_beyond_its_range_is_unsupported():

@@ -250,6 +250,48 @@ def test_streaming_units_of_any_height(rows, tmp_path):
 
 
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_gradient(dtype):
+    """Morphological gradient against the oracle: the one-pass form (wave kernel,
+    aligned rows: every direct window pair, doubling horizontal windows, any anchor,
+    ragged strips) and the composed form (unaligned rows, vertical windows over 9,
+    wide rows, forced vHGW), on images from one pixel to several strips; bytes
+    outside the image untouched."""
+    rng = np.random.default_rng(88)
+    dn = "u8" if dtype == np.uint8 else "u16"
+    wins = [(1, 1), (3, 3), (2, 5), (9, 9), (5, 1), (1, 7), (4, 8), (31, 3), (128, 9),
+            (15, 15), (63, 63), (300, 1), (1, 255)]
+    for i, (H, W) in enumerate([(1, 1), (5, 7), (37, 300), (130, 517)]):
+        img = synth.uniform(H, W, dtype, seed=1500 + i)
+        for wx, wy in wins:
+            ax = int(rng.integers(-1, wx))
+            ay = int(rng.integers(-1, wy))
+            want = oracle.gradient(img, wx, wy, ax, ay)
+            for pitch, off in ((W + (-W) % 4, 0), (W + 3, 1)):
+                d, _ = to_dev(img, pitch_elems=pitch, offset_elems=off)
+                out, obuf = empty_like_dev(d)
+                morph.gradient(d, wx, wy, ax, ay, out=out)
+                torch.cuda.synchronize()
+                got = to_host(out)
+                if not np.array_equal(got, want):
+                    bad = np.argwhere(got != want)
+                    raise AssertionError("gradient %dx%d a=(%d,%d) %s pitch %d off %d: %d bad, "
+                                         "first at %s" % (wx, wy, ax, ay, img.shape, pitch, off,
+                                                          len(bad), bad[0]))
+                # the padding between rows is untouched
+                full = to_host(obuf)
+                rows = full[off:off + H * pitch].reshape(H, pitch)
+                assert (rows[:, W:] == (0x5a if dtype == np.uint8 else 0x5a5a)).all()
+            if wy <= 9 and wx <= 128:  # the one-pass form on the aligned rows
+                assert morph.resolve_plan(dn, H, W, wx, wy)["kernel"] == "wave"
+    # forced vHGW: the composed form through the tile kernel
+    img = synth.uniform(40, 90, dtype, seed=1600)
+    d, _ = to_dev(img, pitch_elems=92)
+    out = morph.gradient(d, 7, 5, method_x="vhgw", method_y="vhgw")
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out), oracle.gradient(img, 7, 5))
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 def test_pitch_offset_and_guard_bytes(dtype):
     """Strided rows, a base pointer off by one element, and sentinel bytes around
     the image and in the pitch gap that must stay untouched."""
