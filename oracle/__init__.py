@@ -15,7 +15,8 @@ means the Eq. (1) placement ``ax = wx - 1 - wx // 2`` (likewise for y).  Pixels
 outside the image count as the identity of the operation (the type's largest
 value for erosion, 0 for dilation).  Opening is dilation after erosion and
 closing erosion after dilation, with the same rectangle (§2); the morphological
-gradient is dilation minus erosion, again with the same rectangle.
+gradient is dilation minus erosion, again with the same rectangle; the top-hat is
+the image minus its opening and the black-hat the closing minus the image.
 """
 from __future__ import annotations
 
@@ -161,8 +162,21 @@ def gradient(img, wx, wy, ax=-1, ay=-1, **kw):
     return (d - e).astype(img.dtype)
 
 
+def tophat(img, wx, wy, ax=-1, ay=-1, **kw):
+    """White top-hat: the image minus its opening (§2's combinations of erosion and
+    dilation); never negative, since an opening never exceeds the image."""
+    o = opening(img, wx, wy, ax, ay, **kw).astype(np.int64)
+    return (img.astype(np.int64) - o).astype(img.dtype)
+
+
+def blackhat(img, wx, wy, ax=-1, ay=-1, **kw):
+    """Black top-hat: the closing minus the image; never negative."""
+    c = closing(img, wx, wy, ax, ay, **kw).astype(np.int64)
+    return (c - img.astype(np.int64)).astype(img.dtype)
+
+
 OPS = {"erode": erode, "dilate": dilate, "open": opening, "close": closing,
-       "gradient": gradient}
+       "gradient": gradient, "tophat": tophat, "blackhat": blackhat}
 
 
 def apply(op_name: str, img, wx, wy, ax=-1, ay=-1, **kw):

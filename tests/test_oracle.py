@@ -289,6 +289,59 @@ def test_gradient_pins(dtype):
     assert np.array_equal(oracle.gradient((maxv - img).astype(dtype), 7, 3), g)
 
 
+def _extremum_by_hand(img, wx, wy, ax, ay, use_max):
+    """Erosion (min) or dilation (max) over the clipped window, by pure Python loops."""
+    H, W = img.shape
+    out = np.zeros_like(img)
+    f = max if use_max else min
+    for y in range(H):
+        for x in range(W):
+            out[y, x] = f(int(img[yy, xx])
+                          for yy in range(max(0, y - ay), min(H, y - ay + wy))
+                          for xx in range(max(0, x - ax), min(W, x - ax + wx)))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_tophat_blackhat_pins(dtype):
+    """Top-hat (image minus opening) and black-hat (closing minus image) against
+    openings and closings formed by hand on tiny images for every anchor; a lone
+    bright pixel, which an opening removes, is exactly the top-hat, and a lone dark
+    pixel, which a closing fills, exactly the black-hat; both never negative, and
+    each the other's mirror under the complement."""
+    rng = np.random.default_rng(43)
+    maxv = np.iinfo(dtype).max
+    for H, W in ((1, 1), (4, 5), (6, 3)):
+        img = rng.integers(0, maxv + 1, size=(H, W)).astype(dtype)
+        for wx, wy in ((1, 1), (2, 3), (3, 2)):
+            for ax, ay in itertools.product(range(wx), range(wy)):
+                e = _extremum_by_hand(img, wx, wy, ax, ay, False)
+                o = _extremum_by_hand(e, wx, wy, ax, ay, True)
+                d = _extremum_by_hand(img, wx, wy, ax, ay, True)
+                c = _extremum_by_hand(d, wx, wy, ax, ay, False)
+                assert np.array_equal(oracle.tophat(img, wx, wy, ax, ay),
+                                      (img.astype(np.int64) - o).astype(dtype))
+                assert np.array_equal(oracle.blackhat(img, wx, wy, ax, ay),
+                                      (c.astype(np.int64) - img).astype(dtype))
+    v = 180 if dtype == np.uint8 else 40000
+    img = np.full((9, 9), 10, dtype)
+    img[4, 4] = v
+    want = np.zeros_like(img)
+    want[4, 4] = v - 10
+    assert np.array_equal(oracle.tophat(img, 3, 3), want)
+    assert not oracle.blackhat(img, 3, 3).any()  # a closing keeps a lone peak as it is
+    dark = np.full((9, 9), v, dtype)
+    dark[4, 4] = 10
+    want = np.zeros_like(dark)
+    want[4, 4] = v - 10
+    assert np.array_equal(oracle.blackhat(dark, 3, 3), want)
+    img = synth.uniform(25, 31, dtype, seed=9)
+    t = oracle.tophat(img, 5, 3)
+    b = oracle.blackhat(img, 5, 3)
+    assert np.array_equal(oracle.blackhat((maxv - img).astype(dtype), 5, 3), t)
+    assert np.array_equal(oracle.tophat((maxv - img).astype(dtype), 5, 3), b)
+
+
 def test_u8_u16_consistency_scaled_by_257():
     img = synth.uniform(19, 23, np.uint8, seed=14)
     img16 = img.astype(np.uint16) * 257
