@@ -164,15 +164,19 @@ def gradient(img, wx, wy, ax=-1, ay=-1, **kw):
 
 def tophat(img, wx, wy, ax=-1, ay=-1, **kw):
     """White top-hat: the image minus its opening (§2's combinations of erosion and
-    dilation); never negative, since an opening never exceeds the image."""
+    dilation), clamped at 0.  The opening uses the same rectangle and anchor in both
+    passes, so with an even window or an off-centre anchor it can exceed the image
+    (it stays below it only when the anchor is the centre, 2 a = w - 1); there the
+    difference is 0 rather than negative."""
     o = opening(img, wx, wy, ax, ay, **kw).astype(np.int64)
-    return (img.astype(np.int64) - o).astype(img.dtype)
+    return np.maximum(img.astype(np.int64) - o, 0).astype(img.dtype)
 
 
 def blackhat(img, wx, wy, ax=-1, ay=-1, **kw):
-    """Black top-hat: the closing minus the image; never negative."""
+    """Black top-hat: the closing minus the image, clamped at 0 (as for the top-hat,
+    a closing with an off-centre anchor can fall below the image)."""
     c = closing(img, wx, wy, ax, ay, **kw).astype(np.int64)
-    return (c - img.astype(np.int64)).astype(img.dtype)
+    return np.maximum(c - img.astype(np.int64), 0).astype(img.dtype)
 
 
 OPS = {"erode": erode, "dilate": dilate, "open": opening, "close": closing,

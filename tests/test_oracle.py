@@ -304,25 +304,31 @@ def _extremum_by_hand(img, wx, wy, ax, ay, use_max):
 
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 def test_tophat_blackhat_pins(dtype):
-    """Top-hat (image minus opening) and black-hat (closing minus image) against
-    openings and closings formed by hand on tiny images for every anchor; a lone
-    bright pixel, which an opening removes, is exactly the top-hat, and a lone dark
-    pixel, which a closing fills, exactly the black-hat; both never negative, and
-    each the other's mirror under the complement."""
+    """Top-hat (image minus opening) and black-hat (closing minus image), clamped at
+    0, against openings and closings formed by hand on tiny images for every anchor
+    (the differences are never negative for a centred anchor, and can be otherwise);
+    a lone bright pixel, which an opening removes, is exactly the top-hat, and a lone
+    dark pixel, which a closing fills, exactly the black-hat; each the other's mirror
+    under the complement."""
     rng = np.random.default_rng(43)
     maxv = np.iinfo(dtype).max
     for H, W in ((1, 1), (4, 5), (6, 3)):
         img = rng.integers(0, maxv + 1, size=(H, W)).astype(dtype)
-        for wx, wy in ((1, 1), (2, 3), (3, 2)):
+        for wx, wy in ((1, 1), (2, 3), (3, 2), (3, 3)):
             for ax, ay in itertools.product(range(wx), range(wy)):
                 e = _extremum_by_hand(img, wx, wy, ax, ay, False)
                 o = _extremum_by_hand(e, wx, wy, ax, ay, True)
                 d = _extremum_by_hand(img, wx, wy, ax, ay, True)
                 c = _extremum_by_hand(d, wx, wy, ax, ay, False)
+                t = img.astype(np.int64) - o
+                b = c.astype(np.int64) - img
+                # the centred anchor keeps opening <= image <= closing
+                if 2 * ax == wx - 1 and 2 * ay == wy - 1:
+                    assert (t >= 0).all() and (b >= 0).all()
                 assert np.array_equal(oracle.tophat(img, wx, wy, ax, ay),
-                                      (img.astype(np.int64) - o).astype(dtype))
+                                      np.maximum(t, 0).astype(dtype))
                 assert np.array_equal(oracle.blackhat(img, wx, wy, ax, ay),
-                                      (c.astype(np.int64) - img).astype(dtype))
+                                      np.maximum(b, 0).astype(dtype))
     v = 180 if dtype == np.uint8 else 40000
     img = np.full((9, 9), 10, dtype)
     img[4, 4] = v
