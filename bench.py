@@ -173,8 +173,9 @@ def c3_lines(torch, morph, dev, steps):
 def gradient_lines(torch, morph, dev, steps):
     """4096x4096 morphological gradients (dilation - erosion), uint8 and uint16: one
     pass at 3x3 and 9x9 (both extrema from one read), composed at 15x15 (dilation,
-    erosion to a workspace, subtraction); GB/s over the gradient's own 2 sizeof(T)
-    bytes a pixel, 10 launches over 10 buffer sets in one graph."""
+    erosion to a workspace, subtraction); and the 3x3 top-hat (opening through the
+    workspace, then a subtraction).  GB/s over 2 sizeof(T) bytes a pixel (one read,
+    one write), 10 launches over 10 buffer sets in one graph."""
     out = []
     stream = torch.cuda.current_stream()
     for dt, es in (("u8", 1), ("u16", 2)):
@@ -188,12 +189,13 @@ def gradient_lines(torch, morph, dev, steps):
             srcs = [s.view(torch.uint16) for s in srcs]
         dsts = [torch.empty_like(s) for s in srcs]
         wss = [torch.empty(4096 * 4096 * es, dtype=torch.uint8, device=dev) for _ in srcs]
-        for w, form in ((3, "one pass"), (9, "one pass"), (15, "composed")):
-            fns = [(lambda i=i: morph.gradient(srcs[i], w, w, out=dsts[i], workspace=wss[i]))
+        for op, w, form in (("gradient", 3, "one pass"), ("gradient", 9, "one pass"),
+                            ("gradient", 15, "composed"), ("tophat", 3, "composed")):
+            fns = [(lambda i=i: morph.apply(op, srcs[i], w, w, out=dsts[i], workspace=wss[i]))
                    for i in range(nbuf)]
             us = graph_time(torch, fns, max(5, steps // 2), stream) * 1e3
             gbs = 2 * es * 4096 * 4096 / (us * 1e-6) / 1e9
-            out.append(dict(dtype=dt, w="%dx%d" % (w, w), form=form, us=round(us, 2),
+            out.append(dict(dtype=dt, op=op, w="%dx%d" % (w, w), form=form, us=round(us, 2),
                             gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4)))
         del srcs, dsts, wss
     return out

@@ -65,6 +65,8 @@ extern "C" {
 #define MORPH_OP_OPEN 2  /* dilate(erode(src)), same rectangle and anchor (§2) */
 #define MORPH_OP_CLOSE 3 /* erode(dilate(src)), same rectangle and anchor (§2) */
 #define MORPH_OP_GRADIENT 4 /* dilate(src) - erode(src), same rectangle and anchor (§2) */
+#define MORPH_OP_TOPHAT 5   /* max(src - open(src), 0) (§2: erosion, dilation, arithmetic) */
+#define MORPH_OP_BLACKHAT 6 /* max(close(src) - src, 0) */
 
 /* element types */
 #define MORPH_U8 0
@@ -157,10 +159,28 @@ int morph_gradient_u16(const void *src, void *dst, int H, int W, size_t pitch, i
                        int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
                        hipStream_t stream);
 
+/* Top-hat (src minus its opening) and black-hat (closing minus src), clamped at 0:
+ * with the same rectangle and anchor in both passes, an even window or an
+ * off-centre anchor can put the opening above src (the closing below it), and
+ * there the result is 0.  The opening or closing as above (workspace required,
+ * same rules), then one subtraction kernel on dst. */
+int morph_tophat(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                 int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                 hipStream_t stream);
+int morph_blackhat(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                   int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                   hipStream_t stream);
+int morph_tophat_u16(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                     int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                     hipStream_t stream);
+int morph_blackhat_u16(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
+                       int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* General entry: any op (MORPH_OP_*) and dtype (MORPH_U8 / MORPH_U16) with an
- * optional plan (NULL = tuned defaults).  workspace is needed only for OPEN and
- * CLOSE, and for GRADIENT where its one-pass form does not apply (see
- * morph_gradient).  The named entry points above are this call with plan = NULL.
+ * optional plan (NULL = tuned defaults).  workspace is needed only for OPEN,
+ * CLOSE, TOPHAT and BLACKHAT, and for GRADIENT where its one-pass form does not
+ * apply (see morph_gradient).  The named entry points above are this call with plan = NULL.
  * Batch descriptors take ERODE and DILATE only. */
 int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
                 int wx, int wy, int anchor_x, int anchor_y, int border,

@@ -19,7 +19,7 @@ import os
 from . import _lib
 from ._lib import MorphError, Plan  # noqa: F401
 
-__all__ = ["erode", "dilate", "opening", "closing", "gradient", "apply", "Batch", "workspace_bytes",
+__all__ = ["erode", "dilate", "opening", "closing", "gradient", "tophat", "blackhat", "apply", "Batch", "workspace_bytes",
            "load_tuning", "get_thresholds", "set_thresholds", "resolve_plan", "MorphError",
            "version"]
 
@@ -71,8 +71,8 @@ def workspace_bytes(H: int, W: int, pitch: int, elem_bytes: int) -> int:
 def apply(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = -1, out=None,
           workspace=None, method_x: str | None = None, method_y: str | None = None,
           tile=None, stream=None):
-    """Run ``op`` in {"erode", "dilate", "open", "close", "gradient"} on ``src``;
-    returns ``out``.
+    """Run ``op`` in {"erode", "dilate", "open", "close", "gradient", "tophat",
+    "blackhat"} on ``src``; returns ``out``.
 
     ``method_x`` / ``method_y`` force "direct" or "vhgw" for a pass (and
     ``method_x="doubling"`` the streaming kernel's lane doubling) and ``tile`` =
@@ -89,7 +89,7 @@ def apply(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = 
     if out.shape != src.shape or out.dtype != src.dtype or _geom(out)[2] != pitch:
         raise ValueError("out must match src in shape, dtype and row pitch")
     ws_ptr, ws_bytes = None, 0
-    if code in (_lib.OP_OPEN, _lib.OP_CLOSE, _lib.OP_GRADIENT):
+    if code not in (_lib.OP_ERODE, _lib.OP_DILATE):
         if workspace is None:
             workspace = torch.empty(workspace_bytes(H, W, pitch, src.element_size()),
                                     dtype=torch.uint8, device=src.device)
@@ -122,6 +122,16 @@ def closing(src, wx, wy=None, ax=-1, ay=-1, **kw):
 def gradient(src, wx, wy=None, ax=-1, ay=-1, **kw):
     """Morphological gradient: dilation minus erosion, same rectangle and anchor."""
     return apply("gradient", src, wx, wy, ax, ay, **kw)
+
+
+def tophat(src, wx, wy=None, ax=-1, ay=-1, **kw):
+    """Top-hat: the image minus its opening."""
+    return apply("tophat", src, wx, wy, ax, ay, **kw)
+
+
+def blackhat(src, wx, wy=None, ax=-1, ay=-1, **kw):
+    """Black-hat: the closing minus the image."""
+    return apply("blackhat", src, wx, wy, ax, ay, **kw)
 
 
 class Batch:

@@ -21,9 +21,9 @@ MORPH_EUNSUPPORTED = -3
 MORPH_EHIP = -4
 MORPH_ENOMEM = -5
 
-OP_ERODE, OP_DILATE, OP_OPEN, OP_CLOSE, OP_GRADIENT = 0, 1, 2, 3, 4
+OP_ERODE, OP_DILATE, OP_OPEN, OP_CLOSE, OP_GRADIENT, OP_TOPHAT, OP_BLACKHAT = range(7)
 OP_CODES = {"erode": OP_ERODE, "dilate": OP_DILATE, "open": OP_OPEN, "close": OP_CLOSE,
-            "gradient": OP_GRADIENT}
+            "gradient": OP_GRADIENT, "tophat": OP_TOPHAT, "blackhat": OP_BLACKHAT}
 U8, U16 = 0, 1
 METHOD_AUTO, METHOD_DIRECT, METHOD_VHGW = 0, 1, 2
 METHOD_CODES = {None: 0, "auto": 0, "direct": 1, "vhgw": 2, "doubling": 3}
@@ -32,7 +32,8 @@ METHOD_CODES = {None: 0, "auto": 0, "direct": 1, "vhgw": 2, "doubling": 3}
 EXPORTS = (
     "morph_erode", "morph_dilate", "morph_erode_u16", "morph_dilate_u16",
     "morph_workspace_bytes", "morph_open", "morph_close", "morph_open_u16", "morph_close_u16",
-    "morph_gradient", "morph_gradient_u16",
+    "morph_gradient", "morph_gradient_u16", "morph_tophat", "morph_blackhat",
+    "morph_tophat_u16", "morph_blackhat_u16",
     "morph_apply", "morph_batch_create", "morph_batch_set", "morph_batch_enqueue",
     "morph_batch_launch",
     "morph_batch_tiles", "morph_batch_destroy", "morph_load_tuning", "morph_get_thresholds",
@@ -92,7 +93,8 @@ def lib():
         f.restype = I
     composed = [P, P, I, I, Z, I, I, I, I, I, P, Z, P]
     for n in ("morph_open", "morph_close", "morph_open_u16", "morph_close_u16",
-              "morph_gradient", "morph_gradient_u16"):
+              "morph_gradient", "morph_gradient_u16", "morph_tophat", "morph_blackhat",
+              "morph_tophat_u16", "morph_blackhat_u16"):
         f = getattr(L, n)
         f.argtypes = composed
         f.restype = I

@@ -463,7 +463,7 @@ static int run_gradient(int dtype, const void *src, void *dst, int H, int W, siz
     rc = run_single(MORPH_OP_ERODE, dtype, src, workspace, H, W, pitch, wx, wy, ax, ay, plan,
                     stream);
     if (rc != MORPH_OK) return rc;
-    if ((e = launch_subtract(workspace, dst, H, W, pitch, dtype, stream)) != hipSuccess)
+    if ((e = launch_subtract(workspace, dst, H, W, pitch, dtype, false, stream)) != hipSuccess)
         return hip_fail(e);
     return MORPH_OK;
 }
@@ -472,7 +472,7 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
                 int wx, int wy, int anchor_x, int anchor_y, int border, const morph_plan *plan,
                 void *workspace, size_t ws_bytes, hipStream_t stream)
 {
-    if (op < MORPH_OP_ERODE || op > MORPH_OP_GRADIENT) return MORPH_EINVAL;
+    if (op < MORPH_OP_ERODE || op > MORPH_OP_BLACKHAT) return MORPH_EINVAL;
     int rc = check_image(dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, border);
     if (rc != MORPH_OK || H == 0 || W == 0) return rc;
     const size_t span = image_span(H, W, pitch, dtype);
@@ -488,12 +488,17 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
         return MORPH_ENOMEM;
     if (ranges_overlap(workspace, span, src, span) || ranges_overlap(workspace, span, dst, span))
         return MORPH_EALIAS;
-    const int first = (op == MORPH_OP_OPEN) ? MORPH_OP_ERODE : MORPH_OP_DILATE;
+    // (top-hat: src - opening; black-hat: closing - src)
+    const bool opens = op == MORPH_OP_OPEN || op == MORPH_OP_TOPHAT;
+    const int first = opens ? MORPH_OP_ERODE : MORPH_OP_DILATE;
     rc = run_single(first, dtype, src, workspace, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
                     stream);
     if (rc != MORPH_OK) return rc;
-    return run_single(1 - first, dtype, workspace, dst, H, W, pitch, wx, wy, anchor_x, anchor_y,
-                      plan, stream);
+    rc = run_single(1 - first, dtype, workspace, dst, H, W, pitch, wx, wy, anchor_x, anchor_y,
+                    plan, stream);
+    if (rc != MORPH_OK || op == MORPH_OP_OPEN || op == MORPH_OP_CLOSE) return rc;
+    hipError_t e = launch_subtract(src, dst, H, W, pitch, dtype, op == MORPH_OP_TOPHAT, stream);
+    return e == hipSuccess ? MORPH_OK : hip_fail(e);
 }
 
 #define MORPH_SINGLE(name, op, dt)                                                            \
@@ -522,6 +527,10 @@ MORPH_COMPOSED(morph_open_u16, MORPH_OP_OPEN, MORPH_U16)
 MORPH_COMPOSED(morph_close_u16, MORPH_OP_CLOSE, MORPH_U16)
 MORPH_COMPOSED(morph_gradient, MORPH_OP_GRADIENT, MORPH_U8)
 MORPH_COMPOSED(morph_gradient_u16, MORPH_OP_GRADIENT, MORPH_U16)
+MORPH_COMPOSED(morph_tophat, MORPH_OP_TOPHAT, MORPH_U8)
+MORPH_COMPOSED(morph_blackhat, MORPH_OP_BLACKHAT, MORPH_U8)
+MORPH_COMPOSED(morph_tophat_u16, MORPH_OP_TOPHAT, MORPH_U16)
+MORPH_COMPOSED(morph_blackhat_u16, MORPH_OP_BLACKHAT, MORPH_U16)
 #undef MORPH_COMPOSED
 
 size_t morph_workspace_bytes(int H, int W, size_t pitch, int elem_bytes_)

@@ -83,9 +83,10 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);
 // the morphological gradient of a wave-kernel job (kind KIND_WAVE, rows aligned):
 // both extrema from one read, their difference stored
 hipError_t launch_gradient_job(const TileJob &job, hipStream_t stream);
-// dst -= lo over an H x W image of the given pitch (bytes) and dtype
-hipError_t launch_subtract(const void *lo, void *dst, int H, int W, size_t pitch, int dtype,
-                           hipStream_t stream);
+// dst = dst - a (reverse false) or a - dst (reverse true) over an H x W image of
+// the given pitch (bytes) and dtype
+hipError_t launch_subtract(const void *a, void *dst, int H, int W, size_t pitch, int dtype,
+                           bool reverse, hipStream_t stream);
 
 // persistent batch kernel
 struct BatchTables {

@@ -84,8 +84,13 @@ def test_open_close_workspace_checks():
                             None) == E.MORPH_ENOMEM
     assert L.morph_gradient_u16(FAKE_SRC, FAKE_DST, 8, 8, 16, 31, 31, -1, -1, 0, FAKE_SRC + 8,
                                 128, None) == E.MORPH_EALIAS
-    assert L.morph_apply(5, 0, FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, None, 0,
+    assert L.morph_apply(7, 0, FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, None, 0,
                          None) == E.MORPH_EINVAL
+    # top-hat and black-hat always need it
+    assert L.morph_tophat(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, 0,
+                          None) == E.MORPH_ENOMEM
+    assert L.morph_blackhat_u16(FAKE_SRC, FAKE_DST, 8, 8, 16, 3, 3, -1, -1, 0, FAKE_DST, 128,
+                                None) == E.MORPH_EALIAS
 
 
 def test_forced_direct_beyond_its_range_is_unsupported():

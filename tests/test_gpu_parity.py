@@ -325,6 +325,23 @@ def test_open_close(dtype):
             assert np.array_equal(got, want), (op, w)
 
 
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_tophat_blackhat(dtype):
+    """Top-hat (image minus opening) and black-hat (closing minus image) against the
+    oracle: small and large windows, off-centre anchors, aligned and unaligned rows."""
+    img = synth.document(130, 170, seed=27, n_rect=30)
+    if dtype == np.uint16:
+        img = img.astype(np.uint16) * 257
+    for (wx, wy, ax, ay) in ((3, 3, -1, -1), (5, 2, 0, 1), (15, 15, 3, 9), (31, 7, -1, 6)):
+        for op, f in (("tophat", oracle.tophat), ("blackhat", oracle.blackhat)):
+            want = f(img, wx, wy, ax, ay)
+            assert np.array_equal(_gpu(img, op, wx, wy, ax, ay), want), (op, wx, wy)
+            d, _ = to_dev(img, pitch_elems=173, offset_elems=1)
+            out = morph.apply(op, d, wx, wy, ax, ay)
+            torch.cuda.synchronize()
+            assert np.array_equal(to_host(out), want), (op, wx, wy, "unaligned")
+
+
 def test_empty_images_and_errors():
     e = torch.empty((0, 5), dtype=torch.uint8, device="cuda")
     assert morph.erode(e, 3).shape == (0, 5)
