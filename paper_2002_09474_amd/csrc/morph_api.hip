@@ -47,12 +47,13 @@ struct DtypeTuning {
     // the unit heights above for images of a batch, whose many units fill the GPU
     // whatever their height, so that longer units (less vertical warm-up) pay
     int batch_wave_rows, batch_stream_rows, batch_stream_rows_runs;
+    int fit_units; // single images: shorten units until the launch fills the GPU (0 / 1)
 };
 
 std::mutex g_tuning_mu;
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48, 1},
+    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48, 1},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -156,6 +157,13 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
         (key[0] == 'b' ? t.batch_wave_rows : t.wave_rows) = r;
     }
+    it = o.obj.find("fit_units");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r != 0 && r != 1) return false;
+        t.fit_units = r;
+    }
     it = o.obj.find("fuse");
     if (it != o.obj.end()) {
         if (it->second.k != JVal::NUM) return false;
@@ -240,6 +248,20 @@ size_t image_span(int H, int W, size_t pitch, int dtype)
 
 int default_anchor(int w) { return w - 1 - w / 2; }
 
+// Single images: a wave or streaming unit's rows go one chunk after another, so an
+// image with fewer units than the GPU holds waves finishes in about one unit's time,
+// which grows with its height.  Units are shortened (in steps of 8 rows, to no fewer
+// than 8) until the launch has about kUnitTarget of them: 8 waves per CU of a 256-CU
+// MI355X.  Batches fill the GPU with many images and keep the tuned heights.
+constexpr int kUnitTarget = 2048;
+
+static int fit_rows(int tuned, int H, int strips)
+{
+    const int64_t need = ((int64_t)H * strips + kUnitTarget - 1) / kUnitTarget; // rows a unit
+    const int tb = (int)std::min<int64_t>(tuned, (need + 7) / 8 * 8);
+    return std::max(std::min(tuned, 8), tb);
+}
+
 // Fill a TileJob for one erosion/dilation.  Windows are clipped to the image: with
 // anchor a and right extent r = w - 1 - a, only min(a, W-1) columns to the left and
 // min(r, W-1) to the right can ever be inside the image.
@@ -321,6 +343,7 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         j.TB = std::min(batch ? tu.batch_wave_rows : tu.wave_rows,
                         (H + kWaveRows - 1) / kWaveRows * kWaveRows);
         j.tiles_x = (W + j.TW - 1) / j.TW;
+        if (!batch && tu.fit_units) j.TB = fit_rows(j.TB, H, j.tiles_x);
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
         return MORPH_OK;
@@ -342,6 +365,7 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         j.TB = std::min(stream_two_level(j.wy) ? (batch ? tu.batch_stream_rows_runs : tu.stream_rows_runs)
                                                : (batch ? tu.batch_stream_rows : tu.stream_rows),
                         H);
+        if (!batch && tu.fit_units) j.TB = fit_rows(j.TB, H, j.tiles_x);
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
         return MORPH_OK;

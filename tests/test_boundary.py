@@ -114,25 +114,35 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert p["method_x"] == "direct" and p["method_y"] == "vhgw"
         p = morph.resolve_plan("u8", 1080, 1920, 7, 7)
         assert p["method_x"] == "direct" and p["method_y"] == "direct"
-        # both passes direct: one wave per strip of 60 quads x 24 rows
+        # both passes direct: one wave per strip of 60 quads x 24 rows, on an image
+        # with enough units (18 strips x 171 units) to fill the GPU
+        p = morph.resolve_plan("u8", 4096, 4096, 7, 7)
         assert (p["tile_w"], p["tile_h"], p["kernel"]) == (240, 24, "wave")
+        # a smaller single image takes shorter units, until it has about 2048 of them
+        # (in steps of 8 rows, no fewer than 8): 1080 x 1920 has 8 strips, so
+        # ceil(1080 * 8 / 2048) = 5 rows -> 8
+        assert morph.resolve_plan("u8", 1080, 1920, 7, 7)["tile_h"] == 8
+        assert morph.resolve_plan("u8", 3000, 1920, 7, 7)["tile_h"] == 16
         # a window of 1 skips the pass
         assert morph.resolve_plan("u8", 100, 100, 1, 31)["method_x"] is None
         # larger windows: the streaming kernel (vertical vHGW, horizontal doubling)
         # up to 128 x 256, the tile kernel beyond
         p = morph.resolve_plan("u8", 1080, 1920, 31, 31)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
-        # streaming units of 32 rows for wy > 16 (run-total form), 48 below (LDS ring)
+        # streaming units of 32 rows for wy > 16 (run-total form), 48 below (LDS ring),
+        # on images with units enough; 4096 x 4096 (19 strips) takes 40 for the ring
+        p = morph.resolve_plan("u8", 8192, 4096, 31, 31)
         assert (p["tile_w"], p["tile_h"]) == (4 * 55, 32)
-        assert morph.resolve_plan("u8", 1080, 1920, 31, 15)["tile_h"] == 48
+        assert morph.resolve_plan("u8", 8192, 4096, 31, 15)["tile_h"] == 48
+        assert morph.resolve_plan("u8", 4096, 4096, 31, 15)["tile_h"] == 40
+        assert morph.resolve_plan("u8", 1080, 1920, 31, 15)["tile_h"] == 8
         p = morph.resolve_plan("u8", 1080, 1920, 7, 63)
         assert (p["method_x"], p["method_y"]) == ("direct", "vhgw")
         # doubling with a direct-size vertical window: the wave kernel, 24-row units
-        # (rounded up to 8 rows for short images), strips of stream_quads(wx) quads
-        p = morph.resolve_plan("u8", 100, 90, 3, 3, method_x="doubling")
+        # (8 on small images), strips of stream_quads(wx) quads
+        p = morph.resolve_plan("u8", 100000, 90, 3, 3, method_x="doubling")
         assert (p["kernel"], p["tile_w"], p["tile_h"]) == ("wave", 4 * 62, 24)
-        assert morph.resolve_plan("u8", 20, 90, 3, 3, method_x="doubling")["tile_h"] == 24
-        assert morph.resolve_plan("u8", 12, 90, 3, 3, method_x="doubling")["tile_h"] == 16
+        assert morph.resolve_plan("u8", 20, 90, 3, 3, method_x="doubling")["tile_h"] == 8
         # automatic: wide and short windows stay on the wave kernel with doubling
         p = morph.resolve_plan("u8", 1080, 1920, 63, 1)
         assert (p["method_x"], p["kernel"], p["tile_w"]) == ("doubling", "wave", 4 * 47)
@@ -177,20 +187,24 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert (p["tile_w"], p["tile_h"]) == (160 - 32, 16)
         # automatic methods beyond the thresholds: the streaming kernel, whose strip
         # stores the quads whose input fits in 64: (250 - wx) // 4 + 1 of them
-        p = morph.resolve_plan("u8", 1000, 1000, 5, 5)
+        p = morph.resolve_plan("u8", 100000, 1000, 5, 5)
         assert (p["method_x"], p["method_y"]) == ("doubling", "vhgw")
         assert (p["tile_w"], p["tile_h"]) == (4 * 62, 48)
         f.write_text(json.dumps({"u8": {"stream_rows": 100, "stream_rows_runs": 40,
                                         "wide_rows": 7}}))
         morph.load_tuning(str(f))
-        assert morph.resolve_plan("u8", 1000, 1000, 5, 5)["tile_h"] == 100
+        assert morph.resolve_plan("u8", 100000, 1000, 5, 5)["tile_h"] == 100
         assert morph.resolve_plan("u8", 1000, 1000, 200, 1)["tile_h"] == 7
-        assert morph.resolve_plan("u8", 1000, 1000, 5, 17)["tile_h"] == 40
+        assert morph.resolve_plan("u8", 100000, 1000, 5, 17)["tile_h"] == 40
         # batch unit heights and the fused batch dispatch are keys of their own
         f.write_text(json.dumps({"u8": {"batch_wave_rows": 16, "batch_stream_rows": 20,
-                                        "batch_stream_rows_runs": 30, "fuse": 0}}))
+                                        "batch_stream_rows_runs": 30, "fuse": 0,
+                                        "fit_units": 0}}))
         morph.load_tuning(str(f))
-        for bad_t in ({"batch_wave_rows": 12}, {"fuse": 2}, {"batch_stream_rows": 0}):
+        # fit_units 0: a small single image keeps the tuned height
+        assert morph.resolve_plan("u8", 1080, 1920, 3, 3)["tile_h"] == 24
+        for bad_t in ({"batch_wave_rows": 12}, {"fuse": 2}, {"batch_stream_rows": 0},
+                      {"fit_units": 3}):
             f.write_text(json.dumps({"u8": bad_t}))
             with pytest.raises(morph.MorphError):
                 morph.load_tuning(str(f))

@@ -116,7 +116,9 @@ def test_wave_units_of_several_row_chunks(rows, tmp_path):
     gives the oracle's result, with ragged last units and any anchor."""
     import json
     f = tmp_path / "t.json"
-    f.write_text(json.dumps({"u8": {"wave_rows": rows}, "u16": {"wave_rows": rows}}))
+    # (fit_units 0: small images keep the given height instead of shortening units)
+    t = {"wave_rows": rows, "fit_units": 0}
+    f.write_text(json.dumps({"u8": t, "u16": t}))
     morph.load_tuning(str(f))
     try:
         rng = np.random.default_rng(rows)
@@ -225,7 +227,7 @@ def test_streaming_units_of_any_height(rows, tmp_path):
     wide."""
     import json
     f = tmp_path / "t.json"
-    t = {"stream_rows": rows, "stream_rows_runs": rows}
+    t = {"stream_rows": rows, "stream_rows_runs": rows, "fit_units": 0}
     f.write_text(json.dumps({"u8": t, "u16": t}))
     morph.load_tuning(str(f))
     try:
