@@ -54,7 +54,12 @@ def sweep(H=600, W=800, windows=WINDOWS):
         for w in windows:
             wx, wy = (w, 1) if axis == "x" else (1, w)
             r = {"axis": axis, "w": w, "kernel": morph.resolve_plan("u8", H, W, wx, wy)["kernel"]}
-            for name, kw in (("auto", {}), ("direct", {"method_x": "direct", "method_y": "direct"}),
+            # the paper's direct pass on the tile kernel needs a tile (forced methods
+            # without one plan the wave kernel): the tile the tuned rule for w <= 9 gives
+            tw = max(4 * 32 - ((w + 2 + 3) & ~3), (2 * w + 3) & ~3)
+            for name, kw in (("auto", {}),
+                             ("direct", {"method_x": "direct", "method_y": "direct",
+                                         "tile": (tw, 64)}),
                              ("vhgw", {"method_x": "vhgw", "method_y": "vhgw"})):
                 if name == "direct" and w > 9:
                     continue
