@@ -201,6 +201,27 @@ def gradient_lines(torch, morph, dev, steps):
     return out
 
 
+def small_image_lines(torch, morph, synth, dev, steps):
+    """Single-image erosions on the smaller configurations: a 640x480 uint8 image at
+    3x3 and the 1920x1080 uint8 document page at windows 3 .. 63 (per-launch time of
+    10 launches over 10 buffer pairs in one graph)."""
+    out = []
+    stream = torch.cuda.current_stream()
+    for (H, W), ws in (((480, 640), (3,)), ((1080, 1920), (3, 5, 9, 15, 31, 63))):
+        page = torch.from_numpy(synth.document(H, W, seed=2)).to(dev)
+        srcs = [page.clone() for _ in range(10)]
+        dsts = [torch.empty_like(s) for s in srcs]
+        for w in ws:
+            fns = [(lambda i=i: morph.apply("erode", srcs[i], w, w, out=dsts[i])) for i in range(10)]
+            us = graph_time(torch, fns, max(5, steps // 2), stream) * 1e3
+            gbs = 2 * H * W / (us * 1e-6) / 1e9
+            out.append(dict(image="%dx%d" % (W, H), w="%dx%d" % (w, w), us=round(us, 2),
+                            gpixel_s=round(H * W / (us * 1e-6) / 1e9, 1), gbs=round(gbs, 1),
+                            kernel=morph.resolve_plan("u8", H, W, w, w)["kernel"]))
+        del srcs, dsts
+    return out
+
+
 def _effective(w, extent):
     """A window clipped to the image (default anchor), as the library plans it."""
     a = w - 1 - w // 2
@@ -370,6 +391,8 @@ def main():
         }
         _log("4096x4096 kernels")
         res["c3_4096"] = c3_lines(torch, morph, dev, max(10, args.steps))
+        _log("640x480 and 1920x1080 single images")
+        res["small_images"] = small_image_lines(torch, morph, synth, dev, max(10, args.steps))
         _log("4096x4096 gradients")
         res["gradient_4096"] = gradient_lines(torch, morph, dev, max(10, args.steps))
 

@@ -250,8 +250,9 @@ int morph_batch_destroy(morph_batch_t b);
  * batch_stream_rows_runs (48) in place of the first three; and fuse (0 or 1,
  * default 1): a batch runs its wave and streaming units of one element type and
  * row alignment as one kernel dispatch; and fit_units (0 or 1, default 1): a
- * single image whose wave or streaming units would number under about 2048 gets
- * shorter ones (in steps of 8 rows, no fewer than 8), e.g.
+ * single image, or a batch, whose wave and streaming units would number under
+ * about 2048 gets shorter ones (in steps of 8 rows, no fewer than 8; a batch only
+ * while its tile table holds them), e.g.
  *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 64,
  *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
  * A dtype missing from the file keeps its table; a key missing keeps its value.

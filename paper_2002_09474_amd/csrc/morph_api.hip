@@ -792,6 +792,39 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         if (rc != MORPH_OK) return rc;
         jobs[group_of(j)].push_back(j);
     }
+    // a batch of few or small images (a serving loop's micro-batch, often one image)
+    // would have too few wave and streaming units to fill the GPU: as for a single
+    // image, shorten them until the batch has about kUnitTarget
+    {
+        int64_t units = 0, rows_strips = 0;
+        for (int g = 0; g < kBatchGroups; g++)
+            for (const TileJob &j : jobs[g])
+                if ((j.kind == KIND_WAVE || j.kind == KIND_STREAM) && tuning_for(j.dtype).fit_units) {
+                    units += (int64_t)j.tiles_x * j.tiles_y;
+                    rows_strips += (int64_t)j.H * j.tiles_x;
+                }
+        if (units > 0 && units < kUnitTarget) {
+            const int64_t need = (rows_strips + kUnitTarget - 1) / kUnitTarget;
+            const int tb = (int)std::min<int64_t>((need + 7) / 8 * 8, INT32_MAX);
+            auto fitted = [&](const TileJob &j) { return std::max(std::min(j.TB, 8), std::min(j.TB, tb)); };
+            // (only if the batch's tile table still holds the longer list)
+            int64_t total = 0;
+            for (int g = 0; g < kBatchGroups; g++)
+                for (const TileJob &j : jobs[g]) {
+                    const bool fit = (j.kind == KIND_WAVE || j.kind == KIND_STREAM) &&
+                                     tuning_for(j.dtype).fit_units;
+                    total += (int64_t)j.tiles_x * (fit ? (j.H + fitted(j) - 1) / fitted(j) : j.tiles_y);
+                }
+            if (total <= b->max_tiles)
+                for (int g = 0; g < kBatchGroups; g++)
+                    for (TileJob &j : jobs[g])
+                        if ((j.kind == KIND_WAVE || j.kind == KIND_STREAM) &&
+                            tuning_for(j.dtype).fit_units) {
+                            j.TB = fitted(j);
+                            j.tiles_y = (j.H + j.TB - 1) / j.TB;
+                        }
+        }
+    }
     std::vector<BatchGroup> groups;
     int64_t tiles = 0;
     int m = 0, starts = 0;
