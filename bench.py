@@ -13,8 +13,8 @@ launches (eager and captured in one graph), the 4096x4096 uint8 and uint16
 erosion/dilation kernels at the four large windows and at 3x3, and the CPU oracle
 timed on a bounded sample of the batch on the host's cores.
 
-Prints ONE JSON line.  ``--gpus`` other than 1 exits with a message: this build
-runs on one GPU.
+Prints ONE JSON line.  ``--gpus`` other than 1 exits with a message: the library
+runs on one GPU (images are independent; sharding them across GPUs is not built).
 """
 from __future__ import annotations
 
@@ -272,7 +272,7 @@ def main():
                          "reference for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

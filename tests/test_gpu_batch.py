@@ -46,13 +46,16 @@ def _want(it):
                         it["ax"], it["ay"], method="direct")
 
 
-@pytest.mark.parametrize("fuse", [1, 0])
-def test_batch_matches_oracle_and_single_calls(fuse, tmp_path):
+@pytest.mark.parametrize("fuse,fit", [(1, 1), (0, 1), (1, 0)])
+def test_batch_matches_oracle_and_single_calls(fuse, fit, tmp_path):
     """With the wave and streaming groups fused into one dispatch per element type
-    and row alignment (the default) and launched one group at a time."""
+    and row alignment (the default) and launched one group at a time; with units
+    shortened to fill the GPU (the default for a batch this small) and at the tuned
+    batch heights."""
     import json
     f = tmp_path / "t.json"
-    f.write_text(json.dumps({"u8": {"fuse": fuse}, "u16": {"fuse": fuse}}))
+    t = {"fuse": fuse, "fit_units": fit}
+    f.write_text(json.dumps({"u8": t, "u16": t}))
     morph.load_tuning(str(f))
     try:
         _batch_matches_oracle_and_single_calls()
