@@ -201,6 +201,58 @@ def gradient_lines(torch, morph, dev, steps):
     return out
 
 
+def transpose_lines(torch, morph, dev, steps):
+    """Transposes (§4): 4096x4096 uint8 and uint16 images, and stacks of 16x16
+    uint8 / 8x8 uint16 blocks (the two block shapes of the paper's Table 1, 64 MB
+    a stack), each beside a plain device copy of the same bytes.  GB/s over
+    2 sizeof(T) bytes an element; launches over several buffer sets in one graph."""
+    out = []
+    stream = torch.cuda.current_stream()
+
+    def _u(t, dt):
+        return t.view(torch.uint16) if dt == "u16" else t
+
+    for dt, es in (("u8", 1), ("u16", 2)):
+        nbuf = 10
+        g = torch.Generator(device=dev).manual_seed(7 if dt == "u8" else 8)
+        tdt = torch.uint8 if dt == "u8" else torch.int16
+        srcs = [_u(torch.randint(0, 256 if dt == "u8" else 65536, (4096, 4096), generator=g,
+                                 dtype=torch.int32, device=dev).to(tdt), dt)
+                for _ in range(nbuf)]
+        dsts = [torch.empty_like(s) for s in srcs]
+        nbytes = 2 * es * 4096 * 4096
+        us = graph_time(torch, [(lambda i=i: morph.transpose(srcs[i], out=dsts[i]))
+                                for i in range(nbuf)], max(5, steps // 2), stream) * 1e3
+        cus = graph_time(torch, [(lambda i=i: dsts[i].copy_(srcs[i])) for i in range(nbuf)],
+                         max(5, steps // 2), stream) * 1e3
+        out.append(dict(what="image 4096x4096", dtype=dt, us=round(us, 2),
+                        gbs=round(nbytes / (us * 1e-6) / 1e9, 1),
+                        frac=round(nbytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                        copy_us=round(cus, 2),
+                        copy_gbs=round(nbytes / (cus * 1e-6) / 1e9, 1)))
+        del srcs, dsts
+        k = 16 if dt == "u8" else 8
+        n = (64 << 20) // (k * k * es)
+        nbuf = 4
+        srcs = [_u(torch.randint(0, 256 if dt == "u8" else 65536, (n, k, k), generator=g,
+                                 dtype=torch.int32, device=dev).to(tdt), dt)
+                for _ in range(nbuf)]
+        dsts = [torch.empty_like(s) for s in srcs]
+        nbytes = 2 * (64 << 20)
+        us = graph_time(torch, [(lambda i=i: morph.transpose_blocks(srcs[i], out=dsts[i]))
+                                for i in range(nbuf)], max(5, steps // 2), stream) * 1e3
+        cus = graph_time(torch, [(lambda i=i: dsts[i].copy_(srcs[i])) for i in range(nbuf)],
+                         max(5, steps // 2), stream) * 1e3
+        out.append(dict(what="blocks %dx%d x %d" % (k, k, n), dtype=dt, us=round(us, 2),
+                        ns_per_block=round(us * 1e3 / n, 4),
+                        gbs=round(nbytes / (us * 1e-6) / 1e9, 1),
+                        frac=round(nbytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                        copy_us=round(cus, 2),
+                        copy_gbs=round(nbytes / (cus * 1e-6) / 1e9, 1)))
+        del srcs, dsts
+    return out
+
+
 def small_image_lines(torch, morph, synth, dev, steps):
     """Single-image erosions on the smaller configurations: a 640x480 uint8 image at
     3x3 and the 1920x1080 uint8 document page at windows 3 .. 63 (per-launch time of
@@ -395,6 +447,8 @@ def main():
         res["small_images"] = small_image_lines(torch, morph, synth, dev, max(10, args.steps))
         _log("4096x4096 gradients")
         res["gradient_4096"] = gradient_lines(torch, morph, dev, max(10, args.steps))
+        _log("transposes")
+        res["transpose"] = transpose_lines(torch, morph, dev, max(10, args.steps))
 
     if not args.no_cpu_baseline:
         _log("CPU oracle baseline")

@@ -238,6 +238,32 @@ int64_t morph_batch_tiles(morph_batch_t b);
 /* Free the device tables and graphs.  The caller must have synchronized. */
 int morph_batch_destroy(morph_batch_t b);
 
+/* ---- transposes -------------------------------------------------------------- */
+/* Image transpose (§4; §1 gives its use: a filter along rows as a transpose, a
+ * filter along columns and a second transpose).  dst(x, y) = src(y, x): src is H
+ * rows of W elements with src_pitch bytes between rows, dst is W rows of H
+ * elements with dst_pitch bytes between rows.  uint8 (morph_transpose) or uint16
+ * (morph_transpose_u16).  Requirements: H, W >= 0 (H == 0 or W == 0 is a no-op
+ * returning MORPH_OK); src_pitch >= W * sizeof(T), dst_pitch >= H * sizeof(T),
+ * both multiples of sizeof(T) (else MORPH_EINVAL); uint16 pointers 2-byte
+ * aligned (else MORPH_EINVAL); the byte ranges of src and dst must not overlap
+ * (MORPH_EALIAS).  Any alignment is correct; 16-byte aligned pointers and pitches
+ * take vector loads and stores.  Device pointers, caller-owned; asynchronous on
+ * `stream`; launch failures return MORPH_EHIP. */
+int morph_transpose(const void *src, void *dst, int H, int W, size_t src_pitch,
+                    size_t dst_pitch, hipStream_t stream);
+int morph_transpose_u16(const void *src, void *dst, int H, int W, size_t src_pitch,
+                        size_t dst_pitch, hipStream_t stream);
+/* Transpose of n_blocks independent square blocks, the two sizes §4 builds and
+ * times in Table 1: dtype MORPH_U8 takes 16x16 uint8 blocks (256 bytes each),
+ * MORPH_U16 8x8 uint16 blocks (128 bytes each).  Blocks are stored one after
+ * another, each row-major with no padding; block b of dst is the transpose of
+ * block b of src.  n_blocks in [0, 2^34] (0 is a no-op), src and dst 4-byte
+ * aligned (else MORPH_EINVAL), other dtypes MORPH_EUNSUPPORTED, overlapping
+ * ranges MORPH_EALIAS.  Device pointers, caller-owned; asynchronous on `stream`. */
+int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dtype,
+                           hipStream_t stream);
+
 /* ---- misc ------------------------------------------------------------------ */
 /* Load a tuning table (JSON written by the autotuner) replacing the current one:
  * per-dtype direct/vHGW thresholds, tile shapes per window bucket (tq = input

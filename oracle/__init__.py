@@ -17,6 +17,8 @@ value for erosion, 0 for dilation).  Opening is dilation after erosion and
 closing erosion after dilation, with the same rectangle (§2); the morphological
 gradient is dilation minus erosion, again with the same rectangle; the top-hat is
 the image minus its opening and the black-hat the closing minus the image.
+The transpose (§4, used as §1 describes) takes element (y, x) to (x, y), for a
+whole image or for each of a stack of square blocks.
 """
 from __future__ import annotations
 
@@ -74,6 +76,10 @@ def _load():
         f = getattr(lib, "oracle_line_vhgw_" + suf)
         f.argtypes = [P, L, P, L, I, I, I, I, P]
         f.restype = None
+    lib.oracle_transpose.argtypes = [P, P, I, I, L, L, I]
+    lib.oracle_transpose.restype = I
+    lib.oracle_transpose_blocks.argtypes = [P, P, L, I, I]
+    lib.oracle_transpose_blocks.restype = I
     lib.oracle_default_anchor.argtypes = [I]
     lib.oracle_default_anchor.restype = I
     lib.oracle_get_max_threads.restype = I
@@ -205,4 +211,35 @@ def line(x: np.ndarray, w: int, a: int = -1, op: int = ERODE, method: str = "dir
                                                 n, w, a, op, pad.ctypes.data)
     else:
         raise ValueError("unknown method %r" % method)
+    return out
+
+
+def transpose(img: np.ndarray) -> np.ndarray:
+    """Image transpose by its definition (§4): out[x, y] = img[y, x]."""
+    _suffix(img)
+    if img.ndim != 2:
+        raise ValueError("expected a 2-D image")
+    img = np.ascontiguousarray(img)
+    H, W = img.shape
+    out = np.empty((W, H), dtype=img.dtype)
+    es = img.itemsize
+    rc = _load().oracle_transpose(img.ctypes.data, out.ctypes.data, H, W, W * es, H * es, es)
+    if rc:
+        raise ValueError("oracle_transpose failed (%d)" % rc)
+    return out
+
+
+def transpose_blocks(blocks: np.ndarray) -> np.ndarray:
+    """Each k x k block of an (n, k, k) stack transposed (§4: 16x16 8-bit and
+    8x8 16-bit blocks)."""
+    _suffix(blocks)
+    if blocks.ndim != 3 or blocks.shape[1] != blocks.shape[2]:
+        raise ValueError("expected an (n, k, k) stack of blocks")
+    blocks = np.ascontiguousarray(blocks)
+    out = np.empty_like(blocks)
+    n, k = blocks.shape[0], blocks.shape[1]
+    rc = _load().oracle_transpose_blocks(blocks.ctypes.data, out.ctypes.data, n, k,
+                                         blocks.itemsize)
+    if rc:
+        raise ValueError("oracle_transpose_blocks failed (%d)" % rc)
     return out

@@ -281,3 +281,37 @@ int oracle_hybrid_##SUF(const T *src, T *dst, int H, int W, long pitch,         
 
 DEFINE_ORACLE(uint8_t, u8, 255)
 DEFINE_ORACLE(uint16_t, u16, 65535)
+
+/*
+ * Transpose (§4; §1 states its use: a filter along rows run as a transpose, a
+ * filter along columns and a second transpose).  The definition, element by
+ * element: dst row x, column y takes src row y, column x.  Elements are es bytes
+ * (1 or 2); pitches are in bytes.
+ */
+int oracle_transpose(const void *src, void *dst, int H, int W, long spitch, long dpitch, int es)
+{
+    if (H < 0 || W < 0 || (es != 1 && es != 2)) return -1;
+    const unsigned char *s = (const unsigned char *)src;
+    unsigned char *d = (unsigned char *)dst;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++)
+            memcpy(d + (long)x * dpitch + (long)y * es, s + (long)y * spitch + (long)x * es,
+                   (size_t)es);
+    return 0;
+}
+
+/*
+ * n independent k-by-k blocks stored one after another, each row-major with no
+ * padding (§4 builds these for 8x8 16-bit and 16x16 8-bit blocks): block b of dst
+ * is the transpose of block b of src.
+ */
+int oracle_transpose_blocks(const void *src, void *dst, long n, int k, int es)
+{
+    if (n < 0 || k < 1 || (es != 1 && es != 2)) return -1;
+    const long bb = (long)k * k * es;
+    for (long b = 0; b < n; b++)
+        if (oracle_transpose((const unsigned char *)src + b * bb, (unsigned char *)dst + b * bb,
+                             k, k, (long)k * es, (long)k * es, es))
+            return -1;
+    return 0;
+}

@@ -20,6 +20,7 @@ from . import _lib
 from ._lib import MorphError, Plan  # noqa: F401
 
 __all__ = ["erode", "dilate", "opening", "closing", "gradient", "tophat", "blackhat", "apply", "Batch", "workspace_bytes",
+           "transpose", "transpose_blocks",
            "load_tuning", "get_thresholds", "set_thresholds", "resolve_plan", "MorphError",
            "version"]
 
@@ -100,6 +101,45 @@ def apply(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = 
                                 ax, ay, 0, ctypes.byref(plan) if plan is not None else None,
                                 ws_ptr, ws_bytes, _stream_ptr(stream))
     _lib.check(rc, "morph_apply(%s, %dx%d)" % (op, wx, wy))
+    return out
+
+
+def transpose(src, out=None, stream=None):
+    """Transpose a 2-D uint8 or uint16 image: ``out[x, y] = src[y, x]`` (§4).
+
+    ``out`` (W x H, same dtype, any row pitch with a contiguous last dimension)
+    is allocated contiguous when not given; returns ``out``."""
+    torch = _torch()
+    dt = dtype_code(src.dtype)
+    H, W, spitch = _geom(src)
+    if out is None:
+        out = torch.empty((W, H), dtype=src.dtype, device=src.device)
+    if tuple(out.shape) != (W, H) or out.dtype != src.dtype:
+        raise ValueError("out must be W x H with the dtype of src")
+    _, _, dpitch = _geom(out)
+    f = _lib.lib().morph_transpose_u16 if dt == _lib.U16 else _lib.lib().morph_transpose
+    rc = f(src.data_ptr(), out.data_ptr(), H, W, spitch, dpitch, _stream_ptr(stream))
+    _lib.check(rc, "morph_transpose(%dx%d)" % (H, W))
+    return out
+
+
+def transpose_blocks(src, out=None, stream=None):
+    """Transpose every block of an (n, 16, 16) uint8 or (n, 8, 8) uint16 tensor
+    (the 16x16.8 and 8x8.16 blocks of §4, Table 1); returns ``out``."""
+    torch = _torch()
+    dt = dtype_code(src.dtype)
+    k = 16 if dt == _lib.U8 else 8
+    if src.dim() != 3 or tuple(src.shape[1:]) != (k, k) or not src.is_contiguous():
+        raise ValueError("expected a contiguous (n, %d, %d) tensor" % (k, k))
+    if not src.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if out is None:
+        out = torch.empty_like(src)
+    if out.shape != src.shape or out.dtype != src.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor like src")
+    rc = _lib.lib().morph_transpose_blocks(src.data_ptr(), out.data_ptr(), src.shape[0], dt,
+                                           _stream_ptr(stream))
+    _lib.check(rc, "morph_transpose_blocks(%d)" % src.shape[0])
     return out
 
 

@@ -34,6 +34,7 @@ EXPORTS = (
     "morph_workspace_bytes", "morph_open", "morph_close", "morph_open_u16", "morph_close_u16",
     "morph_gradient", "morph_gradient_u16", "morph_tophat", "morph_blackhat",
     "morph_tophat_u16", "morph_blackhat_u16",
+    "morph_transpose", "morph_transpose_u16", "morph_transpose_blocks",
     "morph_apply", "morph_batch_create", "morph_batch_set", "morph_batch_enqueue",
     "morph_batch_launch",
     "morph_batch_tiles", "morph_batch_destroy", "morph_load_tuning", "morph_get_thresholds",
@@ -98,6 +99,12 @@ def lib():
         f = getattr(L, n)
         f.argtypes = composed
         f.restype = I
+    for n in ("morph_transpose", "morph_transpose_u16"):
+        f = getattr(L, n)
+        f.argtypes = [P, P, I, I, Z, Z, P]
+        f.restype = I
+    L.morph_transpose_blocks.argtypes = [P, P, I64, I, P]
+    L.morph_transpose_blocks.restype = I
     L.morph_workspace_bytes.argtypes = [I, I, Z, I]
     L.morph_workspace_bytes.restype = Z
     L.morph_apply.argtypes = [I, I, P, P, I, I, Z, I, I, I, I, I, ctypes.POINTER(Plan), P, Z, P]

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libmorph_hip.so"
-SOURCES = ("morph_kernels.hip", "morph_api.hip")
+SOURCES = ("morph_kernels.hip", "morph_api.hip", "morph_transpose.hip")
 ARCH = os.environ.get("MORPH_OFFLOAD_ARCH", "gfx950")
 
 
@@ -21,14 +21,13 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
-    out = os.path.join(OUT_DIR, LIB_NAME)
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
-           "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _flags():
+    return [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -39,7 +38,30 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed (%d)" % res.returncode)
     if verbose and lines:
         print("\n".join(lines))
-    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel), then link the library."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(OUT_DIR, exist_ok=True)
+    out = os.path.join(OUT_DIR, LIB_NAME)
+    tag = ".tmp%d" % os.getpid()
+    objs = [os.path.join(OUT_DIR, os.path.splitext(s)[0] + tag + ".o") for s in SOURCES]
+    cmds = [_flags() + ["-x", "hip", "-c", os.path.join(CSRC, s), "-o", o]
+            for s, o in zip(SOURCES, objs)]
+    try:
+        with ThreadPoolExecutor(len(cmds)) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = out + tag
+        _run([hipcc(), "--offload-arch=" + ARCH, "-fPIC", "-shared"] + objs + ["-o", tmp],
+             verbose)
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 

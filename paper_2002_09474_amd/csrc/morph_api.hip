@@ -652,6 +652,51 @@ const char *morph_strerror(int status)
     }
 }
 
+// ---------------- transposes (§4; their use in §1) ----------------
+static int transpose_image(int dtype, const void *src, void *dst, int H, int W,
+                           size_t src_pitch, size_t dst_pitch, hipStream_t stream)
+{
+    const size_t es = elem_bytes(dtype);
+    if (H < 0 || W < 0) return MORPH_EINVAL;
+    if (H == 0 || W == 0) return MORPH_OK;
+    if (!src || !dst) return MORPH_EINVAL;
+    if (src_pitch < (size_t)W * es || src_pitch % es || dst_pitch < (size_t)H * es ||
+        dst_pitch % es)
+        return MORPH_EINVAL;
+    if (src_pitch > (size_t)1 << 40 || dst_pitch > (size_t)1 << 40) return MORPH_EINVAL;
+    if (es == 2 && (((uintptr_t)src | (uintptr_t)dst) & 1)) return MORPH_EINVAL;
+    const size_t sspan = (size_t)(H - 1) * src_pitch + (size_t)W * es;
+    const size_t dspan = (size_t)(W - 1) * dst_pitch + (size_t)H * es;
+    if (ranges_overlap(src, sspan, dst, dspan)) return MORPH_EALIAS;
+    const hipError_t e = launch_transpose(src, dst, H, W, src_pitch, dst_pitch, dtype, stream);
+    return e == hipSuccess ? MORPH_OK : hip_fail(e);
+}
+
+int morph_transpose(const void *src, void *dst, int H, int W, size_t src_pitch,
+                    size_t dst_pitch, hipStream_t stream)
+{
+    return transpose_image(MORPH_U8, src, dst, H, W, src_pitch, dst_pitch, stream);
+}
+
+int morph_transpose_u16(const void *src, void *dst, int H, int W, size_t src_pitch,
+                        size_t dst_pitch, hipStream_t stream)
+{
+    return transpose_image(MORPH_U16, src, dst, H, W, src_pitch, dst_pitch, stream);
+}
+
+int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dtype,
+                           hipStream_t stream)
+{
+    if (dtype != MORPH_U8 && dtype != MORPH_U16) return MORPH_EUNSUPPORTED;
+    if (n_blocks < 0 || n_blocks > ((int64_t)1 << 34)) return MORPH_EINVAL;
+    if (n_blocks == 0) return MORPH_OK;
+    if (!src || !dst || (((uintptr_t)src | (uintptr_t)dst) & 3)) return MORPH_EINVAL;
+    const size_t span = (size_t)n_blocks * (dtype == MORPH_U8 ? 256 : 128);
+    if (ranges_overlap(src, span, dst, span)) return MORPH_EALIAS;
+    const hipError_t e = launch_transpose_blocks(src, dst, n_blocks, dtype, stream);
+    return e == hipSuccess ? MORPH_OK : hip_fail(e);
+}
+
 int morph_last_hip_error(void) { return g_last_hip_error; }
 
 const char *morph_version(void) { return "morph-gfx950 0.1"; }

@@ -88,6 +88,12 @@ hipError_t launch_gradient_job(const TileJob &job, hipStream_t stream);
 hipError_t launch_subtract(const void *a, void *dst, int H, int W, size_t pitch, int dtype,
                            bool reverse, hipStream_t stream);
 
+// transposes (morph_transpose.hip): an H x W image of dtype (0 u8, 1 u16) into a
+// W x H one, pitches in bytes; n independent 16x16 u8 / 8x8 u16 row-major blocks
+hipError_t launch_transpose(const void *src, void *dst, int H, int W, size_t spitch,
+                            size_t dpitch, int dtype, hipStream_t stream);
+hipError_t launch_transpose_blocks(const void *src, void *dst, int64_t n, int dtype,
+                                   hipStream_t stream);
 // persistent batch kernel
 struct BatchTables {
     const TileJob *jobs;       // device array of jobs
