@@ -201,6 +201,45 @@ def gradient_lines(torch, morph, dev, steps):
     return out
 
 
+def openclose_lines(torch, morph, dev, steps):
+    """4096x4096 openings and closings, uint8 and uint16, at 3x3, 9x9 and 15x15: the
+    single-pass kernel without workspace (morph_openclose_fused: both operations on
+    one LDS tile) beside the two launches of the default path (erosion into a
+    workspace, dilation of the workspace, each on the kernel the single operation
+    takes).  GB/s over 2 sizeof(T) bytes a pixel, 10
+    launches over 10 buffer sets in one graph."""
+    out = []
+    stream = torch.cuda.current_stream()
+    for dt, es in (("u8", 1), ("u16", 2)):
+        nbuf = 10
+        g = torch.Generator(device=dev).manual_seed(7 if dt == "u8" else 8)
+        srcs = [torch.randint(0, 256 if dt == "u8" else 65536, (4096, 4096), generator=g,
+                              dtype=torch.int32, device=dev).to(torch.uint8 if dt == "u8"
+                                                                else torch.int16)
+                for _ in range(nbuf)]
+        if dt == "u16":
+            srcs = [s.view(torch.uint16) for s in srcs]
+        dsts = [torch.empty_like(s) for s in srcs]
+        wss = [torch.empty_like(s) for s in srcs]
+        for op, first, second in (("open", "erode", "dilate"), ("close", "dilate", "erode")):
+            for w in (3, 9, 15):
+                fused = [(lambda i=i: morph.openclose_fused(op, srcs[i], w, w, out=dsts[i]))
+                         for i in range(nbuf)]
+                two = []
+                for i in range(nbuf):
+                    two.append(lambda i=i: morph.apply(first, srcs[i], w, w, out=wss[i]))
+                    two.append(lambda i=i: morph.apply(second, wss[i], w, w, out=dsts[i]))
+                us = graph_time(torch, fused, max(5, steps // 2), stream) * 1e3
+                us2 = 2 * graph_time(torch, two, max(5, steps // 2), stream) * 1e3  # two a set
+                gbs = 2 * es * 4096 * 4096 / (us * 1e-6) / 1e9
+                out.append(dict(dtype=dt, op=op, w="%dx%d" % (w, w), us=round(us, 2),
+                                gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4),
+                                two_launch_us=round(us2, 2),
+                                fused_over_two_launch=round(us / us2, 2)))
+        del srcs, dsts, wss
+    return out
+
+
 def transpose_lines(torch, morph, dev, steps):
     """Transposes (§4): 4096x4096 uint8 and uint16 images, and stacks of 16x16
     uint8 / 8x8 uint16 blocks (the two block shapes of the paper's Table 1, 64 MB
@@ -447,6 +486,8 @@ def main():
         res["small_images"] = small_image_lines(torch, morph, synth, dev, max(10, args.steps))
         _log("4096x4096 gradients")
         res["gradient_4096"] = gradient_lines(torch, morph, dev, max(10, args.steps))
+        _log("4096x4096 openings and closings")
+        res["openclose_4096"] = openclose_lines(torch, morph, dev, max(10, args.steps))
         _log("transposes")
         res["transpose"] = transpose_lines(torch, morph, dev, max(10, args.steps))
 

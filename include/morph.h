@@ -144,6 +144,22 @@ int morph_close_u16(const void *src, void *dst, int H, int W, size_t pitch, int 
                     int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
                     hipStream_t stream);
 
+/* Opening (opening != 0) or closing in one launch with no workspace (§2: an
+ * opening is the dilation of the erosion, a closing the erosion of the dilation,
+ * same rectangle and anchor).  dtype MORPH_U8 or MORPH_U16; every other argument
+ * as for morph_open.  A workgroup reads its output tile grown by 2(w - 1) per
+ * axis into LDS once, runs both operations' direct passes there (intermediate
+ * pixels outside the image enter the second operation as its identity) and
+ * stores the tile: the intermediate image never reaches HBM.  Windows up to
+ * MORPH_OPENCLOSE_FUSED_MAX_W on each axis, else MORPH_EUNSUPPORTED; src and dst
+ * must not overlap (MORPH_EALIAS).  For callers that cannot spare the
+ * intermediate image's memory: its per-pixel direct passes make it slower than
+ * morph_open / morph_close, which remain the fast path. */
+#define MORPH_OPENCLOSE_FUSED_MAX_W 16
+int morph_openclose_fused(int dtype, int opening, const void *src, void *dst, int H, int W,
+                          size_t pitch, int wx, int wy, int anchor_x, int anchor_y, int border,
+                          hipStream_t stream);
+
 /* Morphological gradient (§2 names the arithmetic combinations of erosion and
  * dilation): dst = dilation - erosion with the same rectangle and anchor, never
  * negative.  Where the wave kernel takes the job (vertical window <= 9, horizontal

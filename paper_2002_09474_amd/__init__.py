@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import MorphError, Plan  # noqa: F401
 
 __all__ = ["erode", "dilate", "opening", "closing", "gradient", "tophat", "blackhat", "apply", "Batch", "workspace_bytes",
-           "transpose", "transpose_blocks",
+           "openclose_fused", "transpose", "transpose_blocks",
            "load_tuning", "get_thresholds", "set_thresholds", "resolve_plan", "MorphError",
            "version"]
 
@@ -101,6 +101,29 @@ def apply(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = 
                                 ax, ay, 0, ctypes.byref(plan) if plan is not None else None,
                                 ws_ptr, ws_bytes, _stream_ptr(stream))
     _lib.check(rc, "morph_apply(%s, %dx%d)" % (op, wx, wy))
+    return out
+
+
+def openclose_fused(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = -1,
+                    out=None, stream=None):
+    """Opening (``op="open"``) or closing (``"close"``) in one launch with no
+    workspace: both operations' direct passes on one LDS tile (windows up to 16 per
+    axis).  Same result as ``apply(op, ...)``, which stays the faster path;
+    returns ``out``."""
+    torch = _torch()
+    if op not in ("open", "close"):
+        raise ValueError("op must be 'open' or 'close'")
+    wy = wx if wy is None else wy
+    dt = dtype_code(src.dtype)
+    H, W, pitch = _geom(src)
+    if out is None:
+        out = torch.empty_strided(src.shape, src.stride(), dtype=src.dtype, device=src.device)
+    if out.shape != src.shape or out.dtype != src.dtype or _geom(out)[2] != pitch:
+        raise ValueError("out must match src in shape, dtype and row pitch")
+    rc = _lib.lib().morph_openclose_fused(dt, 1 if op == "open" else 0, src.data_ptr(),
+                                          out.data_ptr(), H, W, pitch, wx, wy, ax, ay, 0,
+                                          _stream_ptr(stream))
+    _lib.check(rc, "morph_openclose_fused(%s, %dx%d)" % (op, wx, wy))
     return out
 
 

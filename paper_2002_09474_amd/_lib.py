@@ -35,7 +35,7 @@ EXPORTS = (
     "morph_gradient", "morph_gradient_u16", "morph_tophat", "morph_blackhat",
     "morph_tophat_u16", "morph_blackhat_u16",
     "morph_transpose", "morph_transpose_u16", "morph_transpose_blocks",
-    "morph_apply", "morph_batch_create", "morph_batch_set", "morph_batch_enqueue",
+    "morph_openclose_fused", "morph_apply", "morph_batch_create", "morph_batch_set", "morph_batch_enqueue",
     "morph_batch_launch",
     "morph_batch_tiles", "morph_batch_destroy", "morph_load_tuning", "morph_get_thresholds",
     "morph_set_thresholds", "morph_resolve_plan", "morph_strerror", "morph_last_hip_error",
@@ -105,6 +105,8 @@ def lib():
         f.restype = I
     L.morph_transpose_blocks.argtypes = [P, P, I64, I, P]
     L.morph_transpose_blocks.restype = I
+    L.morph_openclose_fused.argtypes = [I, I, P, P, I, I, Z, I, I, I, I, I, P]
+    L.morph_openclose_fused.restype = I
     L.morph_workspace_bytes.argtypes = [I, I, Z, I]
     L.morph_workspace_bytes.restype = Z
     L.morph_apply.argtypes = [I, I, P, P, I, I, Z, I, I, I, I, I, ctypes.POINTER(Plan), P, Z, P]

@@ -557,6 +557,24 @@ MORPH_COMPOSED(morph_tophat_u16, MORPH_OP_TOPHAT, MORPH_U16)
 MORPH_COMPOSED(morph_blackhat_u16, MORPH_OP_BLACKHAT, MORPH_U16)
 #undef MORPH_COMPOSED
 
+static_assert(kOcMaxW == MORPH_OPENCLOSE_FUSED_MAX_W, "fused opening/closing window limit");
+
+int morph_openclose_fused(int dtype, int opening, const void *src, void *dst, int H, int W,
+                          size_t pitch, int wx, int wy, int anchor_x, int anchor_y, int border,
+                          hipStream_t stream)
+{
+    int rc = check_image(dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, border);
+    if (rc != MORPH_OK || H == 0 || W == 0) return rc;
+    if (wx > kOcMaxW || wy > kOcMaxW) return MORPH_EUNSUPPORTED;
+    const size_t span = image_span(H, W, pitch, dtype);
+    if (ranges_overlap(src, span, dst, span)) return MORPH_EALIAS;
+    const int ax = anchor_x < 0 ? default_anchor(wx) : anchor_x;
+    const int ay = anchor_y < 0 ? default_anchor(wy) : anchor_y;
+    hipError_t e = launch_openclose(src, dst, H, W, pitch, wx, wy, ax, ay, opening != 0, dtype,
+                                    stream);
+    return e == hipSuccess ? MORPH_OK : hip_fail(e);
+}
+
 size_t morph_workspace_bytes(int H, int W, size_t pitch, int elem_bytes_)
 {
     (void)elem_bytes_;

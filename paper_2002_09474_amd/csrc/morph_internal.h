@@ -94,6 +94,13 @@ hipError_t launch_transpose(const void *src, void *dst, int H, int W, size_t spi
                             size_t dpitch, int dtype, hipStream_t stream);
 hipError_t launch_transpose_blocks(const void *src, void *dst, int64_t n, int dtype,
                                    hipStream_t stream);
+// fused opening / closing (morph_openclose.hip): both operations' direct passes on
+// one LDS tile of kOcTileH x kOcTileW output pixels, windows up to kOcMaxW per axis
+constexpr int kOcTileH = 32;
+constexpr int kOcTileW = 128;
+constexpr int kOcMaxW = 16; // MORPH_OPENCLOSE_FUSED_MAX_W
+hipError_t launch_openclose(const void *src, void *dst, int H, int W, size_t pitch, int wx,
+                            int wy, int ax, int ay, bool opening, int dtype, hipStream_t stream);
 // persistent batch kernel
 struct BatchTables {
     const TileJob *jobs;       // device array of jobs

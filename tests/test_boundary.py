@@ -93,6 +93,29 @@ def test_open_close_workspace_checks():
                                 None) == E.MORPH_EALIAS
 
 
+def test_openclose_fused_argument_checks():
+    """The single-pass opening/closing rejects bad arguments before any launch:
+    windows above 16 per axis, bad dtype, anchors, pitch, overlap, border."""
+    L = _lib.lib()
+    E = _lib
+
+    def oc(dtype=0, opening=1, src=FAKE_SRC, dst=FAKE_DST, H=8, W=8, pitch=8, wx=3, wy=3,
+           ax=-1, ay=-1, border=0):
+        return L.morph_openclose_fused(dtype, opening, src, dst, H, W, pitch, wx, wy, ax, ay,
+                                       border, None)
+
+    assert oc(wx=17) == E.MORPH_EUNSUPPORTED
+    assert oc(wy=17, opening=0) == E.MORPH_EUNSUPPORTED
+    assert oc(dtype=5) == E.MORPH_EUNSUPPORTED
+    assert oc(border=1) == E.MORPH_EUNSUPPORTED
+    assert oc(ax=3) == E.MORPH_EINVAL
+    assert oc(wx=0) == E.MORPH_EINVAL
+    assert oc(pitch=7) == E.MORPH_EINVAL
+    assert oc(dtype=1, pitch=15) == E.MORPH_EINVAL
+    assert oc(dst=FAKE_SRC + 7 * 8) == E.MORPH_EALIAS
+    assert oc(H=0, src=0, dst=0) == E.MORPH_OK
+
+
 def test_forced_direct_beyond_its_range_is_unsupported():
     p = _lib.Plan(_lib.METHOD_DIRECT, 0, 0, 0)
     rc = _lib.lib().morph_apply(0, 0, FAKE_SRC, FAKE_DST, 64, 64, 64, 17, 1, -1, -1, 0,
