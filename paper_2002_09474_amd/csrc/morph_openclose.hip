@@ -51,17 +51,31 @@ __global__ __launch_bounds__(kOcThreads) void openclose_kernel(const uint8_t *__
     const int ry = threadIdx.x / 128;
     constexpr int kRowStep = kOcThreads / 128;
 
-    // 1. input region: rows y0 - 2ay .., columns x0 - 2ax .., identity outside
+    // 1. input region: rows y0 - 2ay .., columns x0 - 2ax .., identity outside.
+    // Each thread loads kLoadRows rows of a column with no branch around the loads
+    // (the address clamped into the image, the identity selected afterwards), so
+    // that all of them are in flight before the first store to LDS.
     const int in_h = kOcTileH + 2 * (wy - 1), in_w = kOcTileW + 2 * (wx - 1);
-    for (int r = ry; r < in_h; r += kRowStep) {
-        const int gy = y0 - 2 * ay + r;
-        const bool row_in = gy >= 0 && gy < H;
-        const T *srow = (const T *)(src + (row_in ? (int64_t)gy * pitch : 0));
+    constexpr int kLoadRows = 8;
+    for (int rb = ry; rb < in_h; rb += kRowStep * kLoadRows)
         for (int c = cx; c < in_w; c += 128) {
             const int gx = x0 - 2 * ax + c;
-            A[r * kOcLdsW + c] = (row_in && gx >= 0 && gx < W) ? srow[gx] : (T)id1;
+            const bool col_in = gx >= 0 && gx < W;
+            const int gxc = min(max(gx, 0), W - 1);
+            T v[kLoadRows];
+#pragma unroll
+            for (int k = 0; k < kLoadRows; ++k) {
+                const int gy = y0 - 2 * ay + rb + k * kRowStep;
+                const int gyc = min(max(gy, 0), H - 1);
+                v[k] = ((const T *)(src + (int64_t)gyc * pitch))[gxc];
+            }
+#pragma unroll
+            for (int k = 0; k < kLoadRows; ++k) {
+                const int r = rb + k * kRowStep;
+                const int gy = y0 - 2 * ay + r;
+                if (r < in_h) A[r * kOcLdsW + c] = (col_in && gy >= 0 && gy < H) ? v[k] : (T)id1;
+            }
         }
-    }
     __syncthreads();
 
     // 2. first operation, horizontal: B[r][c] = op1 of A[r][c .. c + wx - 1]
