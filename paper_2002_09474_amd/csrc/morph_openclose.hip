@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "morph_internal.h"
 
 namespace morph {
@@ -30,6 +32,23 @@ __device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b)
 {
     return IsMin ? (a < b ? a : b) : (a > b ? a : b);
 }
+
+// Calls fn(std::integral_constant<int, w>) for 1 <= w <= kOcMaxW, so that a pass's
+// per-tap loop has a compile-time trip count and unrolls (no loop control per pixel).
+template <typename Fn>
+__device__ __forceinline__ void with_window(int w, Fn &&fn)
+{
+    switch (w) {
+#define OC_CASE(n)                                                                            \
+    case n: fn(std::integral_constant<int, n>{}); break;
+        OC_CASE(1) OC_CASE(2) OC_CASE(3) OC_CASE(4) OC_CASE(5) OC_CASE(6) OC_CASE(7) OC_CASE(8)
+        OC_CASE(9) OC_CASE(10) OC_CASE(11) OC_CASE(12) OC_CASE(13) OC_CASE(14) OC_CASE(15)
+        OC_CASE(16)
+#undef OC_CASE
+    default: break;
+    }
+}
+static_assert(kOcMaxW == 16, "with_window covers windows 1..16");
 
 // FirstMin: the first operation is an erosion (opening), else a dilation (closing).
 template <typename T, bool FirstMin>
@@ -80,55 +99,68 @@ __global__ __launch_bounds__(kOcThreads) void openclose_kernel(const uint8_t *__
 
     // 2. first operation, horizontal: B[r][c] = op1 of A[r][c .. c + wx - 1]
     const int h1_w = kOcTileW + wx - 1;
-    for (int r = ry; r < in_h; r += kRowStep)
-        for (int c = cx; c < h1_w; c += 128) {
-            const T *a = &A[r * kOcLdsW + c];
-            uint32_t v = a[0];
-            for (int j = 1; j < wx; ++j) v = pick<FirstMin>(v, (uint32_t)a[j]);
-            B[r * kOcLdsW + c] = (T)v;
-        }
+    with_window(wx, [&](auto n) {
+        constexpr int N = decltype(n)::value;
+        for (int r = ry; r < in_h; r += kRowStep)
+            for (int c = cx; c < h1_w; c += 128) {
+                const T *a = &A[r * kOcLdsW + c];
+                uint32_t v = a[0];
+#pragma unroll
+                for (int j = 1; j < N; ++j) v = pick<FirstMin>(v, (uint32_t)a[j]);
+                B[r * kOcLdsW + c] = (T)v;
+            }
+    });
     __syncthreads();
 
     // 3. first operation, vertical, into A: the intermediate image at rows
     // y0 - ay + r, columns x0 - ax + c; positions outside the image take the
     // second operation's identity
     const int mid_h = kOcTileH + wy - 1;
-    for (int r = ry; r < mid_h; r += kRowStep) {
-        const int gy = y0 - ay + r;
-        const bool row_in = gy >= 0 && gy < H;
-        for (int c = cx; c < h1_w; c += 128) {
-            const int gx = x0 - ax + c;
-            uint32_t v = id2;
-            if (row_in && gx >= 0 && gx < W) {
+    with_window(wy, [&](auto n) {
+        constexpr int N = decltype(n)::value;
+        for (int r = ry; r < mid_h; r += kRowStep) {
+            const int gy = y0 - ay + r;
+            const bool row_in = gy >= 0 && gy < H;
+            for (int c = cx; c < h1_w; c += 128) {
+                const int gx = x0 - ax + c;
                 const T *b = &B[r * kOcLdsW + c];
-                v = b[0];
-                for (int i = 1; i < wy; ++i) v = pick<FirstMin>(v, (uint32_t)b[i * kOcLdsW]);
+                uint32_t v = b[0];
+#pragma unroll
+                for (int i = 1; i < N; ++i) v = pick<FirstMin>(v, (uint32_t)b[i * kOcLdsW]);
+                A[r * kOcLdsW + c] = (T)((row_in && gx >= 0 && gx < W) ? v : id2);
             }
-            A[r * kOcLdsW + c] = (T)v;
         }
-    }
+    });
     __syncthreads();
 
     // 4. second operation, horizontal: B[r][c] = op2 of A[r][c .. c + wx - 1]
-    for (int r = ry; r < mid_h; r += kRowStep) {
-        const T *a = &A[r * kOcLdsW + cx];
-        uint32_t v = a[0];
-        for (int j = 1; j < wx; ++j) v = pick<!FirstMin>(v, (uint32_t)a[j]);
-        B[r * kOcLdsW + cx] = (T)v;
-    }
+    with_window(wx, [&](auto n) {
+        constexpr int N = decltype(n)::value;
+        for (int r = ry; r < mid_h; r += kRowStep) {
+            const T *a = &A[r * kOcLdsW + cx];
+            uint32_t v = a[0];
+#pragma unroll
+            for (int j = 1; j < N; ++j) v = pick<!FirstMin>(v, (uint32_t)a[j]);
+            B[r * kOcLdsW + cx] = (T)v;
+        }
+    });
     __syncthreads();
 
     // 5. second operation, vertical, to the output tile
     const int gx = x0 + cx;
     if (gx >= W) return;
-    for (int r = ry; r < kOcTileH; r += kRowStep) {
-        const int gy = y0 + r;
-        if (gy >= H) break;
-        const T *b = &B[r * kOcLdsW + cx];
-        uint32_t v = b[0];
-        for (int i = 1; i < wy; ++i) v = pick<!FirstMin>(v, (uint32_t)b[i * kOcLdsW]);
-        ((T *)(dst + (int64_t)gy * pitch))[gx] = (T)v;
-    }
+    with_window(wy, [&](auto n) {
+        constexpr int N = decltype(n)::value;
+        for (int r = ry; r < kOcTileH; r += kRowStep) {
+            const int gy = y0 + r;
+            if (gy >= H) break;
+            const T *b = &B[r * kOcLdsW + cx];
+            uint32_t v = b[0];
+#pragma unroll
+            for (int i = 1; i < N; ++i) v = pick<!FirstMin>(v, (uint32_t)b[i * kOcLdsW]);
+            ((T *)(dst + (int64_t)gy * pitch))[gx] = (T)v;
+        }
+    });
 }
 
 static_assert(kOcTileW == 128, "one thread per output column of a tile row");
