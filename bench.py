@@ -40,9 +40,11 @@ def _log(msg):
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("morph_kernels.hip", "morph_api.hip", "morph_internal.h"):
-        with open(os.path.join(ROOT, "paper_2002_09474_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2002_09474_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

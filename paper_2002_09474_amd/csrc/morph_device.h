@@ -30,6 +30,7 @@
 // units are (line group, block): phase F writes g shifted by w - 1 into the output
 // slot it pairs with; phase B walks each block backwards, forms h on the fly and
 // combines it in place.  Per pixel that is three min/max ops whatever w is.
+#pragma once
 #include "morph_internal.h"
 
 #include <type_traits>
@@ -1997,328 +1998,13 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-template <typename T, bool MAXOP, bool AL>
-__global__ __launch_bounds__(NT) void tile_kernel(TileJob J)
-{
-    extern __shared__ uint32_t lds[];
-    tile_body<T, MAXOP, AL>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
-}
-
 typedef void (*TileKernelFn)(TileJob);
 
-// Rows are "aligned" when the pitch is a multiple of 4 bytes (uint8) or 8 bytes
-// (uint16): with the tile origin placed where the address is a multiple of the quad
-// size, each quad of 4 pixels in every row is then one natural load.  The image
-// must also span less than 4 GiB, so 32-bit offsets address it.
-__host__ __device__ inline bool rows_aligned(const TileJob &j)
-{
-    const uintptr_t m = j.dtype == 0 ? 3u : 7u;
-    const uint64_t span = (uint64_t)(j.H - 1) * (uint64_t)j.pitch + (uint64_t)j.W * (j.dtype ? 2 : 1);
-    return ((uintptr_t)j.pitch & m) == 0 && span + 8 < (1ull << 32);
-}
 
-static TileKernelFn pick_kernel(const TileJob &j)
-{
-    const bool al = rows_aligned(j);
-    if (j.dtype == 0) {
-        if (j.op) return al ? tile_kernel<uint8_t, true, true> : tile_kernel<uint8_t, true, false>;
-        return al ? tile_kernel<uint8_t, false, true> : tile_kernel<uint8_t, false, false>;
-    }
-    if (j.op) return al ? tile_kernel<uint16_t, true, true> : tile_kernel<uint16_t, true, false>;
-    return al ? tile_kernel<uint16_t, false, true> : tile_kernel<uint16_t, false, false>;
-}
-
-template <typename T, bool MAXOP, bool AL>
-__global__ __launch_bounds__(NT) void wave_kernel(TileJob J)
-{
-    const int units = J.tiles_x * J.tiles_y;
-    const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
-                                                 (int)(threadIdx.x >> 6));
-    if (u >= units) return; // the whole wave leaves
-    wave_body<T, MAXOP, AL>(J, u);
-}
-
-static TileKernelFn pick_wave_kernel(const TileJob &j)
-{
-    const bool al = rows_aligned(j);
-    if (j.dtype == 0) {
-        if (j.op) return al ? wave_kernel<uint8_t, true, true> : wave_kernel<uint8_t, true, false>;
-        return al ? wave_kernel<uint8_t, false, true> : wave_kernel<uint8_t, false, false>;
-    }
-    if (j.op) return al ? wave_kernel<uint16_t, true, true> : wave_kernel<uint16_t, true, false>;
-    return al ? wave_kernel<uint16_t, false, true> : wave_kernel<uint16_t, false, false>;
-}
-
-template <typename T, bool MAXOP, bool AL, bool RUNS>
-__global__ __launch_bounds__(64) void stream_kernel(TileJob J)
-{
-    extern __shared__ uint32_t lds[];
-    stream_body<T, MAXOP, AL, RUNS>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
-}
-
-template <bool RUNS>
-static TileKernelFn pick_stream_kernel_v(const TileJob &j)
-{
-    const bool al = rows_aligned(j);
-    if (j.dtype == 0) {
-        if (j.op) return al ? stream_kernel<uint8_t, true, true, RUNS> : stream_kernel<uint8_t, true, false, RUNS>;
-        return al ? stream_kernel<uint8_t, false, true, RUNS> : stream_kernel<uint8_t, false, false, RUNS>;
-    }
-    if (j.op) return al ? stream_kernel<uint16_t, true, true, RUNS> : stream_kernel<uint16_t, true, false, RUNS>;
-    return al ? stream_kernel<uint16_t, false, true, RUNS> : stream_kernel<uint16_t, false, false, RUNS>;
-}
-
-static TileKernelFn pick_stream_kernel(const TileJob &j)
-{
-    return stream_two_level(j.wy) ? pick_stream_kernel_v<true>(j) : pick_stream_kernel_v<false>(j);
-}
-
-template <typename T, bool MAXOP, bool AL>
-__global__ __launch_bounds__(NT) void rows_kernel(TileJob J)
-{
-    const int units = J.tiles_x * J.tiles_y;
-    const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
-                                                 (int)(threadIdx.x >> 6));
-    if (u >= units) return; // the whole wave leaves
-    __shared__ __align__(16) uint32_t lds[4 * kRowsWaveLdsDwords];
-    rows_body<T, MAXOP, AL>(J, u, lds + (threadIdx.x >> 6) * kRowsWaveLdsDwords);
-}
-
-static TileKernelFn pick_rows_kernel(const TileJob &j)
-{
-    const bool al = rows_aligned(j);
-    if (j.dtype == 0) {
-        if (j.op) return al ? rows_kernel<uint8_t, true, true> : rows_kernel<uint8_t, true, false>;
-        return al ? rows_kernel<uint8_t, false, true> : rows_kernel<uint8_t, false, false>;
-    }
-    if (j.op) return al ? rows_kernel<uint16_t, true, true> : rows_kernel<uint16_t, true, false>;
-    return al ? rows_kernel<uint16_t, false, true> : rows_kernel<uint16_t, false, false>;
-}
-
-template <typename T>
-__global__ __launch_bounds__(NT) void grad_kernel(TileJob J)
-{
-    const int units = J.tiles_x * J.tiles_y;
-    const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
-                                                 (int)(threadIdx.x >> 6));
-    if (u >= units) return; // the whole wave leaves
-    grad_body<T>(J, u);
-}
-
-// p - q clamped at 0
-template <typename T>
-__device__ __forceinline__ T sub_clamped(T p, T q)
-{
-    return p > q ? (T)(p - q) : (T)0;
-}
-
-// dst = dst - a (REV false) or a - dst (REV true), clamped at 0, pixel by pixel,
-// for the combinations composed from separate passes (gradient, top-hat,
-// black-hat): block b covers 256 pixels of row b / nseg
-template <typename T, bool REV>
-__global__ __launch_bounds__(256) void sub_kernel(const uint8_t *a, uint8_t *dst, int W,
-                                                  int64_t pitch, int nseg)
-{
-    const int y = blockIdx.x / nseg;
-    const int x = (blockIdx.x - y * nseg) * 256 + (int)threadIdx.x;
-    if (x >= W) return;
-    const T v = *((const GLOBAL T *)(a + (int64_t)y * pitch) + x);
-    GLOBAL T *d = (GLOBAL T *)(dst + (int64_t)y * pitch) + x;
-    *d = REV ? sub_clamped<T>(v, *d) : sub_clamped<T>(*d, v);
-}
-
-static hipError_t set_lds_limit(const void *fn, int lds)
+static inline hipError_t set_lds_limit(const void *fn, int lds)
 {
     if (lds <= 64 * 1024) return hipSuccess;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-}
-
-hipError_t launch_gradient_job(const TileJob &job, hipStream_t stream)
-{
-    const int units = job.tiles_x * job.tiles_y;
-    hipLaunchKernelGGL(job.dtype == 0 ? grad_kernel<uint8_t> : grad_kernel<uint16_t>,
-                       dim3((units + 3) / 4), dim3(NT), 0, stream, job);
-    return hipGetLastError();
-}
-
-// p - q clamped at 0 in each 16-bit half (v_pk_sub_u16 with clamp)
-__device__ __forceinline__ uint32_t pk_sub_clamped(uint32_t p, uint32_t q)
-{
-    const u16x2 x = __builtin_bit_cast(u16x2, p), y = __builtin_bit_cast(u16x2, q);
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(x, y));
-}
-
-// The same four bytes at a time, where a and dst have the same alignment: a thread
-// takes one 4-byte-aligned dword of a dst row (four uint8 pixels, widened to two
-// pairs, or two uint16 pixels) and subtracts with a clamp per pixel; dwords that
-// reach past either end of the row go pixel by pixel.
-template <typename T, bool REV>
-__global__ __launch_bounds__(256) void sub4_kernel(const uint8_t *a, uint8_t *dst,
-                                                   int64_t rowbytes, int64_t pitch, int nseg)
-{
-    const int y = blockIdx.x / nseg;
-    const int64_t k = (int64_t)(blockIdx.x - y * nseg) * 256 + threadIdx.x;
-    const uintptr_t rs = (uintptr_t)(dst + (int64_t)y * pitch), re = rs + (uintptr_t)rowbytes;
-    const uintptr_t A = (rs & ~(uintptr_t)3) + 4 * (uintptr_t)k;
-    if (A >= re) return;
-    const intptr_t delta = (intptr_t)a - (intptr_t)dst;
-    if (A >= rs && A + 4 <= re) {
-        const uint32_t v = load_u32(A + delta);
-        const uint32_t d = load_u32(A);
-        const uint32_t p = REV ? v : d, q = REV ? d : v;
-        if constexpr (sizeof(T) == 1) {
-            const uint32_t lo = pk_sub_clamped(perm(0u, p, SEL_U8_01), perm(0u, q, SEL_U8_01));
-            const uint32_t hi = pk_sub_clamped(perm(0u, p, SEL_U8_23), perm(0u, q, SEL_U8_23));
-            store_u32(A, perm(hi, lo, SEL_NARROW));
-        } else {
-            store_u32(A, pk_sub_clamped(p, q));
-        }
-    } else {
-        for (uintptr_t p = A > rs ? A : rs; p < A + 4 && p < re; p += sizeof(T)) {
-            const T v = *(const GLOBAL T *)(p + delta);
-            GLOBAL T *d = (GLOBAL T *)p;
-            *d = REV ? sub_clamped<T>(v, *d) : sub_clamped<T>(*d, v);
-        }
-    }
-}
-
-hipError_t launch_subtract(const void *a, void *dst, int H, int W, size_t pitch, int dtype,
-                           bool reverse, hipStream_t stream)
-{
-    if ((((uintptr_t)a - (uintptr_t)dst) & 3) == 0) {
-        const int64_t rowbytes = (int64_t)W * (dtype ? 2 : 1);
-        const int nseg = (int)(((rowbytes + 3) / 4 + 1 + 255) / 256);
-        if ((int64_t)nseg * H > INT32_MAX) return hipErrorInvalidValue;
-        typedef void (*Sub4Fn)(const uint8_t *, uint8_t *, int64_t, int64_t, int);
-        const Sub4Fn fn = dtype == 0 ? (reverse ? sub4_kernel<uint8_t, true> : sub4_kernel<uint8_t, false>)
-                                     : (reverse ? sub4_kernel<uint16_t, true> : sub4_kernel<uint16_t, false>);
-        hipLaunchKernelGGL(fn, dim3(nseg * H), dim3(256), 0, stream, (const uint8_t *)a,
-                           (uint8_t *)dst, rowbytes, (int64_t)pitch, nseg);
-        return hipGetLastError();
-    }
-    const int nseg = (W + 255) / 256;
-    if ((int64_t)nseg * H > INT32_MAX) return hipErrorInvalidValue;
-    typedef void (*SubFn)(const uint8_t *, uint8_t *, int, int64_t, int);
-    const SubFn fn = dtype == 0 ? (reverse ? sub_kernel<uint8_t, true> : sub_kernel<uint8_t, false>)
-                                : (reverse ? sub_kernel<uint16_t, true> : sub_kernel<uint16_t, false>);
-    hipLaunchKernelGGL(fn, dim3(nseg * H), dim3(256), 0, stream, (const uint8_t *)a,
-                       (uint8_t *)dst, W, (int64_t)pitch, nseg);
-    return hipGetLastError();
-}
-
-hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
-{
-    if (job.kind == KIND_ROWS) {
-        const int units = job.tiles_x * job.tiles_y;
-        hipLaunchKernelGGL(pick_rows_kernel(job), dim3((units + 3) / 4), dim3(NT), 0, stream, job);
-        return hipGetLastError();
-    }
-    if (job.kind == KIND_STREAM) {
-        TileKernelFn fn = pick_stream_kernel(job);
-        const int lds = lds_bytes(job);
-        hipError_t e = set_lds_limit((const void *)fn, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3(job.tiles_x * job.tiles_y), dim3(64), lds, stream, job);
-        return hipGetLastError();
-    }
-    if (job.kind == KIND_WAVE) {
-        const int units = job.tiles_x * job.tiles_y;
-        hipLaunchKernelGGL(pick_wave_kernel(job), dim3((units + 3) / 4), dim3(NT), 0, stream, job);
-        return hipGetLastError();
-    }
-    TileKernelFn fn = pick_kernel(job);
-    const int lds = lds_bytes(job);
-    hipError_t e = set_lds_limit((const void *)fn, lds);
-    if (e != hipSuccess) return e;
-    const int grid = job.tiles_x * job.tiles_y;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, stream, job);
-    return hipGetLastError();
-}
-
-// ---------------- persistent batch kernel ----------------
-// One launch per group of jobs sharing the element type and row alignment; erosion
-// and dilation jobs share it through the complement (tile_body's flip).  Every
-// workgroup takes tile indices from one atomic counter (counter[0]) until the group
-// is exhausted; a tile index is mapped to its image by binary search over the prefix
-// sums of tiles per image.  Every wave leaves the loop once the counter passes the
-// tile count, so the grid always drains.
-template <typename T, bool AL>
-__global__ __launch_bounds__(NT) void batch_kernel(BatchTables bt)
-{
-    extern __shared__ uint32_t lds[];
-    __shared__ long long next_tile;
-    constexpr uint32_t all_ones = Px<T>::maxv | (Px<T>::maxv << 16);
-    if (threadIdx.x == 0) next_tile = (long long)atomicAdd(bt.counter, 1ull);
-    __syncthreads();
-    long long t = next_tile;
-    while (t < bt.n_tiles) {
-        __syncthreads(); // everyone has read next_tile
-        // claim the following tile now, so the atomic's round trip overlaps this tile
-        if (threadIdx.x == 0) next_tile = (long long)atomicAdd(bt.counter, 1ull);
-        const int jb = bt.tile_job[t];
-        const TileJob J = bt.jobs[jb];
-        tile_body<T, false, AL>(J, (int)(t - bt.tile_start[jb]), lds, J.op ? all_ones : 0u);
-        __syncthreads(); // LDS is reused by the next tile; next_tile is visible
-        t = next_tile;
-    }
-    // The last workgroup to finish puts both counters back to zero for the next
-    // launch (every other workgroup has left the loop by then), so a replayed graph
-    // needs no separate reset.
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(bt.counter + 1, 1ull) == (unsigned long long)gridDim.x - 1) {
-            atomicExch(bt.counter, 0ull);
-            atomicExch(bt.counter + 1, 0ull);
-        }
-    }
-}
-
-
-// The batch form of the wave kernel: one wave per unit of the group's tile table (four
-// per workgroup), no persistence and no shared counter: units cost about the same,
-// so the hardware's workgroup dispatch balances them, and a hundred thousand small
-// units would serialise on one counter.
-template <typename T, bool AL>
-__global__ __launch_bounds__(NT) void batch_wave_kernel(BatchTables bt)
-{
-    const int t = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
-                                                 (int)(threadIdx.x >> 6));
-    if (t >= bt.n_tiles) return; // the whole wave leaves
-    const int jb = bt.tile_job[t];
-    const TileJob J = bt.jobs[jb];
-    const int u = (int)(t - bt.tile_start[jb]);
-    if (J.op) wave_body<T, true, AL>(J, u);
-    else wave_body<T, false, AL>(J, u);
-}
-
-// The batch form of the wide-row kernel: one wave per unit, four per workgroup.
-template <typename T, bool AL>
-__global__ __launch_bounds__(NT) void batch_rows_kernel(BatchTables bt)
-{
-    const int t = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
-                                                 (int)(threadIdx.x >> 6));
-    if (t >= bt.n_tiles) return; // the whole wave leaves
-    const int jb = bt.tile_job[t];
-    const TileJob J = bt.jobs[jb];
-    const int u = (int)(t - bt.tile_start[jb]);
-    __shared__ __align__(16) uint32_t lds[4 * kRowsWaveLdsDwords];
-    uint32_t *wl = lds + (threadIdx.x >> 6) * kRowsWaveLdsDwords;
-    if (J.op) rows_body<T, true, AL>(J, u, wl);
-    else rows_body<T, false, AL>(J, u, wl);
-}
-
-// The batch form of the stream kernel: one single-wave workgroup per unit.
-template <typename T, bool AL, bool RUNS>
-__global__ __launch_bounds__(64) void batch_stream_kernel(BatchTables bt)
-{
-    extern __shared__ uint32_t lds[];
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    if (t >= bt.n_tiles) return;
-    const int jb = bt.tile_job[t];
-    const TileJob J = bt.jobs[jb];
-    const int u = (int)(t - bt.tile_start[jb]);
-    if (J.op) stream_body<T, true, AL, RUNS>(J, u, lds);
-    else stream_body<T, false, AL, RUNS>(J, u, lds);
 }
 
 // Batches are launched per group of jobs with the same kernel kind, element type and
@@ -2350,48 +2036,5 @@ __global__ __launch_bounds__(64) void batch_fused_kernel(FusedTables ft)
         else wave_body<T, false, AL>(J, u);
     }
 }
-
-hipError_t launch_fused(const FusedTables &t, int dtype, bool aligned, int lds, hipStream_t stream)
-{
-    typedef void (*FusedFn)(FusedTables);
-    const FusedFn fn = dtype == 0 ? (aligned ? batch_fused_kernel<uint8_t, true> : batch_fused_kernel<uint8_t, false>)
-                                  : (aligned ? batch_fused_kernel<uint16_t, true> : batch_fused_kernel<uint16_t, false>);
-    hipError_t e = set_lds_limit((const void *)fn, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(t.b0[kFusedClasses]), dim3(64), lds, stream, t);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, bool aligned, int grid,
-                        int lds, hipStream_t stream)
-{
-    typedef void (*BatchFn)(BatchTables);
-    BatchFn fn;
-    int block = NT;
-    if (kind == KIND_ROWS)
-        fn = dtype == 0 ? (aligned ? batch_rows_kernel<uint8_t, true> : batch_rows_kernel<uint8_t, false>)
-                        : (aligned ? batch_rows_kernel<uint16_t, true> : batch_rows_kernel<uint16_t, false>);
-    else if (kind == KIND_WAVE)
-        fn = dtype == 0 ? (aligned ? batch_wave_kernel<uint8_t, true> : batch_wave_kernel<uint8_t, false>)
-                        : (aligned ? batch_wave_kernel<uint16_t, true> : batch_wave_kernel<uint16_t, false>);
-    else if (kind == KIND_STREAM) {
-        if (variant)
-            fn = dtype == 0 ? (aligned ? batch_stream_kernel<uint8_t, true, true> : batch_stream_kernel<uint8_t, false, true>)
-                            : (aligned ? batch_stream_kernel<uint16_t, true, true> : batch_stream_kernel<uint16_t, false, true>);
-        else
-            fn = dtype == 0 ? (aligned ? batch_stream_kernel<uint8_t, true, false> : batch_stream_kernel<uint8_t, false, false>)
-                            : (aligned ? batch_stream_kernel<uint16_t, true, false> : batch_stream_kernel<uint16_t, false, false>);
-        block = 64;
-    }
-    else
-        fn = dtype == 0 ? (aligned ? batch_kernel<uint8_t, true> : batch_kernel<uint8_t, false>)
-                        : (aligned ? batch_kernel<uint16_t, true> : batch_kernel<uint16_t, false>);
-    hipError_t e = set_lds_limit((const void *)fn, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, stream, t);
-    return hipGetLastError();
-}
-
-bool job_rows_aligned(const TileJob &j) { return rows_aligned(j); }
 
 } // namespace morph

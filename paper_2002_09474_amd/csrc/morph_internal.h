@@ -80,6 +80,11 @@ inline int lds_bytes(const TileJob &j)
 
 // kernels (morph_kernels.hip)
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);
+// one launcher per kernel family (each family is a translation unit of its own)
+hipError_t launch_tile_kernel(const TileJob &job, hipStream_t stream);
+hipError_t launch_wave_kernel(const TileJob &job, hipStream_t stream);
+hipError_t launch_stream_kernel(const TileJob &job, hipStream_t stream);
+hipError_t launch_rows_kernel(const TileJob &job, hipStream_t stream);
 // the morphological gradient of a wave-kernel job (kind KIND_WAVE, rows aligned):
 // both extrema from one read, their difference stored
 hipError_t launch_gradient_job(const TileJob &job, hipStream_t stream);
@@ -124,9 +129,29 @@ struct FusedTables {
 };
 constexpr int kFusedClasses = 3;
 hipError_t launch_fused(const FusedTables &t, int dtype, bool aligned, int lds, hipStream_t stream);
+hipError_t launch_fused_u8(const FusedTables &t, bool aligned, int lds, hipStream_t stream);
+hipError_t launch_fused_u16(const FusedTables &t, bool aligned, int lds, hipStream_t stream);
+hipError_t launch_batch_tile(const BatchTables &t, int dtype, bool aligned, int grid, int lds,
+                             hipStream_t stream);
+hipError_t launch_batch_wave(const BatchTables &t, int dtype, bool aligned, int grid,
+                             hipStream_t stream);
+hipError_t launch_batch_rows(const BatchTables &t, int dtype, bool aligned, int grid,
+                             hipStream_t stream);
+hipError_t launch_batch_stream(const BatchTables &t, bool runs, int dtype, bool aligned, int grid,
+                               int lds, hipStream_t stream);
 // output quads of a stream-kernel strip for a horizontal window wx (worst-case
 // origin offset 3): the last one's input, 4Q + 3 + wx + 2, must lie in 64 quads
 inline int stream_quads(int wx) { return (250 - wx) / 4 + 1; }
-bool job_rows_aligned(const TileJob &j);
+// Rows are "aligned" when the pitch is a multiple of 4 bytes (uint8) or 8 bytes
+// (uint16): with the tile origin placed where the address is a multiple of the quad
+// size, each quad of 4 pixels in every row is then one natural load.  The image
+// must also span less than 4 GiB, so 32-bit offsets address it.
+__host__ __device__ inline bool rows_aligned(const TileJob &j)
+{
+    const uintptr_t m = j.dtype == 0 ? 3u : 7u;
+    const uint64_t span = (uint64_t)(j.H - 1) * (uint64_t)j.pitch + (uint64_t)j.W * (j.dtype ? 2 : 1);
+    return ((uintptr_t)j.pitch & m) == 0 && span + 8 < (1ull << 32);
+}
+inline bool job_rows_aligned(const TileJob &j) { return rows_aligned(j); }
 
 } // namespace morph
