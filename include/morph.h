@@ -202,6 +202,24 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
                 int wx, int wy, int anchor_x, int anchor_y, int border,
                 const morph_plan *plan, void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): morph_apply with the
+ * workspace taken from a fixed device array of MORPH_STATIC_SCRATCH_BYTES bytes
+ * that the library holds on each GPU it runs on until the process ends, so that
+ * nothing is allocated on any call.  Every argument as for morph_apply.  The ops
+ * that need a workspace there (OPEN, CLOSE, TOPHAT, BLACKHAT, and GRADIENT where
+ * its one-pass form does not apply) need H * pitch <= MORPH_STATIC_SCRATCH_BYTES,
+ * else MORPH_ENOMEM and nothing is enqueued; ERODE and DILATE use no workspace.
+ * All calls on one GPU share its array: calls whose work overlaps on the device
+ * (other streams, other threads) race on it, so the caller serializes them, e.g.
+ * on one stream.  The array's contents after a call are unspecified (every call
+ * writes the intermediate before reading it).  The first call on a device looks
+ * the array's address up (hipGetSymbolAddress) and may return MORPH_EHIP. */
+#define MORPH_STATIC_SCRATCH_BYTES (64u << 20)
+int morph_apply_static(int op, int dtype, const void *src, void *dst, int H, int W,
+                       size_t pitch, int wx, int wy, int anchor_x, int anchor_y, int border,
+                       const morph_plan *plan, hipStream_t stream);
+
 /* ---- batched launch ---------------------------------------------------------
  * Many images of uneven sizes, windows and ops in a few kernel launches, one per
  * group of images sharing a kernel kind, element type and row alignment.  Images

@@ -19,7 +19,8 @@ import os
 from . import _lib
 from ._lib import MorphError, Plan  # noqa: F401
 
-__all__ = ["erode", "dilate", "opening", "closing", "gradient", "tophat", "blackhat", "apply", "Batch", "workspace_bytes",
+__all__ = ["erode", "dilate", "opening", "closing", "gradient", "tophat", "blackhat", "apply",
+           "apply_static", "Batch", "workspace_bytes",
            "openclose_fused", "transpose", "transpose_blocks",
            "load_tuning", "get_thresholds", "set_thresholds", "resolve_plan", "MorphError",
            "version"]
@@ -102,6 +103,34 @@ def apply(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = 
                                 ws_ptr, ws_bytes, _stream_ptr(stream))
     _lib.check(rc, "morph_apply(%s, %dx%d)" % (op, wx, wy))
     return out
+
+
+def apply_static(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = -1,
+                 out=None, method_x: str | None = None, method_y: str | None = None, tile=None,
+                 stream=None):
+    """``apply`` without a workspace argument: ops that need one take it from the
+    library's fixed per-GPU array (``morph_apply_static``; images of up to
+    ``STATIC_SCRATCH_BYTES`` bytes of rows), so that the call allocates nothing.
+    Calls whose work overlaps on one GPU share that array and must be serialized."""
+    torch = _torch()
+    wy = wx if wy is None else wy
+    code = _lib.OP_CODES[op]
+    dt = dtype_code(src.dtype)
+    H, W, pitch = _geom(src)
+    if out is None:
+        out = torch.empty_strided(src.shape, src.stride(), dtype=src.dtype, device=src.device)
+    if out.shape != src.shape or out.dtype != src.dtype or _geom(out)[2] != pitch:
+        raise ValueError("out must match src in shape, dtype and row pitch")
+    plan = _plan(method_x, method_y, tile)
+    rc = _lib.lib().morph_apply_static(code, dt, src.data_ptr(), out.data_ptr(), H, W, pitch,
+                                       wx, wy, ax, ay, 0,
+                                       ctypes.byref(plan) if plan is not None else None,
+                                       _stream_ptr(stream))
+    _lib.check(rc, "morph_apply_static(%s, %dx%d)" % (op, wx, wy))
+    return out
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # MORPH_STATIC_SCRATCH_BYTES
 
 
 def openclose_fused(op: str, src, wx: int, wy: int | None = None, ax: int = -1, ay: int = -1,

@@ -39,7 +39,7 @@ EXPORTS = (
     "morph_batch_launch",
     "morph_batch_tiles", "morph_batch_destroy", "morph_load_tuning", "morph_get_thresholds",
     "morph_set_thresholds", "morph_resolve_plan", "morph_strerror", "morph_last_hip_error",
-    "morph_version",
+    "morph_version", "morph_apply_static",
 )
 
 
@@ -111,6 +111,8 @@ def lib():
     L.morph_workspace_bytes.restype = Z
     L.morph_apply.argtypes = [I, I, P, P, I, I, Z, I, I, I, I, I, ctypes.POINTER(Plan), P, Z, P]
     L.morph_apply.restype = I
+    L.morph_apply_static.argtypes = [I, I, P, P, I, I, Z, I, I, I, I, I, ctypes.POINTER(Plan), P]
+    L.morph_apply_static.restype = I
     L.morph_batch_create.argtypes = [I, I64, ctypes.POINTER(P)]
     L.morph_batch_create.restype = I
     L.morph_batch_set.argtypes = [P, ctypes.POINTER(Desc), I, P]

@@ -459,6 +459,10 @@ int run_single(int op, int dtype, const void *src, void *dst, int H, int W, size
 
 } // namespace
 
+namespace morph {
+int record_hip_error(hipError_t e) { return hip_fail(e); }
+} // namespace morph
+
 // ---------------- C ABI ----------------
 extern "C" {
 

@@ -78,6 +78,10 @@ inline int lds_bytes(const TileJob &j)
     return (j.TB * j.SA + (b > j.vtt ? b : j.vtt)) * 4;
 }
 
+// Keep e as the calling thread's last HIP error (morph_last_hip_error) and return
+// MORPH_EHIP (-4).
+int record_hip_error(hipError_t e);
+
 // kernels (morph_kernels.hip)
 hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);
 // one launcher per kernel family (each family is a translation unit of its own)

@@ -1,0 +1,74 @@
+"""The allocation-free entry point (morph_apply_static): for callers that cannot
+allocate device memory, the workspace of opening, closing, top-hat, black-hat and
+the composed gradient comes from the library's fixed per-GPU array.  Its output
+must equal morph_apply's (caller workspace) bit for bit, call after call, also
+when a smaller image follows a larger one in the same array; an image whose
+intermediate does not fit is refused before anything is enqueued."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2002_09474_amd as morph  # noqa: E402
+from paper_2002_09474_amd import _lib, synth  # noqa: E402
+from gpuutil import to_dev, to_host  # noqa: E402
+
+SCRATCH = 64 << 20
+
+
+def _static(op, dt, src, dst, wx, wy):
+    H, W = src.shape
+    pitch = src.stride(0) * src.element_size()
+    return _lib.lib().morph_apply_static(_lib.OP_CODES[op], dt, src.data_ptr(), dst.data_ptr(),
+                                         H, W, pitch, wx, wy, -1, -1, 0, None,
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_static_matches_workspace_entry_point(dtype):
+    dt = _lib.U8 if dtype == np.uint8 else _lib.U16
+    # first call large (4096 x 4096 plus a padded pitch: 16.8 / 33.6 MB of rows),
+    # then a smaller, ragged one in the same array
+    cases = [((4096, 4096), 4096 + 64, "open", 9, 9), ((517, 389), 389 + 3, "close", 15, 7),
+             ((300, 1001), 1001, "tophat", 5, 3), ((257, 130), 131, "blackhat", 31, 31),
+             ((129, 77), 77, "gradient", 21, 15), ((64, 64), 64, "erode", 3, 3)]
+    for (H, W), pitch, op, wx, wy in cases:
+        img = synth.uniform(H, W, dtype, seed=H * 7 + W)
+        src, _ = to_dev(img, pitch_elems=pitch)
+        ref, _ = to_dev(np.zeros_like(img), pitch_elems=pitch)
+        got, _ = to_dev(np.zeros_like(img), pitch_elems=pitch)
+        morph.apply(op, src, wx, wy, out=ref)
+        rc = _static(op, dt, src, got, wx, wy)
+        assert rc == 0, (op, H, W, _lib._strerror(rc))
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(got), to_host(ref)), (op, H, W, wx, wy)
+        # the binding's wrapper of the same entry point
+        again = morph.apply_static(op, src, wx, wy)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(again), to_host(ref)), (op, H, W, wx, wy, "binding")
+
+
+def test_static_refuses_an_intermediate_larger_than_the_array():
+    # 8193 rows of 8192 bytes = 64 MiB + 8 KiB: one row more than the array holds
+    src = torch.zeros((8193, 8192), dtype=torch.uint8, device="cuda")
+    dst = torch.full_like(src, 7)
+    assert _static("open", _lib.U8, src, dst, 3, 3) == _lib.MORPH_ENOMEM
+    torch.cuda.synchronize()
+    assert int(dst.min()) == 7 and int(dst.max()) == 7  # nothing was enqueued
+    # the largest image that fits: 8192 rows of 8192 bytes, a 1x1 window copy
+    src2 = src[:8192]
+    dst2 = dst[:8192]
+    src2.random_(0, 256)
+    assert _static("open", _lib.U8, src2, dst2, 1, 1) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(dst2, src2)
+    # erosion and dilation need no workspace, whatever the size
+    assert _static("erode", _lib.U8, src, dst, 1, 1) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
