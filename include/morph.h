@@ -197,7 +197,7 @@ int morph_blackhat_u16(const void *src, void *dst, int H, int W, size_t pitch, i
  * optional plan (NULL = tuned defaults).  workspace is needed only for OPEN,
  * CLOSE, TOPHAT and BLACKHAT, and for GRADIENT where its one-pass form does not
  * apply (see morph_gradient).  The named entry points above are this call with plan = NULL.
- * Batch descriptors take ERODE and DILATE only. */
+ * Batch descriptors take ERODE, DILATE, OPEN and CLOSE. */
 int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
                 int wx, int wy, int anchor_x, int anchor_y, int border,
                 const morph_plan *plan, void *workspace, size_t ws_bytes, hipStream_t stream);
@@ -227,7 +227,12 @@ int morph_apply_static(int op, int dtype, const void *src, void *dst, int H, int
  * (a unit table, no shared state); the others to a persistent kernel whose
  * workgroups take tiles from an atomic work queue.  Not in the paper (which
  * handles one image at a time); it applies the same per-image computation, so
- * every image's result equals its single-image call. */
+ * every image's result equals its single-image call.
+ * Openings and closings (§2: an opening is the dilation of the erosion, a closing
+ * the erosion of the dilation, same rectangle and anchor) run as two phases of the
+ * same launch: every first operation (into an intermediate image in the caller's
+ * workspace) with the batch's erosions and dilations, then every second operation
+ * (from the intermediate into dst). */
 typedef struct morph_desc {
     const void *src;
     void *dst;
@@ -235,7 +240,7 @@ typedef struct morph_desc {
     int64_t pitch;     /* bytes between source rows */
     int32_t wx, wy;
     int32_t ax, ay;    /* -1 = Eq. (1) placement */
-    int32_t op;        /* MORPH_OP_ERODE or MORPH_OP_DILATE */
+    int32_t op;        /* MORPH_OP_ERODE, _DILATE, _OPEN or _CLOSE */
     int32_t dtype;     /* MORPH_U8 or MORPH_U16 */
     int64_t dst_pitch; /* bytes between destination rows; 0 = pitch */
 } morph_desc;
@@ -243,30 +248,47 @@ typedef struct morph_desc {
 typedef struct morph_batch *morph_batch_t;
 
 /* Create a batch object able to hold up to max_images descriptors and max_tiles
- * tiles (work units) in total, 1 <= max_tiles < 2^31 - 4, else MORPH_EINVAL.  It owns device tables (descriptors, tile prefix sums, a job
- * index per tile: 4 bytes per tile, queue counters) and pinned staging copies of
- * them, allocated here, once; nothing is allocated per launch. */
+ * tiles (work units) in total (an opening or closing counts its tiles twice),
+ * 1 <= max_tiles < 2^31 - 4, else MORPH_EINVAL.  It owns device tables (two jobs
+ * per descriptor, tile prefix sums, a job index per tile: 4 bytes per tile, queue
+ * counters) and pinned staging copies of them, allocated here, once; nothing is
+ * allocated per launch. */
 int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out);
-/* Validate n descriptors (as the single-image calls do; overlapping src/dst of one
- * descriptor -> MORPH_EALIAS), plan their tiles and copy the tables to the device
- * on `stream`, staged through pinned memory owned by the batch (a later set first
- * waits, on the host, for that copy to finish).  Launches enqueued before a set
- * on the same stream read the old tables.  Too many images or tiles ->
- * MORPH_ENOMEM. */
+/* Validate n descriptors (as the single-image calls do; an op other than ERODE,
+ * DILATE, OPEN, CLOSE -> MORPH_EINVAL; overlapping src/dst of one descriptor ->
+ * MORPH_EALIAS), plan their tiles and copy the tables to the device on `stream`,
+ * staged through pinned memory owned by the batch (a later set first waits, on the
+ * host, for that copy to finish).  Launches enqueued before a set on the same
+ * stream read the old tables; launch the batch on the stream of its set (or
+ * synchronize first).  Too many images or tiles -> MORPH_ENOMEM.  An invalid
+ * descriptor leaves the previous batch in place; a failure after the tables
+ * started to change (MORPH_ENOMEM for tiles, MORPH_EHIP) leaves the batch without
+ * work: enqueue and launch return MORPH_EINVAL until a set succeeds. */
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream);
-/* Enqueue the whole batch on `stream`: one kernel dispatch for the wave and
- * streaming units of each element type and row alignment (long streaming units
- * dealt out first), then the tile and wide-row groups' kernels (the last
+/* Enqueue the whole batch on `stream`: per phase, one kernel dispatch for the
+ * wave and streaming units of each element type and row alignment (long streaming
+ * units dealt out first), then the tile and wide-row groups' kernels (the last
  * workgroup of a persistent one leaves its queue counter at zero for the next
- * launch).  The first call
- * on a stream captures the launch into a hipGraph that later calls replay; the
- * graph is re-captured when the stream or the batch's shape changes.  Launches of
- * one batch object must not overlap (they share the counter).  workspace /
- * ws_bytes are reserved (pass NULL, 0). */
+ * launch).  The first call on a stream captures the launch into a hipGraph that
+ * later calls replay; the graph is re-captured when the stream or the batch's
+ * shape changes.  Launches of one batch object must not overlap (they share the
+ * counter and the job table).
+ * workspace / ws_bytes: device memory for the intermediates of the batch's
+ * openings and closings, at least morph_batch_workspace_bytes(b) bytes (else
+ * MORPH_ENOMEM; NULL, 0 when the batch has none).  It must not overlap any
+ * image of the batch (MORPH_EALIAS) and is in use until the stream has passed the
+ * launch.  When it differs from the previous launch's, the job table is rewritten
+ * (pinned staging, an asynchronous copy on `stream` ahead of the launch; the host
+ * first waits for the previous such copy). */
 int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream);
 /* Enqueue the batch on `stream` as plain kernel launches, without a graph: for
- * callers whose batch changes on every launch (a serving loop). */
-int morph_batch_launch(morph_batch_t b, hipStream_t stream);
+ * callers whose batch changes on every launch (a serving loop).  workspace /
+ * ws_bytes as for morph_batch_enqueue. */
+int morph_batch_launch(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream);
+/* Bytes of workspace the current batch's openings and closings need (0 if none):
+ * one intermediate per such image, rows of W elements padded to 64 bytes, each
+ * image starting on a 256-byte boundary. */
+size_t morph_batch_workspace_bytes(morph_batch_t b);
 /* Number of tiles of the current batch (after morph_batch_set), or -1. */
 int64_t morph_batch_tiles(morph_batch_t b);
 /* Free the device tables and graphs.  The caller must have synchronized. */

@@ -238,8 +238,8 @@ class Batch:
 
     def set(self, items, stream=None) -> int:
         """items: iterable of dicts with src, dst (tensors of the same shape and dtype;
-        each may have its own row pitch), wx, wy, op ("erode" / "dilate") and
-        optional ax, ay.  Returns the number of tiles."""
+        each may have its own row pitch), wx, wy, op ("erode", "dilate", "open",
+        "close") and optional ax, ay.  Returns the number of tiles."""
         items = list(items)
         arr = (_lib.Desc * max(1, len(items)))()
         keep = []
@@ -263,14 +263,40 @@ class Batch:
     def tiles(self) -> int:
         return int(_lib.lib().morph_batch_tiles(self._h))
 
-    def enqueue(self, stream=None) -> None:
-        """Graph-replayed launch (captured on first use per stream and layout)."""
-        _lib.check(_lib.lib().morph_batch_enqueue(self._h, None, 0, _stream_ptr(stream)),
+    @property
+    def workspace_bytes(self) -> int:
+        """Device bytes the current batch's openings and closings need."""
+        return int(_lib.lib().morph_batch_workspace_bytes(self._h))
+
+    def _workspace(self, workspace, stream=None):
+        """(pointer, bytes) of the workspace to pass: the caller's, else one kept by
+        this object and grown as the batch needs (torch device memory)."""
+        need = self.workspace_bytes
+        if need == 0:
+            return None, 0
+        if workspace is None:
+            ws = getattr(self, "_ws", None)
+            if ws is None or ws.numel() < need:
+                torch = _torch()
+                dev = self._keep[0][0].device if self._keep else torch.device("cuda")
+                if ws is not None and stream is not None:
+                    ws.record_stream(stream)  # the last launch may still use it
+                self._ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            workspace = self._ws
+        return workspace.data_ptr(), workspace.numel() * workspace.element_size()
+
+    def enqueue(self, stream=None, workspace=None) -> None:
+        """Graph-replayed launch (captured on first use per stream and layout).
+        ``workspace``: a device tensor for the openings' and closings'
+        intermediates (``workspace_bytes`` bytes); by default one kept here."""
+        ptr, nb = self._workspace(workspace, stream)
+        _lib.check(_lib.lib().morph_batch_enqueue(self._h, ptr, nb, _stream_ptr(stream)),
                    "morph_batch_enqueue")
 
-    def launch(self, stream=None) -> None:
+    def launch(self, stream=None, workspace=None) -> None:
         """Plain launch without a graph, for batches that change every time."""
-        _lib.check(_lib.lib().morph_batch_launch(self._h, _stream_ptr(stream)),
+        ptr, nb = self._workspace(workspace, stream)
+        _lib.check(_lib.lib().morph_batch_launch(self._h, ptr, nb, _stream_ptr(stream)),
                    "morph_batch_launch")
 
     def close(self) -> None:

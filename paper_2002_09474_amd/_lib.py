@@ -36,7 +36,7 @@ EXPORTS = (
     "morph_tophat_u16", "morph_blackhat_u16",
     "morph_transpose", "morph_transpose_u16", "morph_transpose_blocks",
     "morph_openclose_fused", "morph_apply", "morph_batch_create", "morph_batch_set", "morph_batch_enqueue",
-    "morph_batch_launch",
+    "morph_batch_launch", "morph_batch_workspace_bytes",
     "morph_batch_tiles", "morph_batch_destroy", "morph_load_tuning", "morph_get_thresholds",
     "morph_set_thresholds", "morph_resolve_plan", "morph_strerror", "morph_last_hip_error",
     "morph_version", "morph_apply_static",
@@ -119,8 +119,10 @@ def lib():
     L.morph_batch_set.restype = I
     L.morph_batch_enqueue.argtypes = [P, P, Z, P]
     L.morph_batch_enqueue.restype = I
-    L.morph_batch_launch.argtypes = [P, P]
+    L.morph_batch_launch.argtypes = [P, P, Z, P]
     L.morph_batch_launch.restype = I
+    L.morph_batch_workspace_bytes.argtypes = [P]
+    L.morph_batch_workspace_bytes.restype = Z
     L.morph_batch_tiles.argtypes = [P]
     L.morph_batch_tiles.restype = I64
     L.morph_batch_destroy.argtypes = [P]

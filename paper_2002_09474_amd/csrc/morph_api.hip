@@ -729,8 +729,16 @@ const char *morph_version(void) { return "morph-gfx950 0.1"; }
 struct BatchGroup {
     int job0 = 0, njobs = 0; // jobs [job0, job0 + njobs) of the (group-sorted) table
     int64_t tiles = 0;
-    int lds = 0, grid = 0, dtype = 0, kind = 0, variant = 0;
+    int lds = 0, grid = 0, dtype = 0, kind = 0, variant = 0, phase = 0;
     bool aligned = true;
+};
+
+// A job of the table that reads or writes an intermediate image in the enqueue
+// workspace: its pointer is set to workspace + offset when the workspace is bound.
+struct WsPatch {
+    int job;        // index into the job table
+    bool writes;    // first operation (dst = intermediate) or second (src = intermediate)
+    size_t offset;  // bytes from the workspace start
 };
 
 // groups: kernel kind x element type x row alignment, and for the streaming kernel
@@ -738,7 +746,12 @@ struct BatchGroup {
 static constexpr int kRingClasses = 2;
 // group classes: tile, wave, streaming (ring), streaming (run totals), wide rows
 static constexpr int kGroupClasses = kKinds + kRingClasses - 1;
-static constexpr int kBatchGroups = 4 * kGroupClasses;
+static constexpr int kPhaseGroups = 4 * kGroupClasses;
+// an opening or closing descriptor is two jobs: its first operation (src into the
+// workspace) in phase 0 with every erosion and dilation, its second (workspace into
+// dst) in phase 1, launched after all of phase 0
+static constexpr int kPhases = 2;
+static constexpr int kBatchGroups = kPhases * kPhaseGroups;
 
 struct morph_batch {
     int max_images = 0;
@@ -761,6 +774,14 @@ struct morph_batch {
     // previous copy before it overwrites them
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
+    // openings and closings: intermediates in the caller's workspace
+    std::vector<WsPatch> ws_patch;
+    size_t ws_needed = 0;          // bytes of workspace the current batch needs
+    const void *ws_bound = nullptr; // workspace the device job table points into
+    int n_jobs = 0;                 // jobs in the table
+    TileJob *h_jobs_ws = nullptr;  // pinned staging of the job table with the pointers set
+    hipEvent_t ws_staged = nullptr; // its copy to the device
+    bool ws_staged_pending = false;
 };
 
 
@@ -789,10 +810,11 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
     morph_batch *b = new morph_batch();
     b->max_images = max_images;
     b->max_tiles = max_tiles;
-    const size_t nstart = (size_t)max_images + kBatchGroups;
+    const size_t njobs = (size_t)kPhases * max_images; // an opening/closing is two jobs
+    const size_t nstart = njobs + kBatchGroups;
     const size_t ncount = 2 * kBatchGroups;
     hipError_t e;
-    if ((e = hipMalloc((void **)&b->d_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
+    if ((e = hipMalloc((void **)&b->d_jobs, sizeof(TileJob) * njobs)) != hipSuccess ||
         (e = hipMalloc((void **)&b->d_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
         (e = hipMalloc((void **)&b->d_tile_job, sizeof(int32_t) * (size_t)max_tiles)) !=
             hipSuccess ||
@@ -801,7 +823,9 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
         (e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long) * ncount)) !=
             hipSuccess ||
         (e = hipMemset(b->d_counter, 0, sizeof(unsigned long long) * ncount)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * max_images)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * njobs)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_jobs_ws, sizeof(TileJob) * njobs)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->ws_staged, hipEventDisableTiming)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess) {
         morph_batch_destroy(b);
@@ -813,22 +837,26 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
 
 // Group index of a job: (dtype, alignment) in the low two bits; above them the
 // kernel kind, the streaming kernel split by ring size.
-static int group_of(const TileJob &j)
+static int group_of(const TileJob &j, int phase)
 {
     int k = j.kind;
     if (j.kind == KIND_STREAM && stream_two_level(j.wy)) k = KIND_STREAM + 1;
     else if (j.kind == KIND_ROWS) k = kGroupClasses - 1;
-    return 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
+    return phase * kPhaseGroups + 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
 }
 
-// Launch order of the groups: streaming groups (run totals, then ring), then the
-// tile, wave and wide-row groups.
+// Launch order of the groups: phase 0 before phase 1; within a phase the streaming
+// groups (run totals, then ring), then the tile, wave and wide-row groups.
 static int group_order(int gi)
 {
     static const int order[kGroupClasses] = {KIND_STREAM + 1, KIND_STREAM, KIND_TILE, KIND_WAVE,
                                              kGroupClasses - 1};
-    return 4 * order[gi / 4] + gi % 4;
+    const int ph = gi / kPhaseGroups, r = gi % kPhaseGroups;
+    return ph * kPhaseGroups + 4 * order[r / 4] + r % 4;
 }
+
+// Row pitch of an intermediate image in the workspace: whole 64-byte granules.
+static size_t ws_pitch(int W, int dtype) { return ((size_t)W * elem_bytes(dtype) + 63) & ~(size_t)63; }
 
 int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t stream)
 {
@@ -840,9 +868,13 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         b->staged_pending = false;
     }
     std::vector<TileJob> jobs[kBatchGroups];
+    // per group, for each job: the workspace offset of its intermediate and whether
+    // it writes (first operation) or reads it (second); -1 = none
+    std::vector<std::pair<int64_t, bool>> wsrole[kBatchGroups];
+    size_t ws_total = 0;
     for (int i = 0; i < n; i++) {
         const morph_desc &d = descs[i];
-        if (d.op != MORPH_OP_ERODE && d.op != MORPH_OP_DILATE) return MORPH_EINVAL;
+        if (d.op < MORPH_OP_ERODE || d.op > MORPH_OP_CLOSE) return MORPH_EINVAL;
         if (d.pitch < 0 || d.dst_pitch < 0) return MORPH_EINVAL;
         const size_t dp = d.dst_pitch ? (size_t)d.dst_pitch : (size_t)d.pitch;
         int rc = check_image(d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, d.wx, d.wy, d.ax,
@@ -854,10 +886,34 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
                            image_span(d.H, d.W, dp, d.dtype)))
             return MORPH_EALIAS;
         TileJob j;
-        rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, dp, d.wx, d.wy, d.ax,
+        if (d.op == MORPH_OP_ERODE || d.op == MORPH_OP_DILATE) {
+            rc = plan_job(d.op, d.dtype, d.src, d.dst, d.H, d.W, (size_t)d.pitch, dp, d.wx, d.wy,
+                          d.ax, d.ay, nullptr, j, true);
+            if (rc != MORPH_OK) return rc;
+            const int g = group_of(j, 0);
+            jobs[g].push_back(j);
+            wsrole[g].push_back({-1, false});
+            continue;
+        }
+        // opening = dilate(erode(src)), closing = erode(dilate(src)) (§2): the first
+        // operation into an intermediate in the workspace (placed when the workspace
+        // is bound at enqueue; null until then), the second from it into dst
+        const int first = d.op == MORPH_OP_OPEN ? MORPH_OP_ERODE : MORPH_OP_DILATE;
+        const size_t wp = ws_pitch(d.W, d.dtype);
+        const size_t off = ws_total;
+        ws_total += ((size_t)d.H * wp + 255) & ~(size_t)255;
+        rc = plan_job(first, d.dtype, d.src, nullptr, d.H, d.W, (size_t)d.pitch, wp, d.wx, d.wy,
+                      d.ax, d.ay, nullptr, j, true);
+        if (rc != MORPH_OK) return rc;
+        int g = group_of(j, 0);
+        jobs[g].push_back(j);
+        wsrole[g].push_back({(int64_t)off, true});
+        rc = plan_job(1 - first, d.dtype, nullptr, d.dst, d.H, d.W, wp, dp, d.wx, d.wy, d.ax,
                       d.ay, nullptr, j, true);
         if (rc != MORPH_OK) return rc;
-        jobs[group_of(j)].push_back(j);
+        g = group_of(j, 1);
+        jobs[g].push_back(j);
+        wsrole[g].push_back({(int64_t)off, false});
     }
     // a batch of few or small images (a serving loop's micro-batch, often one image)
     // would have too few wave and streaming units to fill the GPU: as for a single
@@ -892,7 +948,13 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
                         }
         }
     }
+    // from here on the staged tables change: until this set succeeds the batch has no
+    // work (enqueue and launch return MORPH_EINVAL)
+    b->n_tiles = -1;
+    b->ws_needed = 0;
+    b->ws_bound = nullptr;
     std::vector<BatchGroup> groups;
+    std::vector<WsPatch> patches;
     int64_t tiles = 0;
     int m = 0, starts = 0;
     const int cus = device_cus();
@@ -907,8 +969,12 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         G.dtype = jobs[g][0].dtype;
         G.aligned = job_rows_aligned(jobs[g][0]);
         G.variant = (G.kind == KIND_STREAM && stream_two_level(jobs[g][0].wy)) ? 1 : 0;
+        G.phase = g / kPhaseGroups;
         int64_t t = 0;
-        for (const TileJob &j : jobs[g]) {
+        for (size_t q = 0; q < jobs[g].size(); q++) {
+            const TileJob &j = jobs[g][q];
+            if (wsrole[g][q].first >= 0)
+                patches.push_back(WsPatch{m, wsrole[g][q].second, (size_t)wsrole[g][q].first});
             b->h_tile_start[starts++] = t;
             b->h_jobs[m++] = j;
             t += (int64_t)j.tiles_x * j.tiles_y;
@@ -945,11 +1011,12 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
                        return x.job0 == y.job0 && x.njobs == y.njobs && x.tiles == y.tiles &&
                               x.lds == y.lds && x.grid == y.grid && x.dtype == y.dtype &&
                               x.aligned == y.aligned && x.kind == y.kind &&
-                              x.variant == y.variant;
+                              x.variant == y.variant && x.phase == y.phase;
                    });
     if (!same_layout) drop_graph(b);
     b->groups = groups;
-    b->n_tiles = tiles;
+    b->n_jobs = m;
+    b->ws_patch = patches;
     hipError_t e;
     if (m > 0) {
         if ((e = hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(TileJob) * m, hipMemcpyHostToDevice,
@@ -964,6 +1031,8 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         if ((e = hipEventRecord(b->staged, stream)) != hipSuccess) return hip_fail(e);
         b->staged_pending = true;
     }
+    b->n_tiles = tiles;
+    b->ws_needed = ws_total; // (the table just copied points into no workspace yet)
     return MORPH_OK;
 }
 
@@ -991,6 +1060,7 @@ static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
         start += G.njobs + 1;
         tstart += G.tiles;
     }
+    for (int ph = 0; ph < kPhases; ph++) {
     for (int dt = 0; dt < 2; dt++)
         for (int al = 0; al < 2; al++) {
             FusedTables ft{};
@@ -999,7 +1069,7 @@ static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
             for (size_t g = 0; g < b->groups.size(); g++) {
                 const BatchGroup &G = b->groups[g];
                 const int c = fused_class(G);
-                if (c < 0 || G.dtype != dt || G.aligned != (al == 0)) continue;
+                if (c < 0 || G.phase != ph || G.dtype != dt || G.aligned != (al == 0)) continue;
                 ft.g[c] = tabs[g];
                 n[c] = G.tiles;
                 lds = std::max(lds, G.lds);
@@ -1016,19 +1086,59 @@ static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
         }
     for (size_t g = 0; g < b->groups.size(); g++) {
         const BatchGroup &G = b->groups[g];
-        if (fused_class(G) >= 0) continue;
+        if (fused_class(G) >= 0 || G.phase != ph) continue;
         hipError_t e = launch_batch(tabs[g], G.kind, G.variant, G.dtype, G.aligned, G.grid, G.lds, stream);
         if (e != hipSuccess) return e;
+    }
     }
     return hipSuccess;
 }
 
+// Point the intermediates of the batch's openings and closings into `workspace`:
+// check it (size, no overlap with any image of the batch), write the pointers into
+// the staged job table and copy it to the device on `stream`, ahead of the launch.
+static int bind_workspace(morph_batch *b, void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    if (b->ws_needed == 0) return MORPH_OK;
+    if (!workspace || ws_bytes < b->ws_needed) return MORPH_ENOMEM;
+    if (workspace == b->ws_bound) return MORPH_OK;
+    // (h_jobs holds the images' own pointers, null where an intermediate goes)
+    for (int i = 0; i < b->n_jobs; i++) {
+        const TileJob &j = b->h_jobs[i];
+        const size_t es = elem_bytes(j.dtype);
+        if ((j.src && ranges_overlap(workspace, b->ws_needed, j.src,
+                                     (size_t)(j.H - 1) * j.pitch + (size_t)j.W * es)) ||
+            (j.dst && ranges_overlap(workspace, b->ws_needed, j.dst,
+                                     (size_t)(j.H - 1) * j.dpitch + (size_t)j.W * es)))
+            return MORPH_EALIAS;
+    }
+    hipError_t e;
+    // a staging buffer of its own, so that binding never waits for set()'s copy
+    if (b->ws_staged_pending) {
+        if ((e = hipEventSynchronize(b->ws_staged)) != hipSuccess) return hip_fail(e);
+        b->ws_staged_pending = false;
+    }
+    std::memcpy(b->h_jobs_ws, b->h_jobs, sizeof(TileJob) * b->n_jobs);
+    for (const WsPatch &p : b->ws_patch) {
+        uint8_t *ptr = (uint8_t *)workspace + p.offset;
+        if (p.writes) b->h_jobs_ws[p.job].dst = ptr;
+        else b->h_jobs_ws[p.job].src = ptr;
+    }
+    if ((e = hipMemcpyAsync(b->d_jobs, b->h_jobs_ws, sizeof(TileJob) * b->n_jobs,
+                            hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e);
+    if ((e = hipEventRecord(b->ws_staged, stream)) != hipSuccess) return hip_fail(e);
+    b->ws_staged_pending = true;
+    b->ws_bound = workspace;
+    return MORPH_OK;
+}
+
 int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream)
 {
-    (void)workspace;
-    (void)ws_bytes;
     if (!b || b->n_tiles < 0) return MORPH_EINVAL;
     if (b->n_tiles == 0) return MORPH_OK;
+    int rc = bind_workspace(b, workspace, ws_bytes, stream);
+    if (rc != MORPH_OK) return rc;
     hipError_t e;
     if (stream == nullptr) {
         // the legacy null stream cannot be captured: launch directly
@@ -1060,21 +1170,27 @@ int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipSt
     return MORPH_OK;
 }
 
-int morph_batch_launch(morph_batch_t b, hipStream_t stream)
+int morph_batch_launch(morph_batch_t b, void *workspace, size_t ws_bytes, hipStream_t stream)
 {
     if (!b || b->n_tiles < 0) return MORPH_EINVAL;
     if (b->n_tiles == 0) return MORPH_OK;
+    int rc = bind_workspace(b, workspace, ws_bytes, stream);
+    if (rc != MORPH_OK) return rc;
     hipError_t e = launch_groups(b, stream);
     return e == hipSuccess ? MORPH_OK : hip_fail(e);
 }
 
 int64_t morph_batch_tiles(morph_batch_t b) { return b ? b->n_tiles : -1; }
 
+size_t morph_batch_workspace_bytes(morph_batch_t b) { return b ? b->ws_needed : 0; }
+
 int morph_batch_destroy(morph_batch_t b)
 {
     if (!b) return MORPH_EINVAL;
     drop_graph(b);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->ws_staged) (void)hipEventDestroy(b->ws_staged);
+    if (b->h_jobs_ws) (void)hipHostFree(b->h_jobs_ws);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_tile_start) (void)hipFree(b->d_tile_start);
     if (b->d_tile_job) (void)hipFree(b->d_tile_job);

@@ -158,6 +158,7 @@ class Scheduler:
         px = sum(r.pixels for r in self.done)
         return {"completed": len(self.done), "rejected": len(self.rejected),
                 "batches": self.batches, "wall_s": wall,
+                "mean_batch": len(self.done) / self.batches if self.batches else None,
                 "gpixel_s": px / wall / 1e9 if wall > 0 else None,
                 "p50_ms": None if not lat else pct(0.50) * 1e3,
                 "p99_ms": None if not lat else pct(0.99) * 1e3,
@@ -169,9 +170,10 @@ def _pitch(W: int) -> int:
 
 
 class GpuExecutor:
-    """Runs micro-batches as HIP batch launches on a ring of streams.  Each stream
-    owns two batch objects: the first op of every request (and the only op of an
-    erosion/dilation), then the second op of openings/closings."""
+    """Runs micro-batches as HIP batch launches on a ring of streams, one batch
+    object per stream.  Openings and closings are batch descriptors of their own:
+    both operations run in the same launch, the intermediates in a workspace
+    allocated per micro-batch and held until it completes."""
 
     def __init__(self, pool, n_streams: int = 4, max_images: int = 256):
         import torch
@@ -183,14 +185,16 @@ class GpuExecutor:
         self.slots = []
         for _ in range(n_streams):
             self.slots.append({"stream": torch.cuda.Stream(device=self.dev),
-                               "b1": morph.Batch(max_images, 1 << 20),
-                               "b2": morph.Batch(max_images, 1 << 20),
+                               "batch": morph.Batch(max_images, 1 << 20),
                                "busy": None})
 
     @staticmethod
     def need_bytes(req: Request) -> int:
+        """Device bytes a request holds while it runs: its output and, for an opening
+        or closing, its intermediate in the batch workspace (rows padded to 64
+        bytes, the image on a 256-byte boundary)."""
         out = req.H * _pitch(req.W)
-        return out * (2 if req.op in ("open", "close") else 1)
+        return out + ((out + 255) // 256 * 256 if req.op in ("open", "close") else 0)
 
     def has_slot(self) -> bool:
         return any(s["busy"] is None for s in self.slots)
@@ -203,28 +207,21 @@ class GpuExecutor:
         torch = self.torch
         slot = next(s for s in self.slots if s["busy"] is None)
         st = slot["stream"]
-        first, second, keep = [], [], []
+        items = []
         with torch.cuda.stream(st):
             for r in reqs:
                 src = self.pool[r.img][r.y:r.y + r.H, r.x:r.x + r.W]
                 out = self._alloc(r.H, r.W)
                 r.out = out
-                if r.op in ("erode", "dilate"):
-                    first.append(dict(src=src, dst=out, wx=r.w, wy=r.w, op=r.op))
-                else:
-                    ws = self._alloc(r.H, r.W)
-                    keep.append(ws)
-                    a, b = ("erode", "dilate") if r.op == "open" else ("dilate", "erode")
-                    first.append(dict(src=src, dst=ws, wx=r.w, wy=r.w, op=a))
-                    second.append(dict(src=ws, dst=out, wx=r.w, wy=r.w, op=b))
-            slot["b1"].set(first, stream=st)
-            slot["b1"].launch(stream=st)
-            if second:
-                slot["b2"].set(second, stream=st)
-                slot["b2"].launch(stream=st)
+                items.append(dict(src=src, dst=out, wx=r.w, wy=r.w, op=r.op))
+            b = slot["batch"]
+            b.set(items, stream=st)
+            nws = b.workspace_bytes
+            ws = torch.empty(nws, dtype=torch.uint8, device=self.dev) if nws else None
+            b.launch(stream=st, workspace=ws)
             ev = torch.cuda.Event()
             ev.record(st)
-        slot["busy"] = (ev, keep)
+        slot["busy"] = (ev, ws)
         return slot
 
     def finished(self, slot) -> bool:

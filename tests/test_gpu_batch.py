@@ -163,3 +163,83 @@ def test_batch_with_many_wave_units(tmp_path):
         b.close()
     finally:
         morph.load_tuning(None)
+
+
+def _want_any(it):
+    return oracle.apply(it["op"], it["img"], it["wx"], it["wy"], it["ax"], it["ay"],
+                        method="vhgw" if max(it["wx"], it["wy"]) > 15 else "direct")
+
+
+def test_batch_openings_and_closings_with_workspace():
+    """Openings and closings as batch descriptors (§2: the dilation of the erosion and
+    the erosion of the dilation, same rectangle and anchor), mixed with erosions and
+    dilations, uint8 and uint16, odd pitches: the first operation into the enqueue
+    workspace, the second from it, in one graph; each image equals the oracle and its
+    single-image call, on the first launch, on a replay, and after the workspace is
+    replaced by another buffer (the job table is rewritten, the graph kept)."""
+    items = _items(36, seed=11)
+    rng = np.random.default_rng(11)
+    for it in items:
+        it["op"] = str(rng.choice(["erode", "dilate", "open", "close", "open", "close"]))
+    b = morph.Batch(64, 1 << 20)
+    b.set(items)
+    need = b.workspace_bytes
+    n_oc = sum(it["op"] in ("open", "close") for it in items)
+    assert n_oc > 10 and need > 0
+    ws1 = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ws2 = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")[1000:1000 + need]
+    for rep, ws in enumerate((ws1, ws1, ws2, ws1)):
+        for it in items:
+            it["dst"].zero_()
+        torch.cuda.synchronize()
+        b.enqueue(workspace=ws)
+        torch.cuda.synchronize()
+        for k, it in enumerate(items):
+            got = to_host(it["dst"])
+            assert np.array_equal(got, _want_any(it)), (rep, k, it["op"], it["img"].shape,
+                                                       it["wx"], it["wy"], it["ax"], it["ay"])
+    for it in items[:12]:
+        single = morph.apply(it["op"], it["src"], it["wx"], it["wy"], it["ax"], it["ay"])
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(single), to_host(it["dst"]))
+    # a plain launch (no graph) with the binding's own workspace
+    for it in items:
+        it["dst"].zero_()
+    b.launch()
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        assert np.array_equal(to_host(it["dst"]), _want_any(it)), ("launch", k)
+    # workspace too small, missing, or overlapping an image of the batch
+    for bad in (ws1[:need - 1], None):
+        ptr = 0 if bad is None else bad.data_ptr()
+        nb = 0 if bad is None else bad.numel()
+        rc = morph._lib.lib().morph_batch_enqueue(b._h, ptr or None, nb, None)
+        assert rc == -5, rc
+    src0 = items[0]["src"]
+    base = src0.data_ptr()
+    rc = morph._lib.lib().morph_batch_enqueue(b._h, base, need, None)
+    assert rc == -2, rc
+    b.close()
+
+
+def test_bench_batch_matches_oracle():
+    """The benchmark's exact workload: the 512-image batch of document-like pages
+    (H, W log-uniform 64..2048, windows 3..63, erosion or dilation; seed 5; 159.85
+    Mpx in ~22.8k units) in one pool with 64-byte row pitches, captured then
+    replayed; every output pixel of all 512 images equals the oracle's."""
+    import os
+    import bench
+    specs, imgs, items, npx, pools = bench.build_batch(torch, morph, synth, torch.device("cuda"))
+    assert len(items) == 512 and npx == 159_850_750
+    b = morph.Batch(len(items), 1 << 22)
+    assert b.set(items) > 20_000
+    dst_pool = pools[1]
+    nth = os.cpu_count() or 1
+    for rep in range(2):  # capture, then replay into a cleared pool
+        dst_pool.fill_(0x5a)
+        b.enqueue()
+        torch.cuda.synchronize()
+        for k, (s, im, it) in enumerate(zip(specs, imgs, items)):
+            want = oracle.apply(s["op"], im, s["w"], s["w"], method="hybrid", nthreads=nth)
+            assert np.array_equal(to_host(it["dst"]), want), (rep, k, s)
+    b.close()

@@ -44,3 +44,50 @@ def test_budget_smaller_than_requests_rejects_them():
     assert st["rejected"] > 0
     assert st["completed"] + st["rejected"] == st["requests"]
     assert sch.max_inflight_bytes <= 100_000
+
+
+def test_serving_stream_shaped_like_the_request_config():
+    """The request configuration's shape: a pool of 4096 x 4096 uint8 images, crops
+    with H and W log-uniform 128..4096, odd windows 3..101, erosion, dilation,
+    opening and closing, admission under the 8 GB budget.  Every one of the
+    >= 200 results equals the same request run alone, and each equals the CPU
+    oracle (tolerance 0)."""
+    import os
+    pool = serve.make_pool(n=4, hw=4096, seed=6)
+    budget = 8 << 30
+    st, sch = serve.serve(rate=2000.0, duration=0.12, budget=budget, n_streams=4, max_batch=64,
+                          seed=6, pool=pool, keep_outputs=lambda r: True)
+    assert st["completed"] == st["requests"] >= 200 and st["rejected"] == 0
+    assert sch.max_inflight_bytes <= budget
+    done = sorted(sch.done, key=lambda r: r.rid)
+    assert {r.op for r in done} == {"erode", "dilate", "open", "close"}
+    assert max(r.w for r in done) > 90 and max(max(r.H, r.W) for r in done) > 3000
+    host = [p.cpu().numpy() for p in pool]
+    nth = os.cpu_count() or 1
+    for r in done:
+        src = pool[r.img][r.y:r.y + r.H, r.x:r.x + r.W]
+        alone = morph.apply(r.op, src, r.w, r.w)
+        torch.cuda.synchronize()
+        got = r.out.cpu().numpy()
+        assert np.array_equal(got, alone.cpu().numpy()), (r.rid, r.op, r.w, r.H, r.W)
+        crop = np.ascontiguousarray(host[r.img][r.y:r.y + r.H, r.x:r.x + r.W])
+        want = oracle.apply(r.op, crop, r.w, r.w, method="hybrid", nthreads=nth)
+        assert np.array_equal(got, want), (r.rid, r.op, r.w, r.H, r.W)
+
+
+def test_saturating_stream_is_held_to_the_budget():
+    """Ten times the configured rate under a 256 MB budget: admission binds (the
+    micro-batches hold several requests, in-flight bytes stay within the budget)
+    and every request completes with the result it has alone."""
+    pool = serve.make_pool(n=2, hw=4096, seed=8)
+    budget = 256 << 20
+    st, sch = serve.serve(rate=20000.0, duration=0.03, budget=budget, n_streams=4,
+                          max_batch=64, seed=8, pool=pool, keep_outputs=lambda r: True)
+    assert st["completed"] + st["rejected"] == st["requests"] > 400
+    assert sch.max_inflight_bytes <= budget
+    assert st["mean_batch"] > 2.0, st
+    for r in sorted(sch.done, key=lambda r: r.rid)[::7]:
+        src = pool[r.img][r.y:r.y + r.H, r.x:r.x + r.W]
+        alone = morph.apply(r.op, src, r.w, r.w)
+        torch.cuda.synchronize()
+        assert np.array_equal(r.out.cpu().numpy(), alone.cpu().numpy()), (r.rid, r.op, r.w)
