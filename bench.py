@@ -4,17 +4,21 @@
 Workload (one "step"): the mixed-size batch -- 512 uint8 document-like images,
 H and W each log-uniform in [64, 2048], a square window per image drawn from
 {3, 5, 9, 15, 31, 63}, erosion or dilation at random (seed 5) -- run as one
-graph-replayed batch: one kernel dispatch per launch group (the wave kernel for the
-images whose two passes are direct, the streaming kernel in its two vertical forms
-for the others).  Images are resident in HBM before timing; rows are padded to a 64-byte
-pitch.  The roofline figure is that of the slowest dispatch of the step, timed
-alone on its images.  Reported beside it: the same 512 images as 512 separate
-launches (eager and captured in one graph), the 4096x4096 uint8 and uint16
-erosion/dilation kernels at the four large windows and at 3x3, and the CPU oracle
-timed on a bounded sample of the batch on the host's cores.
+graph-replayed batch, one fused kernel dispatch (wave and streaming units).  Images
+are resident in HBM before timing; rows are padded to a 64-byte pitch.  Four
+copies of the batch (1.28 GB) take turns, one per step, so that no step finds
+its images in the 256 MB Infinity Cache.  The roofline figure is that of the
+step's one dispatch, timed by HIP events on the launch stream.  Reported beside
+it: each class of units alone, the same 512 images as 512 separate launches
+(eager and captured in one graph), the 4096x4096 uint8 and uint16 kernels at the
+large windows and at 3x3 (32 buffer pairs in turn), the smaller single images,
+gradients, openings/closings, transposes, the serving loop at the configured and
+at a saturating rate, and the CPU oracle timed on a bounded sample of the batch
+on all the host's cores and on one.
 
 Prints ONE JSON line.  ``--gpus`` other than 1 exits with a message: the library
 runs on one GPU (images are independent; sharding them across GPUs is not built).
+``--only LEGS`` runs selected legs alone (for profiler runs).
 """
 from __future__ import annotations
 
@@ -32,6 +36,7 @@ if ROOT not in sys.path:
 METRIC = ("Gpixel/s and % peak HBM GB/s, erode/dilate uint8; batched vs per-image; p50/p99")
 PEAK_HBM_GBS = 8000.0
 PITCH_ALIGN = 64
+STEP_POOLS = 4  # copies of the batch the timed steps take turns over (4 x 320 MB)
 
 
 def _log(msg):
@@ -63,10 +68,14 @@ def load_traffic(workload: str, group: str):
     return t.get("groups", {}).get(group, {}).get("hbm_bytes_per_launch")
 
 
-def build_batch(torch, morph, synth, dev):
+def build_batch(torch, morph, synth, dev, copies=1):
+    """The 512-image batch in one pool per copy: every image padded to a 64-byte row
+    pitch, a source pool and a destination pool per copy (the copies hold the same
+    images, so that timed steps can take turns over more memory than the Infinity
+    Cache holds).  Returns specs, host images, the first copy's items, pixels per
+    step and the pools; with copies > 1 also the items of every copy."""
     specs = synth.batch_specs(512, seed=5)
     imgs = synth.batch_images(specs, seed=5)
-    # one pool: every image padded to a 64-byte row pitch, src then dst
     offs, total = [], 0
     for s in specs:
         pitch = (s["W"] + PITCH_ALIGN - 1) // PITCH_ALIGN * PITCH_ALIGN
@@ -76,15 +85,22 @@ def build_batch(torch, morph, synth, dev):
     host = np.zeros(total, np.uint8)
     for (o, pitch), s, im in zip(offs, specs, imgs):
         host[o:o + pitch * s["H"]].reshape(s["H"], pitch)[:, :s["W"]] = im
-    src_pool = torch.from_numpy(host).to(dev)
-    dst_pool = torch.zeros(total, dtype=torch.uint8, device=dev)
-    items = []
-    for (o, pitch), s in zip(offs, specs):
-        sv = src_pool[o:o + pitch * s["H"]].view(s["H"], pitch)[:, :s["W"]]
-        dv = dst_pool[o:o + pitch * s["H"]].view(s["H"], pitch)[:, :s["W"]]
-        items.append(dict(src=sv, dst=dv, wx=s["w"], wy=s["w"], op=s["op"]))
+    src0 = torch.from_numpy(host).to(dev)
+    pools, all_items = [], []
+    for c in range(copies):
+        src_pool = src0 if c == 0 else src0.clone()
+        dst_pool = torch.zeros(total, dtype=torch.uint8, device=dev)
+        items = []
+        for (o, pitch), s in zip(offs, specs):
+            sv = src_pool[o:o + pitch * s["H"]].view(s["H"], pitch)[:, :s["W"]]
+            dv = dst_pool[o:o + pitch * s["H"]].view(s["H"], pitch)[:, :s["W"]]
+            items.append(dict(src=sv, dst=dv, wx=s["w"], wy=s["w"], op=s["op"]))
+        pools.append((src_pool, dst_pool))
+        all_items.append(items)
     npx = sum(s["H"] * s["W"] for s in specs)
-    return specs, imgs, items, npx, (src_pool, dst_pool)
+    if copies == 1:
+        return specs, imgs, all_items[0], npx, pools[0]
+    return specs, imgs, all_items[0], npx, pools, all_items
 
 
 def time_launches(torch, fn, steps, warmup, stream):
@@ -104,12 +120,21 @@ def time_launches(torch, fn, steps, warmup, stream):
     return per, wall
 
 
-def cpu_baseline(specs, imgs, budget_s):
-    """The oracle's per-pass hybrid (direct below the paper's thresholds, 59 along x
-    and 69 along y, vHGW above) on the host's cores, over the batch's images in order
-    (repeating the batch if it is done sooner) until about budget_s of CPU time."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(specs, imgs, budget_s, nthreads):
+    """Gpixel/s of the oracle's hybrid over the batch's images in order (repeating
+    the batch if it is done sooner) until about budget_s of CPU time."""
     import oracle
-    nthreads = os.cpu_count() or 1
     # warm (loads the library, starts the OpenMP pool)
     oracle.erode(imgs[0][:64, :64].copy(), 3, 3, method="hybrid", thresholds=(59, 69),
                  nthreads=nthreads)
@@ -122,11 +147,22 @@ def cpu_baseline(specs, imgs, budget_s):
         t_used += time.perf_counter() - t0
         done_px += s["H"] * s["W"]
         n += 1
-    return dict(value=round(done_px / t_used / 1e9, 4), unit="Gpixel/s", cores=nthreads,
-                kind="oracle",
+    return done_px / t_used / 1e9, n, done_px, t_used
+
+
+def cpu_baseline(specs, imgs, budget_s):
+    """The oracle's per-pass hybrid (direct below the paper's thresholds, 59 along x
+    and 69 along y, vHGW above) on all the host's cores for about budget_s, and on
+    one thread for about budget_s / 2."""
+    nthreads = os.cpu_count() or 1
+    v, n, px, t = _oracle_rate(specs, imgs, budget_s, nthreads)
+    v1, n1, px1, t1 = _oracle_rate(specs, imgs, budget_s / 2, 1)
+    return dict(value=round(v, 4), unit="Gpixel/s", cores=nthreads, kind="oracle",
+                value_1_thread=round(v1, 4), cpu_model=cpu_model(),
                 sample="%d images of the batch in order (%.2f passes, %.1f Mpx), oracle hybrid "
-                       "direct/vHGW with the paper's thresholds (x 59, y 69), %.1f s" %
-                       (n, n / len(specs), done_px / 1e6, t_used))
+                       "direct/vHGW with the paper's thresholds (x 59, y 69), %.1f s on %d "
+                       "threads; 1 thread: %d images (%.1f Mpx), %.1f s" %
+                       (n, n / len(specs), px / 1e6, t, nthreads, n1, px1 / 1e6, t1))
 
 
 def graph_time(torch, launches, reps, stream):
@@ -144,14 +180,18 @@ def graph_time(torch, launches, reps, stream):
     return per[len(per) // 2] / len(launches)
 
 
+C3_BUFFERS = 32  # distinct src/dst pairs a 4096x4096 line rotates over (>= 1 GB for u8)
+
+
 def c3_lines(torch, morph, dev, steps):
     """4096x4096 erosion/dilation kernels at the large windows and at 3x3, uint8 and
-    uint16: per-launch GPU time of 10 launches (over 10 buffer pairs, so that most
-    reads miss the 256 MB Infinity Cache) captured in one graph."""
+    uint16: per-launch GPU time of 32 launches over 32 buffer pairs (1.07 GB of
+    uint8, 2.1 GB of uint16: over four times the 256 MB Infinity Cache, so that the
+    reads come from HBM) captured in one graph."""
     out = []
     stream = torch.cuda.current_stream()
     for dt, es in (("u8", 1), ("u16", 2)):
-        nbuf = 10
+        nbuf = C3_BUFFERS
         g = torch.Generator(device=dev).manual_seed(3 if dt == "u8" else 4)
         srcs = [torch.randint(0, 256 if dt == "u8" else 65536, (4096, 4096), generator=g,
                               dtype=torch.int32, device=dev).to(torch.uint8 if dt == "u8"
@@ -363,6 +403,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run --steps plain device copies of MIB mebibytes (the known-size "
                          "reference for the HBM byte counters) and exit")
+    ap.add_argument("--only", default=None, metavar="LEGS",
+                    help="comma-separated legs to run instead of the full report (for the "
+                         "profiler): batch, classes, per_image, c3, small, gradient, openclose, "
+                         "transpose, serving, cpu")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -388,14 +432,40 @@ def main():
                           "gbs": round(2 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
         return
 
-    _log("building the 512-image batch")
-    specs, imgs, items, npx, _pools = build_batch(torch, morph, synth, dev)
-    batch = morph.Batch(len(items), 1 << 22)
-    ntiles = batch.set(items)
+    legs = None if args.only is None else set(args.only.split(","))
+
+    def want(leg):
+        return legs is None or leg in legs
+
+    if legs is not None and not legs & {"batch", "classes", "per_image"}:
+        res = {"only": sorted(legs)}
+        _run_extras(res, args, torch, morph, synth, dev, want)
+        print(json.dumps(res), flush=True)
+        return
+
+    _log("building the 512-image batch (%d copies)" % STEP_POOLS)
+    specs, imgs, items, npx, pools, copies = build_batch(torch, morph, synth, dev,
+                                                         copies=STEP_POOLS)
+    batches = []
+    for its in copies:
+        b = morph.Batch(len(its), 1 << 22)
+        ntiles = b.set(its)
+        batches.append(b)
+    batch = batches[0]
     torch.cuda.synchronize()
 
-    _log("timing %d batched steps (%d tiles, %.1f Mpx per step)" % (args.steps, ntiles, npx / 1e6))
-    per, wall = time_launches(torch, lambda: batch.enqueue(), args.steps, args.warmup, stream)
+    # each step replays the next copy's graph: the steps together read and write
+    # STEP_POOLS x 320 MB, so no step finds its images in the Infinity Cache
+    _log("timing %d batched steps (%d tiles, %.1f Mpx per step, %d pools)" %
+         (args.steps, ntiles, npx / 1e6, STEP_POOLS))
+    turn = [0]
+
+    def step():
+        batches[turn[0] % STEP_POOLS].enqueue()
+        turn[0] += 1
+    for b in batches:  # capture every copy's graph before timing
+        b.enqueue()
+    per, wall = time_launches(torch, step, args.steps, args.warmup, stream)
     ms_per_step = sum(per) / len(per)
     value = npx / (ms_per_step * 1e-3) / 1e9
     sp = sorted(per)
@@ -407,7 +477,7 @@ def main():
     # class alone, as its own batch, is timed beside it for reference.
     _log("timing each class of units alone")
     kernels = []
-    for name, its in sorted(kernel_groups(morph, items).items()):
+    for name, its in (sorted(kernel_groups(morph, items).items()) if want("classes") else []):
         sub = morph.Batch(len(its), 1 << 22)
         units = sub.set(its)
         kp, _ = time_launches(torch, lambda: sub.enqueue(), args.steps, args.warmup, stream)
@@ -419,6 +489,8 @@ def main():
                         "units": units, "pixels": kpx, "ms_per_launch": round(kms, 5),
                         "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)})
         sub.close()
+    for b in batches[1:]:
+        b.close()
     if set(k["group"] for k in kernels) <= FUSED_GROUPS:
         dom = {"kernel": FUSED_LABEL, "group": "fused", "units": ntiles, "pixels": npx,
                "ms_per_launch": round(ms_per_step, 5)}
@@ -446,7 +518,10 @@ def main():
                    "content": "document-like: white page, black rectangles, noise sigma 12",
                    "pixels_per_step": npx, "tiles": ntiles, "row_pitch": "64-byte aligned",
                    "launch": "one fused kernel dispatch (wave and streaming units), "
-                             "hipGraph replay"},
+                             "hipGraph replay",
+                   "pools": "%d copies of the batch (%.2f GB), steps take turns" %
+                            (STEP_POOLS, STEP_POOLS * 2 * sum(
+                                p[0].numel() for p in pools[:1]) / 1e9)},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(dom_gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(dom_gbs / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
@@ -459,7 +534,7 @@ def main():
                        int(0.99 * len(sp)))], 4)},
     }
 
-    if not args.no_extras:
+    if not args.no_extras and want("per_image"):
         _log("per-image baselines")
 
         def per_image():
@@ -482,21 +557,53 @@ def main():
             "batched_over_eager": round(pi_ms / ms_per_step, 2),
             "batched_over_graph": round(pg_ms / ms_per_step, 2),
         }
-        _log("4096x4096 kernels")
-        res["c3_4096"] = c3_lines(torch, morph, dev, max(10, args.steps))
-        _log("640x480 and 1920x1080 single images")
-        res["small_images"] = small_image_lines(torch, morph, synth, dev, max(10, args.steps))
-        _log("4096x4096 gradients")
-        res["gradient_4096"] = gradient_lines(torch, morph, dev, max(10, args.steps))
-        _log("4096x4096 openings and closings")
-        res["openclose_4096"] = openclose_lines(torch, morph, dev, max(10, args.steps))
-        _log("transposes")
-        res["transpose"] = transpose_lines(torch, morph, dev, max(10, args.steps))
-
-    if not args.no_cpu_baseline:
+    del pools, copies
+    if not args.no_extras:
+        _run_extras(res, args, torch, morph, synth, dev, want)
+    if not args.no_cpu_baseline and want("cpu"):
         _log("CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(specs, imgs, args.cpu_budget)
     print(json.dumps(res), flush=True)
+
+
+def _run_extras(res, args, torch, morph, synth, dev, want):
+    steps = max(10, args.steps)
+    if want("c3"):
+        _log("4096x4096 kernels")
+        res["c3_4096"] = c3_lines(torch, morph, dev, steps)
+    if want("small"):
+        _log("640x480 and 1920x1080 single images")
+        res["small_images"] = small_image_lines(torch, morph, synth, dev, steps)
+    if want("gradient"):
+        _log("4096x4096 gradients")
+        res["gradient_4096"] = gradient_lines(torch, morph, dev, steps)
+    if want("openclose"):
+        _log("4096x4096 openings and closings")
+        res["openclose_4096"] = openclose_lines(torch, morph, dev, steps)
+    if want("transpose"):
+        _log("transposes")
+        res["transpose"] = transpose_lines(torch, morph, dev, steps)
+    if want("serving"):
+        _log("serving legs")
+        res["serving"] = serving_lines(torch)
+
+
+def serving_lines(torch):
+    """The request loop (continuous batching under a byte budget) on the request
+    configuration's stream -- crops of 32 device-resident 4096x4096 uint8 images,
+    H and W log-uniform 128..4096, odd windows 3..101, erosion, dilation, opening,
+    closing -- at the configured 2000 requests/s for 5 s under 8 GB, and at 25
+    times that rate for 2 s under 64 MB, where requests queue and admission
+    binds."""
+    from paper_2002_09474_amd import serve
+    pool = serve.make_pool(32, 4096, seed=6)
+    out = []
+    for rate, dur, budget in ((2000.0, 5.0, 8 << 30), (50000.0, 2.0, 64 << 20)):
+        st, _ = serve.serve(rate=rate, duration=dur, budget=budget, n_streams=4, max_batch=64,
+                            seed=6, pool=pool)
+        out.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
+    del pool
+    return out
 
 
 if __name__ == "__main__":
