@@ -4,7 +4,7 @@
 Workload (one "step"): the mixed-size batch -- 512 uint8 document-like images,
 H and W each log-uniform in [64, 2048], a square window per image drawn from
 {3, 5, 9, 15, 31, 63}, erosion or dilation at random (seed 5) -- run as one
-graph-replayed batch, one fused kernel dispatch (wave and streaming units).  Images
+batch launch, one fused kernel dispatch (wave and streaming units).  Images
 are resident in HBM before timing; rows are padded to a 64-byte pitch.  Four
 copies of the batch (1.28 GB) take turns, one per step, so that no step finds
 its images in the 256 MB Infinity Cache.  The roofline figure is that of the
@@ -104,6 +104,8 @@ def build_batch(torch, morph, synth, dev, copies=1):
 
 
 def time_launches(torch, fn, steps, warmup, stream):
+    """Per-step GPU times (ms): each step bracketed by its own pair of HIP events on
+    `stream` (the events' own cost included; for latency percentiles)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -118,6 +120,23 @@ def time_launches(torch, fn, steps, warmup, stream):
     wall = time.perf_counter() - t0
     per = [a.elapsed_time(b) for a, b in ev]  # ms
     return per, wall
+
+
+def time_steps(torch, fn, steps, warmup, stream):
+    """Whole-job time of `steps` back-to-back steps (ms per step): synchronize, one
+    HIP event on `stream`, the steps, one event, synchronize; the host runs ahead,
+    so the time is the device's."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
 
 
 def cpu_model() -> str:
@@ -368,7 +387,7 @@ def kernel_groups(morph, items):
     groups = {}
     for it in items:
         H, W = it["src"].shape
-        k = morph.resolve_plan("u8", H, W, it["wx"], it["wy"])["kernel"]
+        k = morph.resolve_plan("u8", H, W, it["wx"], it["wy"], batch=True)["kernel"]
         if k == "stream":
             k = "stream_ring" if _effective(it["wy"], H) <= 16 else "stream_runs"
         groups.setdefault(k, []).append(it)
@@ -421,6 +440,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # every launch on a stream of our own: the legacy default stream cannot be
+    # captured (batches of several dispatches replay graphs)
+    torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
         n = args.copy_calibration << 20
@@ -454,7 +476,7 @@ def main():
     batch = batches[0]
     torch.cuda.synchronize()
 
-    # each step replays the next copy's graph: the steps together read and write
+    # each step launches the next copy: the steps together read and write
     # STEP_POOLS x 320 MB, so no step finds its images in the Infinity Cache
     _log("timing %d batched steps (%d tiles, %.1f Mpx per step, %d pools)" %
          (args.steps, ntiles, npx / 1e6, STEP_POOLS))
@@ -463,11 +485,12 @@ def main():
     def step():
         batches[turn[0] % STEP_POOLS].enqueue()
         turn[0] += 1
-    for b in batches:  # capture every copy's graph before timing
+    for b in batches:  # first launch of every copy (any graph captured) before timing
         b.enqueue()
-    per, wall = time_launches(torch, step, args.steps, args.warmup, stream)
-    ms_per_step = sum(per) / len(per)
+    ms_per_step = time_steps(torch, step, args.steps, args.warmup, stream)
     value = npx / (ms_per_step * 1e-3) / 1e9
+    # latency of one step: each step between its own events (their cost included)
+    per, _ = time_launches(torch, step, args.steps, 2, stream)
     sp = sorted(per)
 
     # The step is one kernel dispatch: the wave units (both passes direct) and the
@@ -480,8 +503,7 @@ def main():
     for name, its in (sorted(kernel_groups(morph, items).items()) if want("classes") else []):
         sub = morph.Batch(len(its), 1 << 22)
         units = sub.set(its)
-        kp, _ = time_launches(torch, lambda: sub.enqueue(), args.steps, args.warmup, stream)
-        kms = sum(kp) / len(kp)
+        kms = time_steps(torch, lambda: sub.enqueue(), args.steps, args.warmup, stream)
         kpx = sum(it["src"].shape[0] * it["src"].shape[1] for it in its)
         gbs = 2 * kpx / (kms * 1e-3) / 1e9  # one read and one write of every uint8 pixel
         kernels.append({"kernel": kernel_label(name), "alone": True, "group": name,
@@ -518,7 +540,7 @@ def main():
                    "content": "document-like: white page, black rectangles, noise sigma 12",
                    "pixels_per_step": npx, "tiles": ntiles, "row_pitch": "64-byte aligned",
                    "launch": "one fused kernel dispatch (wave and streaming units), "
-                             "hipGraph replay",
+                             "dispatched directly (a batch of one dispatch skips the graph)",
                    "pools": "%d copies of the batch (%.2f GB), steps take turns" %
                             (STEP_POOLS, STEP_POOLS * 2 * sum(
                                 p[0].numel() for p in pools[:1]) / 1e9)},
@@ -540,15 +562,13 @@ def main():
         def per_image():
             for it in items:
                 morph.apply(it["op"], it["src"], it["wx"], it["wy"], out=it["dst"])
-        pi, _ = time_launches(torch, per_image, max(3, args.steps // 4), 2, stream)
-        pi_ms = sum(pi) / len(pi)
+        pi_ms = time_steps(torch, per_image, max(3, args.steps // 4), 2, stream)
         g = torch.cuda.CUDAGraph()
         per_image()
         torch.cuda.synchronize()
         with torch.cuda.graph(g):
             per_image()
-        pg, _ = time_launches(torch, lambda: g.replay(), max(3, args.steps // 2), 2, stream)
-        pg_ms = sum(pg) / len(pg)
+        pg_ms = time_steps(torch, lambda: g.replay(), max(3, args.steps // 2), 2, stream)
         res["per_image"] = {
             "eager_ms_per_step": round(pi_ms, 4),
             "eager_gpixel_s": round(npx / (pi_ms * 1e-3) / 1e9, 3),

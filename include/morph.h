@@ -84,14 +84,16 @@ extern "C" {
  * 1 always skips its pass); tile_w / tile_h set the output tile of one workgroup
  * (tile_w a multiple of 4, tile_h a multiple of 2).  A plan never changes the
  * result, only how it is computed.
- * Kernels: a direct vertical pass (wy <= 9) runs one wave per strip in registers,
- * its horizontal pass direct or (wider windows, up to 128) doubling; with both
- * methods AUTO and no tile, larger vertical windows (wx <= 128, wy <= 256) run one
- * wave per strip that streams down the rows (vertical vHGW through LDS,
- * horizontal direct or doubling); wy = 1 with 128 < wx <= 1000 runs one wave
- * per strip of rows with 16 pixels a lane (horizontal doubling);
- * anything else -- a forced vHGW pass, a tile, larger windows -- runs the
- * workgroup-tile kernel, which implements exactly the paper's two methods.
+ * Kernels: a direct vertical pass (wy <= 31; a kernel of its own past 9) runs one
+ * wave per strip in registers, its horizontal pass direct (wx <= 16) or (wider
+ * windows, up to 128) doubling; with both methods AUTO and no tile, larger
+ * vertical windows (wx <= 128, wy <= 256) run one wave per strip that streams down
+ * the rows (vertical vHGW through LDS, horizontal direct up to 9 or doubling);
+ * wy = 1 with 128 < wx <= 1000 runs one wave per strip of rows with 16 pixels a
+ * lane (horizontal doubling); anything else -- a forced vHGW pass, a tile, a
+ * forced direct pass past those windows, larger windows -- runs the workgroup-tile
+ * kernel, which implements exactly the paper's two methods (direct windows past 9
+ * as a loop over the taps).
  * method_x = DOUBLING takes the wave, streaming or wide-row kernel by the
  * windows (MORPH_EUNSUPPORTED where none fits); DOUBLING for method_y, or with a
  * tile, is MORPH_EINVAL.
@@ -103,6 +105,8 @@ typedef struct morph_plan {
     int32_t tile_w;
     int32_t tile_h;
     int32_t kernel; /* out (morph_resolve_plan): MORPH_KERNEL_*; ignored on input */
+    int32_t batch;  /* in (morph_resolve_plan only): nonzero = plan the image as one of a
+                     * batch (its thresholds and unit heights); ignored elsewhere */
 } morph_plan;
 
 /* kernels (morph_plan.kernel) */
@@ -269,10 +273,12 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
  * wave and streaming units of each element type and row alignment (long streaming
  * units dealt out first), then the tile and wide-row groups' kernels (the last
  * workgroup of a persistent one leaves its queue counter at zero for the next
- * launch).  The first call on a stream captures the launch into a hipGraph that
- * later calls replay; the graph is re-captured when the stream or the batch's
- * shape changes.  Launches of one batch object must not overlap (they share the
- * counter and the job table).
+ * launch).  When that is more than one dispatch, the first call on a stream
+ * captures the launch into a hipGraph that later calls replay (the graph is
+ * re-captured when the stream or the batch's shape changes); a batch of one
+ * dispatch, and any batch on the legacy null stream (which cannot be captured), is
+ * dispatched directly.  Launches of one batch object must not overlap (they share
+ * the counter and the job table).
  * workspace / ws_bytes: device memory for the intermediates of the batch's
  * openings and closings, at least morph_batch_workspace_bytes(b) bytes (else
  * MORPH_ENOMEM; NULL, 0 when the batch has none).  It must not overlap any
@@ -322,7 +328,9 @@ int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dty
 
 /* ---- misc ------------------------------------------------------------------ */
 /* Load a tuning table (JSON written by the autotuner) replacing the current one:
- * per-dtype direct/vHGW thresholds, tile shapes per window bucket (tq = input
+ * per-dtype direct/vHGW thresholds (t_x, t_y for single images; batch_t_x,
+ * batch_t_y for the images of a batch; direct when w <= t, the compiled direct
+ * windows capping it: 16 along x, 31 along y), tile shapes per window bucket (tq = input
  * quads of a tile row, tb = output rows), the output rows of a direct wave unit
  * (a multiple of 8, at most 64; default 24) and of a streaming unit (1 .. 4096;
  * stream_rows for vertical windows up to 16, default 48, stream_rows_runs above,
@@ -341,9 +349,11 @@ int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dty
  * NULL restores the built-in defaults.  A malformed file returns MORPH_EINVAL and
  * changes nothing. */
 int morph_load_tuning(const char *json_path);
-/* Current per-pass direct->vHGW thresholds for a dtype (direct when w <= t). */
+/* Current per-pass direct->vHGW thresholds of single images for a dtype (direct
+ * when w <= t). */
 int morph_get_thresholds(int dtype, int *t_x, int *t_y);
-/* Override the thresholds (for sweeps); t <= 0 leaves a value unchanged. */
+/* Override the single-image thresholds (for sweeps); t <= 0 leaves a value
+ * unchanged.  The batch thresholds come from the tuning table. */
 int morph_set_thresholds(int dtype, int t_x, int t_y);
 /* Resolve the plan the library would use for these arguments (after threshold
  * and tuning lookup); fills *plan with concrete methods and tile shape. */

@@ -63,7 +63,7 @@ def _plan(method_x, method_y, tile):
     if method_x is None and method_y is None and tile is None:
         return None
     tw, th = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
-    return Plan(_lib.METHOD_CODES[method_x], _lib.METHOD_CODES[method_y], tw, th, 0)
+    return Plan(_lib.METHOD_CODES[method_x], _lib.METHOD_CODES[method_y], tw, th, 0, 0)
 
 
 def workspace_bytes(H: int, W: int, pitch: int, elem_bytes: int) -> int:
@@ -337,8 +337,11 @@ def set_thresholds(dtype_name: str, t_x: int, t_y: int) -> None:
 
 
 def resolve_plan(dtype_name: str, H: int, W: int, wx: int, wy: int, method_x=None,
-                 method_y=None, tile=None):
-    p = _plan(method_x, method_y, tile) or Plan(0, 0, 0, 0, 0)
+                 method_y=None, tile=None, batch=False):
+    """The plan the library takes for these arguments (``batch``: as an image of a
+    batch, whose thresholds and unit heights are keys of their own)."""
+    p = _plan(method_x, method_y, tile) or Plan(0, 0, 0, 0, 0, 0)
+    p.batch = 1 if batch else 0
     _lib.check(_lib.lib().morph_resolve_plan(_lib.U8 if dtype_name == "u8" else _lib.U16,
                                              H, W, wx, wy, ctypes.byref(p)), "resolve_plan")
     names = {0: None, 1: "direct", 2: "vhgw", 3: "doubling"}

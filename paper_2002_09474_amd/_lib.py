@@ -58,7 +58,7 @@ class MorphError(RuntimeError):
 class Plan(ctypes.Structure):
     _fields_ = [("method_x", ctypes.c_int32), ("method_y", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("batch", ctypes.c_int32)]
 
 
 KERNEL_NAMES = {0: "tile", 1: "wave", 2: "stream", 3: "rows"}

@@ -11,8 +11,10 @@ GPU kernels the automatic plan picks between: for a pass of window w, the direct
 pass (the register-only wave kernel when both passes are direct) against the
 large-window pass (the streaming kernel: vHGW through an LDS ring vertically,
 doubling across lanes horizontally), as single-pass sweeps along x (w x 1) and
-along y (1 x w) on the 1920x1080 document page.  The threshold of a pass is the
+along y (1 x w) on a 4096x4096 document page.  The threshold of a pass is the
 largest window up to which direct is never slower by more than the timing noise.
+The thresholds of batched images are then chosen on the whole benchmark batch
+(direct passes that leave the fused dispatch can cost it more than they save).
 Unit heights of batched images are then chosen on the whole 512-image batch of the
 benchmark (one key at a time), those of single images on 4096x4096 images (the
 wave kernel's at 3x3, the streaming kernel's at 15x15 and 31x31), the unit height
@@ -30,7 +32,8 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning_gfx950.json")
-DIRECT_MAX = 9
+# largest windows of the library's direct passes (wave kernel) per axis
+DIRECT_MAX = {"x": 16, "y": 31}
 BUCKETS = ((9, 9), (16, 15), (32, 31), (64, 63), (1 << 30, 101))  # (wmax, representative w)
 TQ = (16, 32, 48, 64, 96)
 TB = (16, 32, 64, 128)
@@ -77,14 +80,16 @@ def _with_table(morph, table):
         os.unlink(path)
 
 
-def pass_sweep(torch, morph, dname, srcs, dsts, iters=40):
-    """Time each single pass for w = 2 .. DIRECT_MAX, direct (threshold >= w) against
-    the large-window pass (threshold w - 1), with automatic methods."""
+def pass_sweep(torch, morph, dname, srcs, dsts, iters=40, windows=None):
+    """Time each single pass for w = 2 .. DIRECT_MAX[axis] (or the given windows per
+    axis), direct (threshold >= w) against the large-window pass (threshold w - 1),
+    with automatic methods."""
     rows = []
     t0 = morph.get_thresholds(dname)
     try:
         for axis in ("x", "y"):
-            for w in range(2, DIRECT_MAX + 1):
+            ws = windows[axis] if windows else range(2, DIRECT_MAX[axis] + 1)
+            for w in ws:
                 wx, wy = (w, 1) if axis == "x" else (1, w)
                 t = {}
                 for name, thr in (("direct", w), ("large", w - 1)):
@@ -96,7 +101,8 @@ def pass_sweep(torch, morph, dname, srcs, dsts, iters=40):
                         i = k[0] % len(srcs)
                         k[0] += 1
                         morph.apply("erode", srcs[i], wx, wy, out=dsts[i])
-                    t[name] = _timer(torch, fn, iters)
+                    # the median of three timings
+                    t[name] = sorted(_timer(torch, fn, iters) for _ in range(3))[1]
                 rows.append({"axis": axis, "w": w, "direct_us": round(t["direct"], 3),
                              "large_us": round(t["large"], 3)})
     finally:
@@ -105,14 +111,39 @@ def pass_sweep(torch, morph, dname, srcs, dsts, iters=40):
 
 
 def threshold(rows, axis, tol=0.03):
-    """Largest w such that direct <= large * (1 + tol) for every w' <= w (1 if none)."""
+    """The window before the first sustained loss of the direct pass: the largest
+    swept w such that no two consecutive swept windows up to w + 1 both have
+    direct > large * (1 + tol) (a single loss within the noise does not end the
+    direct range; 1 if direct loses from the start)."""
+    rs = sorted((r for r in rows if r["axis"] == axis), key=lambda r: r["w"])
+    lose = [r["direct_us"] > r["large_us"] * (1 + tol) for r in rs]
     t = 1
-    for r in sorted((r for r in rows if r["axis"] == axis), key=lambda r: r["w"]):
-        if r["direct_us"] <= r["large_us"] * (1 + tol):
-            t = r["w"]
-        else:
+    for i, r in enumerate(rs):
+        if lose[i] and (i + 1 == len(rs) or lose[i + 1]):
             break
+        if not lose[i]:
+            t = r["w"]
     return t
+
+
+def batch_thresholds(torch, morph, dname, items, base, tx, ty, iters=10):
+    """(batch_t_x, batch_t_y): the thresholds under which the whole batch runs
+    fastest, among the classic pair (9, 9), the single-image thresholds and mixes
+    of them -- a pass taken off the fused dispatch can cost the batch more than it
+    saves on its own images."""
+    cands = sorted({(9, 9), (min(tx, 9), 9), (9, min(ty, 15)), (tx, min(ty, 15)), (tx, ty)})
+    res = []
+    for cx, cy in cands:
+        _with_table(morph, {dname: dict(base, batch_t_x=cx, batch_t_y=cy)})
+        b = morph.Batch(len(items), 1 << 22)
+        try:
+            b.set(items)
+            us = _timer(torch, lambda: b.enqueue(), iters, warmup=3)
+        finally:
+            b.close()
+        res.append({"batch_t_x": cx, "batch_t_y": cy, "us": round(us, 2)})
+    best = min(res, key=lambda r: r["us"])
+    return best["batch_t_x"], best["batch_t_y"], res
 
 
 def best_rows(torch, morph, dname, items, key, choices, base, iters=10):
@@ -132,15 +163,15 @@ def best_rows(torch, morph, dname, items, key, choices, base, iters=10):
     return best, res
 
 
-def tile_sweep(torch, morph, srcs, dsts, dname, iters=20):
+def tile_sweep(torch, morph, srcs, dsts, dname, iters=20, buckets=BUCKETS, tqs=TQ, tbs=TB):
     """Tile shapes of the workgroup-tile kernel (forced vHGW passes) per window bucket."""
     rules, table = [], []
     H, W = srcs[0].shape
     v = dict(method_x="vhgw", method_y="vhgw")
-    for wmax, w in BUCKETS:
+    for wmax, w in buckets:
         best = None
-        for tq in TQ:
-            for tb in TB:
+        for tq in tqs:
+            for tb in tbs:
                 tw = max(4 * tq - ((w + 2 + 3) // 4 * 4), (2 * w + 3) // 4 * 4)
                 try:
                     plan = morph.resolve_plan(dname, H, W, w, w, tile=(tw, tb), **v)
@@ -181,11 +212,11 @@ def best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w, ite
     return min(res, key=lambda r: r["us"])[key], res
 
 
-def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20):
+def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20, choices=WIDE_ROWS):
     """Rows of a wide-row unit: the sum over WIDE_WINDOWS (w x 1) on uint8 4096x4096
     images, per choice; the fastest."""
     res = []
-    for c in WIDE_ROWS:
+    for c in choices:
         _with_table(morph, {"u8": dict(base, wide_rows=c)})
         us = 0.0
         for w in WIDE_WINDOWS:
@@ -200,61 +231,107 @@ def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20):
     return min(res, key=lambda r: r["us"])["wide_rows"], res
 
 
-def _batch_items(torch, morph, dev, dname):
-    """The benchmark's 512-image batch (uint8, or the same images scaled to uint16)."""
+def _batch_items(torch, morph, dev, dname, n=512, hi=2048):
+    """The benchmark's 512-image batch (uint8, or the same images scaled to uint16);
+    n and hi give a smaller batch of the same kind."""
     from . import synth
-    specs = synth.batch_specs(512, seed=5)
+    specs = synth.batch_specs(n, seed=5, hi=hi)
     imgs = synth.batch_images(specs, seed=5)
     items = []
     for s, im in zip(specs, imgs):
         t = torch.from_numpy(im).to(dev)
         if dname == "u16":
             t = (t.to(torch.int32) * 257).to(torch.int16).view(torch.uint16)
-        items.append(dict(src=t, dst=torch.empty_like(t), wx=s["w"], wy=s["w"], op=s["op"]))
+        # rows padded to 64 bytes, as the benchmark lays the batch out
+        es = t.element_size()
+        p = (s["W"] * es + 63) // 64 * 64 // es
+        src = torch.zeros((s["H"], p), dtype=t.dtype, device=dev)[:, :s["W"]]
+        src.copy_(t)
+        dst = torch.empty((s["H"], p), dtype=t.dtype, device=dev)[:, :s["W"]]
+        items.append(dict(src=src, dst=dst, wx=s["w"], wy=s["w"], op=s["op"]))
     return items
 
 
-def tune(out_path=DEFAULT_OUT, quick=False):
+# the reduced grid: a few windows and choices per key on smaller images, for a
+# check that the tuner runs end to end and writes a table the library loads
+REDUCED = {"windows": {"x": (2, 3, 9, 12, 16), "y": (2, 3, 9, 15, 31)},
+           "batch": (48, 300), "big": 1024,
+           "batch_keys": tuple((k, c[:2]) for k, c in BATCH_KEYS),
+           "single_keys": tuple((k, c[:2], w) for k, c, w in SINGLE_KEYS),
+           "wide_rows": WIDE_ROWS[:2], "buckets": BUCKETS[:1], "tq": TQ[:2], "tb": TB[:2]}
+
+
+def tune(out_path=DEFAULT_OUT, quick=False, reduced=False):
     import torch
 
     import paper_2002_09474_amd as morph
     from paper_2002_09474_amd import synth
     dev = torch.device("cuda")
     morph._lib.lib().morph_load_tuning(None)  # start from the built-in table
-    result = {"device": torch.cuda.get_device_name(0), "version": morph.version()}
-    doc = torch.from_numpy(synth.document(1080, 1920, seed=2)).to(dev)
+    # (on a stream of its own: the legacy default stream cannot be captured, so
+    # batches launched there would not replay graphs as they do in use)
+    side = torch.cuda.Stream()
+    prev = torch.cuda.current_stream()
+    torch.cuda.set_stream(side)
+    try:
+        return _tune(torch, morph, synth, dev, out_path, quick, reduced)
+    finally:
+        torch.cuda.synchronize()
+        torch.cuda.set_stream(prev)
+
+
+def _tune(torch, morph, synth, dev, out_path, quick, reduced):
+    result = {"device": torch.cuda.get_device_name(0), "version": morph.version(),
+              "grid": "reduced" if reduced else ("quick" if quick else "full")}
+    R = REDUCED if reduced else None
+    # the pass sweep's page: document-like content (as the 1920x1080 configuration)
+    # at 4096 x 4096, where the kernels' time, not a launch's fixed cost, decides
+    doc = torch.from_numpy(synth.document(540 if R else 4096, 960 if R else 4096, seed=2)).to(dev)
     for dname in ("u8", "u16"):
         img = doc if dname == "u8" else (doc.to(torch.int32) * 257).to(torch.int16).view(torch.uint16)
         srcs, dsts = _bufs(torch, img, 8)
-        rows = pass_sweep(torch, morph, dname, srcs, dsts, iters=20 if quick else 40)
+        rows = pass_sweep(torch, morph, dname, srcs, dsts, iters=10 if R else (20 if quick else 40),
+                          windows=R["windows"] if R else None)
         tx, ty = threshold(rows, "x"), threshold(rows, "y")
         del srcs, dsts
         base = {"t_x": tx, "t_y": ty}
-        items = _batch_items(torch, morph, dev, dname)
-        it = 5 if quick else 10
-        for key, choices in BATCH_KEYS:
+        items = (_batch_items(torch, morph, dev, dname, *R["batch"]) if R
+                 else _batch_items(torch, morph, dev, dname))
+        it = 3 if R else (5 if quick else 10)
+        btx, bty, bt_table = batch_thresholds(torch, morph, dname, items, base, tx, ty, it)
+        base.update(batch_t_x=btx, batch_t_y=bty)
+        result[dname + "_batch_threshold_sweep"] = bt_table
+        for key, choices in (R["batch_keys"] if R else BATCH_KEYS):
             best, table = best_rows(torch, morph, dname, items, key, choices, base, it)
             base[key] = best
             result[dname + "_" + key + "_sweep"] = table
         del items
         _with_table(morph, {dname: base})
         g = torch.Generator(device=dev).manual_seed(3)
-        big = torch.randint(0, 256 if dname == "u8" else 65536, (4096, 4096), generator=g,
+        n = R["big"] if R else 4096
+        big = torch.randint(0, 256 if dname == "u8" else 65536, (n, n), generator=g,
                             dtype=torch.int32, device=dev)
         big = big.to(torch.uint8) if dname == "u8" else big.to(torch.int16).view(torch.uint16)
         srcs, dsts = _bufs(torch, big, 6)
-        for key, choices, w in SINGLE_KEYS:
+        for key, choices, w in (R["single_keys"] if R else SINGLE_KEYS):
             best, table = best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w,
-                                           8 if quick else 20)
+                                           3 if R else (8 if quick else 20))
             base[key] = best
             result[dname + "_" + key + "_sweep"] = table
         _with_table(morph, {dname: base})
         if dname == "u8":
-            wr2, wr2_table = wide_rows_sweep(torch, morph, srcs, dsts, base, 8 if quick else 20)
+            wr2, wr2_table = wide_rows_sweep(torch, morph, srcs, dsts, base,
+                                             3 if R else (8 if quick else 20),
+                                             choices=R["wide_rows"] if R else WIDE_ROWS)
             base["wide_rows"] = wr2
             result["u8_wide_rows_sweep"] = wr2_table
             _with_table(morph, {dname: base})
-        rules, table = tile_sweep(torch, morph, srcs, dsts, dname, iters=8 if quick else 20)
+        if R:
+            rules, table = tile_sweep(torch, morph, srcs, dsts, dname, iters=3,
+                                      buckets=R["buckets"], tqs=R["tq"], tbs=R["tb"])
+        else:
+            rules, table = tile_sweep(torch, morph, srcs, dsts, dname,
+                                      iters=8 if quick else 20)
         del srcs, dsts, big
         result[dname] = dict(base, tiles=rules)
         result[dname + "_pass_sweep"] = rows
@@ -270,8 +347,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--reduced", action="store_true",
+                    help="a few windows and choices per key on smaller images")
     a = ap.parse_args(argv)
-    r = tune(a.out, a.quick)
+    r = tune(a.out, a.quick, a.reduced)
     print(json.dumps({k: r[k] for k in ("device", "u8", "u16")}), flush=True)
 
 

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 
@@ -11,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libmorph_hip.so"
 SOURCES = ("k_fused_u8.hip", "k_fused_u16.hip", "k_tile.hip", "k_stream.hip", "k_wave.hip",
-           "k_rows.hip", "morph_launch.hip", "morph_api.hip", "morph_transpose.hip",
+           "k_rows.hip", "k_wave_tall_u8.hip", "k_wave_tall_u16.hip", "morph_launch.hip", "morph_api.hip", "morph_transpose.hip",
            "morph_openclose.hip", "morph_static.hip")
 ARCH = os.environ.get("MORPH_OFFLOAD_ARCH", "gfx950")
 
@@ -26,20 +27,34 @@ def hipcc() -> str:
 def _flags():
     return [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
+            "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
+            "-Rpass-analysis=kernel-resource-usage"]
+
+
+_SCRATCH = re.compile(r"ScratchSize \[bytes/lane\]: (\d+)")
 
 
 def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    # the host pass does not know the packed-fp32 feature and says so; keep real errors
-    lines = [ln for ln in res.stdout.splitlines() if "packed-fp32-ops" not in ln]
+    # the host pass does not know the packed-fp32 feature and says so; the
+    # resource-usage remarks are read below, not printed; keep real errors
+    lines = [ln for ln in res.stdout.splitlines()
+             if "packed-fp32-ops" not in ln and "kernel-resource-usage" not in ln]
     if res.returncode != 0:
         sys.stderr.write("\n".join(lines) + "\n")
         raise RuntimeError("hipcc failed (%d)" % res.returncode)
-    if verbose and lines:
-        print("\n".join(lines))
+    # a kernel whose registers spill to scratch memory runs many times slower with
+    # no other sign: refuse to build one
+    spills = [int(m) for m in _SCRATCH.findall(res.stdout) if int(m) > 0]
+    if spills:
+        raise RuntimeError("a kernel of %s uses %d bytes of scratch per lane (register "
+                           "spills)" % (cmd[cmd.index("-c") + 1] if "-c" in cmd else "?",
+                                        max(spills)))
+    warnings = [ln for ln in lines if "warning:" in ln]
+    if verbose and warnings:
+        print("\n".join(warnings))
 
 
 def build(verbose: bool = False) -> str:

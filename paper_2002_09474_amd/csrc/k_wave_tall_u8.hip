@@ -1,0 +1,18 @@
+// The wave kernel's tall form for uint8_t images (a translation unit of its own: the
+// tall windows take long to compile).
+#include "k_wave_tall.h"
+
+namespace morph {
+
+hipError_t launch_wave_tall_u8(const TileJob &job, hipStream_t stream)
+{
+    return launch_wave_tall_t<uint8_t>(job, stream);
+}
+
+hipError_t launch_batch_wave_tall_u8(const BatchTables &t, bool aligned, int grid,
+                                     hipStream_t stream)
+{
+    return launch_batch_wave_tall_t<uint8_t>(t, aligned, grid, stream);
+}
+
+} // namespace morph

@@ -48,12 +48,21 @@ struct DtypeTuning {
     // whatever their height, so that longer units (less vertical warm-up) pay
     int batch_wave_rows, batch_stream_rows, batch_stream_rows_runs;
     int fit_units; // single images: shorten units until the launch fills the GPU (0 / 1)
+    // the thresholds for the images of a batch, measured on a batch: there a pass that
+    // leaves the fused dispatch (the wave kernel's tall form) can cost more than it
+    // saves on its own images
+    int batch_t_x, batch_t_y;
 };
 
 std::mutex g_tuning_mu;
+// The autotuner's table for gfx950 (its sweeps are kept in tuning_gfx950.json next to
+// the Python package): direct passes up to 9 along x (16 for uint16) and 31 along y on
+// single images, 9 and 9 for the images of a batch; unit heights and tile shapes.
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48, 1},
-    {9, 9, {{9, 32, 64}, {16, 32, 64}, {64, 48, 64}, {1 << 30, 64, 64}}, 24, 48, 32, 4, 1, 32, 48, 48, 1},
+    {9, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 96, 48, 4,
+     1, 24, 96, 64, 1, 9, 9},
+    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 32, 32}}, 8, 96, 64, 4,
+     1, 16, 64, 64, 1, 9, 9},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -149,6 +158,10 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_x = (int)it->second.num;
     it = o.obj.find("t_y");
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.t_y = (int)it->second.num;
+    it = o.obj.find("batch_t_x");
+    if (it != o.obj.end() && it->second.k == JVal::NUM) t.batch_t_x = (int)it->second.num;
+    it = o.obj.find("batch_t_y");
+    if (it != o.obj.end() && it->second.k == JVal::NUM) t.batch_t_y = (int)it->second.num;
     for (const char *key : {"wave_rows", "batch_wave_rows"}) {
         it = o.obj.find(key);
         if (it == o.obj.end()) continue;
@@ -212,7 +225,7 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
             t.tiles = rules;
         }
     }
-    return t.t_x >= 1 && t.t_y >= 1;
+    return t.t_x >= 1 && t.t_y >= 1 && t.batch_t_x >= 1 && t.batch_t_y >= 1;
 }
 
 // ---------------- planning ----------------
@@ -254,6 +267,16 @@ int default_anchor(int w) { return w - 1 - w / 2; }
 // than 8) until the launch has about kUnitTarget of them: 8 waves per CU of a 256-CU
 // MI355X.  Batches fill the GPU with many images and keep the tuned heights.
 constexpr int kUnitTarget = 2048;
+
+// Output quads a strip of the wave or streaming kernel stores: no more than sq (those
+// whose input lies in the wave's 64 quads), as few strips as that allows, and the
+// strips as even as possible (a 1920-pixel row: 8 strips of 60 quads, none partial).
+static int strip_quads(int W, int sq)
+{
+    const int nq = (W + 3) / 4;
+    const int n = (nq + sq - 1) / sq;
+    return (nq + n - 1) / n;
+}
 
 static int fit_rows(int tuned, int H, int strips)
 {
@@ -302,14 +325,15 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     else if (mx == MORPH_METHOD_DIRECT) j.hm = PASS_DIRECT;
     else if (mx == MORPH_METHOD_VHGW) j.hm = PASS_VHGW;
     else if (mx == MORPH_METHOD_DOUBLING) j.hm = PASS_DOUBLING;
-    else j.hm = (j.wx <= std::min(tu.t_x, kDirectMax)) ? PASS_DIRECT : PASS_VHGW;
+    else j.hm = (j.wx <= std::min(batch ? tu.batch_t_x : tu.t_x, kDirectMaxX)) ? PASS_DIRECT
+                                                                                 : PASS_VHGW;
     // vertical pass (a window of 1 is the direct pass's plain load)
     if (j.wy == 1) j.vm = PASS_DIRECT;
     else if (my == MORPH_METHOD_DIRECT) j.vm = PASS_DIRECT;
     else if (my == MORPH_METHOD_VHGW) j.vm = PASS_VHGW;
-    else j.vm = (j.wy <= std::min(tu.t_y, kDirectMax)) ? PASS_DIRECT : PASS_VHGW;
-    if ((j.hm == PASS_DIRECT && j.wx > kDirectMax) || (j.vm == PASS_DIRECT && j.wy > kDirectMax))
-        return MORPH_EUNSUPPORTED;
+    else j.vm = (j.wy <= std::min(batch ? tu.batch_t_y : tu.t_y, kDirectMaxTall)) ? PASS_DIRECT
+                                                                                  : PASS_VHGW;
+    // (direct windows past the compiled ones run on the tile kernel's tap loops)
     j.vcode = (j.vm == PASS_DIRECT) ? j.wy : 0;
     j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
     j.SA = j.SB = 0;
@@ -333,13 +357,17 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     // vertical pass direct and no tile asked for: the register-only wave kernel, with
     // the horizontal pass direct or (wider windows, automatic or asked for) doubling
     j.kind = KIND_TILE;
-    const bool h_wave = j.hm == PASS_DIRECT || j.hm == PASS_NONE || j.hm == PASS_DOUBLING ||
+    const bool h_wave = (j.hm == PASS_DIRECT && j.wx <= kDirectMaxX) || j.hm == PASS_NONE ||
+                        j.hm == PASS_DOUBLING ||
                         (j.hm == PASS_VHGW && mx == MORPH_METHOD_AUTO && j.wx <= kStreamMaxWx);
-    if (j.vm == PASS_DIRECT && h_wave && !user_tile && (my != MORPH_METHOD_VHGW)) {
+    if (j.vm == PASS_DIRECT && j.wy <= kDirectMaxTall && h_wave && !user_tile &&
+        (my != MORPH_METHOD_VHGW)) {
         j.kind = KIND_WAVE;
         if (j.hm == PASS_VHGW) j.hm = PASS_DOUBLING;
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
-        j.TW = j.hm == PASS_DOUBLING ? 4 * stream_quads(j.wx) : 4 * kWaveQuads;
+        // (a strip stores at most the quads whose input lies in its 64 quads,
+        // stream_quads(wx) of them, whatever the horizontal pass)
+        j.TW = 4 * strip_quads(W, stream_quads(j.wx));
         j.TB = std::min(batch ? tu.batch_wave_rows : tu.wave_rows,
                         (H + kWaveRows - 1) / kWaveRows * kWaveRows);
         j.tiles_x = (W + j.TW - 1) / j.TW;
@@ -352,11 +380,12 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     // kernel (its vertical pass is vHGW through the LDS ring whatever wy is)
     if (j.hm == PASS_DOUBLING || (auto_both && !user_tile && stream_fits)) {
         j.kind = KIND_STREAM;
-        if (j.hm == PASS_VHGW) j.hm = PASS_DOUBLING;
+        // (its direct horizontal pass takes windows up to kDirectMax)
+        if (j.hm == PASS_VHGW || (j.hm == PASS_DIRECT && j.wx > kDirectMax)) j.hm = PASS_DOUBLING;
         j.vm = PASS_VHGW;
         j.vcode = 0;
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
-        j.TW = 4 * stream_quads(j.wx);
+        j.TW = 4 * strip_quads(W, stream_quads(j.wx));
         j.tiles_x = (W + j.TW - 1) / j.TW;
         // (by measurement: single images, 48 rows for the LDS-ring form and 32 for
         // the run-total form, which give a 4096x4096 image units enough to fill the
@@ -401,7 +430,9 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         // last one; odd stride in dwords.  B: row pairs of the output columns (+ 3 for
         // the store's last quad); odd stride.
         const int acols = std::max(tw + j.wx - 1 + 3,
-                                   j.hm == PASS_DIRECT ? tw + kDirectChunkX + kDirectMax + 3 : 0) +
+                                   j.hm == PASS_DIRECT
+                                       ? tw + kDirectChunkX + std::max(j.wx, kDirectMax) + 3
+                                       : 0) +
                           4;
         j.SA = ((acols + 1) / 2) | 1;
         j.SB = (j.hm == PASS_NONE) ? 0 : ((tw + 4) | 1);
@@ -477,7 +508,7 @@ static int run_gradient(int dtype, const void *src, void *dst, int H, int W, siz
     int rc = plan_job(MORPH_OP_ERODE, dtype, src, dst, H, W, pitch, pitch, wx, wy, ax, ay, plan, j);
     if (rc != MORPH_OK) return rc;
     hipError_t e;
-    if (j.kind == KIND_WAVE && job_rows_aligned(j)) {
+    if (j.kind == KIND_WAVE && !wave_tall(j) && job_rows_aligned(j)) {
         if ((e = launch_gradient_job(j, stream)) != hipSuccess) return hip_fail(e);
         return MORPH_OK;
     }
@@ -647,7 +678,7 @@ int morph_resolve_plan(int dtype, int H, int W, int wx, int wy, morph_plan *plan
     const morph_plan in = *plan;
     const size_t p = (size_t)W * elem_bytes(dtype);
     int rc = plan_job(MORPH_OP_ERODE, dtype, (const void *)16, (void *)16, H, W, p, p, wx, wy, -1,
-                      -1, &in, j);
+                      -1, &in, j, in.batch != 0);
     if (rc != MORPH_OK) return rc;
     plan->method_x = j.hm == PASS_NONE        ? MORPH_METHOD_AUTO
                      : j.hm == PASS_DIRECT   ? MORPH_METHOD_DIRECT
@@ -741,11 +772,14 @@ struct WsPatch {
     size_t offset;  // bytes from the workspace start
 };
 
-// groups: kernel kind x element type x row alignment, and for the streaming kernel
-// its two vertical forms (LDS ring for wy <= kStreamRingMaxWy, run totals above)
-static constexpr int kRingClasses = 2;
-// group classes: tile, wave, streaming (ring), streaming (run totals), wide rows
-static constexpr int kGroupClasses = kKinds + kRingClasses - 1;
+// groups: kernel kind x element type x row alignment, for the streaming kernel its
+// two vertical forms (LDS ring for wy <= kStreamRingMaxWy, run totals above) and for
+// the wave kernel its two forms (vertical windows up to kDirectMax, tall beyond)
+// group classes: tile, wave, streaming (ring), streaming (run totals), wide rows, wave
+// (tall)
+static constexpr int kGroupClasses = kKinds + 2;
+static constexpr int kClassRows = kKinds;          // wide rows
+static constexpr int kClassWaveTall = kKinds + 1;  // tall wave units
 static constexpr int kPhaseGroups = 4 * kGroupClasses;
 // an opening or closing descriptor is two jobs: its first operation (src into the
 // workspace) in phase 0 with every erosion and dilation, its second (workspace into
@@ -841,7 +875,8 @@ static int group_of(const TileJob &j, int phase)
 {
     int k = j.kind;
     if (j.kind == KIND_STREAM && stream_two_level(j.wy)) k = KIND_STREAM + 1;
-    else if (j.kind == KIND_ROWS) k = kGroupClasses - 1;
+    else if (j.kind == KIND_ROWS) k = kClassRows;
+    else if (wave_tall(j)) k = kClassWaveTall;
     return phase * kPhaseGroups + 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
 }
 
@@ -849,8 +884,8 @@ static int group_of(const TileJob &j, int phase)
 // groups (run totals, then ring), then the tile, wave and wide-row groups.
 static int group_order(int gi)
 {
-    static const int order[kGroupClasses] = {KIND_STREAM + 1, KIND_STREAM, KIND_TILE, KIND_WAVE,
-                                             kGroupClasses - 1};
+    static const int order[kGroupClasses] = {KIND_STREAM + 1, KIND_STREAM, kClassWaveTall,
+                                             KIND_TILE, KIND_WAVE, kClassRows};
     const int ph = gi / kPhaseGroups, r = gi % kPhaseGroups;
     return ph * kPhaseGroups + 4 * order[r / 4] + r % 4;
 }
@@ -968,7 +1003,10 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         G.kind = jobs[g][0].kind;
         G.dtype = jobs[g][0].dtype;
         G.aligned = job_rows_aligned(jobs[g][0]);
-        G.variant = (G.kind == KIND_STREAM && stream_two_level(jobs[g][0].wy)) ? 1 : 0;
+        G.variant = ((G.kind == KIND_STREAM && stream_two_level(jobs[g][0].wy)) ||
+                     wave_tall(jobs[g][0]))
+                        ? 1
+                        : 0;
         G.phase = g / kPhaseGroups;
         int64_t t = 0;
         for (size_t q = 0; q < jobs[g].size(); q++) {
@@ -1041,7 +1079,7 @@ static int fused_class(const BatchGroup &G)
 {
     if (!tuning_for(G.dtype).fuse) return -1;
     if (G.kind == KIND_STREAM) return G.variant ? 0 : 1;
-    return G.kind == KIND_WAVE ? 2 : -1;
+    return (G.kind == KIND_WAVE && !G.variant) ? 2 : -1;
 }
 
 // The wave and streaming groups of each element type and row alignment as one
@@ -1094,6 +1132,22 @@ static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
     return hipSuccess;
 }
 
+// Kernel dispatches launch_groups makes: per phase, one per element type and row
+// alignment with fused units, and one per other group.
+static int count_dispatches(const morph_batch *b)
+{
+    int n = 0;
+    bool fused[kPhases][2][2] = {};
+    for (const BatchGroup &G : b->groups) {
+        if (fused_class(G) < 0) n++;
+        else if (!fused[G.phase][G.dtype][G.aligned ? 0 : 1]) {
+            fused[G.phase][G.dtype][G.aligned ? 0 : 1] = true;
+            n++;
+        }
+    }
+    return n;
+}
+
 // Point the intermediates of the batch's openings and closings into `workspace`:
 // check it (size, no overlap with any image of the batch), write the pointers into
 // the staged job table and copy it to the device on `stream`, ahead of the launch.
@@ -1140,8 +1194,10 @@ int morph_batch_enqueue(morph_batch_t b, void *workspace, size_t ws_bytes, hipSt
     int rc = bind_workspace(b, workspace, ws_bytes, stream);
     if (rc != MORPH_OK) return rc;
     hipError_t e;
-    if (stream == nullptr) {
-        // the legacy null stream cannot be captured: launch directly
+    // The legacy null stream cannot be captured, and a batch of one dispatch gains
+    // nothing from a graph (a one-node graph's replay measured ~4% slower than the
+    // dispatch itself on the 512-image batch): launch directly.
+    if (stream == nullptr || count_dispatches(b) <= 1) {
         if ((e = launch_groups(b, stream)) != hipSuccess) return hip_fail(e);
         return MORPH_OK;
     }

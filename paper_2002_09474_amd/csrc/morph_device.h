@@ -464,6 +464,45 @@ __device__ __forceinline__ void vpass_direct(const TileCtx<T, AL> &c)
     }
 }
 
+// ---- vertical pass, direct, any window (w > DMAX) ----
+// The definition with a loop over the taps: each of a unit's KV + w - 1 input rows
+// (read KV at a time) enters the extremum of every output row whose window holds
+// it, so a pixel costs O(w) operations, the direct pass's cost (§5.1.2) without its
+// compiled sharing.  Work unit: one quad of columns and KV output rows.
+template <bool MAXOP, typename T, bool AL>
+__device__ __forceinline__ void vpass_direct_any(const TileCtx<T, AL> &c, int w)
+{
+    const int NKV = (c.out_h + KV - 1) / KV;
+    const int nin = KV + w - 1;
+    for (int u = c.tid; u < c.NQ * NKV; u += NT) {
+        const int k = c.fq.div(u), q = u - k * c.NQ, s0 = k * KV;
+        uint32_t o01[KV], o23[KV];
+#pragma unroll
+        for (int m = 0; m < KV; m++) o01[m] = o23[m] = c.id;
+        for (int i0 = 0; i0 < nin; i0 += KV) {
+            uint32_t x01[KV], x23[KV];
+            load_rows<KV>(c.L, c.cy0 + s0 + i0, 1, c.cxa + 4 * q, nin - i0, x01, x23);
+#pragma unroll
+            for (int r = 0; r < KV; r++)
+#pragma unroll
+                for (int m = 0; m < KV; m++) {
+                    const int i = i0 + r; // input row i is in output m's window
+                    if (i >= m && i < m + w) {
+                        o01[m] = pk<MAXOP>(o01[m], x01[r]);
+                        o23[m] = pk<MAXOP>(o23[m], x23[r]);
+                    }
+                }
+        }
+#pragma unroll
+        for (int m = 0; m < KV; m++)
+            if (s0 + m < c.out_h) {
+                uint32_t *d = c.arow(s0 + m, q);
+                d[0] = o01[m];
+                d[1] = o23[m];
+            }
+    }
+}
+
 // ---- vertical pass, vHGW ----
 // Phase F: g over each block of wy input rows, stored in the output row it pairs with
 // (s = i - wy + 1).  Phase B: walk each block backwards; h[s] = op of rows s .. block
@@ -639,6 +678,33 @@ __device__ __forceinline__ void hpass_direct(const TileCtx<T, AL> &c)
     else hpass_direct_par<W, MAXOP, 0>(c);
 }
 
+// ---- horizontal pass, direct, any window (w > DMAX) ----
+// As vpass_direct_any along the row pairs of A: work unit one row pair and KH
+// output columns, a loop over its KH + w - 1 input columns.
+template <bool MAXOP, typename T, bool AL>
+__device__ __forceinline__ void hpass_direct_any(const TileCtx<T, AL> &c, int w)
+{
+    const int NKH = (c.out_w + KH - 1) / KH;
+    const int nin = KH + w - 1;
+    for (int u = c.tid; u < c.NP * NKH; u += NT) {
+        const int k = c.fp.div(u), p = u - k * c.NP, c0 = k * KH;
+        const uint32_t *r0 = c.A + 2 * p * c.SA;
+        uint32_t o[KH];
+#pragma unroll
+        for (int m = 0; m < KH; m++) o[m] = c.id;
+        for (int e = 0; e < nin; e++) {
+            const uint32_t x = col_pair(c, r0, c.co + c0 + e);
+#pragma unroll
+            for (int m = 0; m < KH; m++)
+                if (e >= m && e < m + w) o[m] = pk<MAXOP>(o[m], x);
+        }
+        uint32_t *d = c.B + p * c.SB + c0;
+#pragma unroll
+        for (int m = 0; m < KH; m++)
+            if (c0 + m < c.out_w) d[m] = o[m];
+    }
+}
+
 // ---- horizontal pass, vHGW ----
 // Work unit: one row pair and one block of wx input columns.  Phase F writes g
 // shifted by wx - 1 into B; phase B walks the block backwards and combines h with g
@@ -760,7 +826,10 @@ __device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *
     case 7: vpass_direct<7, MAXOP>(c); break;
     case 8: vpass_direct<8, MAXOP>(c); break;
     case 9: vpass_direct<9, MAXOP>(c); break;
-    default: vpass_vhgw<MAXOP>(c, J.vrun, (J.TW + J.wx - 1 + 3 + 3) / 4); break;
+    default:
+        if (J.vm == PASS_DIRECT) vpass_direct_any<MAXOP>(c, J.wy);
+        else vpass_vhgw<MAXOP>(c, J.vrun, (J.TW + J.wx - 1 + 3 + 3) / 4);
+        break;
     }
     __syncthreads();
     if (J.hcode == 1) {
@@ -776,7 +845,10 @@ __device__ __forceinline__ void tile_body(const TileJob &J, int tile, uint32_t *
     case 7: hpass_direct<7, MAXOP>(c); break;
     case 8: hpass_direct<8, MAXOP>(c); break;
     case 9: hpass_direct<9, MAXOP>(c); break;
-    default: hpass_vhgw<MAXOP>(c); break;
+    default:
+        if (J.hm == PASS_DIRECT) hpass_direct_any<MAXOP>(c, J.wx);
+        else hpass_vhgw<MAXOP>(c);
+        break;
     }
     __syncthreads();
     store_pairs(c, J);
@@ -910,7 +982,7 @@ __device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, u
 // of its own quad from the next lanes with wave-wide DPP shifts (v_mov_b32_dpp
 // wave_shl:1): the direct pass, or for wider windows the doubling pass.  No LDS,
 // no barrier.  The last lanes of the wave only supply those columns: a wave stores
-// wq = J.TW / 4 quads (60 for the direct pass, stream_quads(wx) for doubling).
+// wq = J.TW / 4 = stream_quads(wx) quads, those whose input lies in its 64.
 // Input quad Q starts at image column gxa + 4Q, gxa = 4 wq sx - ax - co, where co
 // puts the quad grid on multiples of the load size; output quad Q (columns 4Q ..
 // 4Q + 3 of the strip) reads input pixels 4Q + co .. 4Q + co + 3 + wx - 1.  The
@@ -927,7 +999,8 @@ __device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, u
 // byte selectors of the widening v_perm (uint8) or of one v_perm per output row
 // (uint16).
 constexpr int KR = kWaveRows;
-constexpr int RING = KR + kDirectMax - 1;
+// registers of the row ring: the short form (wy <= kDirectMax) and the tall one
+template <bool TALL> constexpr int ring_rows() { return KR + (TALL ? kDirectMaxTall : kDirectMax) - 1; }
 
 // Rows with 4-aligned (uint8) / 8-aligned (uint16) pitch: lane set-up for a unit.
 // Loads go through a buffer resource on the image (it spans < 4 GiB): the row
@@ -1050,6 +1123,63 @@ __device__ __forceinline__ void wv_vertical(const Ld &L, const typename Ld::Raw 
     }
 }
 
+// The tall form keeps its ring of input rows as loaded (one register a row for
+// uint8 quads), widening each row where a chunk uses it: the same pairs of outputs
+// share their WY - 1 middle rows as in pair_window, with the rows visited once each.
+template <int WY, typename Ld>
+__device__ __forceinline__ void wv_first_raw(const Ld &L, int gy0, typename Ld::Raw *ring,
+                                             typename Ld::Raw *raw)
+{
+#pragma unroll
+    for (int k = 0; k < WY - 1; k++) ring[k] = L.issue(gy0 + k);
+#pragma unroll
+    for (int m = 0; m < KR; m++) raw[m] = L.issue(gy0 + WY - 1 + m);
+}
+
+template <int WY, bool MAXOP, typename Ld>
+__device__ __forceinline__ void wv_vertical_raw(const Ld &L, const typename Ld::Raw *cur,
+                                                typename Ld::Raw *ring, uint32_t *o01,
+                                                uint32_t *o23)
+{
+    static_assert(WY >= 3, "the tall form's windows");
+#pragma unroll
+    for (int m = 0; m < KR; m++) ring[WY - 1 + m] = cur[m];
+    uint32_t c01[KR / 2], c23[KR / 2]; // output pair p: the extremum of rows 2p + 1 .. 2p + WY - 1
+#pragma unroll
+    for (int r = 0; r < WY + KR - 1; r++) {
+        uint32_t x01, x23;
+        L.widen(ring[r], x01, x23);
+#pragma unroll
+        for (int p = 0; p < KR / 2; p++) {
+            const int a = 2 * p; // outputs a (rows a .. a + WY - 1) and a + 1
+            if (r == a) {
+                o01[a] = x01;
+                o23[a] = x23;
+            } else if (r == a + 1) {
+                c01[p] = x01;
+                c23[p] = x23;
+            } else if (r < a + WY) {
+                if (r > a + 1) {
+                    c01[p] = pk<MAXOP>(c01[p], x01);
+                    c23[p] = pk<MAXOP>(c23[p], x23);
+                }
+            } else if (r == a + WY) {
+                o01[a + 1] = x01;
+                o23[a + 1] = x23;
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < KR / 2; p++) {
+        o01[2 * p] = pk<MAXOP>(c01[p], o01[2 * p]);
+        o23[2 * p] = pk<MAXOP>(c23[p], o23[2 * p]);
+        o01[2 * p + 1] = pk<MAXOP>(c01[p], o01[2 * p + 1]);
+        o23[2 * p + 1] = pk<MAXOP>(c23[p], o23[2 * p + 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < WY - 1; k++) ring[k] = ring[k + KR];
+}
+
 // Rows of any pitch: the general loader (identity outside the image).
 template <typename T> struct WaveLoaderAny {
     RowLoader<T, false> L;
@@ -1129,9 +1259,11 @@ __device__ __forceinline__ void wv_horizontal_any(int wx, int co, uint32_t *v01,
     case W * 4 + 3: wv_horizontal<W, 3, MAXOP>(v01, v23); break;
     switch (wx * 4 + co) {
         MORPH_WH(1) MORPH_WH(2) MORPH_WH(3) MORPH_WH(4) MORPH_WH(5) MORPH_WH(6) MORPH_WH(7)
-        MORPH_WH(8) MORPH_WH(9)
+        MORPH_WH(8) MORPH_WH(9) MORPH_WH(10) MORPH_WH(11) MORPH_WH(12) MORPH_WH(13)
+        MORPH_WH(14) MORPH_WH(15) MORPH_WH(16)
     default: break;
     }
+    static_assert(kDirectMaxX == 16, "horizontal direct windows compiled");
 #undef MORPH_WH
 }
 
@@ -1148,9 +1280,39 @@ __device__ __forceinline__ void wv_horizontal_any(int wx, int co, uint32_t *v01,
     default: CALL(9); break;                                                                 \
     }
 
-template <typename T, bool MAXOP, bool AL>
+#define MORPH_WY_SWITCH_TALL(WYV, CALL)                                                      \
+    switch (WYV) {                                                                           \
+    case 10: CALL(10); break;                                                                \
+    case 11: CALL(11); break;                                                                \
+    case 12: CALL(12); break;                                                                \
+    case 13: CALL(13); break;                                                                \
+    case 14: CALL(14); break;                                                                \
+    case 15: CALL(15); break;                                                                \
+    case 16: CALL(16); break;                                                                \
+    case 17: CALL(17); break;                                                                \
+    case 18: CALL(18); break;                                                                \
+    case 19: CALL(19); break;                                                                \
+    case 20: CALL(20); break;                                                                \
+    case 21: CALL(21); break;                                                                \
+    case 22: CALL(22); break;                                                                \
+    case 23: CALL(23); break;                                                                \
+    case 24: CALL(24); break;                                                                \
+    case 25: CALL(25); break;                                                                \
+    case 26: CALL(26); break;                                                                \
+    case 27: CALL(27); break;                                                                \
+    case 28: CALL(28); break;                                                                \
+    case 29: CALL(29); break;                                                                \
+    case 30: CALL(30); break;                                                                \
+    default: CALL(31); break;                                                                \
+    }
+static_assert(kDirectMaxTall == 31, "tall vertical windows compiled");
+
+// TALL: the vertical window is kDirectMax + 1 .. kDirectMaxTall (a longer register ring,
+// so fewer waves fit a SIMD; a kernel of its own); else 1 .. kDirectMax.
+template <typename T, bool MAXOP, bool AL, bool TALL = false>
 __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 {
+    constexpr int RING = ring_rows<TALL>();
     const int lane = threadIdx.x & 63;
     const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
     const int mis = AL ? (int)(((uintptr_t)J.src & (4 * sizeof(T) - 1)) / sizeof(T)) : 0;
@@ -1167,14 +1329,23 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
         if constexpr (AL) return WaveLoader<T>(J, mis, gx);
         else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)), gx);
     }();
-    uint32_t r01[RING], r23[RING];
     using Raw = typename Ld::Raw;
+    // the ring of input rows: widened (short form) or as loaded (tall form)
+    uint32_t r01[TALL ? 1 : RING], r23[TALL ? 1 : RING];
+    Raw rr[TALL ? RING : 1];
     Raw ra[KR], rb[KR];
-#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, r01, r23, ra)
-    MORPH_WY_SWITCH(J.wy, MORPH_FIRST)
+    if constexpr (TALL) {
+#define MORPH_FIRST(W) wv_first_raw<W>(L, y0 - J.ay, rr, ra)
+        MORPH_WY_SWITCH_TALL(J.wy, MORPH_FIRST)
 #undef MORPH_FIRST
+    } else {
+#define MORPH_FIRST(W) wv_first<W>(L, y0 - J.ay, r01, r23, ra)
+        MORPH_WY_SWITCH(J.wy, MORPH_FIRST)
+#undef MORPH_FIRST
+    }
     // destination: 4-byte aligned rows and a strip wholly inside the image take
-    // one plain store per row and lane
+    // one plain store per row and lane (a choice the whole wave makes, outside the
+    // row loop)
     const int Q = wq * sx + lane;
     const bool fast_store = (((uintptr_t)J.dst | (uintptr_t)J.dpitch) & 3) == 0 &&
                             4 * (wq * sx + wq) <= J.W;
@@ -1193,9 +1364,15 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 #pragma unroll
             for (int m = 0; m < KR; m++) nxt[m] = L.issue(gn + m);
         }
-#define MORPH_VERT(W) wv_vertical<W, MAXOP>(L, cur, r01, r23, v01, v23)
-        MORPH_WY_SWITCH(J.wy, MORPH_VERT)
+        if constexpr (TALL) {
+#define MORPH_VERT(W) wv_vertical_raw<W, MAXOP>(L, cur, rr, v01, v23)
+            MORPH_WY_SWITCH_TALL(J.wy, MORPH_VERT)
 #undef MORPH_VERT
+        } else {
+#define MORPH_VERT(W) wv_vertical<W, MAXOP>(L, cur, r01, r23, v01, v23)
+            MORPH_WY_SWITCH(J.wy, MORPH_VERT)
+#undef MORPH_VERT
+        }
         if constexpr (AL && sizeof(T) == 2) {
             if (edge) {
 #pragma unroll
@@ -1287,6 +1464,7 @@ __device__ __forceinline__ void grad_body(const TileJob &J, int unit)
     const bool edge = gxa < 0 || gxa + 4 * 64 > J.W;
     using Ld = WaveLoader<T>;
     const Ld L(J, mis, gx);
+    constexpr int RING = ring_rows<false>(); // vertical windows up to kDirectMax
     uint32_t r01[RING], r23[RING];
     using Raw = typename Ld::Raw;
     Raw ra[KR], rb[KR];
@@ -1629,6 +1807,8 @@ __device__ __forceinline__ void direct_rows_any(int wx, int co, uint32_t *v01, u
             wv_horizontal_row<W, C, MAXOP>(v01[r], v23[r]);                                  \
         break;
 #define MORPH_WH(W) MORPH_WH1(W, 0) MORPH_WH1(W, 1) MORPH_WH1(W, 2) MORPH_WH1(W, 3)
+    // (the streaming kernel's direct windows stop at kDirectMax: more cases make the
+    // chunk too large to keep its arrays in registers)
     switch (wx * 4 + co) {
         MORPH_WH(1) MORPH_WH(2) MORPH_WH(3) MORPH_WH(4) MORPH_WH(5) MORPH_WH(6) MORPH_WH(7)
         MORPH_WH(8) MORPH_WH(9)

@@ -7,14 +7,20 @@
 namespace morph {
 
 constexpr int kThreads = 256;  // threads per workgroup of every kernel
-constexpr int kDirectMax = 9;  // largest window the direct (sliding) passes take
+// Direct (sliding) passes: compiled per window up to kDirectMax on every kernel; the
+// wave kernel's tall form compiles vertical windows kDirectMax + 1 .. kDirectMaxTall,
+// and the wave and streaming kernels' horizontal direct pass windows up to
+// kDirectMaxX; the tile kernel runs larger direct windows with a loop over the taps.
+constexpr int kDirectMax = 9;
+constexpr int kDirectMaxTall = 31;
+constexpr int kDirectMaxX = 16;
 constexpr int kDirectChunkX = 8; // output columns per direct horizontal work unit
 constexpr int kVhgwBatch = 8;    // rows the vertical vHGW pass loads at a time
 constexpr int kMaxLdsBytes = 160 * 1024;
 
 enum PassMode { PASS_NONE = 0, PASS_DIRECT = 1, PASS_VHGW = 2, PASS_DOUBLING = 3 };
-// KIND_TILE: a workgroup per tile through LDS (any windows).  KIND_WAVE: both passes
-// direct, a wave per strip of kWaveQuads output quads and TB rows (a multiple of
+// KIND_TILE: a workgroup per tile through LDS (any windows).  KIND_WAVE: vertical pass
+// direct, a wave per strip of stream_quads(wx) output quads and TB rows (a multiple of
 // kWaveRows, done kWaveRows at a time), in registers.  KIND_STREAM: a wave per strip
 // of TW / 4 output quads and TB rows, walking down the rows once: vertical vHGW
 // through a ring of wy rows in LDS, horizontal direct or log-step doubling across
@@ -39,7 +45,6 @@ __host__ __device__ inline bool stream_two_level(int wy) { return wy > kStreamRi
 // ring entries: wy, plus slack so that a chunk may read kStreamChunk entries from any
 // position
 __host__ __device__ inline int stream_ring_entries(int wy) { return wy + kStreamChunk - 1; }
-constexpr int kWaveQuads = 60;
 constexpr int kWaveRows = 8;
 
 // One image as the tile kernels see it.  Windows and anchors are the effective
@@ -57,8 +62,9 @@ struct TileJob {
     int32_t tiles_x, tiles_y;
     int32_t SA, SB;  // LDS row-pair strides in dwords (odd)
     int32_t vm, hm;  // PassMode of the vertical / horizontal pass
-    int32_t vcode;   // vertical pass: 1..9 direct with that window, 0 vHGW
-    int32_t hcode;   // horizontal pass: 1 none, 2..9 direct with that window, 0 vHGW
+    int32_t vcode;   // vertical pass: w >= 1 direct with that window, 0 vHGW
+    int32_t hcode;   // horizontal pass: 1 none, w >= 2 direct with that window, 0 vHGW
+                     // or doubling
     int32_t vrun;    // vertical vHGW: rows per run (a multiple of kVhgwBatch); a block of wy
                      // rows is scanned as ceil(wy / vrun) runs joined by their totals
     int32_t vtt;     // dwords of LDS for the run totals (shares B's space)
@@ -87,6 +93,9 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream);
 // one launcher per kernel family (each family is a translation unit of its own)
 hipError_t launch_tile_kernel(const TileJob &job, hipStream_t stream);
 hipError_t launch_wave_kernel(const TileJob &job, hipStream_t stream);
+// the wave kernel's tall form: vertical windows kDirectMax + 1 .. kDirectMaxTall
+hipError_t launch_wave_tall_kernel(const TileJob &job, hipStream_t stream);
+inline bool wave_tall(const TileJob &j) { return j.kind == KIND_WAVE && j.wy > kDirectMax; }
 hipError_t launch_stream_kernel(const TileJob &job, hipStream_t stream);
 hipError_t launch_rows_kernel(const TileJob &job, hipStream_t stream);
 // the morphological gradient of a wave-kernel job (kind KIND_WAVE, rows aligned):
@@ -139,6 +148,14 @@ hipError_t launch_batch_tile(const BatchTables &t, int dtype, bool aligned, int 
                              hipStream_t stream);
 hipError_t launch_batch_wave(const BatchTables &t, int dtype, bool aligned, int grid,
                              hipStream_t stream);
+hipError_t launch_batch_wave_tall(const BatchTables &t, int dtype, bool aligned, int grid,
+                                  hipStream_t stream);
+hipError_t launch_wave_tall_u8(const TileJob &job, hipStream_t stream);
+hipError_t launch_wave_tall_u16(const TileJob &job, hipStream_t stream);
+hipError_t launch_batch_wave_tall_u8(const BatchTables &t, bool aligned, int grid,
+                                     hipStream_t stream);
+hipError_t launch_batch_wave_tall_u16(const BatchTables &t, bool aligned, int grid,
+                                      hipStream_t stream);
 hipError_t launch_batch_rows(const BatchTables &t, int dtype, bool aligned, int grid,
                              hipStream_t stream);
 hipError_t launch_batch_stream(const BatchTables &t, bool runs, int dtype, bool aligned, int grid,

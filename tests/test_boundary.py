@@ -116,19 +116,41 @@ def test_openclose_fused_argument_checks():
     assert oc(H=0, src=0, dst=0) == E.MORPH_OK
 
 
-def test_forced_direct_beyond_its_range_is_unsupported():
-    p = _lib.Plan(_lib.METHOD_DIRECT, 0, 0, 0)
-    rc = _lib.lib().morph_apply(0, 0, FAKE_SRC, FAKE_DST, 64, 64, 64, 17, 1, -1, -1, 0,
-                                ctypes.byref(p), None, 0, None)
-    assert rc == _lib.MORPH_EUNSUPPORTED
+def test_forced_direct_plans_past_the_compiled_windows():
+    import paper_2002_09474_amd as morph
+    # the wave kernel's direct passes: horizontal up to 16, vertical up to 31 (its
+    # tall form past 9); beyond them the tile kernel's tap loops
+    p = morph.resolve_plan("u8", 64, 64, 16, 31, method_x="direct", method_y="direct")
+    # (a 64-pixel row is one strip of its 16 quads: at most stream_quads(16) = 59)
+    assert (p["kernel"], p["method_x"], p["method_y"], p["tile_w"]) == ("wave", "direct",
+                                                                       "direct", 64)
+    p = morph.resolve_plan("u8", 64, 64, 17, 1, method_x="direct")
+    assert (p["kernel"], p["method_x"]) == ("tile", "direct")
+    p = morph.resolve_plan("u16", 64, 64, 3, 32, method_y="direct")
+    assert (p["kernel"], p["method_y"]) == ("tile", "direct")
+    p = morph.resolve_plan("u8", 64, 64, 200, 200, method_x="direct", method_y="direct")
+    assert (p["kernel"], p["method_x"], p["method_y"]) == ("tile", "direct", "direct")
     p = _lib.Plan(0, 0, 6, 0)  # tile width must be a multiple of 4
     rc = _lib.lib().morph_apply(0, 0, FAKE_SRC, FAKE_DST, 64, 64, 64, 3, 3, -1, -1, 0,
                                 ctypes.byref(p), None, 0, None)
     assert rc == _lib.MORPH_EINVAL
 
 
+# A fixed table for the plan checks below (the shipped one is the autotuner's
+# measurement and may change): unit heights and thresholds of its own.
+PLAN_TABLE = {"t_x": 9, "t_y": 9, "wave_rows": 24, "stream_rows": 48, "stream_rows_runs": 32,
+              "wide_rows": 4, "batch_wave_rows": 32, "batch_stream_rows": 48,
+              "batch_stream_rows_runs": 48, "batch_t_x": 9, "batch_t_y": 9,
+              "tiles": [{"wmax": 9, "tq": 32, "tb": 64}, {"wmax": 16, "tq": 32, "tb": 64},
+                        {"wmax": 64, "tq": 48, "tb": 64}, {"wmax": 1 << 30, "tq": 64, "tb": 64}]}
+
+
 def test_plan_resolution_and_thresholds(tmp_path):
+    import json
     import paper_2002_09474_amd as morph
+    f0 = tmp_path / "plan_table.json"
+    f0.write_text(json.dumps({"u8": PLAN_TABLE, "u16": PLAN_TABLE}))
+    morph.load_tuning(str(f0))
     t0 = morph.get_thresholds("u8")
     try:
         morph.set_thresholds("u8", 9, 7)
@@ -137,10 +159,10 @@ def test_plan_resolution_and_thresholds(tmp_path):
         assert p["method_x"] == "direct" and p["method_y"] == "vhgw"
         p = morph.resolve_plan("u8", 1080, 1920, 7, 7)
         assert p["method_x"] == "direct" and p["method_y"] == "direct"
-        # both passes direct: one wave per strip of 60 quads x 24 rows, on an image
-        # with enough units (18 strips x 171 units) to fill the GPU
+        # both passes direct: one wave per strip of stream_quads(7) = 61 quads x 24
+        # rows, on an image with enough units (17 strips x 171 units) to fill the GPU
         p = morph.resolve_plan("u8", 4096, 4096, 7, 7)
-        assert (p["tile_w"], p["tile_h"], p["kernel"]) == (240, 24, "wave")
+        assert (p["tile_w"], p["tile_h"], p["kernel"]) == (4 * 61, 24, "wave")
         # a smaller single image takes shorter units, until it has about 2048 of them
         # (in steps of 8 rows, no fewer than 8): 1080 x 1920 has 8 strips, so
         # ceil(1080 * 8 / 2048) = 5 rows -> 8
@@ -153,22 +175,27 @@ def test_plan_resolution_and_thresholds(tmp_path):
         p = morph.resolve_plan("u8", 1080, 1920, 31, 31)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
         # streaming units of 32 rows for wy > 16 (run-total form), 48 below (LDS ring),
-        # on images with units enough; 4096 x 4096 (19 strips) takes 40 for the ring
+        # on images with units enough; 4096 x 4096 (19 strips) takes 40 for the ring.
+        # Strips store at most stream_quads(31) = 55 quads, as even as possible: a
+        # 1024-quad row in 19 strips of 54
         p = morph.resolve_plan("u8", 8192, 4096, 31, 31)
-        assert (p["tile_w"], p["tile_h"]) == (4 * 55, 32)
+        assert (p["tile_w"], p["tile_h"]) == (4 * 54, 32)
         assert morph.resolve_plan("u8", 8192, 4096, 31, 15)["tile_h"] == 48
         assert morph.resolve_plan("u8", 4096, 4096, 31, 15)["tile_h"] == 40
         assert morph.resolve_plan("u8", 1080, 1920, 31, 15)["tile_h"] == 8
         p = morph.resolve_plan("u8", 1080, 1920, 7, 63)
         assert (p["method_x"], p["method_y"]) == ("direct", "vhgw")
         # doubling with a direct-size vertical window: the wave kernel, 24-row units
-        # (8 on small images), strips of stream_quads(wx) quads
+        # (8 on small images), strips of up to stream_quads(wx) quads (a 90-pixel row:
+        # one strip of its 23 quads)
         p = morph.resolve_plan("u8", 100000, 90, 3, 3, method_x="doubling")
-        assert (p["kernel"], p["tile_w"], p["tile_h"]) == ("wave", 4 * 62, 24)
+        assert (p["kernel"], p["tile_w"], p["tile_h"]) == ("wave", 4 * 23, 24)
+        p = morph.resolve_plan("u8", 100000, 4000, 3, 3, method_x="doubling")
+        assert (p["kernel"], p["tile_w"]) == ("wave", 4 * 59)  # 1000 quads: 17 strips
         assert morph.resolve_plan("u8", 20, 90, 3, 3, method_x="doubling")["tile_h"] == 8
         # automatic: wide and short windows stay on the wave kernel with doubling
-        p = morph.resolve_plan("u8", 1080, 1920, 63, 1)
-        assert (p["method_x"], p["kernel"], p["tile_w"]) == ("doubling", "wave", 4 * 47)
+        p = morph.resolve_plan("u8", 1080, 1920, 63, 1)  # 480 quads: 11 strips of <= 47
+        assert (p["method_x"], p["kernel"], p["tile_w"]) == ("doubling", "wave", 4 * 44)
         p = morph.resolve_plan("u8", 1080, 1920, 101, 101)
         assert (p["method_x"], p["method_y"], p["kernel"]) == ("doubling", "vhgw", "stream")
         p = morph.resolve_plan("u8", 1080, 1920, 129, 129)
@@ -209,10 +236,11 @@ def test_plan_resolution_and_thresholds(tmp_path):
         p = morph.resolve_plan("u8", 1000, 1000, 30, 30, **v)
         assert (p["tile_w"], p["tile_h"]) == (160 - 32, 16)
         # automatic methods beyond the thresholds: the streaming kernel, whose strip
-        # stores the quads whose input fits in 64: (250 - wx) // 4 + 1 of them
+        # stores at most the quads whose input fits in 64, (250 - wx) // 4 + 1 of them,
+        # the strips as even as that allows: 250 quads in 5 strips of 50
         p = morph.resolve_plan("u8", 100000, 1000, 5, 5)
         assert (p["method_x"], p["method_y"]) == ("doubling", "vhgw")
-        assert (p["tile_w"], p["tile_h"]) == (4 * 62, 48)
+        assert (p["tile_w"], p["tile_h"]) == (4 * 50, 48)
         f.write_text(json.dumps({"u8": {"stream_rows": 100, "stream_rows_runs": 40,
                                         "wide_rows": 7}}))
         morph.load_tuning(str(f))
@@ -239,7 +267,7 @@ def test_plan_resolution_and_thresholds(tmp_path):
             morph.load_tuning(str(tmp_path / "missing.json"))
     finally:
         assert _lib.lib().morph_load_tuning(None) == 0  # built-in defaults back
-        morph.set_thresholds("u8", *t0)
+        morph.load_tuning(None)  # and the package's table
 
 
 def test_strerror():

@@ -21,7 +21,9 @@ from paper_2002_09474_amd import synth  # noqa: E402
 from gpuutil import empty_like_dev, to_dev, to_host  # noqa: E402
 
 OPN = {"erode": oracle.ERODE, "dilate": oracle.DILATE}
-DMAX = 9  # largest window the direct passes take
+DMAX = 9  # largest window of the short wave kernel's vertical pass
+TALL = 31  # the tall wave kernel's vertical windows: DMAX + 1 .. TALL
+XMAX = 16  # the wave and streaming kernels' horizontal direct windows
 
 
 def _ref(img, op, wx, wy, ax=-1, ay=-1):
@@ -64,8 +66,6 @@ def test_small_shapes_all_methods(dtype):
             for op in ("erode", "dilate"):
                 for mx, my in (("direct", "direct"), ("vhgw", "vhgw"), ("direct", "vhgw"),
                                ("vhgw", "direct")):
-                    if (mx == "direct" and wx > DMAX) or (my == "direct" and wy > DMAX):
-                        continue
                     _check(img, op, wx, wy, ax, ay, method_x=mx, method_y=my)
 
 
@@ -75,17 +75,18 @@ def test_every_window_1_to_64_both_methods(axis):
     for w in range(1, 65):
         wx, wy = (w, 1) if axis == "x" else (1, w)
         for op in ("erode", "dilate"):
-            methods = ("vhgw",) if w > DMAX else ("direct", "vhgw")
-            for m in methods:
+            # direct: the wave kernel up to 16 along x and 31 along y, the tile
+            # kernel's tap loops beyond
+            for m in ("direct", "vhgw"):
                 kw = {"method_x": m} if axis == "x" else {"method_y": m}
                 _check(img, op, wx, wy, **kw)
 
 
 def test_all_anchors_and_even_windows():
     img = synth.uniform(70, 90, np.uint8, seed=22)
-    for w in (2, 4, 6, 9, 20):
+    for w in (2, 4, 6, 9, 12, 16, 20, 21, 30):
         for a in sorted({0, 1, w // 2, w - 1}):
-            for m in ("direct", "vhgw") if w <= DMAX else ("vhgw",):
+            for m in ("direct", "vhgw"):
                 _check(img, "erode", w, 3, a, 1, method_x=m)
                 _check(img, "dilate", 3, w, 0, a, method_y=m)
 
@@ -370,8 +371,9 @@ def test_config_1920x1080_document_sweep():
         for op in ("erode", "dilate"):
             _check(img, op, w, w)  # wave kernel up to 9, streaming kernel beyond
             _check(img, op, w, w, method_x="vhgw", method_y="vhgw")  # tile kernel
-            if w <= DMAX:
-                _check(img, op, w, w, method_x="direct", method_y="direct")
+            # direct: the wave kernel (tall form past 9) while both windows fit it,
+            # the tile kernel's tap loops beyond
+            _check(img, op, w, w, method_x="direct", method_y="direct")
 
 
 @pytest.mark.parametrize("dtype,seed", [(np.uint8, 3), (np.uint16, 4)])
@@ -387,3 +389,58 @@ def test_config_4096_square_all_ops(dtype, seed):
             kw = dict(method="hybrid", thresholds=(16, 16), nthreads=8)
             want = oracle.apply(op, img, wx, wy, **kw)
             assert np.array_equal(got, want), (op, wx, wy, dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_direct_windows_past_nine(dtype):
+    """The direct passes past the short wave kernel: the tall wave kernel's vertical
+    windows 10..31 and the horizontal direct windows 10..16 (both with every
+    anchor class, on aligned and unaligned rows, with ragged strips and units), and
+    the tile kernel's tap loops for windows past those (a tile forces it)."""
+    img = synth.uniform(203, 517, dtype, seed=31)
+    rng = np.random.default_rng(31)
+    for wy in range(DMAX + 1, TALL + 1):
+        wx = int(rng.choice([1, 3, 9, 12, 16, 40]))
+        for ay in sorted({-1, 0, wy - 1}):
+            for op in ("erode", "dilate"):
+                mx = "direct" if wx <= XMAX else None
+                plan = morph.resolve_plan("u8" if dtype == np.uint8 else "u16", 203, 517, wx, wy,
+                                          method_x=mx, method_y="direct")
+                assert plan["kernel"] == "wave", (wx, wy, plan)
+                _check(img, op, wx, wy, -1, ay, method_x=mx, method_y="direct")
+    for wx in range(DMAX + 1, XMAX + 1):
+        for ax in sorted({-1, 0, wx - 1}):
+            _check(img, "erode", wx, 3, ax, -1, method_x="direct")
+            _check(img, "dilate", wx, 31, ax, -1, method_x="direct")  # streaming kernel
+    # unaligned rows (odd pitch, odd offset)
+    d, _ = to_dev(img, pitch_elems=517 + 1, offset_elems=1)
+    for wx, wy in ((13, 17), (16, 31), (1, 11)):
+        out = morph.apply("erode", d, wx, wy, method_x="direct", method_y="direct")
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out), _ref(img, "erode", wx, wy)), (wx, wy)
+    # the tile kernel's direct tap loops, for windows past the compiled ones
+    for wx, wy in ((10, 1), (1, 10), (23, 22), (40, 3), (3, 57), (70, 70)):
+        for tile in ((64, 32), (128, 64)):
+            _check(img, "dilate", wx, wy, -1, -1, method_x="direct", method_y="direct",
+                   tile=tile)
+
+
+def test_thresholds_route_windows_to_the_direct_passes():
+    """With the thresholds raised, the automatic plan sends windows up to 16 (x) and
+    31 (y) to the wave kernel's direct passes; results are unchanged."""
+    img = synth.document(300, 700, seed=32, n_rect=80)
+    t0 = morph.get_thresholds("u8")
+    try:
+        morph.set_thresholds("u8", 16, 31)
+        for wx, wy in ((16, 31), (11, 15), (3, 19), (15, 1), (9, 27)):
+            plan = morph.resolve_plan("u8", 300, 700, wx, wy)
+            assert plan["kernel"] == "wave" and plan["method_y"] in ("direct", None), plan
+            for op in ("erode", "dilate"):
+                _check(img, op, wx, wy)
+        # beyond the compiled windows the automatic plan takes the large-window passes
+        morph.set_thresholds("u8", 40, 40)
+        for wx, wy in ((17, 3), (3, 32), (31, 33)):
+            assert morph.resolve_plan("u8", 300, 700, wx, wy)["kernel"] in ("stream", "wave")
+            _check(img, "erode", wx, wy)
+    finally:
+        morph.set_thresholds("u8", *t0)
