@@ -4,28 +4,32 @@
 
 namespace morph {
 
-template <typename T, bool MAXOP, bool AL, bool RUNS>
+// XV: the horizontal pass is the cross-lane vHGW (a plan that asks for vHGW along x).
+template <typename T, bool MAXOP, bool AL, bool RUNS, bool XV>
 __global__ __launch_bounds__(64) void stream_kernel(TileJob J)
 {
     extern __shared__ uint32_t lds[];
-    stream_body<T, MAXOP, AL, RUNS>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+    stream_body<T, MAXOP, AL, RUNS, XV>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
-template <bool RUNS>
+template <bool RUNS, bool XV>
 static TileKernelFn pick_stream_kernel_v(const TileJob &j)
 {
     const bool al = rows_aligned(j);
     if (j.dtype == 0) {
-        if (j.op) return al ? stream_kernel<uint8_t, true, true, RUNS> : stream_kernel<uint8_t, true, false, RUNS>;
-        return al ? stream_kernel<uint8_t, false, true, RUNS> : stream_kernel<uint8_t, false, false, RUNS>;
+        if (j.op) return al ? stream_kernel<uint8_t, true, true, RUNS, XV> : stream_kernel<uint8_t, true, false, RUNS, XV>;
+        return al ? stream_kernel<uint8_t, false, true, RUNS, XV> : stream_kernel<uint8_t, false, false, RUNS, XV>;
     }
-    if (j.op) return al ? stream_kernel<uint16_t, true, true, RUNS> : stream_kernel<uint16_t, true, false, RUNS>;
-    return al ? stream_kernel<uint16_t, false, true, RUNS> : stream_kernel<uint16_t, false, false, RUNS>;
+    if (j.op) return al ? stream_kernel<uint16_t, true, true, RUNS, XV> : stream_kernel<uint16_t, true, false, RUNS, XV>;
+    return al ? stream_kernel<uint16_t, false, true, RUNS, XV> : stream_kernel<uint16_t, false, false, RUNS, XV>;
 }
 
 static TileKernelFn pick_stream_kernel(const TileJob &j)
 {
-    return stream_two_level(j.wy) ? pick_stream_kernel_v<true>(j) : pick_stream_kernel_v<false>(j);
+    const bool xv = j.hm == PASS_VHGW;
+    if (stream_two_level(j.wy))
+        return xv ? pick_stream_kernel_v<true, true>(j) : pick_stream_kernel_v<true, false>(j);
+    return xv ? pick_stream_kernel_v<false, true>(j) : pick_stream_kernel_v<false, false>(j);
 }
 
 // The batch form of the stream kernel: one single-wave workgroup per unit.

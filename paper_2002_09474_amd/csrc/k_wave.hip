@@ -4,25 +4,32 @@
 
 namespace morph {
 
-template <typename T, bool MAXOP, bool AL>
+// XV: the horizontal pass is the cross-lane vHGW (a plan that asks for vHGW along x).
+template <typename T, bool MAXOP, bool AL, bool XV>
 __global__ __launch_bounds__(NT) void wave_kernel(TileJob J)
 {
     const int units = J.tiles_x * J.tiles_y;
     const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
                                                  (int)(threadIdx.x >> 6));
     if (u >= units) return; // the whole wave leaves
-    wave_body<T, MAXOP, AL>(J, u);
+    wave_body<T, MAXOP, AL, false, XV>(J, u);
+}
+
+template <bool XV>
+static TileKernelFn pick_wave_kernel_x(const TileJob &j)
+{
+    const bool al = rows_aligned(j);
+    if (j.dtype == 0) {
+        if (j.op) return al ? wave_kernel<uint8_t, true, true, XV> : wave_kernel<uint8_t, true, false, XV>;
+        return al ? wave_kernel<uint8_t, false, true, XV> : wave_kernel<uint8_t, false, false, XV>;
+    }
+    if (j.op) return al ? wave_kernel<uint16_t, true, true, XV> : wave_kernel<uint16_t, true, false, XV>;
+    return al ? wave_kernel<uint16_t, false, true, XV> : wave_kernel<uint16_t, false, false, XV>;
 }
 
 static TileKernelFn pick_wave_kernel(const TileJob &j)
 {
-    const bool al = rows_aligned(j);
-    if (j.dtype == 0) {
-        if (j.op) return al ? wave_kernel<uint8_t, true, true> : wave_kernel<uint8_t, true, false>;
-        return al ? wave_kernel<uint8_t, false, true> : wave_kernel<uint8_t, false, false>;
-    }
-    if (j.op) return al ? wave_kernel<uint16_t, true, true> : wave_kernel<uint16_t, true, false>;
-    return al ? wave_kernel<uint16_t, false, true> : wave_kernel<uint16_t, false, false>;
+    return j.hm == PASS_VHGW ? pick_wave_kernel_x<true>(j) : pick_wave_kernel_x<false>(j);
 }
 
 template <typename T>

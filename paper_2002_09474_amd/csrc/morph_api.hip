@@ -356,14 +356,20 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
 
     // vertical pass direct and no tile asked for: the register-only wave kernel, with
     // the horizontal pass direct or (wider windows, automatic or asked for) doubling
+    // A horizontal vHGW asked for (single images, no tile, wx <= kStreamMaxWx) runs
+    // across the lanes of the wave or streaming kernel (their XV forms); automatic
+    // large horizontal windows take doubling.
     j.kind = KIND_TILE;
+    const bool lane_vhgw = j.hm == PASS_VHGW && mx == MORPH_METHOD_VHGW && !user_tile && !batch &&
+                           j.wx <= kStreamMaxWx;
     const bool h_wave = (j.hm == PASS_DIRECT && j.wx <= kDirectMaxX) || j.hm == PASS_NONE ||
                         j.hm == PASS_DOUBLING ||
-                        (j.hm == PASS_VHGW && mx == MORPH_METHOD_AUTO && j.wx <= kStreamMaxWx);
+                        (j.hm == PASS_VHGW && mx == MORPH_METHOD_AUTO && j.wx <= kStreamMaxWx) ||
+                        (lane_vhgw && j.wy <= kDirectMax);
     if (j.vm == PASS_DIRECT && j.wy <= kDirectMaxTall && h_wave && !user_tile &&
         (my != MORPH_METHOD_VHGW)) {
         j.kind = KIND_WAVE;
-        if (j.hm == PASS_VHGW) j.hm = PASS_DOUBLING;
+        if (j.hm == PASS_VHGW && !lane_vhgw) j.hm = PASS_DOUBLING;
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
         // (a strip stores at most the quads whose input lies in its 64 quads,
         // stream_quads(wx) of them, whatever the horizontal pass)
@@ -378,10 +384,12 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     }
     // doubling asked for, or everything automatic and the windows fit: the streaming
     // kernel (its vertical pass is vHGW through the LDS ring whatever wy is)
-    if (j.hm == PASS_DOUBLING || (auto_both && !user_tile && stream_fits)) {
+    if (j.hm == PASS_DOUBLING || (auto_both && !user_tile && stream_fits) ||
+        (lane_vhgw && my != MORPH_METHOD_DIRECT && j.wy <= kStreamMaxWy)) {
         j.kind = KIND_STREAM;
         // (its direct horizontal pass takes windows up to kDirectMax)
-        if (j.hm == PASS_VHGW || (j.hm == PASS_DIRECT && j.wx > kDirectMax)) j.hm = PASS_DOUBLING;
+        if ((j.hm == PASS_VHGW && !lane_vhgw) || (j.hm == PASS_DIRECT && j.wx > kDirectMax))
+            j.hm = PASS_DOUBLING;
         j.vm = PASS_VHGW;
         j.vcode = 0;
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
@@ -508,7 +516,7 @@ static int run_gradient(int dtype, const void *src, void *dst, int H, int W, siz
     int rc = plan_job(MORPH_OP_ERODE, dtype, src, dst, H, W, pitch, pitch, wx, wy, ax, ay, plan, j);
     if (rc != MORPH_OK) return rc;
     hipError_t e;
-    if (j.kind == KIND_WAVE && !wave_tall(j) && job_rows_aligned(j)) {
+    if (j.kind == KIND_WAVE && !wave_tall(j) && j.hm != PASS_VHGW && job_rows_aligned(j)) {
         if ((e = launch_gradient_job(j, stream)) != hipSuccess) return hip_fail(e);
         return MORPH_OK;
     }

@@ -975,6 +975,160 @@ __device__ __forceinline__ void doubling_rows(const Doubling &S, uint32_t *e0, u
 #undef MORPH_FIN1
 }
 
+// ======================= horizontal vHGW across the lanes ==========================
+// The paper's van Herk/Gil-Werman pass (§5.1.1, along x as in §5.2.1) on a row held
+// across the wave's lanes (lane L holds strip positions p = 4L .. 4L + 3 as two pair
+// dwords).  Blocks of w positions start at p = 0.  g[p] is the extremum from p's
+// block start to p, h[p] from p to its block end, both by segmented Hillis-Steele
+// scans: K = ceil(log2 w) steps of shifts s = 1, 2, 4, ... (one or two pixels within
+// the lane and the neighbouring lane by DPP, whole lanes by DPP or ds_bpermute), the
+// shifted value taking part only where it lies in the same block (per-lane masks that
+// substitute the identity).  Then m_w[k] = op(h[k], g[k + w - 1]) at k = co .. co + 3
+// past the lane's first position, the output quad's window starts.
+constexpr int kVhgwLaneSteps = 7; // w <= 128 = kStreamMaxWx
+
+// Lane i gets x of lane i - 1 (DPP wave_shr:1; lane 0 gets 0).
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+}
+
+template <bool MAXOP> struct LaneVhgw {
+    int K;                                   // steps: 2^K >= w
+    uint32_t gm[kVhgwLaneSteps][2];          // per step and pair dword: identity where the
+    uint32_t hm[kVhgwLaneSteps][2];          // shifted value lies in another block
+    int c0, c1;                              // offsets co and co + w - 1 within their quads
+    uint32_t ad0, ad1;                       // ds_bpermute addresses of lanes + q1, + q1 + 1
+
+    __device__ __forceinline__ LaneVhgw(int w, int co)
+    {
+        const int lane = threadIdx.x & 63;
+        K = 0;
+        while ((1 << K) < w) K++;
+        int r[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) r[j] = (4 * lane + j) % w; // position in its block
+#pragma unroll
+        for (int k = 0; k < kVhgwLaneSteps; k++) {
+            const int st = 1 << k;
+#pragma unroll
+            for (int d = 0; d < 2; d++) {
+                // 16-bit half of pixel 2d (low) and 2d + 1 (high): all ones where the
+                // shifted value is outside the block, for an erosion's OR; the opposite
+                // for a dilation's AND
+                const uint32_t gi = (r[2 * d] < st ? 0xffffu : 0u) |
+                                    (r[2 * d + 1] < st ? 0xffff0000u : 0u);
+                const uint32_t hi = (r[2 * d] + st > w - 1 ? 0xffffu : 0u) |
+                                    (r[2 * d + 1] + st > w - 1 ? 0xffff0000u : 0u);
+                gm[k][d] = MAXOP ? ~gi : gi;
+                hm[k][d] = MAXOP ? ~hi : hi;
+            }
+        }
+        const int d1 = co + w - 1;
+        c0 = co;
+        c1 = d1 & 3;
+        ad0 = (uint32_t)(lane + (d1 >> 2)) << 2;
+        ad1 = (uint32_t)(lane + (d1 >> 2) + 1) << 2;
+    }
+    // the shifted value where it is in the block, else the identity
+    static __device__ __forceinline__ uint32_t keep(uint32_t y, uint32_t m)
+    {
+        return MAXOP ? (y & m) : (y | m);
+    }
+};
+
+// One scan step of shift 1 << k for G rows: g from lower positions, h from higher.
+template <int k, int G, bool MAXOP>
+__device__ __forceinline__ void lane_vhgw_step(const LaneVhgw<MAXOP> &V, uint32_t *g0, uint32_t *g1,
+                                               uint32_t *h0, uint32_t *h1)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int q = (1 << k) / 4; // whole lanes (k >= 2)
+#pragma unroll
+    for (int r = 0; r < G; r++) {
+        uint32_t a0, a1, b0, b1; // g[p - s], h[p + s] as pair dwords
+        if constexpr (k == 0) {
+            const uint32_t pv = from_prev_lane(g1[r]);
+            a0 = __builtin_amdgcn_alignbit(g0[r], pv, 16);
+            a1 = __builtin_amdgcn_alignbit(g1[r], g0[r], 16);
+            const uint32_t nx = from_next_lane(h0[r]);
+            b0 = __builtin_amdgcn_alignbit(h1[r], h0[r], 16);
+            b1 = __builtin_amdgcn_alignbit(nx, h1[r], 16);
+        } else if constexpr (k == 1) {
+            a0 = from_prev_lane(g1[r]);
+            a1 = g0[r];
+            b0 = h1[r];
+            b1 = from_next_lane(h0[r]);
+        } else if constexpr (q == 1) {
+            a0 = from_prev_lane(g0[r]);
+            a1 = from_prev_lane(g1[r]);
+            b0 = from_next_lane(h0[r]);
+            b1 = from_next_lane(h1[r]);
+        } else {
+            const uint32_t adp = (uint32_t)((lane - q) & 63) << 2, adn = (uint32_t)((lane + q) & 63) << 2;
+            a0 = lane_fetch(g0[r], adp);
+            a1 = lane_fetch(g1[r], adp);
+            b0 = lane_fetch(h0[r], adn);
+            b1 = lane_fetch(h1[r], adn);
+        }
+        g0[r] = pk<MAXOP>(g0[r], LaneVhgw<MAXOP>::keep(a0, V.gm[k][0]));
+        g1[r] = pk<MAXOP>(g1[r], LaneVhgw<MAXOP>::keep(a1, V.gm[k][1]));
+        h0[r] = pk<MAXOP>(h0[r], LaneVhgw<MAXOP>::keep(b0, V.hm[k][0]));
+        h1[r] = pk<MAXOP>(h1[r], LaneVhgw<MAXOP>::keep(b1, V.hm[k][1]));
+    }
+}
+
+// m_w[k] = op(h[k], g[k + w - 1]) at k = co .. co + 3: h's pairs from the lane and the
+// next one, g's from lanes + q1 and + q1 + 1.
+template <int C0, int C1, int G, bool MAXOP>
+__device__ __forceinline__ void lane_vhgw_final(const LaneVhgw<MAXOP> &V, uint32_t *h0,
+                                                uint32_t *h1, const uint32_t *g0,
+                                                const uint32_t *g1)
+{
+#pragma unroll
+    for (int r = 0; r < G; r++) {
+        const uint32_t n0 = from_next_lane(h0[r]), n1 = (C0 >> 1) ? from_next_lane(h1[r]) : 0u;
+        uint32_t p0, p2, r0, r2;
+        pairs_at<C0>(h0[r], h1[r], n0, n1, p0, p2);
+        const uint32_t f0 = (C1 >> 1) ? 0u : lane_fetch(g0[r], V.ad0), f1 = lane_fetch(g1[r], V.ad0);
+        const uint32_t f2 = lane_fetch(g0[r], V.ad1), f3 = (C1 >> 1) ? lane_fetch(g1[r], V.ad1) : 0u;
+        pairs_at<C1>(f0, f1, f2, f3, r0, r2);
+        h0[r] = pk<MAXOP>(p0, r0);
+        h1[r] = pk<MAXOP>(p2, r2);
+    }
+}
+
+// The horizontal vHGW pass on G rows: e0, e1 hold the rows on entry and the outputs
+// on return.  The rows go through each step together so their lane moves interleave.
+template <int G, bool MAXOP>
+__device__ __forceinline__ void lane_vhgw_rows(const LaneVhgw<MAXOP> &V, uint32_t *e0, uint32_t *e1)
+{
+    uint32_t g0[G], g1[G];
+#pragma unroll
+    for (int r = 0; r < G; r++) {
+        g0[r] = e0[r];
+        g1[r] = e1[r];
+    }
+    // (e0, e1 become h)
+    if (V.K > 0) lane_vhgw_step<0, G, MAXOP>(V, g0, g1, e0, e1);
+    if (V.K > 1) lane_vhgw_step<1, G, MAXOP>(V, g0, g1, e0, e1);
+    if (V.K > 2) lane_vhgw_step<2, G, MAXOP>(V, g0, g1, e0, e1);
+    if (V.K > 3) lane_vhgw_step<3, G, MAXOP>(V, g0, g1, e0, e1);
+    if (V.K > 4) lane_vhgw_step<4, G, MAXOP>(V, g0, g1, e0, e1);
+    if (V.K > 5) lane_vhgw_step<5, G, MAXOP>(V, g0, g1, e0, e1);
+    if (V.K > 6) lane_vhgw_step<6, G, MAXOP>(V, g0, g1, e0, e1);
+    static_assert(kVhgwLaneSteps == 7, "steps unrolled");
+#define MORPH_VF1(A, B)                                                                      \
+    case A * 4 + B: lane_vhgw_final<A, B, G, MAXOP>(V, e0, e1, g0, g1); break;
+#define MORPH_VF(A) MORPH_VF1(A, 0) MORPH_VF1(A, 1) MORPH_VF1(A, 2) MORPH_VF1(A, 3)
+    switch (V.c0 * 4 + V.c1) {
+        MORPH_VF(0) MORPH_VF(1) MORPH_VF(2) MORPH_VF(3)
+    default: break;
+    }
+#undef MORPH_VF
+#undef MORPH_VF1
+}
+
 // ======================= direct vertical pass: one wave per strip ==================
 // When the vertical window is at most kDirectMax, a wave works alone on a strip of
 // 64 column quads and J.TB output rows, KR rows at a time: the vertical pass in
@@ -1309,7 +1463,9 @@ static_assert(kDirectMaxTall == 31, "tall vertical windows compiled");
 
 // TALL: the vertical window is kDirectMax + 1 .. kDirectMaxTall (a longer register ring,
 // so fewer waves fit a SIMD; a kernel of its own); else 1 .. kDirectMax.
-template <typename T, bool MAXOP, bool AL, bool TALL = false>
+// XV: the horizontal pass is the cross-lane vHGW (wx <= kStreamMaxWx; a kernel of its
+// own, for single images whose plan asks for it).
+template <typename T, bool MAXOP, bool AL, bool TALL = false, bool XV = false>
 __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 {
     constexpr int RING = ring_rows<TALL>();
@@ -1351,6 +1507,7 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
                             4 * (wq * sx + wq) <= J.W;
     const bool doubling = J.hm == PASS_DOUBLING;
     const Doubling S(J.wx, co);
+    const LaneVhgw<MAXOP> V(XV ? J.wx : 1, co);
     int y = y0;
     // rows y .. y + KR - 1 from the loads in cur, the next chunk's issued into nxt
     // (two buffers taking turns, so no load in flight is ever copied)
@@ -1380,7 +1537,8 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
             }
         }
         // every lane takes part in the shifts
-        if (doubling) doubling_rows<KR, MAXOP>(S, v01, v23);
+        if constexpr (XV) lane_vhgw_rows<KR, MAXOP>(V, v01, v23);
+        else if (doubling) doubling_rows<KR, MAXOP>(S, v01, v23);
         else wv_horizontal_any<MAXOP>(J.wx, co, v01, v23);
         if (lane < wq) {
             uint8_t *drow = J.dst + (int64_t)y * J.dpitch;
@@ -1958,7 +2116,7 @@ template <> struct RunTable<uint16_t> {
 // keeps 2 stream_runs(wy) + 1 small LDS entries instead of a ring of wy rows, at the
 // price of a second (cached) load of every row: a win where the ring's LDS would
 // limit the waves resident per CU.
-template <typename T, bool MAXOP, bool AL, bool RUNS>
+template <typename T, bool MAXOP, bool AL, bool RUNS, bool XV = false>
 __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t *lds)
 {
     const int lane = threadIdx.x & 63;
@@ -1981,6 +2139,7 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
         else return WaveLoaderAny<T>(J, MAXOP ? 0u : (Px<T>::maxv | (Px<T>::maxv << 16)), gx);
     }();
     const Doubling S(J.wx, co);
+    const LaneVhgw<MAXOP> V(XV ? J.wx : 1, co); // XV: the horizontal pass is vHGW
     const bool hdirect = J.hm != PASS_DOUBLING; // direct (wx <= kDirectMax) or none
     const int nruns = stream_runs(wy);
     const RunTable<T> tot(lds);                  // runs: T, entries 0 .. nruns - 1
@@ -2112,7 +2271,8 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
 #pragma unroll
                     for (int k = 0; k < SD; k++) L.fix(o01[k], o23[k]);
                 }
-            if (hdirect) direct_rows_any<SD, MAXOP>(J.wx, co, o01, o23);
+            if constexpr (XV) lane_vhgw_rows<SD, MAXOP>(V, o01, o23);
+            else if (hdirect) direct_rows_any<SD, MAXOP>(J.wx, co, o01, o23);
             else doubling_rows<SD, MAXOP>(S, o01, o23);
             if (store_lane) {
                 const int y = y0 + t - wy;

@@ -6,6 +6,8 @@ swept, on an 800x600 uint8 page (the paper's image size).  Two comparisons:
   pass (compiled per window up to 9, a loop over the taps beyond) and the vHGW
   pass for every w, so both curves cover the whole range and cross where the
   direct pass's O(w) work overtakes vHGW's constant work;
+- along x, the paper's vHGW run across the wave kernel's lanes beside the
+  doubling pass the library takes for large horizontal windows;
 - the production choice: the library's direct pass (the register-only wave
   kernel: vertical windows up to 31, horizontal up to 16) against its
   large-window pass (vertically vHGW on the streaming kernel, horizontally
@@ -77,7 +79,12 @@ def sweep(H=600, W=800, windows=WINDOWS, dname="u8"):
                 variants = [("auto", {}),
                             ("tile_direct", {"method_x": "direct", "method_y": "direct",
                                              "tile": (tw, 64)}),
-                            ("tile_vhgw", {"method_x": "vhgw", "method_y": "vhgw"})]
+                            ("tile_vhgw", {"method_x": "vhgw", "method_y": "vhgw",
+                                           "tile": (tw, 64)})]
+                if axis == "x" and w <= 128:
+                    # vHGW across the wave kernel's lanes, beside its doubling
+                    variants.append(("lanes_vhgw", {"method_x": "vhgw"}))
+                    variants.append(("lanes_doubling", {"method_x": "doubling"}))
                 for name, kw in variants:
                     fns = [(lambda i=i: morph.apply("erode", srcs[i], wx, wy, out=dsts[i], **kw))
                            for i in range(nbuf) for _ in range(20 // nbuf + 1)][:20]
@@ -119,7 +126,9 @@ def main(argv=None):
     res = sweep(H=H, W=W, dname=a.dtype)
     res["crossovers"] = {
         axis: {"tile_direct_to_vhgw": crossover(res["rows"], axis, "tile_direct", "tile_vhgw"),
-               "direct_to_large": crossover(res["rows"], axis, "direct", "large")}
+               "direct_to_large": crossover(res["rows"], axis, "direct", "large"),
+               "doubling_to_lanes_vhgw": crossover(res["rows"], axis, "lanes_doubling",
+                                                    "lanes_vhgw")}
         for axis in ("x", "y")}
     print(json.dumps(res["crossovers"]), flush=True)
     if a.out:

@@ -228,12 +228,21 @@ def test_plan_resolution_and_thresholds(tmp_path):
             {"wmax": 8, "tq": 16, "tb": 32}, {"wmax": 1000000, "tq": 40, "tb": 16}]}}))
         morph.load_tuning(str(f))
         assert morph.get_thresholds("u8") == (3, 4)
-        # forced vHGW runs the workgroup-tile kernel, whose input row fills tq quads:
+        # forced vHGW without a tile runs across the lanes of the streaming kernel
+        # (horizontal windows up to 128) ...
+        p = morph.resolve_plan("u8", 1000, 1000, 5, 5, method_x="vhgw", method_y="vhgw")
+        assert (p["kernel"], p["method_x"], p["method_y"]) == ("stream", "vhgw", "vhgw")
+        p = morph.resolve_plan("u8", 1000, 1000, 33, 3, method_x="vhgw")
+        assert (p["kernel"], p["method_x"]) == ("wave", "vhgw")  # vertical direct
+        p = morph.resolve_plan("u8", 1000, 1000, 129, 3, method_x="vhgw")
+        assert p["kernel"] == "tile"
+        # ... and with a tile (here only its height given: the width from the rule), or
+        # beyond, on the workgroup-tile kernel, whose input row fills tq quads:
         # tw + wx - 1 + 3 <= 4 tq
         v = dict(method_x="vhgw", method_y="vhgw")
-        p = morph.resolve_plan("u8", 1000, 1000, 5, 5, **v)
-        assert (p["tile_w"], p["tile_h"]) == (64 - 8, 32)
-        p = morph.resolve_plan("u8", 1000, 1000, 30, 30, **v)
+        p = morph.resolve_plan("u8", 1000, 1000, 5, 5, tile=(0, 32), **v)
+        assert (p["kernel"], p["tile_w"], p["tile_h"]) == ("tile", 64 - 8, 32)
+        p = morph.resolve_plan("u8", 1000, 1000, 30, 30, tile=(0, 16), **v)
         assert (p["tile_w"], p["tile_h"]) == (160 - 32, 16)
         # automatic methods beyond the thresholds: the streaming kernel, whose strip
         # stores at most the quads whose input fits in 64, (250 - wx) // 4 + 1 of them,

@@ -444,3 +444,26 @@ def test_thresholds_route_windows_to_the_direct_passes():
             _check(img, "erode", wx, wy)
     finally:
         morph.set_thresholds("u8", *t0)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_horizontal_vhgw_across_lanes(dtype):
+    """The paper's vHGW along x run across the lanes of the wave kernel (vertical
+    window direct) and of the streaming kernel (vertical vHGW), when a plan asks for
+    vHGW without a tile: every horizontal window 1..128 against the oracle, with
+    several anchors, both operations, aligned and unaligned rows and ragged strips."""
+    img = synth.uniform(77, 1031, dtype, seed=51)
+    dn = "u8" if dtype == np.uint8 else "u16"
+    for wx in list(range(1, 40)) + [45, 63, 64, 65, 100, 101, 127, 128]:
+        ax = (-1, 0, wx - 1)[wx % 3]
+        for wy, my in ((1, None), (3, "direct"), (13, "vhgw")):
+            k = morph.resolve_plan(dn, 77, 1031, wx, wy, method_x="vhgw", method_y=my)["kernel"]
+            if wx > 1:  # (a window of 1 has no horizontal pass to run)
+                assert k == ("wave" if my != "vhgw" else "stream"), (wx, wy, k)
+            _check(img, "erode" if wx % 2 else "dilate", wx, wy, ax, -1, method_x="vhgw",
+                   method_y=my)
+    d, _ = to_dev(img, pitch_elems=1031 + 3, offset_elems=1)  # unaligned rows
+    for wx in (5, 31, 128):
+        out = morph.apply("dilate", d, wx, 5, method_x="vhgw", method_y="vhgw")
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out), _ref(img, "dilate", wx, 5)), wx
