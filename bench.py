@@ -264,11 +264,12 @@ def gradient_lines(torch, morph, dev, steps):
 
 def openclose_lines(torch, morph, dev, steps):
     """4096x4096 openings and closings, uint8 and uint16, at 3x3, 9x9 and 15x15: the
-    single-pass kernel without workspace (morph_openclose_fused: both operations on
-    one LDS tile) beside the two launches of the default path (erosion into a
-    workspace, dilation of the workspace, each on the kernel the single operation
-    takes).  GB/s over 2 sizeof(T) bytes a pixel, 10
-    launches over 10 buffer sets in one graph."""
+    one-pass form without workspace (morph_openclose_fused, here the wave kernel's
+    one-pass form: the intermediate rows in a register queue; what morph_open /
+    morph_close run for these windows) beside two launches through a workspace
+    (erosion into it, dilation of it, each on the kernel the single operation
+    takes).  GB/s over 2 sizeof(T) bytes a pixel, 10 launches over 10 buffer sets in
+    one graph."""
     out = []
     stream = torch.cuda.current_stream()
     for dt, es in (("u8", 1), ("u16", 2)):

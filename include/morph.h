@@ -132,9 +132,17 @@ int morph_dilate_u16(const void *src, void *dst, int H, int W, size_t pitch, int
  * Returns 0 for an empty image. */
 size_t morph_workspace_bytes(int H, int W, size_t pitch, int elem_bytes);
 
-/* Opening and closing (§2: compositions of erosion and dilation).  The
- * intermediate image goes to `workspace` (at least morph_workspace_bytes(),
- * else MORPH_ENOMEM), which must not overlap src or dst (MORPH_EALIAS). */
+/* Opening and closing (§2: compositions of erosion and dilation).  Where the one-pass
+ * form applies -- rows aligned (pitch a multiple of 4 bytes for uint8, 8 for uint16),
+ * windows (clipped to the image) up to MORPH_OPENCLOSE_ONE_PASS_MAX_WX by
+ * MORPH_OPENCLOSE_ONE_PASS_MAX_WY -- both operations run in one kernel that keeps the
+ * intermediate rows in registers and workspace may be NULL.  Elsewhere the
+ * intermediate image goes to `workspace` (at least morph_workspace_bytes(), else
+ * MORPH_ENOMEM), which must not overlap src or dst (MORPH_EALIAS), and the two
+ * operations run as two launches.  (A tuning table with "oc_one_pass": 0 takes the
+ * two launches everywhere.) */
+#define MORPH_OPENCLOSE_ONE_PASS_MAX_WX 64
+#define MORPH_OPENCLOSE_ONE_PASS_MAX_WY 15
 int morph_open(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
                int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
                hipStream_t stream);
@@ -151,14 +159,13 @@ int morph_close_u16(const void *src, void *dst, int H, int W, size_t pitch, int 
 /* Opening (opening != 0) or closing in one launch with no workspace (§2: an
  * opening is the dilation of the erosion, a closing the erosion of the dilation,
  * same rectangle and anchor).  dtype MORPH_U8 or MORPH_U16; every other argument
- * as for morph_open.  A workgroup reads its output tile grown by 2(w - 1) per
- * axis into LDS once, runs both operations' direct passes there (intermediate
- * pixels outside the image enter the second operation as its identity) and
- * stores the tile: the intermediate image never reaches HBM.  Windows up to
- * MORPH_OPENCLOSE_FUSED_MAX_W on each axis, else MORPH_EUNSUPPORTED; src and dst
- * must not overlap (MORPH_EALIAS).  For callers that cannot spare the
- * intermediate image's memory: its per-pixel direct passes make it slower than
- * morph_open / morph_close, which remain the fast path. */
+ * as for morph_open.  Where the one-pass form of morph_open applies (see there) it
+ * runs; elsewhere a workgroup reads its output tile grown by 2(w - 1) per axis into
+ * LDS once, runs both operations' direct passes there (intermediate pixels outside
+ * the image enter the second operation as its identity) and stores the tile,
+ * windows up to MORPH_OPENCLOSE_FUSED_MAX_W on each axis, else MORPH_EUNSUPPORTED.
+ * Either way the intermediate image never reaches HBM.  src and dst must not
+ * overlap (MORPH_EALIAS). */
 #define MORPH_OPENCLOSE_FUSED_MAX_W 16
 int morph_openclose_fused(int dtype, int opening, const void *src, void *dst, int H, int W,
                           size_t pitch, int wx, int wy, int anchor_x, int anchor_y, int border,
@@ -182,8 +189,9 @@ int morph_gradient_u16(const void *src, void *dst, int H, int W, size_t pitch, i
 /* Top-hat (src minus its opening) and black-hat (closing minus src), clamped at 0:
  * with the same rectangle and anchor in both passes, an even window or an
  * off-centre anchor can put the opening above src (the closing below it), and
- * there the result is 0.  The opening or closing as above (workspace required,
- * same rules), then one subtraction kernel on dst. */
+ * there the result is 0.  The opening or closing as above (in one pass where that
+ * applies, workspace NULL allowed; else through the workspace, same rules), then
+ * one subtraction kernel on dst. */
 int morph_tophat(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
                  int anchor_x, int anchor_y, int border, void *workspace, size_t ws_bytes,
                  hipStream_t stream);
@@ -327,26 +335,39 @@ int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dty
                            hipStream_t stream);
 
 /* ---- misc ------------------------------------------------------------------ */
-/* Load a tuning table (JSON written by the autotuner) replacing the current one:
- * per-dtype direct/vHGW thresholds (t_x, t_y for single images; batch_t_x,
- * batch_t_y for the images of a batch; direct when w <= t, the compiled direct
- * windows capping it: 16 along x, 31 along y), tile shapes per window bucket (tq = input
- * quads of a tile row, tb = output rows), the output rows of a direct wave unit
- * (a multiple of 8, at most 64; default 24) and of a streaming unit (1 .. 4096;
- * stream_rows for vertical windows up to 16, default 48, stream_rows_runs above,
- * default 32) and of a wide-row unit (wide_rows, 1 .. 4096, default 4; the
- * kernel takes rows in groups of 4 for uint8, 2 for uint16); for the
- * images of a batch, batch_wave_rows (default 32), batch_stream_rows (48) and
- * batch_stream_rows_runs (48) in place of the first three; and fuse (0 or 1,
- * default 1): a batch runs its wave and streaming units of one element type and
- * row alignment as one kernel dispatch; and fit_units (0 or 1, default 1): a
- * single image, or a batch, whose wave and streaming units would number under
- * about 2048 gets shorter ones (in steps of 8 rows, no fewer than 8; a batch only
- * while its tile table holds them), e.g.
- *   {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 64,
- *           "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
- * A dtype missing from the file keeps its table; a key missing keeps its value.
- * NULL restores the built-in defaults.  A malformed file returns MORPH_EINVAL and
+/* Load a tuning table (JSON written by the autotuner) replacing the current one.
+ * Per dtype ("u8", "u16"), every key optional:
+ *   t_x, t_y            direct/large-window thresholds of single images' passes
+ *                       (direct when w <= t; the compiled direct windows cap them:
+ *                       16 along x, 31 along y)
+ *   batch_t_x, batch_t_y  the same for the images of a batch
+ *   tiles               tile kernel shapes per window bucket: [{"wmax", "tq" (input
+ *                       quads of a tile row), "tb" (output rows)}, ...]
+ *   wave_rows           output rows of a direct wave unit (a multiple of 8, <= 64)
+ *   stream_rows, stream_rows_runs  output rows of a streaming unit (1 .. 4096), for
+ *                       vertical windows up to 16 and above
+ *   wide_rows           rows of a wide-row unit (1 .. 4096; taken in groups of 4 for
+ *                       uint8, 2 for uint16)
+ *   batch_wave_rows, batch_stream_rows, batch_stream_rows_runs  the same three for
+ *                       the images of a batch
+ *   fuse                0 / 1: a batch runs its wave and streaming units of one dtype
+ *                       and row alignment as one kernel dispatch
+ *   oc_one_pass         0 / 1: openings and closings take the one-pass form where it
+ *                       applies
+ *   oc_rows, oc_rows_tall  output rows of a one-pass unit (multiples of 8, <= 64), for
+ *                       vertical windows up to 9 and above
+ *   oc_t_x              largest horizontal window the one-pass form takes direct
+ *                       (doubling above; at most 9)
+ *   fit_units           0 / 1: a single image, or a batch, whose wave and streaming
+ *                       units would number under about 2048 gets shorter ones (in
+ *                       steps of 8 rows, no fewer than 8; a batch only while its tile
+ *                       table holds them)
+ * e.g. {"u8": {"t_x": 5, "t_y": 5, "wave_rows": 16, "stream_rows": 64,
+ *              "tiles": [{"wmax": 16, "tq": 32, "tb": 64}, ...]}}
+ * The built-in values are the autotuner's measurement on MI355X (the table shipped
+ * beside the Python package).  A dtype missing from the file keeps its table; a key
+ * missing keeps its value.  NULL restores the built-in table.  A malformed file, or
+ * a unit height, flag or tile shape outside its range, returns MORPH_EINVAL and
  * changes nothing. */
 int morph_load_tuning(const char *json_path);
 /* Current per-pass direct->vHGW thresholds of single images for a dtype (direct

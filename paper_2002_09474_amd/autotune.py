@@ -17,8 +17,9 @@ The thresholds of batched images are then chosen on the whole benchmark batch
 (direct passes that leave the fused dispatch can cost it more than they save).
 Unit heights of batched images are then chosen on the whole 512-image batch of the
 benchmark (one key at a time), those of single images on 4096x4096 images (the
-wave kernel's at 3x3, the streaming kernel's at 15x15 and 31x31), the unit height
-of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same images,
+wave kernel's at 3x3, the streaming kernel's at 15x15 and 31x31, the one-pass
+opening's at 3x3 + 9x9 and at 15x15, and whether the one-pass opening beats the two
+launches at all), the unit height of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same images,
 and tile shapes of the tile kernel per window bucket.  Run
 ``python -m paper_2002_09474_amd.autotune``.
 """
@@ -46,6 +47,9 @@ SINGLE_KEYS = (("wave_rows", WAVE_ROWS, 3), ("stream_rows", STREAM_ROWS, 15),
 # unit heights of batched images, timed on the whole benchmark batch
 BATCH_KEYS = (("batch_wave_rows", (16, 24, 32, 48)), ("batch_stream_rows", (32, 48, 64, 96)),
               ("batch_stream_rows_runs", (32, 48, 64)))
+# unit heights of single images' one-pass openings, each timed on 4096x4096 images
+# over its windows (the short kernel's, vertical windows up to 9, and the tall one's)
+OC_KEYS = (("oc_rows", (8, 16, 24, 32, 48), (3, 9)), ("oc_rows_tall", (16, 32, 48, 64), (15,)))
 WIDE_ROWS = (2, 4, 8, 16)            # wide-row units (uint8, wy = 1, wx > 128)
 WIDE_WINDOWS = (200, 255, 511)
 
@@ -193,6 +197,7 @@ def tile_sweep(torch, morph, srcs, dsts, dname, iters=20, buckets=BUCKETS, tqs=T
                     best = (us, tq, plan["tile_h"])
         if best is not None:
             rules.append({"wmax": wmax, "tq": best[1], "tb": best[2]})
+            _log("%s: tiles up to %d: tq %d, tb %d" % (dname, wmax, best[1], best[2]))
     return rules, table
 
 
@@ -210,6 +215,45 @@ def best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w, ite
             morph.apply("erode", srcs[i], w, w, out=dsts[i])
         res.append({key: c, "us": round(_timer(torch, fn, iters), 3)})
     return min(res, key=lambda r: r["us"])[key], res
+
+
+def oc_rows_sweep(torch, morph, dname, srcs, dsts, key, choices, base, windows, iters=20):
+    """The `key` (a unit height of the one-pass opening) among `choices` whose sum of
+    w x w opening times over `windows` is least, the rest of the table being `base`."""
+    res = []
+    for c in choices:
+        _with_table(morph, {dname: dict(base, **{key: c})})
+        us = 0.0
+        for w in windows:
+            k = [0]
+
+            def fn():
+                i = k[0] % len(srcs)
+                k[0] += 1
+                morph.openclose_fused("open", srcs[i], w, w, out=dsts[i])
+            us += _timer(torch, fn, iters)
+        res.append({key: c, "us": round(us, 3)})
+    return min(res, key=lambda r: r["us"])[key], res
+
+
+def oc_one_pass_check(torch, morph, dname, srcs, dsts, base, windows=(3, 9, 15), iters=20):
+    """1 if the one-pass openings beat the two launches through a workspace (the sum
+    over `windows` of w x w openings), else 0; and the timings."""
+    ws = [torch.empty_like(d) for d in dsts]
+    res = []
+    for one in (1, 0):
+        _with_table(morph, {dname: dict(base, oc_one_pass=one)})
+        us = 0.0
+        for w in windows:
+            k = [0]
+
+            def fn():
+                i = k[0] % len(srcs)
+                k[0] += 1
+                morph.apply("open", srcs[i], w, w, out=dsts[i], workspace=ws[i])
+            us += _timer(torch, fn, iters)
+        res.append({"oc_one_pass": one, "us": round(us, 3)})
+    return int(res[0]["us"] <= res[1]["us"]), res
 
 
 def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20, choices=WIDE_ROWS):
@@ -258,6 +302,7 @@ REDUCED = {"windows": {"x": (2, 3, 9, 12, 16), "y": (2, 3, 9, 15, 31)},
            "batch": (48, 300), "big": 1024,
            "batch_keys": tuple((k, c[:2]) for k, c in BATCH_KEYS),
            "single_keys": tuple((k, c[:2], w) for k, c, w in SINGLE_KEYS),
+           "oc_keys": tuple((k, c[:2], w) for k, c, w in OC_KEYS),
            "wide_rows": WIDE_ROWS[:2], "buckets": BUCKETS[:1], "tq": TQ[:2], "tb": TB[:2]}
 
 
@@ -280,6 +325,10 @@ def tune(out_path=DEFAULT_OUT, quick=False, reduced=False):
         torch.cuda.set_stream(prev)
 
 
+def _log(msg):
+    print("[autotune] " + msg, file=sys.stderr, flush=True)
+
+
 def _tune(torch, morph, synth, dev, out_path, quick, reduced):
     result = {"device": torch.cuda.get_device_name(0), "version": morph.version(),
               "grid": "reduced" if reduced else ("quick" if quick else "full")}
@@ -293,6 +342,7 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
         rows = pass_sweep(torch, morph, dname, srcs, dsts, iters=10 if R else (20 if quick else 40),
                           windows=R["windows"] if R else None)
         tx, ty = threshold(rows, "x"), threshold(rows, "y")
+        _log("%s: pass sweep done, thresholds x %d, y %d" % (dname, tx, ty))
         del srcs, dsts
         base = {"t_x": tx, "t_y": ty}
         items = (_batch_items(torch, morph, dev, dname, *R["batch"]) if R
@@ -300,10 +350,12 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
         it = 3 if R else (5 if quick else 10)
         btx, bty, bt_table = batch_thresholds(torch, morph, dname, items, base, tx, ty, it)
         base.update(batch_t_x=btx, batch_t_y=bty)
+        _log("%s: batch thresholds x %d, y %d" % (dname, btx, bty))
         result[dname + "_batch_threshold_sweep"] = bt_table
         for key, choices in (R["batch_keys"] if R else BATCH_KEYS):
             best, table = best_rows(torch, morph, dname, items, key, choices, base, it)
             base[key] = best
+            _log("%s: %s %d" % (dname, key, best))
             result[dname + "_" + key + "_sweep"] = table
         del items
         _with_table(morph, {dname: base})
@@ -317,7 +369,19 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
             best, table = best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w,
                                            3 if R else (8 if quick else 20))
             base[key] = best
+            _log("%s: %s %d" % (dname, key, best))
             result[dname + "_" + key + "_sweep"] = table
+        _with_table(morph, {dname: base})
+        oc_it = 3 if R else (8 if quick else 20)
+        for key, choices, ws in (R["oc_keys"] if R else OC_KEYS):
+            best, table = oc_rows_sweep(torch, morph, dname, srcs, dsts, key, choices, base, ws,
+                                        oc_it)
+            base[key] = best
+            _log("%s: %s %d" % (dname, key, best))
+            result[dname + "_" + key + "_sweep"] = table
+        base["oc_one_pass"], result[dname + "_oc_one_pass_check"] = oc_one_pass_check(
+            torch, morph, dname, srcs, dsts, base, iters=oc_it)
+        _log("%s: oc_one_pass %d" % (dname, base["oc_one_pass"]))
         _with_table(morph, {dname: base})
         if dname == "u8":
             wr2, wr2_table = wide_rows_sweep(torch, morph, srcs, dsts, base,
@@ -336,7 +400,7 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
         result[dname] = dict(base, tiles=rules)
         result[dname + "_pass_sweep"] = rows
         result[dname + "_tile_sweep"] = table
-        print("[autotune] %s: %s" % (dname, result[dname]), file=sys.stderr, flush=True)
+        _log("%s: %s" % (dname, result[dname]))
     with open(out_path, "w") as f:
         json.dump(result, f, indent=1)
     morph.load_tuning(out_path)

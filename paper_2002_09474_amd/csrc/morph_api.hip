@@ -52,6 +52,11 @@ struct DtypeTuning {
     // leaves the fused dispatch (the wave kernel's tall form) can cost more than it
     // saves on its own images
     int batch_t_x, batch_t_y;
+    // single images' openings and closings in one pass where it applies (0 / 1), the
+    // output rows of its units (multiples of kWaveRows; vertical windows up to kDirectMax,
+    // then the tall ones), and the largest horizontal window its passes take direct
+    // (doubling above)
+    int oc_one_pass, oc_rows, oc_t_x, oc_rows_tall;
 };
 
 std::mutex g_tuning_mu;
@@ -59,10 +64,10 @@ std::mutex g_tuning_mu;
 // the Python package): direct passes up to 9 along x (16 for uint16) and 31 along y on
 // single images, 9 and 9 for the images of a batch; unit heights and tile shapes.
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 96, 48, 4,
-     1, 24, 96, 64, 1, 9, 9},
-    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 32, 32}}, 8, 96, 64, 4,
-     1, 16, 64, 64, 1, 9, 9},
+    {9, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 32, 32}}, 16, 96, 48, 4,
+     1, 32, 64, 64, 1, 9, 9, 1, 24, 9, 64},
+    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 64, 64, 4,
+     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 64},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -162,13 +167,34 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.batch_t_x = (int)it->second.num;
     it = o.obj.find("batch_t_y");
     if (it != o.obj.end() && it->second.k == JVal::NUM) t.batch_t_y = (int)it->second.num;
-    for (const char *key : {"wave_rows", "batch_wave_rows"}) {
-        it = o.obj.find(key);
+    const struct {
+        const char *key;
+        int DtypeTuning::*field;
+    } chunk_keys[] = {{"wave_rows", &DtypeTuning::wave_rows},
+                      {"batch_wave_rows", &DtypeTuning::batch_wave_rows},
+                      {"oc_rows", &DtypeTuning::oc_rows},
+                      {"oc_rows_tall", &DtypeTuning::oc_rows_tall}};
+    for (const auto &ck : chunk_keys) { // (whole chunks of kWaveRows rows)
+        it = o.obj.find(ck.key);
         if (it == o.obj.end()) continue;
         if (it->second.k != JVal::NUM) return false;
         const int r = (int)it->second.num;
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
-        (key[0] == 'b' ? t.batch_wave_rows : t.wave_rows) = r;
+        t.*ck.field = r;
+    }
+    it = o.obj.find("oc_t_x");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r < 1) return false;
+        t.oc_t_x = std::min(r, kDirectMax);
+    }
+    it = o.obj.find("oc_one_pass");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r != 0 && r != 1) return false;
+        t.oc_one_pass = r;
     }
     it = o.obj.find("fit_units");
     if (it != o.obj.end()) {
@@ -485,6 +511,39 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     return MORPH_OK;
 }
 
+// The one-pass opening (opening) or closing of one image on the wave kernel's form,
+// where it applies: rows aligned, effective windows up to kOcWaveMaxWx x kOcWaveMaxWy.
+bool plan_openclose_wave(bool opening, int dtype, const void *src, void *dst, int H, int W,
+                         size_t pitch, int wx, int wy, int ax, int ay, TileJob &j)
+{
+    if (ax < 0) ax = default_anchor(wx);
+    if (ay < 0) ay = default_anchor(wy);
+    const int axe = std::min(ax, W - 1), rxe = std::min(wx - 1 - ax, W - 1);
+    const int aye = std::min(ay, H - 1), rye = std::min(wy - 1 - ay, H - 1);
+    j = TileJob{};
+    j.src = (const uint8_t *)src;
+    j.dst = (uint8_t *)dst;
+    j.H = H;
+    j.W = W;
+    j.pitch = j.dpitch = (int64_t)pitch;
+    j.wx = axe + rxe + 1;
+    j.wy = aye + rye + 1;
+    j.ax = axe;
+    j.ay = aye;
+    j.op = opening ? 1 : 0;
+    j.dtype = dtype;
+    if (j.wx > kOcWaveMaxWx || j.wy > kOcWaveMaxWy || !rows_aligned(j)) return false;
+    const DtypeTuning tu = tuning_for(dtype);
+    j.hm = j.wx <= tu.oc_t_x ? PASS_DIRECT : PASS_DOUBLING;
+    j.TW = 4 * strip_quads(W, oc_quads(j.wx));
+    j.TB = std::min(j.wy > kDirectMax ? tu.oc_rows_tall : tu.oc_rows,
+                    (H + kWaveRows - 1) / kWaveRows * kWaveRows);
+    j.tiles_x = (W + j.TW - 1) / j.TW;
+    if (tu.fit_units) j.TB = fit_rows(j.TB, H, j.tiles_x);
+    j.tiles_y = (H + j.TB - 1) / j.TB;
+    return (int64_t)j.tiles_x * j.tiles_y <= INT32_MAX - 4;
+}
+
 int run_single(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch, int wx,
                int wy, int ax, int ay, const morph_plan *plan, hipStream_t stream)
 {
@@ -550,13 +609,26 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
     if (op == MORPH_OP_GRADIENT)
         return run_gradient(dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
                             workspace, ws_bytes, stream);
-    // opening = dilate(erode(src)), closing = erode(dilate(src)) (§2)
+    // opening = dilate(erode(src)), closing = erode(dilate(src)) (§2): in one pass
+    // where the wave kernel's form takes it (no plan asked for), else two launches
+    // through the workspace
+    const bool opens = op == MORPH_OP_OPEN || op == MORPH_OP_TOPHAT;
+    // (top-hat: src - opening; black-hat: closing - src, one subtraction after)
+    if (!plan && tuning_for(dtype).oc_one_pass) {
+        TileJob oj;
+        if (plan_openclose_wave(opens, dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y,
+                                oj)) {
+            hipError_t e = launch_openclose_wave(oj, stream);
+            if (e == hipSuccess && (op == MORPH_OP_TOPHAT || op == MORPH_OP_BLACKHAT))
+                e = launch_subtract(src, dst, H, W, pitch, dtype, op == MORPH_OP_TOPHAT, stream);
+            return e == hipSuccess ? MORPH_OK : hip_fail(e);
+        }
+    }
     if (!workspace || ws_bytes < morph_workspace_bytes(H, W, pitch, (int)elem_bytes(dtype)))
         return MORPH_ENOMEM;
     if (ranges_overlap(workspace, span, src, span) || ranges_overlap(workspace, span, dst, span))
         return MORPH_EALIAS;
     // (top-hat: src - opening; black-hat: closing - src)
-    const bool opens = op == MORPH_OP_OPEN || op == MORPH_OP_TOPHAT;
     const int first = opens ? MORPH_OP_ERODE : MORPH_OP_DILATE;
     rc = run_single(first, dtype, src, workspace, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
                     stream);
@@ -601,6 +673,9 @@ MORPH_COMPOSED(morph_blackhat_u16, MORPH_OP_BLACKHAT, MORPH_U16)
 #undef MORPH_COMPOSED
 
 static_assert(kOcMaxW == MORPH_OPENCLOSE_FUSED_MAX_W, "fused opening/closing window limit");
+static_assert(kOcWaveMaxWx == MORPH_OPENCLOSE_ONE_PASS_MAX_WX &&
+                  kOcWaveMaxWy == MORPH_OPENCLOSE_ONE_PASS_MAX_WY,
+              "one-pass opening/closing window limits");
 
 int morph_openclose_fused(int dtype, int opening, const void *src, void *dst, int H, int W,
                           size_t pitch, int wx, int wy, int anchor_x, int anchor_y, int border,
@@ -608,9 +683,16 @@ int morph_openclose_fused(int dtype, int opening, const void *src, void *dst, in
 {
     int rc = check_image(dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y, border);
     if (rc != MORPH_OK || H == 0 || W == 0) return rc;
-    if (wx > kOcMaxW || wy > kOcMaxW) return MORPH_EUNSUPPORTED;
     const size_t span = image_span(H, W, pitch, dtype);
     if (ranges_overlap(src, span, dst, span)) return MORPH_EALIAS;
+    // the wave kernel's form where it applies, else the workgroup-tile kernel
+    TileJob oj;
+    if (plan_openclose_wave(opening != 0, dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y,
+                            oj)) {
+        hipError_t e = launch_openclose_wave(oj, stream);
+        return e == hipSuccess ? MORPH_OK : hip_fail(e);
+    }
+    if (wx > kOcMaxW || wy > kOcMaxW) return MORPH_EUNSUPPORTED;
     const int ax = anchor_x < 0 ? default_anchor(wx) : anchor_x;
     const int ay = anchor_y < 0 ? default_anchor(wy) : anchor_y;
     hipError_t e = launch_openclose(src, dst, H, W, pitch, wx, wy, ax, ay, opening != 0, dtype,

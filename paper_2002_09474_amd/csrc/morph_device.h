@@ -436,6 +436,36 @@ __device__ __forceinline__ void pair_window(const uint32_t *x, uint32_t &o0, uin
     }
 }
 
+// Outputs for the 8 window starts 0 .. 7 over x[0 .. W + 6], W >= 8, each the extremum
+// of its W inputs.  The rows 7 .. W - 1 lie in all eight windows and are reduced once;
+// window r adds the rows r .. 6 before them (a suffix, grown downwards from row 6) and
+// the rows W .. W + r - 1 after them (a prefix, grown upwards from row W): W + 18
+// operations for the eight outputs, where pairs of adjacent outputs take 4 W.  The
+// same values as the definition (the extremum is associative and commutative).
+template <int W, bool MAXOP>
+__device__ __forceinline__ void chunk8_window(const uint32_t *x, uint32_t *o)
+{
+    static_assert(W >= 8, "the eight windows share rows 7 .. W - 1");
+    uint32_t c = x[7];
+#pragma unroll
+    for (int j = 8; j < W; j++) c = pk<MAXOP>(c, x[j]);
+    uint32_t b = x[W]; // rows W .. W + r - 1, for r = 1 .. 7
+    o[1] = pk<MAXOP>(c, b);
+#pragma unroll
+    for (int r = 2; r < 8; r++) {
+        b = pk<MAXOP>(b, x[W + r - 1]);
+        o[r] = pk<MAXOP>(c, b);
+    }
+    uint32_t a = x[6]; // rows r .. 6, for r = 6 .. 0
+    o[6] = pk<MAXOP>(o[6], a);
+#pragma unroll
+    for (int r = 5; r >= 1; r--) {
+        a = pk<MAXOP>(a, x[r]);
+        o[r] = pk<MAXOP>(o[r], a);
+    }
+    o[0] = pk<MAXOP>(c, pk<MAXOP>(a, x[0]));
+}
+
 // ---- vertical pass, direct, window W: A rows [0, out_h) ----
 // Work unit: one quad of columns and KV output rows; its KV + W - 1 input rows are
 // loaded at once.
@@ -1153,6 +1183,7 @@ __device__ __forceinline__ void lane_vhgw_rows(const LaneVhgw<MAXOP> &V, uint32_
 // byte selectors of the widening v_perm (uint8) or of one v_perm per output row
 // (uint16).
 constexpr int KR = kWaveRows;
+static_assert(KR == 8, "chunk8_window takes the vertical windows of a chunk");
 // registers of the row ring: the short form (wy <= kDirectMax) and the tall one
 template <bool TALL> constexpr int ring_rows() { return KR + (TALL ? kDirectMaxTall : kDirectMax) - 1; }
 
@@ -1265,10 +1296,15 @@ __device__ __forceinline__ void wv_vertical(const Ld &L, const typename Ld::Raw 
 {
 #pragma unroll
     for (int m = 0; m < KR; m++) L.widen(cur[m], r01[WY - 1 + m], r23[WY - 1 + m]);
+    if constexpr (WY >= KR) {
+        chunk8_window<WY, MAXOP>(r01, o01);
+        chunk8_window<WY, MAXOP>(r23, o23);
+    } else {
 #pragma unroll
-    for (int m = 0; m < KR; m += 2) {
-        pair_window<WY, MAXOP>(r01 + m, o01[m], o01[m + 1]);
-        pair_window<WY, MAXOP>(r23 + m, o23[m], o23[m + 1]);
+        for (int m = 0; m < KR; m += 2) {
+            pair_window<WY, MAXOP>(r01 + m, o01[m], o01[m + 1]);
+            pair_window<WY, MAXOP>(r23 + m, o23[m], o23[m + 1]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < WY - 1; k++) {
@@ -1295,9 +1331,33 @@ __device__ __forceinline__ void wv_vertical_raw(const Ld &L, const typename Ld::
                                                 typename Ld::Raw *ring, uint32_t *o01,
                                                 uint32_t *o23)
 {
-    static_assert(WY >= 3, "the tall form's windows");
 #pragma unroll
     for (int m = 0; m < KR; m++) ring[WY - 1 + m] = cur[m];
+    if constexpr (WY <= 2) { // (no middle rows to share)
+#pragma unroll
+        for (int m = 0; m < KR; m++) {
+            L.widen(ring[m], o01[m], o23[m]);
+            if constexpr (WY == 2) {
+                uint32_t x01, x23;
+                L.widen(ring[m + 1], x01, x23);
+                o01[m] = pk<MAXOP>(o01[m], x01);
+                o23[m] = pk<MAXOP>(o23[m], x23);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WY - 1; k++) ring[k] = ring[k + KR];
+        return;
+    }
+    if constexpr (WY >= KR) { // (every row widened once, then the chunk's shared form)
+        uint32_t x01[WY + KR - 1], x23[WY + KR - 1];
+#pragma unroll
+        for (int r = 0; r < WY + KR - 1; r++) L.widen(ring[r], x01[r], x23[r]);
+        chunk8_window<WY, MAXOP>(x01, o01);
+        chunk8_window<WY, MAXOP>(x23, o23);
+#pragma unroll
+        for (int k = 0; k < WY - 1; k++) ring[k] = ring[k + KR];
+        return;
+    }
     uint32_t c01[KR / 2], c23[KR / 2]; // output pair p: the extremum of rows 2p + 1 .. 2p + WY - 1
 #pragma unroll
     for (int r = 0; r < WY + KR - 1; r++) {
@@ -1586,12 +1646,19 @@ __device__ __forceinline__ void wv_vertical2(const Ld &L, const typename Ld::Raw
 {
 #pragma unroll
     for (int m = 0; m < KR; m++) L.widen(cur[m], r01[WY - 1 + m], r23[WY - 1 + m]);
+    if constexpr (WY >= KR) {
+        chunk8_window<WY, false>(r01, lo01);
+        chunk8_window<WY, false>(r23, lo23);
+        chunk8_window<WY, true>(r01, hi01);
+        chunk8_window<WY, true>(r23, hi23);
+    } else {
 #pragma unroll
-    for (int m = 0; m < KR; m += 2) {
-        pair_window<WY, false>(r01 + m, lo01[m], lo01[m + 1]);
-        pair_window<WY, false>(r23 + m, lo23[m], lo23[m + 1]);
-        pair_window<WY, true>(r01 + m, hi01[m], hi01[m + 1]);
-        pair_window<WY, true>(r23 + m, hi23[m], hi23[m + 1]);
+        for (int m = 0; m < KR; m += 2) {
+            pair_window<WY, false>(r01 + m, lo01[m], lo01[m + 1]);
+            pair_window<WY, false>(r23 + m, lo23[m], lo23[m + 1]);
+            pair_window<WY, true>(r01 + m, hi01[m], hi01[m + 1]);
+            pair_window<WY, true>(r23 + m, hi23[m], hi23[m + 1]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < WY - 1; k++) {

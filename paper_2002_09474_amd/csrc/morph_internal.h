@@ -112,6 +112,16 @@ hipError_t launch_transpose(const void *src, void *dst, int H, int W, size_t spi
                             size_t dpitch, int dtype, hipStream_t stream);
 hipError_t launch_transpose_blocks(const void *src, void *dst, int64_t n, int dtype,
                                    hipStream_t stream);
+// opening / closing in one pass on the wave kernel's form (k_openclose_wave.hip):
+// job.op 1 = opening, 0 = closing; rows aligned; wy <= kOcWaveMaxWy, wx <= kOcWaveMaxWx;
+// a strip stores oc_quads(wx) output quads at most (both operations' inputs within the
+// wave's 64 quads: 4Q + 3 + 2 (wx - 1) + 3 <= 255)
+constexpr int kOcWaveMaxWy = 15; // MORPH_OPENCLOSE_ONE_PASS_MAX_WY
+constexpr int kOcWaveMaxWx = 64; // MORPH_OPENCLOSE_ONE_PASS_MAX_WX
+inline int oc_quads(int wx) { return (251 - 2 * wx) / 4 + 1; }
+hipError_t launch_openclose_wave(const TileJob &job, hipStream_t stream);
+hipError_t launch_openclose_wave_u8(const TileJob &job, hipStream_t stream);
+hipError_t launch_openclose_wave_u16(const TileJob &job, hipStream_t stream);
 // fused opening / closing (morph_openclose.hip): both operations' direct passes on
 // one LDS tile of kOcTileH x kOcTileW output pixels, windows up to kOcMaxW per axis
 constexpr int kOcTileH = 32;

@@ -39,6 +39,12 @@ hipError_t launch_batch_wave_tall(const BatchTables &t, int dtype, bool aligned,
                       : launch_batch_wave_tall_u16(t, aligned, grid, stream);
 }
 
+hipError_t launch_openclose_wave(const TileJob &job, hipStream_t stream)
+{
+    return job.dtype == 0 ? launch_openclose_wave_u8(job, stream)
+                          : launch_openclose_wave_u16(job, stream);
+}
+
 hipError_t launch_fused(const FusedTables &t, int dtype, bool aligned, int lds, hipStream_t stream)
 {
     return dtype == 0 ? launch_fused_u8(t, aligned, lds, stream)

@@ -70,12 +70,17 @@ def test_open_close_workspace_checks():
     assert L.morph_workspace_bytes(8, 8, 8, 1) == 64
     assert L.morph_workspace_bytes(0, 8, 8, 1) == 0
     ws = 0x40000000
-    assert L.morph_open(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, 0, None) == E.MORPH_ENOMEM
-    assert L.morph_close(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, ws, 63, None) == E.MORPH_ENOMEM
-    assert L.morph_open(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, FAKE_SRC + 8, 64,
+    # (rows of unaligned pitch, 9 bytes for uint8 and 18 for uint16: the one-pass form
+    # does not apply, the two launches need the workspace)
+    assert L.morph_open(FAKE_SRC, FAKE_DST, 8, 8, 9, 3, 3, -1, -1, 0, None, 0, None) == E.MORPH_ENOMEM
+    assert L.morph_close(FAKE_SRC, FAKE_DST, 8, 8, 9, 3, 3, -1, -1, 0, ws, 71, None) == E.MORPH_ENOMEM
+    assert L.morph_open(FAKE_SRC, FAKE_DST, 8, 8, 9, 3, 3, -1, -1, 0, FAKE_SRC + 8, 72,
                         None) == E.MORPH_EALIAS
-    assert L.morph_close_u16(FAKE_SRC, FAKE_DST, 8, 8, 16, 3, 3, -1, -1, 0, FAKE_DST - 16, 128,
+    assert L.morph_close_u16(FAKE_SRC, FAKE_DST, 8, 8, 18, 3, 3, -1, -1, 0, FAKE_DST - 16, 144,
                              None) == E.MORPH_EALIAS
+    # (nor a vertical window over 15)
+    assert L.morph_open(FAKE_SRC, FAKE_DST, 64, 8, 8, 3, 17, -1, -1, 0, None, 0,
+                        None) == E.MORPH_ENOMEM
     # the gradient needs the workspace where its one-pass form does not apply: a
     # vertical window over 9 (the streaming kernel) or rows of unaligned pitch
     assert L.morph_gradient(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 15, -1, -1, 0, None, 0,
@@ -86,16 +91,17 @@ def test_open_close_workspace_checks():
                                 128, None) == E.MORPH_EALIAS
     assert L.morph_apply(7, 0, FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, None, 0,
                          None) == E.MORPH_EINVAL
-    # top-hat and black-hat always need it
-    assert L.morph_tophat(FAKE_SRC, FAKE_DST, 8, 8, 8, 3, 3, -1, -1, 0, None, 0,
+    # top-hat and black-hat need it where their opening or closing does
+    assert L.morph_tophat(FAKE_SRC, FAKE_DST, 8, 8, 9, 3, 3, -1, -1, 0, None, 0,
                           None) == E.MORPH_ENOMEM
-    assert L.morph_blackhat_u16(FAKE_SRC, FAKE_DST, 8, 8, 16, 3, 3, -1, -1, 0, FAKE_DST, 128,
+    assert L.morph_blackhat_u16(FAKE_SRC, FAKE_DST, 8, 8, 18, 3, 3, -1, -1, 0, FAKE_DST, 144,
                                 None) == E.MORPH_EALIAS
 
 
 def test_openclose_fused_argument_checks():
     """The single-pass opening/closing rejects bad arguments before any launch:
-    windows above 16 per axis, bad dtype, anchors, pitch, overlap, border."""
+    windows above 16 per axis where the one-pass form does not apply (here rows of
+    unaligned pitch), bad dtype, anchors, pitch, overlap, border."""
     L = _lib.lib()
     E = _lib
 
@@ -104,8 +110,9 @@ def test_openclose_fused_argument_checks():
         return L.morph_openclose_fused(dtype, opening, src, dst, H, W, pitch, wx, wy, ax, ay,
                                        border, None)
 
-    assert oc(wx=17) == E.MORPH_EUNSUPPORTED
-    assert oc(wy=17, opening=0) == E.MORPH_EUNSUPPORTED
+    assert oc(wx=17, pitch=9) == E.MORPH_EUNSUPPORTED
+    assert oc(wy=17, opening=0, pitch=9) == E.MORPH_EUNSUPPORTED
+    assert oc(H=64, wy=17, pitch=8) == E.MORPH_EUNSUPPORTED  # (wy over 15 and over 16)
     assert oc(dtype=5) == E.MORPH_EUNSUPPORTED
     assert oc(border=1) == E.MORPH_EUNSUPPORTED
     assert oc(ax=3) == E.MORPH_EINVAL
@@ -263,8 +270,12 @@ def test_plan_resolution_and_thresholds(tmp_path):
         morph.load_tuning(str(f))
         # fit_units 0: a small single image keeps the tuned height
         assert morph.resolve_plan("u8", 1080, 1920, 3, 3)["tile_h"] == 24
+        f.write_text(json.dumps({"u8": {"oc_rows": 24, "oc_rows_tall": 64, "oc_t_x": 5,
+                                        "oc_one_pass": 0}}))
+        morph.load_tuning(str(f))  # the one-pass opening's keys
         for bad_t in ({"batch_wave_rows": 12}, {"fuse": 2}, {"batch_stream_rows": 0},
-                      {"fit_units": 3}):
+                      {"fit_units": 3}, {"oc_rows": 12}, {"oc_rows_tall": 0},
+                      {"oc_one_pass": 2}, {"oc_t_x": 0}):
             f.write_text(json.dumps({"u8": bad_t}))
             with pytest.raises(morph.MorphError):
                 morph.load_tuning(str(f))
@@ -277,6 +288,33 @@ def test_plan_resolution_and_thresholds(tmp_path):
     finally:
         assert _lib.lib().morph_load_tuning(None) == 0  # built-in defaults back
         morph.load_tuning(None)  # and the package's table
+
+
+def test_shipped_table_is_the_built_in_one():
+    """The autotuner's table shipped beside the package (loaded at import) and the
+    library's built-in table give the same plans: thresholds, unit heights of single
+    and batched images, tile shapes."""
+    import paper_2002_09474_amd as morph
+    cases = [(H, W, wx, wy, b) for (H, W) in ((4096, 4096), (100000, 1000), (1080, 1920))
+             for (wx, wy) in ((3, 3), (9, 9), (10, 10), (16, 3), (17, 31), (31, 32), (101, 101),
+                              (1, 255), (255, 1), (300, 300))
+             for b in (False, True)]
+    tiles = [(w, t) for w in (5, 12, 30, 60, 101) for t in ((0, 32), (0, 64))]
+
+    def plans():
+        out = [morph.get_thresholds(d) for d in ("u8", "u16")]
+        for d in ("u8", "u16"):
+            out += [morph.resolve_plan(d, H, W, wx, wy, batch=b) for H, W, wx, wy, b in cases]
+            out += [morph.resolve_plan(d, 4096, 4096, w, w, method_x="vhgw", method_y="vhgw",
+                                       tile=t) for w, t in tiles]
+        return out
+    try:
+        assert _lib.lib().morph_load_tuning(None) == 0
+        built_in = plans()
+        morph.load_tuning(None)  # the shipped table
+        assert plans() == built_in
+    finally:
+        morph.load_tuning(None)
 
 
 def test_strerror():

@@ -1,7 +1,8 @@
 """The autotuner on the GPU, on its reduced grid (a few windows and choices per key
 on smaller images): it runs end to end, writes a table the library loads, and with
 that table loaded the results of single images (windows on both sides of the
-measured thresholds) and of a mixed batch still equal the CPU oracle bit for bit.
+measured thresholds; openings and closings, one-pass windows among them) and of a
+mixed batch still equal the CPU oracle bit for bit.
 The package's default table is restored afterwards."""
 import json
 
@@ -31,6 +32,8 @@ def test_reduced_tuning_table_loads_and_keeps_results(tmp_path):
             assert 1 <= t["t_y"] <= autotune.DIRECT_MAX["y"]
             assert t["tiles"] and all(r["tq"] >= 2 for r in t["tiles"])
             assert morph.get_thresholds(d) == (t["t_x"], t["t_y"])  # loaded
+            assert t["oc_rows"] % 8 == 0 and t["oc_rows_tall"] % 8 == 0
+            assert t["oc_one_pass"] in (0, 1)
             assert len(res[d + "_pass_sweep"]) == 10
         for dt, seed in ((np.uint8, 41), (np.uint16, 42)):
             dn = "u8" if dt == np.uint8 else "u16"
@@ -38,8 +41,8 @@ def test_reduced_tuning_table_loads_and_keeps_results(tmp_path):
             img = synth.uniform(333, 517, dt, seed=seed)
             d, _ = to_dev(img)
             for wx, wy in ((tx, ty), (tx + 1, ty + 1), (max(1, tx - 1), ty), (3, 3), (31, 31),
-                           (200, 1), (1, 101)):
-                for op in ("erode", "dilate", "open"):
+                           (200, 1), (1, 101), (15, 15), (9, 12)):
+                for op in ("erode", "dilate", "open", "close"):
                     got = to_host(morph.apply(op, d, wx, wy))
                     torch.cuda.synchronize()
                     want = oracle.apply(op, img, wx, wy, method="vhgw", nthreads=8)

@@ -1,6 +1,8 @@
-"""GPU parity of the single-pass opening and closing (morph_openclose_fused: both
-operations on one LDS tile, no workspace, windows up to 16 on each axis, §2)
-against the CPU oracle, bit for bit: every window pair of a grid over 1..16 with
+"""GPU parity of the single-pass opening and closing (§2) against the CPU oracle, bit
+for bit.  Two kernels: the one-pass form on the wave kernel (rows aligned, windows
+up to 64 x 15; also what morph_open / morph_close run where it applies) and the
+workgroup-tile kernel (both operations on one LDS tile, windows up to 16 on each
+axis) that morph_openclose_fused runs elsewhere.  Every window pair of a grid over 1..16 with
 default and extreme anchors, images spanning several 32 x 128 tiles with ragged
 edges, values 0 and max, windows larger than the image, odd pitches and unaligned
 rows (bytes outside the image untouched), agreement with the two-launch
@@ -113,10 +115,18 @@ def test_matches_composition_and_errors():
             torch.cuda.synchronize()
             assert np.array_equal(fused, auto) and np.array_equal(fused, tile), (op, wx, wy)
             assert np.array_equal(fused, _want(img, op, wx, wy)), (op, wx, wy)
+    # (170-byte rows are not aligned: the tile kernel, windows up to 16)
     for wx, wy, status in ((FUSED_MAX + 1, 3, -3), (3, FUSED_MAX + 1, -3)):
         with pytest.raises(morph.MorphError) as ei:
             morph.openclose_fused("open", d, wx, wy)
         assert ei.value.status == status
+    # aligned rows: the one-pass form takes wx up to 64 (wy up to 15)
+    da, _ = to_dev(img, pitch_elems=176)
+    for wx, wy in ((17, 3), (64, 15), (3, 16)):
+        assert np.array_equal(_run(da, "open", wx, wy), _want(img, "open", wx, wy)), (wx, wy)
+    with pytest.raises(morph.MorphError) as ei:
+        morph.openclose_fused("open", da, 3, FUSED_MAX + 1)
+    assert ei.value.status == -3
     with pytest.raises(morph.MorphError) as ei:
         morph.openclose_fused("close", d, 3, 3, out=d)
     assert ei.value.status == -2
@@ -133,3 +143,27 @@ def test_full_size_images():
         for w in (3, 15):
             for op in ("open", "close"):
                 assert np.array_equal(_run(d, op, w, w), _want(img, op, w, w)), (H, W, op, w)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_one_pass_form(dtype):
+    """The one-pass opening/closing on the wave kernel's form, as morph_open /
+    morph_close run it: horizontal windows direct (1..9) and doubling (10..64),
+    vertical 1..15 (the short and tall kernels), anchors at both ends, images of
+    several strips and units with ragged edges, thin images, even and odd pitches
+    (aligned rows), against the oracle and against the two-launch composition."""
+    rng = np.random.default_rng(61)
+    for H, W in ((1, 37), (5, 3), (123, 611), (301, 257), (64, 1000)):
+        img = _img(H, W, dtype, seed=H + W)
+        d, _ = to_dev(img, pitch_elems=(W + 7) // 8 * 8)
+        for wx, wy in ((1, 1), (2, 9), (3, 3), (9, 10), (10, 2), (15, 15), (33, 7), (64, 12),
+                       (5, 14), (9, 1)):
+            ax = int(rng.integers(-1, wx))
+            ay = int(rng.integers(-1, wy))
+            for op in ("open", "close", "tophat", "blackhat"):
+                got = morph.apply(op, d, wx, wy, ax, ay)  # one pass (no plan)
+                two = morph.apply(op, d, wx, wy, ax, ay, method_x="direct" if wx <= 9 else "doubling")
+                torch.cuda.synchronize()
+                ref = oracle.apply(op, img, wx, wy, ax, ay, method="vhgw", nthreads=8)
+                assert np.array_equal(to_host(got), ref), (H, W, op, wx, wy, ax, ay, dtype)
+                assert np.array_equal(to_host(two), ref), (H, W, op, wx, wy, "two launches")

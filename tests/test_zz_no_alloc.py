@@ -34,8 +34,11 @@ def _static(op, dt, src, dst, wx, wy):
 def test_static_matches_workspace_entry_point(dtype):
     dt = _lib.U8 if dtype == np.uint8 else _lib.U16
     # first call large (4096 x 4096 plus a padded pitch: 16.8 / 33.6 MB of rows),
-    # then a smaller, ragged one in the same array
-    cases = [((4096, 4096), 4096 + 64, "open", 9, 9), ((517, 389), 389 + 3, "close", 15, 7),
+    # then smaller, ragged ones in the same array; each takes the workspace (a
+    # vertical window over 15, or rows of unaligned pitch, keep the one-pass
+    # opening/closing out), the last opening runs in one pass with no workspace
+    cases = [((4096, 4096), 4096 + 64, "open", 9, 17), ((517, 389), 389 + 2, "close", 15, 7),
+             ((200, 300), 304, "open", 7, 7),
              ((300, 1001), 1001, "tophat", 5, 3), ((257, 130), 131, "blackhat", 31, 31),
              ((129, 77), 77, "gradient", 21, 15), ((64, 64), 64, "erode", 3, 3)]
     for (H, W), pitch, op, wx, wy in cases:
@@ -56,16 +59,18 @@ def test_static_matches_workspace_entry_point(dtype):
 
 def test_static_refuses_an_intermediate_larger_than_the_array():
     # 8193 rows of 8192 bytes = 64 MiB + 8 KiB: one row more than the array holds
+    # (a vertical window of 17: the two launches through the workspace)
     src = torch.zeros((8193, 8192), dtype=torch.uint8, device="cuda")
     dst = torch.full_like(src, 7)
-    assert _static("open", _lib.U8, src, dst, 3, 3) == _lib.MORPH_ENOMEM
+    assert _static("open", _lib.U8, src, dst, 3, 17) == _lib.MORPH_ENOMEM
     torch.cuda.synchronize()
     assert int(dst.min()) == 7 and int(dst.max()) == 7  # nothing was enqueued
-    # the largest image that fits: 8192 rows of 8192 bytes, a 1x1 window copy
+    # the largest image that fits: 8192 rows of 8192 bytes (a 1 x 17 opening of a
+    # constant image is the image)
     src2 = src[:8192]
     dst2 = dst[:8192]
-    src2.random_(0, 256)
-    assert _static("open", _lib.U8, src2, dst2, 1, 1) == 0
+    src2.fill_(93)
+    assert _static("open", _lib.U8, src2, dst2, 1, 17) == 0
     torch.cuda.synchronize()
     assert torch.equal(dst2, src2)
     # erosion and dilation need no workspace, whatever the size
