@@ -19,8 +19,11 @@ Unit heights of batched images are then chosen on the whole 512-image batch of t
 benchmark (one key at a time), those of single images on 4096x4096 images (the
 wave kernel's at 3x3, the streaming kernel's at 15x15 and 31x31, the one-pass
 opening's at 3x3 + 9x9 and at 15x15, and whether the one-pass opening beats the two
-launches at all), the unit height of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same images,
-and tile shapes of the tile kernel per window bucket.  Run
+launches at all), the unit height of the wide-row kernel (uint8, vertical window 1,
+wx > 128) on the same images, and tile shapes of the tile kernel per window bucket.  As in the benchmark, timed
+launches take turns over copies of their images that together hold more memory than
+the 256 MB Infinity Cache (four copies of the batch; 512 MB of 4096x4096 buffers),
+so that what is measured is the kernels reading HBM.  Run
 ``python -m paper_2002_09474_amd.autotune``.
 """
 from __future__ import annotations
@@ -50,6 +53,7 @@ BATCH_KEYS = (("batch_wave_rows", (16, 24, 32, 48)), ("batch_stream_rows", (32, 
 # unit heights of single images' one-pass openings, each timed on 4096x4096 images
 # over its windows (the short kernel's, vertical windows up to 9, and the tall one's)
 OC_KEYS = (("oc_rows", (8, 16, 24, 32, 48), (3, 9)), ("oc_rows_tall", (16, 32, 48, 64), (15,)))
+BATCH_COPIES = 4  # copies of the batch that timed launches take turns over (1.3 GB of uint8)
 WIDE_ROWS = (2, 4, 8, 16)            # wide-row units (uint8, wy = 1, wx > 128)
 WIDE_WINDOWS = (200, 255, 511)
 
@@ -68,7 +72,10 @@ def _timer(torch, fn, iters, warmup=5):
     return a.elapsed_time(b) / iters * 1e3  # microseconds
 
 
-def _bufs(torch, img, n):
+def _bufs(torch, img, min_bytes=512 << 20):
+    """Copies of `img` and as many outputs, at least four pairs and together at least
+    `min_bytes` (launches take turns over them)."""
+    n = max(4, -(-min_bytes // (2 * img.numel() * img.element_size())))
     srcs = [img.clone() for _ in range(n)]
     return srcs, [torch.empty_like(s) for s in srcs]
 
@@ -130,7 +137,29 @@ def threshold(rows, axis, tol=0.03):
     return t
 
 
-def batch_thresholds(torch, morph, dname, items, base, tx, ty, iters=10):
+def _time_batches(torch, morph, copies, iters):
+    """Microseconds a launch of the batch, launches taking turns over its copies (so
+    that, as in the benchmark, a launch does not find its images in the Infinity
+    Cache): the median of three timings."""
+    bs = []
+    try:
+        for items in copies:
+            b = morph.Batch(len(items), 1 << 22)
+            bs.append(b)
+            b.set(items)
+        k = [0]
+
+        def fn():
+            bs[k[0] % len(bs)].enqueue()
+            k[0] += 1
+        ts = sorted(_timer(torch, fn, iters, warmup=len(bs)) for _ in range(3))
+        return ts[1]
+    finally:
+        for b in bs:
+            b.close()
+
+
+def batch_thresholds(torch, morph, dname, copies, base, tx, ty, iters=10):
     """(batch_t_x, batch_t_y): the thresholds under which the whole batch runs
     fastest, among the classic pair (9, 9), the single-image thresholds and mixes
     of them -- a pass taken off the fused dispatch can cost the batch more than it
@@ -139,29 +168,19 @@ def batch_thresholds(torch, morph, dname, items, base, tx, ty, iters=10):
     res = []
     for cx, cy in cands:
         _with_table(morph, {dname: dict(base, batch_t_x=cx, batch_t_y=cy)})
-        b = morph.Batch(len(items), 1 << 22)
-        try:
-            b.set(items)
-            us = _timer(torch, lambda: b.enqueue(), iters, warmup=3)
-        finally:
-            b.close()
+        us = _time_batches(torch, morph, copies, iters)
         res.append({"batch_t_x": cx, "batch_t_y": cy, "us": round(us, 2)})
     best = min(res, key=lambda r: r["us"])
     return best["batch_t_x"], best["batch_t_y"], res
 
 
-def best_rows(torch, morph, dname, items, key, choices, base, iters=10):
-    """The `key` (a batch unit height) among `choices` that runs `items` as one batch
-    fastest, the rest of the table being `base`."""
+def best_rows(torch, morph, dname, copies, key, choices, base, iters=10):
+    """The `key` (a batch unit height) among `choices` that runs the batch (launches
+    taking turns over its copies) fastest, the rest of the table being `base`."""
     res = []
     for c in choices:
         _with_table(morph, {dname: dict(base, **{key: c})})
-        b = morph.Batch(len(items), 1 << 22)
-        try:
-            b.set(items)
-            us = _timer(torch, lambda: b.enqueue(), iters, warmup=3)
-        finally:
-            b.close()
+        us = _time_batches(torch, morph, copies, iters)
         res.append({key: c, "us": round(us, 2)})
     best = min(res, key=lambda r: r["us"])[key]
     return best, res
@@ -275,13 +294,14 @@ def wide_rows_sweep(torch, morph, srcs, dsts, base, iters=20, choices=WIDE_ROWS)
     return min(res, key=lambda r: r["us"])["wide_rows"], res
 
 
-def _batch_items(torch, morph, dev, dname, n=512, hi=2048):
-    """The benchmark's 512-image batch (uint8, or the same images scaled to uint16);
-    n and hi give a smaller batch of the same kind."""
+def _batch_items(torch, morph, dev, dname, n=512, hi=2048, copies=BATCH_COPIES):
+    """The benchmark's 512-image batch (uint8, or the same images scaled to uint16) in
+    `copies` copies, each its own source and destination images; n and hi give a
+    smaller batch of the same kind."""
     from . import synth
     specs = synth.batch_specs(n, seed=5, hi=hi)
     imgs = synth.batch_images(specs, seed=5)
-    items = []
+    out = [[] for _ in range(copies)]
     for s, im in zip(specs, imgs):
         t = torch.from_numpy(im).to(dev)
         if dname == "u16":
@@ -289,11 +309,12 @@ def _batch_items(torch, morph, dev, dname, n=512, hi=2048):
         # rows padded to 64 bytes, as the benchmark lays the batch out
         es = t.element_size()
         p = (s["W"] * es + 63) // 64 * 64 // es
-        src = torch.zeros((s["H"], p), dtype=t.dtype, device=dev)[:, :s["W"]]
-        src.copy_(t)
-        dst = torch.empty((s["H"], p), dtype=t.dtype, device=dev)[:, :s["W"]]
-        items.append(dict(src=src, dst=dst, wx=s["w"], wy=s["w"], op=s["op"]))
-    return items
+        for items in out:
+            src = torch.zeros((s["H"], p), dtype=t.dtype, device=dev)[:, :s["W"]]
+            src.copy_(t)
+            dst = torch.empty((s["H"], p), dtype=t.dtype, device=dev)[:, :s["W"]]
+            items.append(dict(src=src, dst=dst, wx=s["w"], wy=s["w"], op=s["op"]))
+    return out
 
 
 # the reduced grid: a few windows and choices per key on smaller images, for a
@@ -338,33 +359,33 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
     doc = torch.from_numpy(synth.document(540 if R else 4096, 960 if R else 4096, seed=2)).to(dev)
     for dname in ("u8", "u16"):
         img = doc if dname == "u8" else (doc.to(torch.int32) * 257).to(torch.int16).view(torch.uint16)
-        srcs, dsts = _bufs(torch, img, 8)
+        srcs, dsts = _bufs(torch, img, (16 << 20) if R else (512 << 20))
         rows = pass_sweep(torch, morph, dname, srcs, dsts, iters=10 if R else (20 if quick else 40),
                           windows=R["windows"] if R else None)
         tx, ty = threshold(rows, "x"), threshold(rows, "y")
         _log("%s: pass sweep done, thresholds x %d, y %d" % (dname, tx, ty))
         del srcs, dsts
         base = {"t_x": tx, "t_y": ty}
-        items = (_batch_items(torch, morph, dev, dname, *R["batch"]) if R
-                 else _batch_items(torch, morph, dev, dname))
-        it = 3 if R else (5 if quick else 10)
-        btx, bty, bt_table = batch_thresholds(torch, morph, dname, items, base, tx, ty, it)
+        copies = (_batch_items(torch, morph, dev, dname, *R["batch"], copies=2) if R
+                  else _batch_items(torch, morph, dev, dname))
+        it = 4 if R else (8 if quick else 16)
+        btx, bty, bt_table = batch_thresholds(torch, morph, dname, copies, base, tx, ty, it)
         base.update(batch_t_x=btx, batch_t_y=bty)
         _log("%s: batch thresholds x %d, y %d" % (dname, btx, bty))
         result[dname + "_batch_threshold_sweep"] = bt_table
         for key, choices in (R["batch_keys"] if R else BATCH_KEYS):
-            best, table = best_rows(torch, morph, dname, items, key, choices, base, it)
+            best, table = best_rows(torch, morph, dname, copies, key, choices, base, it)
             base[key] = best
             _log("%s: %s %d" % (dname, key, best))
             result[dname + "_" + key + "_sweep"] = table
-        del items
+        del copies
         _with_table(morph, {dname: base})
         g = torch.Generator(device=dev).manual_seed(3)
         n = R["big"] if R else 4096
         big = torch.randint(0, 256 if dname == "u8" else 65536, (n, n), generator=g,
                             dtype=torch.int32, device=dev)
         big = big.to(torch.uint8) if dname == "u8" else big.to(torch.int16).view(torch.uint16)
-        srcs, dsts = _bufs(torch, big, 6)
+        srcs, dsts = _bufs(torch, big, (16 << 20) if R else (512 << 20))
         for key, choices, w in (R["single_keys"] if R else SINGLE_KEYS):
             best, table = best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w,
                                            3 if R else (8 if quick else 20))

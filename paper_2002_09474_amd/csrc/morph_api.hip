@@ -64,9 +64,9 @@ std::mutex g_tuning_mu;
 // the Python package): direct passes up to 9 along x (16 for uint16) and 31 along y on
 // single images, 9 and 9 for the images of a batch; unit heights and tile shapes.
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 32, 32}}, 16, 96, 48, 4,
-     1, 32, 64, 64, 1, 9, 9, 1, 24, 9, 64},
-    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 64, 64, 4,
+    {9, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 16, 96, 64, 4,
+     1, 16, 96, 48, 1, 9, 9, 1, 16, 9, 64},
+    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 48, 32}}, 8, 96, 48, 4,
      1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 64},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
