@@ -880,13 +880,17 @@ static constexpr int kBatchGroups = kPhases * kPhaseGroups;
 struct morph_batch {
     int max_images = 0;
     int64_t max_tiles = 0;
-    TileJob *d_jobs = nullptr;
+    // the three tables of a batch, packed into one device block (and one pinned
+    // staging block, so that set() copies them with one transfer): laid out anew by
+    // each set() for its number of jobs, each table on a 256-byte boundary
+    uint8_t *d_tables = nullptr, *h_tables = nullptr;
+    TileJob *d_jobs = nullptr;            // the job table
     int64_t *d_tile_start = nullptr;      // per group: njobs + 1 prefix sums
     int32_t *d_tile_job = nullptr;        // per group: job (within the group) of each tile
-    int32_t *h_tile_job = nullptr;        // pinned staging
+    TileJob *h_jobs = nullptr;            // their places in the staging block
+    int64_t *h_tile_start = nullptr;
+    int32_t *h_tile_job = nullptr;
     unsigned long long *d_counter = nullptr; // per group: next tile, finished workgroups
-    TileJob *h_jobs = nullptr;            // pinned staging
-    int64_t *h_tile_start = nullptr;      // pinned staging
     std::vector<BatchGroup> groups;
     int64_t n_tiles = -1;
     // captured graph of the group launches, valid for one stream and one layout
@@ -918,6 +922,26 @@ static int device_cus()
     return cus > 0 ? cus : 256;
 }
 
+// Lay the batch's tables out for `njobs` jobs in `ngroups` groups and `tiles` tiles:
+// the job table, then the tile starts (njobs + ngroups), then the tile jobs, each on
+// a 256-byte boundary; point the device and staging pointers there (once the blocks
+// exist) and return the bytes the three take.
+static size_t table_layout(morph_batch *b, size_t njobs, size_t ngroups, int64_t tiles)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_start = up(sizeof(TileJob) * njobs);
+    const size_t o_tjob = up(o_start + sizeof(int64_t) * (njobs + ngroups));
+    if (b->d_tables && b->h_tables) {
+        b->d_jobs = (TileJob *)b->d_tables;
+        b->d_tile_start = (int64_t *)(b->d_tables + o_start);
+        b->d_tile_job = (int32_t *)(b->d_tables + o_tjob);
+        b->h_jobs = (TileJob *)b->h_tables;
+        b->h_tile_start = (int64_t *)(b->h_tables + o_start);
+        b->h_tile_job = (int32_t *)(b->h_tables + o_tjob);
+    }
+    return o_tjob + sizeof(int32_t) * (size_t)tiles;
+}
+
 static void drop_graph(morph_batch *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -935,26 +959,21 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
     b->max_images = max_images;
     b->max_tiles = max_tiles;
     const size_t njobs = (size_t)kPhases * max_images; // an opening/closing is two jobs
-    const size_t nstart = njobs + kBatchGroups;
     const size_t ncount = 2 * kBatchGroups;
+    const size_t bytes = table_layout(b, njobs, kBatchGroups, max_tiles);
     hipError_t e;
-    if ((e = hipMalloc((void **)&b->d_jobs, sizeof(TileJob) * njobs)) != hipSuccess ||
-        (e = hipMalloc((void **)&b->d_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
-        (e = hipMalloc((void **)&b->d_tile_job, sizeof(int32_t) * (size_t)max_tiles)) !=
-            hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_tile_job, sizeof(int32_t) * (size_t)max_tiles)) !=
-            hipSuccess ||
+    if ((e = hipMalloc((void **)&b->d_tables, bytes)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_tables, bytes)) != hipSuccess ||
         (e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long) * ncount)) !=
             hipSuccess ||
         (e = hipMemset(b->d_counter, 0, sizeof(unsigned long long) * ncount)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_jobs, sizeof(TileJob) * njobs)) != hipSuccess ||
         (e = hipHostMalloc((void **)&b->h_jobs_ws, sizeof(TileJob) * njobs)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&b->ws_staged, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_tile_start, sizeof(int64_t) * nstart)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess) {
         morph_batch_destroy(b);
         return hip_fail(e);
     }
+    (void)table_layout(b, njobs, kBatchGroups, max_tiles); // (places the pointers)
     *out = b;
     return MORPH_OK;
 }
@@ -1078,6 +1097,17 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
     b->n_tiles = -1;
     b->ws_needed = 0;
     b->ws_bound = nullptr;
+    // the tables laid out for this batch's jobs, groups and tiles (within the
+    // capacity: at most kPhases x max_images jobs, kBatchGroups groups, max_tiles)
+    size_t n_all = 0, n_groups = 0;
+    int64_t t_all = 0;
+    for (int g = 0; g < kBatchGroups; g++) {
+        n_all += jobs[g].size();
+        n_groups += jobs[g].empty() ? 0 : 1;
+        for (const TileJob &j : jobs[g]) t_all += (int64_t)j.tiles_x * j.tiles_y;
+    }
+    if (t_all > b->max_tiles) return MORPH_ENOMEM;
+    const size_t table_bytes = table_layout(b, n_all, n_groups, t_all);
     std::vector<BatchGroup> groups;
     std::vector<WsPatch> patches;
     int64_t tiles = 0;
@@ -1147,14 +1177,9 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
     b->ws_patch = patches;
     hipError_t e;
     if (m > 0) {
-        if ((e = hipMemcpyAsync(b->d_jobs, b->h_jobs, sizeof(TileJob) * m, hipMemcpyHostToDevice,
+        // the three tables in one transfer
+        if ((e = hipMemcpyAsync(b->d_tables, b->h_tables, table_bytes, hipMemcpyHostToDevice,
                                 stream)) != hipSuccess)
-            return hip_fail(e);
-        if ((e = hipMemcpyAsync(b->d_tile_start, b->h_tile_start, sizeof(int64_t) * starts,
-                                hipMemcpyHostToDevice, stream)) != hipSuccess)
-            return hip_fail(e);
-        if ((e = hipMemcpyAsync(b->d_tile_job, b->h_tile_job, sizeof(int32_t) * (size_t)tiles,
-                                hipMemcpyHostToDevice, stream)) != hipSuccess)
             return hip_fail(e);
         if ((e = hipEventRecord(b->staged, stream)) != hipSuccess) return hip_fail(e);
         b->staged_pending = true;
@@ -1337,13 +1362,9 @@ int morph_batch_destroy(morph_batch_t b)
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->ws_staged) (void)hipEventDestroy(b->ws_staged);
     if (b->h_jobs_ws) (void)hipHostFree(b->h_jobs_ws);
-    if (b->d_jobs) (void)hipFree(b->d_jobs);
-    if (b->d_tile_start) (void)hipFree(b->d_tile_start);
-    if (b->d_tile_job) (void)hipFree(b->d_tile_job);
-    if (b->h_tile_job) (void)hipHostFree(b->h_tile_job);
+    if (b->d_tables) (void)hipFree(b->d_tables);
+    if (b->h_tables) (void)hipHostFree(b->h_tables);
     if (b->d_counter) (void)hipFree(b->d_counter);
-    if (b->h_jobs) (void)hipHostFree(b->h_jobs);
-    if (b->h_tile_start) (void)hipHostFree(b->h_tile_start);
     delete b;
     return MORPH_OK;
 }

@@ -46,15 +46,18 @@ def _want(it):
                         it["ax"], it["ay"], method="direct")
 
 
-@pytest.mark.parametrize("fuse,fit", [(1, 1), (0, 1), (1, 0)])
-def test_batch_matches_oracle_and_single_calls(fuse, fit, tmp_path):
+@pytest.mark.parametrize("fuse,fit,ty", [(1, 1, 0), (0, 1, 0), (1, 0, 0), (1, 1, 31), (0, 1, 31)])
+def test_batch_matches_oracle_and_single_calls(fuse, fit, ty, tmp_path):
     """With the wave and streaming groups fused into one dispatch per element type
     and row alignment (the default) and launched one group at a time; with units
     shortened to fill the GPU (the default for a batch this small) and at the tuned
-    batch heights."""
+    batch heights; with vertical windows up to 31 direct (the wave kernel's tall
+    form, a dispatch of its own)."""
     import json
     f = tmp_path / "t.json"
     t = {"fuse": fuse, "fit_units": fit}
+    if ty:
+        t["batch_t_y"] = ty
     f.write_text(json.dumps({"u8": t, "u16": t}))
     morph.load_tuning(str(f))
     try:
