@@ -344,6 +344,8 @@ int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dty
  *   tiles               tile kernel shapes per window bucket: [{"wmax", "tq" (input
  *                       quads of a tile row), "tb" (output rows)}, ...]
  *   wave_rows           output rows of a direct wave unit (a multiple of 8, <= 64)
+ *   wave_rows_tall      the same for the wave kernel's tall form (vertical windows
+ *                       10..31)
  *   stream_rows, stream_rows_runs  output rows of a streaming unit (1 .. 4096), for
  *                       vertical windows up to 16 and above
  *   wide_rows           rows of a wide-row unit (1 .. 4096; taken in groups of 4 for
@@ -358,6 +360,9 @@ int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dty
  *                       vertical windows up to 9 and above
  *   oc_t_x              largest horizontal window the one-pass form takes direct
  *                       (doubling above; at most 9)
+ *   h_vhgw              0 / 1: single images' automatic large horizontal windows take
+ *                       the paper's vHGW across the lanes instead of doubling (where
+ *                       the kernel has that form)
  *   fit_units           0 / 1: a single image, or a batch, whose wave and streaming
  *                       units would number under about 2048 gets shorter ones (in
  *                       steps of 8 rows, no fewer than 8; a batch only while its tile

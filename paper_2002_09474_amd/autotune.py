@@ -13,17 +13,22 @@ large-window pass (the streaming kernel: vHGW through an LDS ring vertically,
 doubling across lanes horizontally), as single-pass sweeps along x (w x 1) and
 along y (1 x w) on a 4096x4096 document page.  The threshold of a pass is the
 largest window up to which direct is never slower by more than the timing noise.
+On the same page, the large horizontal windows' two passes across the lanes, doubling
+and the paper's vHGW, are timed against each other (h_vhgw).
 The thresholds of batched images are then chosen on the whole benchmark batch
 (direct passes that leave the fused dispatch can cost it more than they save).
 Unit heights of batched images are then chosen on the whole 512-image batch of the
-benchmark (one key at a time), those of single images on 4096x4096 images (the
-wave kernel's at 3x3, the streaming kernel's at 15x15 and 31x31, the one-pass
-opening's at 3x3 + 9x9 and at 15x15, and whether the one-pass opening beats the two
-launches at all), the unit height of the wide-row kernel (uint8, vertical window 1,
-wx > 128) on the same images, and tile shapes of the tile kernel per window bucket.  As in the benchmark, timed
-launches take turns over copies of their images that together hold more memory than
-the 256 MB Infinity Cache (four copies of the batch; 512 MB of 4096x4096 buffers),
-so that what is measured is the kernels reading HBM.  Run
+benchmark (one key at a time), those of single images on 4096x4096 images (the wave
+kernel's over 3x3 and 9x9, its tall form's over 15x15 and 1x31, the streaming
+kernel's ring form at 15x15 with vHGW forced and its run-total form over 7x63,
+101x101 and 1x255, the one-pass opening's over 3x3 and 9x9 and at 15x15 -- each the
+height whose worst time over its windows, relative to the best height there, is
+least -- and whether the one-pass opening beats the two launches at all), the unit
+height of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same
+images, and tile shapes of the tile kernel per window bucket.
+As in the benchmark, timed launches take turns over copies of their images that
+together hold more memory than the 256 MB Infinity Cache (four copies of the batch;
+512 MB of 4096x4096 buffers), so that what is measured is the kernels reading HBM.  Run
 ``python -m paper_2002_09474_amd.autotune``.
 """
 from __future__ import annotations
@@ -44,9 +49,14 @@ TB = (16, 32, 64, 128)
 WAVE_ROWS = (8, 16, 24, 32, 48)
 STREAM_ROWS = (32, 48, 64, 96)      # streaming units, LDS-ring form (wy <= 16)
 STREAM_ROWS_RUNS = (24, 32, 48, 64)  # streaming units, run-total form (wy > 16)
-# unit heights of single images, each timed on 4096x4096 images at one window
-SINGLE_KEYS = (("wave_rows", WAVE_ROWS, 3), ("stream_rows", STREAM_ROWS, 15),
-               ("stream_rows_runs", STREAM_ROWS_RUNS, 31))
+# unit heights of single images, each timed on 4096x4096 images over its windows
+# (wx, wy): the wave kernel's short form and its tall form (a kernel of its own); the
+# streaming kernel's ring form (vertical windows up to 16, which the automatic plan
+# takes direct: forced vHGW) and its run-total form
+SINGLE_KEYS = (("wave_rows", WAVE_ROWS, ((3, 3), (9, 9)), {}),
+               ("wave_rows_tall", WAVE_ROWS, ((15, 15), (1, 31)), {}),
+               ("stream_rows", STREAM_ROWS, ((15, 15),), {"method_y": "vhgw"}),
+               ("stream_rows_runs", STREAM_ROWS_RUNS, ((7, 63), (101, 101), (1, 255)), {}))
 # unit heights of batched images, timed on the whole benchmark batch
 BATCH_KEYS = (("batch_wave_rows", (16, 24, 32, 48)), ("batch_stream_rows", (32, 48, 64, 96)),
               ("batch_stream_rows_runs", (32, 48, 64)))
@@ -137,6 +147,27 @@ def threshold(rows, axis, tol=0.03):
     return t
 
 
+H_WINDOWS = (13, 31, 63, 101)  # horizontal windows the doubling / vHGW choice is timed at
+
+
+def h_vhgw_check(torch, morph, srcs, dsts, windows=H_WINDOWS, iters=20):
+    """1 if the paper's vHGW across the lanes beats doubling over w x 1 passes at
+    `windows` (the sum of medians of three timings), else 0; and the timings."""
+    res = []
+    for name in ("doubling", "vhgw"):
+        us = []
+        for w in windows:
+            k = [0]
+
+            def fn():
+                i = k[0] % len(srcs)
+                k[0] += 1
+                morph.apply("erode", srcs[i], w, 1, out=dsts[i], method_x=name)
+            us.append(round(sorted(_timer(torch, fn, iters) for _ in range(3))[1], 3))
+        res.append({"method_x": name, "windows": list(windows), "us": us})
+    return int(sum(res[1]["us"]) < sum(res[0]["us"])), res
+
+
 def _time_batches(torch, morph, copies, iters):
     """Microseconds a launch of the batch, launches taking turns over its copies (so
     that, as in the benchmark, a launch does not find its images in the Infinity
@@ -220,29 +251,45 @@ def tile_sweep(torch, morph, srcs, dsts, dname, iters=20, buckets=BUCKETS, tqs=T
     return rules, table
 
 
-def best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w, iters=20):
-    """The `key` (a single-image unit height) among `choices` that runs a w x w
-    erosion of the images `srcs` fastest, the rest of the table being `base`."""
+def least_worst(res, key):
+    """The choice (value of `key`) whose worst time relative to the best choice at each
+    window is least: res rows hold `key` and "us" (a list over the same windows)."""
+    n = len(res[0]["us"])
+    best = [min(r["us"][i] for r in res) for i in range(n)]
+    return min(res, key=lambda r: max(r["us"][i] / best[i] for i in range(n)))[key]
+
+
+def best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, windows, iters=20,
+                     kw=None):
+    """The `key` (a single-image unit height) among `choices` whose worst erosion time
+    of the images `srcs` over `windows` ((wx, wy) pairs, with the plan arguments `kw`;
+    median of three timings), relative to the best choice there, is least; the rest of
+    the table being `base`."""
+    kw = kw or {}
     res = []
     for c in choices:
         _with_table(morph, {dname: dict(base, **{key: c})})
-        k = [0]
+        us = []
+        for wx, wy in windows:
+            k = [0]
 
-        def fn():
-            i = k[0] % len(srcs)
-            k[0] += 1
-            morph.apply("erode", srcs[i], w, w, out=dsts[i])
-        res.append({key: c, "us": round(_timer(torch, fn, iters), 3)})
-    return min(res, key=lambda r: r["us"])[key], res
+            def fn():
+                i = k[0] % len(srcs)
+                k[0] += 1
+                morph.apply("erode", srcs[i], wx, wy, out=dsts[i], **kw)
+            us.append(round(sorted(_timer(torch, fn, iters) for _ in range(3))[1], 3))
+        res.append({key: c, "windows": ["%dx%d" % w for w in windows], "us": us})
+    return least_worst(res, key), res
 
 
 def oc_rows_sweep(torch, morph, dname, srcs, dsts, key, choices, base, windows, iters=20):
-    """The `key` (a unit height of the one-pass opening) among `choices` whose sum of
-    w x w opening times over `windows` is least, the rest of the table being `base`."""
+    """The `key` (a unit height of the one-pass opening) among `choices` whose worst
+    w x w opening time over `windows`, relative to the best choice there, is least; the
+    rest of the table being `base`."""
     res = []
     for c in choices:
         _with_table(morph, {dname: dict(base, **{key: c})})
-        us = 0.0
+        us = []
         for w in windows:
             k = [0]
 
@@ -250,9 +297,9 @@ def oc_rows_sweep(torch, morph, dname, srcs, dsts, key, choices, base, windows, 
                 i = k[0] % len(srcs)
                 k[0] += 1
                 morph.openclose_fused("open", srcs[i], w, w, out=dsts[i])
-            us += _timer(torch, fn, iters)
-        res.append({key: c, "us": round(us, 3)})
-    return min(res, key=lambda r: r["us"])[key], res
+            us.append(round(sorted(_timer(torch, fn, iters) for _ in range(3))[1], 3))
+        res.append({key: c, "windows": ["%dx%d" % (w, w) for w in windows], "us": us})
+    return least_worst(res, key), res
 
 
 def oc_one_pass_check(torch, morph, dname, srcs, dsts, base, windows=(3, 9, 15), iters=20):
@@ -322,7 +369,7 @@ def _batch_items(torch, morph, dev, dname, n=512, hi=2048, copies=BATCH_COPIES):
 REDUCED = {"windows": {"x": (2, 3, 9, 12, 16), "y": (2, 3, 9, 15, 31)},
            "batch": (48, 300), "big": 1024,
            "batch_keys": tuple((k, c[:2]) for k, c in BATCH_KEYS),
-           "single_keys": tuple((k, c[:2], w) for k, c, w in SINGLE_KEYS),
+           "single_keys": tuple((k, c[:2], w[:1], kw) for k, c, w, kw in SINGLE_KEYS),
            "oc_keys": tuple((k, c[:2], w) for k, c, w in OC_KEYS),
            "wide_rows": WIDE_ROWS[:2], "buckets": BUCKETS[:1], "tq": TQ[:2], "tb": TB[:2]}
 
@@ -364,8 +411,11 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
                           windows=R["windows"] if R else None)
         tx, ty = threshold(rows, "x"), threshold(rows, "y")
         _log("%s: pass sweep done, thresholds x %d, y %d" % (dname, tx, ty))
+        hv, result[dname + "_h_vhgw_check"] = h_vhgw_check(
+            torch, morph, srcs, dsts, (13, 31) if R else H_WINDOWS, 3 if R else 20)
+        _log("%s: h_vhgw %d" % (dname, hv))
         del srcs, dsts
-        base = {"t_x": tx, "t_y": ty}
+        base = {"t_x": tx, "t_y": ty, "h_vhgw": hv}
         copies = (_batch_items(torch, morph, dev, dname, *R["batch"], copies=2) if R
                   else _batch_items(torch, morph, dev, dname))
         it = 4 if R else (8 if quick else 16)
@@ -386,9 +436,9 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
                             dtype=torch.int32, device=dev)
         big = big.to(torch.uint8) if dname == "u8" else big.to(torch.int16).view(torch.uint16)
         srcs, dsts = _bufs(torch, big, (16 << 20) if R else (512 << 20))
-        for key, choices, w in (R["single_keys"] if R else SINGLE_KEYS):
-            best, table = best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, w,
-                                           3 if R else (8 if quick else 20))
+        for key, choices, ws, kw in (R["single_keys"] if R else SINGLE_KEYS):
+            best, table = best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, ws,
+                                           3 if R else (8 if quick else 20), kw)
             base[key] = best
             _log("%s: %s %d" % (dname, key, best))
             result[dname + "_" + key + "_sweep"] = table

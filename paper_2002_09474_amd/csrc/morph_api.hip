@@ -57,6 +57,12 @@ struct DtypeTuning {
     // then the tall ones), and the largest horizontal window its passes take direct
     // (doubling above)
     int oc_one_pass, oc_rows, oc_t_x, oc_rows_tall;
+    // output rows of a unit of the wave kernel's tall form (vertical windows past
+    // kDirectMax; single images and batches), a multiple of kWaveRows
+    int wave_rows_tall;
+    // single images' automatic large horizontal windows: 0 = doubling across the lanes,
+    // 1 = the paper's vHGW across the lanes (where a kernel has that form)
+    int h_vhgw;
 };
 
 std::mutex g_tuning_mu;
@@ -64,10 +70,10 @@ std::mutex g_tuning_mu;
 // the Python package): direct passes up to 9 along x (16 for uint16) and 31 along y on
 // single images, 9 and 9 for the images of a batch; unit heights and tile shapes.
 const DtypeTuning k_builtin_tuning[2] = {
-    {9, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 16, 96, 64, 4,
-     1, 16, 96, 48, 1, 9, 9, 1, 16, 9, 64},
-    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 48, 32}}, 8, 96, 48, 4,
-     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 64},
+    {12, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 64, 32, 4,
+     1, 16, 96, 64, 1, 9, 9, 1, 16, 9, 48, 8, 0},
+    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 96, 64, 4,
+     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 48, 16, 0},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -173,7 +179,8 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
     } chunk_keys[] = {{"wave_rows", &DtypeTuning::wave_rows},
                       {"batch_wave_rows", &DtypeTuning::batch_wave_rows},
                       {"oc_rows", &DtypeTuning::oc_rows},
-                      {"oc_rows_tall", &DtypeTuning::oc_rows_tall}};
+                      {"oc_rows_tall", &DtypeTuning::oc_rows_tall},
+                      {"wave_rows_tall", &DtypeTuning::wave_rows_tall}};
     for (const auto &ck : chunk_keys) { // (whole chunks of kWaveRows rows)
         it = o.obj.find(ck.key);
         if (it == o.obj.end()) continue;
@@ -189,26 +196,20 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         if (r < 1) return false;
         t.oc_t_x = std::min(r, kDirectMax);
     }
-    it = o.obj.find("oc_one_pass");
-    if (it != o.obj.end()) {
+    const struct {
+        const char *key;
+        int DtypeTuning::*field;
+    } flag_keys[] = {{"oc_one_pass", &DtypeTuning::oc_one_pass},
+                     {"h_vhgw", &DtypeTuning::h_vhgw},
+                     {"fit_units", &DtypeTuning::fit_units},
+                     {"fuse", &DtypeTuning::fuse}};
+    for (const auto &fk : flag_keys) { // (0 or 1)
+        it = o.obj.find(fk.key);
+        if (it == o.obj.end()) continue;
         if (it->second.k != JVal::NUM) return false;
         const int r = (int)it->second.num;
         if (r != 0 && r != 1) return false;
-        t.oc_one_pass = r;
-    }
-    it = o.obj.find("fit_units");
-    if (it != o.obj.end()) {
-        if (it->second.k != JVal::NUM) return false;
-        const int r = (int)it->second.num;
-        if (r != 0 && r != 1) return false;
-        t.fit_units = r;
-    }
-    it = o.obj.find("fuse");
-    if (it != o.obj.end()) {
-        if (it->second.k != JVal::NUM) return false;
-        const int r = (int)it->second.num;
-        if (r != 0 && r != 1) return false;
-        t.fuse = r;
+        t.*fk.field = r;
     }
     it = o.obj.find("wide_rows");
     if (it != o.obj.end()) {
@@ -384,10 +385,11 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     // the horizontal pass direct or (wider windows, automatic or asked for) doubling
     // A horizontal vHGW asked for (single images, no tile, wx <= kStreamMaxWx) runs
     // across the lanes of the wave or streaming kernel (their XV forms); automatic
-    // large horizontal windows take doubling.
+    // large horizontal windows take doubling, or that vHGW where the tuning table says
+    // so (h_vhgw; the tall wave form has no XV form and keeps doubling).
     j.kind = KIND_TILE;
-    const bool lane_vhgw = j.hm == PASS_VHGW && mx == MORPH_METHOD_VHGW && !user_tile && !batch &&
-                           j.wx <= kStreamMaxWx;
+    const bool lane_vhgw = j.hm == PASS_VHGW && !user_tile && !batch && j.wx <= kStreamMaxWx &&
+                           (mx == MORPH_METHOD_VHGW || (mx == MORPH_METHOD_AUTO && tu.h_vhgw));
     const bool h_wave = (j.hm == PASS_DIRECT && j.wx <= kDirectMaxX) || j.hm == PASS_NONE ||
                         j.hm == PASS_DOUBLING ||
                         (j.hm == PASS_VHGW && mx == MORPH_METHOD_AUTO && j.wx <= kStreamMaxWx) ||
@@ -395,13 +397,16 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     if (j.vm == PASS_DIRECT && j.wy <= kDirectMaxTall && h_wave && !user_tile &&
         (my != MORPH_METHOD_VHGW)) {
         j.kind = KIND_WAVE;
-        if (j.hm == PASS_VHGW && !lane_vhgw) j.hm = PASS_DOUBLING;
+        if (j.hm == PASS_VHGW && !(lane_vhgw && j.wy <= kDirectMax)) j.hm = PASS_DOUBLING;
         j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
         // (a strip stores at most the quads whose input lies in its 64 quads,
         // stream_quads(wx) of them, whatever the horizontal pass)
         j.TW = 4 * strip_quads(W, stream_quads(j.wx));
-        j.TB = std::min(batch ? tu.batch_wave_rows : tu.wave_rows,
-                        (H + kWaveRows - 1) / kWaveRows * kWaveRows);
+        // (the tall form, a kernel of its own with fewer waves per SIMD, has a height
+        // of its own)
+        const int rows = j.wy > kDirectMax ? tu.wave_rows_tall
+                                           : (batch ? tu.batch_wave_rows : tu.wave_rows);
+        j.TB = std::min(rows, (H + kWaveRows - 1) / kWaveRows * kWaveRows);
         j.tiles_x = (W + j.TW - 1) / j.TW;
         if (!batch && tu.fit_units) j.TB = fit_rows(j.TB, H, j.tiles_x);
         j.tiles_y = (H + j.TB - 1) / j.TB;

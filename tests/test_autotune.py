@@ -29,3 +29,13 @@ def test_a_single_loss_in_the_noise_does_not_end_the_direct_range():
 def test_threshold_unordered_input():
     rows = _rows("x", {5: (1.0, 1.0), 2: (1.0, 1.0), 4: (1.0, 1.0), 3: (1.0, 1.0)})
     assert autotune.threshold(rows, "x") == 5
+
+
+def test_unit_height_least_worst_over_windows():
+    """A unit height is chosen by its worst time relative to the best height at each
+    window, so one window's large loss is not hidden by small gains elsewhere."""
+    res = [{"h": 8, "us": [10.0, 20.0, 30.0]},
+           {"h": 16, "us": [13.0, 19.0, 28.0]},   # sum 60 (least), but 30% worse at the first
+           {"h": 24, "us": [10.5, 19.5, 29.0]}]   # at most 5% worse anywhere
+    assert autotune.least_worst(res, "h") == 24
+    assert autotune.least_worst(res[:1], "h") == 8

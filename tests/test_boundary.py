@@ -317,6 +317,30 @@ def test_shipped_table_is_the_built_in_one():
         morph.load_tuning(None)
 
 
+def test_tuning_h_vhgw_routes_large_horizontal_windows(tmp_path):
+    """"h_vhgw": 1 sends single images' automatic large horizontal windows to the
+    paper's vHGW across the lanes (wave kernel's short form, streaming kernel); the tall
+    wave form and batches keep doubling; 0 (the default) is doubling everywhere."""
+    import json
+    import paper_2002_09474_amd as morph
+    f = tmp_path / "t.json"
+    try:
+        for flag, want in ((1, "vhgw"), (0, "doubling")):
+            f.write_text(json.dumps({"u8": {"h_vhgw": flag, "t_x": 9, "t_y": 31}}))
+            morph.load_tuning(str(f))
+            for wx, wy, kernel, mx in ((33, 3, "wave", want), (101, 1, "wave", want),
+                                       (45, 20, "wave", "doubling"), (63, 63, "stream", want),
+                                       (5, 5, "wave", "direct")):
+                p = morph.resolve_plan("u8", 150, 777, wx, wy)
+                assert (p["kernel"], p["method_x"]) == (kernel, mx), (flag, wx, wy, p)
+            assert morph.resolve_plan("u8", 150, 777, 33, 3, batch=True)["method_x"] == "doubling"
+        f.write_text(json.dumps({"u8": {"h_vhgw": 2}}))
+        with pytest.raises(morph.MorphError):
+            morph.load_tuning(str(f))
+    finally:
+        morph.load_tuning(None)
+
+
 def test_strerror():
     L = _lib.lib()
     for s in (0, -1, -2, -3, -4, -5):

@@ -467,3 +467,28 @@ def test_horizontal_vhgw_across_lanes(dtype):
         out = morph.apply("dilate", d, wx, 5, method_x="vhgw", method_y="vhgw")
         torch.cuda.synchronize()
         assert np.array_equal(to_host(out), _ref(img, "dilate", wx, 5)), wx
+
+
+def test_automatic_horizontal_vhgw_by_tuning_table(tmp_path):
+    """With "h_vhgw": 1 in the tuning table, single images' automatic large horizontal
+    windows run the paper's vHGW across the lanes (the wave kernel's short form and the
+    streaming kernel) and the tall wave form keeps doubling: plans and results against
+    the oracle; batches keep doubling."""
+    import json
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps({"u8": {"h_vhgw": 1}, "u16": {"h_vhgw": 1}}))
+    morph.load_tuning(str(f))
+    try:
+        for dtype in (np.uint8, np.uint16):
+            dn = "u8" if dtype == np.uint8 else "u16"
+            img = synth.uniform(150, 777, dtype, seed=52)
+            for wx, wy, kernel, mx in ((33, 3, "wave", "vhgw"), (101, 1, "wave", "vhgw"),
+                                       (45, 20, "wave", "doubling"), (63, 63, "stream", "vhgw"),
+                                       (5, 5, "wave", "direct")):
+                p = morph.resolve_plan(dn, 150, 777, wx, wy)
+                assert (p["kernel"], p["method_x"]) == (kernel, mx), (dn, wx, wy, p)
+                _check(img, "erode" if wx % 2 else "dilate", wx, wy)
+                _check(img, "dilate", wx, wy, 0, -1)
+            assert morph.resolve_plan(dn, 150, 777, 33, 3, batch=True)["method_x"] == "doubling"
+    finally:
+        morph.load_tuning(None)
