@@ -206,10 +206,12 @@ int morph_blackhat_u16(const void *src, void *dst, int H, int W, size_t pitch, i
                        hipStream_t stream);
 
 /* General entry: any op (MORPH_OP_*) and dtype (MORPH_U8 / MORPH_U16) with an
- * optional plan (NULL = tuned defaults).  workspace is needed only for OPEN,
- * CLOSE, TOPHAT and BLACKHAT, and for GRADIENT where its one-pass form does not
- * apply (see morph_gradient).  The named entry points above are this call with plan = NULL.
- * Batch descriptors take ERODE, DILATE, OPEN and CLOSE. */
+ * optional plan (NULL = tuned defaults).  workspace is needed only for OPEN, CLOSE,
+ * TOPHAT and BLACKHAT where the one-pass opening/closing does not apply (see
+ * morph_open; with a plan given they always take two launches through it), and for
+ * GRADIENT where its one-pass form does not apply (see morph_gradient).  The named
+ * entry points above are this call with plan = NULL.  Batch descriptors take ERODE,
+ * DILATE, OPEN and CLOSE. */
 int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch,
                 int wx, int wy, int anchor_x, int anchor_y, int border,
                 const morph_plan *plan, void *workspace, size_t ws_bytes, hipStream_t stream);
@@ -218,10 +220,11 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
  * tight serving loops, harnesses that forbid hipMalloc): morph_apply with the
  * workspace taken from a fixed device array of MORPH_STATIC_SCRATCH_BYTES bytes
  * that the library holds on each GPU it runs on until the process ends, so that
- * nothing is allocated on any call.  Every argument as for morph_apply.  The ops
- * that need a workspace there (OPEN, CLOSE, TOPHAT, BLACKHAT, and GRADIENT where
- * its one-pass form does not apply) need H * pitch <= MORPH_STATIC_SCRATCH_BYTES,
- * else MORPH_ENOMEM and nothing is enqueued; ERODE and DILATE use no workspace.
+ * nothing is allocated on any call.  Every argument as for morph_apply.  The calls
+ * that need a workspace there (OPEN, CLOSE, TOPHAT, BLACKHAT where the one-pass
+ * form does not apply, GRADIENT where its one-pass form does not apply) need
+ * H * pitch <= MORPH_STATIC_SCRATCH_BYTES, else MORPH_ENOMEM and nothing is
+ * enqueued; the others use no workspace.
  * All calls on one GPU share its array: calls whose work overlaps on the device
  * (other streams, other threads) race on it, so the caller serializes them, e.g.
  * on one stream.  The array's contents after a call are unspecified (every call
