@@ -61,7 +61,7 @@ class Plan(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("batch", ctypes.c_int32)]
 
 
-KERNEL_NAMES = {0: "tile", 1: "wave", 2: "stream", 3: "rows"}
+KERNEL_NAMES = {0: "tile", 1: "wave", 2: "stream", 3: "rows", 4: "stream_coop"}
 
 
 class Desc(ctypes.Structure):

@@ -21,9 +21,11 @@ Unit heights of batched images are then chosen on the whole 512-image batch of t
 benchmark (one key at a time), those of single images on 4096x4096 images (the wave
 kernel's over 3x3 and 9x9, its tall form's over 15x15 and 1x31, the streaming
 kernel's ring form at 15x15 with vHGW forced and its run-total form over 7x63,
-101x101 and 1x255, the one-pass opening's over 3x3 and 9x9 and at 15x15 -- each the
-height whose worst time over its windows, relative to the best height there, is
-least -- and whether the one-pass opening beats the two launches at all), the unit
+101x101 and 1x255, its cooperative form's over 7x63, 101x101, 1x155 and 1x255, the
+one-pass opening's over 3x3 and 9x9 and at 15x15 -- each the height whose worst time
+over its windows, relative to the best height there, is least -- then the vertical
+window from which the cooperative form beats the streaming kernel's own, and whether
+the one-pass opening beats the two launches at all), the unit
 height of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same
 images, and tile shapes of the tile kernel per window bucket.
 As in the benchmark, timed launches take turns over copies of their images that
@@ -57,6 +59,12 @@ SINGLE_KEYS = (("wave_rows", WAVE_ROWS, ((3, 3), (9, 9)), {}),
                ("wave_rows_tall", WAVE_ROWS, ((15, 15), (1, 31)), {}),
                ("stream_rows", STREAM_ROWS, ((15, 15),), {"method_y": "vhgw"}),
                ("stream_rows_runs", STREAM_ROWS_RUNS, ((7, 63), (101, 101), (1, 255)), {}))
+# the streaming kernel's cooperative form (single images, run-total windows): its unit
+# heights over its windows, then the vertical window from which it beats the
+# streaming kernel's own form (1 x wy at COOP_MIN)
+COOP_ROWS = (32, 48, 64, 96, 128)
+COOP_WINDOWS = ((7, 63), (101, 101), (1, 155), (1, 255))
+COOP_MIN = (33, 63, 101, 155, 255)
 # unit heights of batched images, timed on the whole benchmark batch
 BATCH_KEYS = (("batch_wave_rows", (16, 24, 32, 48)), ("batch_stream_rows", (32, 48, 64, 96)),
               ("batch_stream_rows_runs", (32, 48, 64)))
@@ -282,6 +290,35 @@ def best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, window
     return least_worst(res, key), res
 
 
+def coop_sweep(torch, morph, dname, srcs, dsts, base, iters=20, choices=COOP_ROWS,
+               windows=COOP_WINDOWS, mins=COOP_MIN, tol=0.03):
+    """The cooperative form's unit height (least worst over `windows`, the form taken
+    from wy 17), then coop_min_wy: the smallest swept wy (1 x wy) from which it is
+    never slower than the streaming kernel's own form by more than `tol` (0 if it loses
+    at the largest).  Returns (coop_rows, coop_min_wy, height table, threshold rows)."""
+    rows_best, table = best_single_rows(torch, morph, dname, srcs, dsts, "coop_rows", choices,
+                                        dict(base, coop_min_wy=17), windows, iters)
+    rows = []
+    for wy in mins:
+        t = {}
+        for name, m in (("stream", 0), ("coop", 17)):
+            _with_table(morph, {dname: dict(base, coop_min_wy=m, coop_rows=rows_best)})
+            k = [0]
+
+            def fn():
+                i = k[0] % len(srcs)
+                k[0] += 1
+                morph.apply("erode", srcs[i], 1, wy, out=dsts[i])
+            t[name] = sorted(_timer(torch, fn, iters) for _ in range(3))[1]
+        rows.append({"wy": wy, "stream_us": round(t["stream"], 3), "coop_us": round(t["coop"], 3)})
+    thr = 0
+    for r in reversed(rows):
+        if r["coop_us"] > r["stream_us"] * (1 + tol):
+            break
+        thr = r["wy"]
+    return rows_best, thr, table, rows
+
+
 def oc_rows_sweep(torch, morph, dname, srcs, dsts, key, choices, base, windows, iters=20):
     """The `key` (a unit height of the one-pass opening) among `choices` whose worst
     w x w opening time over `windows`, relative to the best choice there, is least; the
@@ -371,6 +408,7 @@ REDUCED = {"windows": {"x": (2, 3, 9, 12, 16), "y": (2, 3, 9, 15, 31)},
            "batch_keys": tuple((k, c[:2]) for k, c in BATCH_KEYS),
            "single_keys": tuple((k, c[:2], w[:1], kw) for k, c, w, kw in SINGLE_KEYS),
            "oc_keys": tuple((k, c[:2], w) for k, c, w in OC_KEYS),
+           "coop_rows": COOP_ROWS[:2], "coop_windows": ((1, 101),), "coop_min": (33, 101),
            "wide_rows": WIDE_ROWS[:2], "buckets": BUCKETS[:1], "tq": TQ[:2], "tb": TB[:2]}
 
 
@@ -442,6 +480,16 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
             base[key] = best
             _log("%s: %s %d" % (dname, key, best))
             result[dname + "_" + key + "_sweep"] = table
+        _with_table(morph, {dname: base})
+        cr, cmin, ctab, crows = coop_sweep(
+            torch, morph, dname, srcs, dsts, base, 3 if R else (8 if quick else 20),
+            choices=R["coop_rows"] if R else COOP_ROWS,
+            windows=R["coop_windows"] if R else COOP_WINDOWS,
+            mins=R["coop_min"] if R else COOP_MIN)
+        base.update(coop_rows=cr, coop_min_wy=cmin)
+        result[dname + "_coop_rows_sweep"] = ctab
+        result[dname + "_coop_threshold_sweep"] = crows
+        _log("%s: coop_rows %d, coop_min_wy %d" % (dname, cr, cmin))
         _with_table(morph, {dname: base})
         oc_it = 3 if R else (8 if quick else 20)
         for key, choices, ws in (R["oc_keys"] if R else OC_KEYS):

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libmorph_hip.so"
-SOURCES = ("k_fused_u8.hip", "k_fused_u16.hip", "k_tile.hip", "k_stream.hip", "k_wave.hip",
+SOURCES = ("k_fused_u8.hip", "k_fused_u16.hip", "k_tile.hip", "k_stream.hip", "k_stream_coop.hip", "k_wave.hip",
            "k_rows.hip", "k_wave_tall_u8.hip", "k_wave_tall_u16.hip", "morph_launch.hip", "morph_api.hip", "morph_transpose.hip",
            "morph_openclose.hip", "k_oc_u8.hip", "k_oc_u16.hip", "morph_static.hip")
 ARCH = os.environ.get("MORPH_OFFLOAD_ARCH", "gfx950")

@@ -63,6 +63,9 @@ struct DtypeTuning {
     // single images' automatic large horizontal windows: 0 = doubling across the lanes,
     // 1 = the paper's vHGW across the lanes (where a kernel has that form)
     int h_vhgw;
+    // single images on aligned rows with vertical vHGW in run totals and wy >= coop_min_wy
+    // (0: never) take the streaming kernel's cooperative form, units of coop_rows rows
+    int coop_min_wy, coop_rows;
 };
 
 std::mutex g_tuning_mu;
@@ -70,10 +73,10 @@ std::mutex g_tuning_mu;
 // the Python package): direct passes up to 9 along x (16 for uint16) and 31 along y on
 // single images, 9 and 9 for the images of a batch; unit heights and tile shapes.
 const DtypeTuning k_builtin_tuning[2] = {
-    {12, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 64, 32, 4,
-     1, 16, 96, 64, 1, 9, 9, 1, 16, 9, 48, 8, 0},
-    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 96, 64, 4,
-     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 48, 16, 0},
+    {12, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 48, 32}}, 8, 96, 32, 4,
+     1, 16, 48, 48, 1, 9, 9, 1, 16, 9, 48, 8, 0, 63, 96},
+    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 64, 64, 4,
+     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 48, 16, 0, 33, 96},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -188,6 +191,20 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         const int r = (int)it->second.num;
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
         t.*ck.field = r;
+    }
+    it = o.obj.find("coop_min_wy");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r < 0) return false;
+        t.coop_min_wy = r;
+    }
+    it = o.obj.find("coop_rows");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r < 8 || r > 1024 || r % 8) return false;
+        t.coop_rows = r;
     }
     it = o.obj.find("oc_t_x");
     if (it != o.obj.end()) {
@@ -365,6 +382,7 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     j.hcode = (j.hm == PASS_NONE) ? 1 : (j.hm == PASS_DIRECT ? j.wx : 0);
     j.SA = j.SB = 0;
     j.vrun = j.vtt = 0;
+    j.coop = 0;
 
     // wide windows along rows: the wide-row kernel (horizontal doubling, 16 pixels a
     // lane), unless a tile or the vHGW passes are asked for
@@ -434,6 +452,16 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
                                                : (batch ? tu.batch_stream_rows : tu.stream_rows),
                         H);
         if (!batch && tu.fit_units) j.TB = fit_rows(j.TB, H, j.tiles_x);
+        // single images with tall vertical windows on aligned rows: the cooperative
+        // form, whose taller units re-read fewer halo rows with as many waves
+        if (!batch && tu.coop_min_wy > 0 && j.wy >= tu.coop_min_wy && stream_two_level(j.wy) &&
+            j.hm != PASS_VHGW && rows_aligned(j)) {
+            TileJob c = j;
+            c.coop = 1;
+            c.TB = std::min(tu.coop_rows, (H + 7) / 8 * 8);
+            if (tu.fit_units) c.TB = fit_rows(c.TB, H, c.tiles_x * kCoopWaves);
+            if (coop_lds_bytes(c) <= kCoopMaxLds) j = c;
+        }
         j.tiles_y = (H + j.TB - 1) / j.TB;
         if ((int64_t)j.tiles_x * j.tiles_y > INT32_MAX - 4) return MORPH_EUNSUPPORTED;
         return MORPH_OK;
@@ -783,7 +811,8 @@ int morph_resolve_plan(int dtype, int H, int W, int wx, int wy, morph_plan *plan
                                  : (j.vm == PASS_DIRECT ? MORPH_METHOD_DIRECT : MORPH_METHOD_VHGW);
     plan->tile_w = j.TW;
     plan->tile_h = j.TB;
-    plan->kernel = j.kind; // KernelKind values are the MORPH_KERNEL_* codes
+    // (KernelKind values are the MORPH_KERNEL_* codes)
+    plan->kernel = j.coop ? MORPH_KERNEL_STREAM_COOP : j.kind;
     return MORPH_OK;
 }
 

@@ -71,6 +71,7 @@ struct TileJob {
     int32_t kind;    // KernelKind
     int32_t op;      // 0 erode, 1 dilate
     int32_t dtype;   // 0 u8, 1 u16
+    int32_t coop;    // KIND_STREAM: 1 = the cooperative form (kCoopWaves waves a unit)
 };
 
 inline int lds_bytes(const TileJob &j)
@@ -97,6 +98,22 @@ hipError_t launch_wave_kernel(const TileJob &job, hipStream_t stream);
 hipError_t launch_wave_tall_kernel(const TileJob &job, hipStream_t stream);
 inline bool wave_tall(const TileJob &j) { return j.kind == KIND_WAVE && j.wy > kDirectMax; }
 hipError_t launch_stream_kernel(const TileJob &job, hipStream_t stream);
+// the streaming kernel's cooperative form (k_stream_coop.hip): single images, rows
+// aligned, vertical vHGW in run totals; a workgroup of kCoopWaves waves per unit of TB
+// output rows builds the unit's run totals, their scans and the output runs side by
+// side.  LDS: the unit's run totals, then S and P of each block (entries of 64 lanes x
+// 4 bytes for uint8, 8 for uint16).
+constexpr int kCoopWaves = 4;
+constexpr int kCoopMaxLds = 64 * 1024;
+inline int coop_lds_bytes(const TileJob &j)
+{
+    const int rows = j.TB < j.H ? j.TB : j.H;
+    const int nr = stream_runs(j.wy), bmax = (rows - 1) / j.wy;
+    const int tail = rows + j.wy - 1 - (bmax + 1) * j.wy;
+    const int n_runs = (bmax + 1) * nr + (nr < (tail + 7) / 8 ? nr : (tail + 7) / 8);
+    return (n_runs + 2 * (bmax + 1) * (nr + 1)) * 64 * (j.dtype ? 8 : 4);
+}
+hipError_t launch_stream_coop(const TileJob &job, hipStream_t stream);
 hipError_t launch_rows_kernel(const TileJob &job, hipStream_t stream);
 // the morphological gradient of a wave-kernel job (kind KIND_WAVE, rows aligned):
 // both extrema from one read, their difference stored

@@ -8,7 +8,8 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
 {
     switch (job.kind) {
     case KIND_ROWS: return launch_rows_kernel(job, stream);
-    case KIND_STREAM: return launch_stream_kernel(job, stream);
+    case KIND_STREAM: return job.coop ? launch_stream_coop(job, stream)
+                                      : launch_stream_kernel(job, stream);
     case KIND_WAVE: return wave_tall(job) ? launch_wave_tall_kernel(job, stream)
                                           : launch_wave_kernel(job, stream);
     default: return launch_tile_kernel(job, stream);

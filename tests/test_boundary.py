@@ -147,7 +147,7 @@ def test_forced_direct_plans_past_the_compiled_windows():
 # measurement and may change): unit heights and thresholds of its own.
 PLAN_TABLE = {"t_x": 9, "t_y": 9, "wave_rows": 24, "stream_rows": 48, "stream_rows_runs": 32,
               "wide_rows": 4, "batch_wave_rows": 32, "batch_stream_rows": 48,
-              "batch_stream_rows_runs": 48, "batch_t_x": 9, "batch_t_y": 9,
+              "batch_stream_rows_runs": 48, "batch_t_x": 9, "batch_t_y": 9, "coop_min_wy": 0,
               "tiles": [{"wmax": 9, "tq": 32, "tb": 64}, {"wmax": 16, "tq": 32, "tb": 64},
                         {"wmax": 64, "tq": 48, "tb": 64}, {"wmax": 1 << 30, "tq": 64, "tb": 64}]}
 
@@ -337,6 +337,44 @@ def test_tuning_h_vhgw_routes_large_horizontal_windows(tmp_path):
         f.write_text(json.dumps({"u8": {"h_vhgw": 2}}))
         with pytest.raises(morph.MorphError):
             morph.load_tuning(str(f))
+    finally:
+        morph.load_tuning(None)
+
+
+def test_tuning_routes_tall_vertical_windows_to_the_cooperative_form(tmp_path):
+    """coop_min_wy / coop_rows: single images on aligned rows whose vertical pass is
+    vHGW in run totals take the streaming kernel's cooperative form from coop_min_wy,
+    with units of coop_rows rows (shorter on small images); batches, rows of odd pitch,
+    windows under coop_min_wy and units whose LDS would pass 64 KB keep the streaming
+    kernel; 0 turns it off."""
+    import json
+    import paper_2002_09474_amd as morph
+    f = tmp_path / "t.json"
+    try:
+        f.write_text(json.dumps({"u8": {"coop_min_wy": 64, "coop_rows": 96, "t_y": 31},
+                                 "u16": {"coop_min_wy": 17, "coop_rows": 512, "t_y": 16,
+                                         "fit_units": 0}}))
+        morph.load_tuning(str(f))
+        p = morph.resolve_plan("u8", 4096, 4096, 1, 255)
+        assert (p["kernel"], p["tile_h"]) == ("stream_coop", 96)
+        assert morph.resolve_plan("u8", 4096, 4096, 101, 101)["kernel"] == "stream_coop"
+        assert morph.resolve_plan("u8", 4096, 4096, 7, 63)["kernel"] == "stream"  # under 64
+        assert morph.resolve_plan("u8", 4096, 4096, 1, 255, batch=True)["kernel"] == "stream"
+        assert morph.resolve_plan("u8", 4096, 4095, 1, 255)["kernel"] == "stream"  # odd pitch
+        assert morph.resolve_plan("u8", 4096, 4096, 5, 255, method_x="vhgw")["kernel"] == "stream"
+        # uint16 units of 512 rows would need over 64 KB of LDS at wy 17
+        assert morph.resolve_plan("u16", 4096, 4096, 1, 17)["kernel"] == "stream"
+        assert morph.resolve_plan("u16", 4096, 4096, 1, 255)["kernel"] == "stream"
+        f.write_text(json.dumps({"u16": {"coop_rows": 64}}))
+        morph.load_tuning(str(f))
+        assert morph.resolve_plan("u16", 4096, 4096, 1, 17)["kernel"] == "stream_coop"
+        f.write_text(json.dumps({"u8": {"coop_min_wy": 0}}))
+        morph.load_tuning(str(f))
+        assert morph.resolve_plan("u8", 4096, 4096, 1, 255)["kernel"] == "stream"
+        for bad in ({"coop_rows": 12}, {"coop_rows": 2048}, {"coop_min_wy": -1}):
+            f.write_text(json.dumps({"u8": bad}))
+            with pytest.raises(morph.MorphError):
+                morph.load_tuning(str(f))
     finally:
         morph.load_tuning(None)
 

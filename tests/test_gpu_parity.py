@@ -492,3 +492,36 @@ def test_automatic_horizontal_vhgw_by_tuning_table(tmp_path):
             assert morph.resolve_plan(dn, 150, 777, 33, 3, batch=True)["method_x"] == "doubling"
     finally:
         morph.load_tuning(None)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_streaming_cooperative_form(dtype, tmp_path):
+    """The streaming kernel's cooperative form (four waves share a unit: run totals,
+    their scans and the output runs side by side), routed by the tuning table from
+    vertical window 17: every vertical window form it meets (several blocks a unit, a
+    block longer than the unit, windows not a multiple of 8, windows larger than the
+    image), units of 8 to 256 rows, horizontal windows none / direct / doubling,
+    anchors at both ends, ragged images; against the oracle.  (Vertical windows past
+    16 take vHGW here, so that 17..31 reach it too.)"""
+    import json
+    dn = "u8" if dtype == np.uint8 else "u16"
+    f = tmp_path / "t.json"
+    rng = np.random.default_rng(71)
+    try:
+        for rows in (8, 64, 256):
+            f.write_text(json.dumps({dn: {"coop_min_wy": 17, "coop_rows": rows,
+                                          "fit_units": 0, "t_y": 16}}))
+            morph.load_tuning(str(f))
+            for H, W in ((301, 776), (1000, 332), (40, 1032)):  # (rows aligned)
+                img = synth.uniform(H, W, dtype, seed=H + W + rows)
+                for wy in (17, 24, 31, 33, 64, 101, 200, 256):
+                    wx = int(rng.choice([1, 3, 9, 15, 31, 101]))
+                    p = morph.resolve_plan(dn, H, W, wx, wy)
+                    # (uint16 units of 256 rows can need more than the form's 64 KB of
+                    # LDS: those keep the streaming kernel)
+                    if wy <= H and (dn == "u8" or rows <= 64):
+                        assert p["kernel"] == "stream_coop", (H, W, wx, wy, p)
+                    ay = int(rng.choice([-1, 0, wy - 1]))
+                    _check(img, "erode" if wy % 2 else "dilate", wx, wy, -1, ay)
+    finally:
+        morph.load_tuning(None)
