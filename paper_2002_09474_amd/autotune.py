@@ -18,14 +18,14 @@ and the paper's vHGW, are timed against each other (h_vhgw).
 The thresholds of batched images are then chosen on the whole benchmark batch
 (direct passes that leave the fused dispatch can cost it more than they save).
 Unit heights of batched images are then chosen on the whole 512-image batch of the
-benchmark (one key at a time), those of single images on 4096x4096 images (the wave
+benchmark (one key at a time), those of single images on 4096x4096 images: the wave
 kernel's over 3x3 and 9x9, its tall form's over 15x15 and 1x31, the streaming
 kernel's ring form at 15x15 with vHGW forced and its run-total form over 7x63,
-101x101 and 1x255, its cooperative form's over 7x63, 101x101, 1x155 and 1x255, the
-one-pass opening's over 3x3 and 9x9 and at 15x15 -- each the height whose worst time
-over its windows, relative to the best height there, is least -- then the vertical
-window from which the cooperative form beats the streaming kernel's own, and whether
-the one-pass opening beats the two launches at all), the unit
+101x101 and 1x255, its cooperative form's (with its waves a unit) over 7x63, 101x101,
+1x155 and 1x255, the one-pass opening's over 3x3 and 9x9 and at 15x15 -- each the
+height whose worst time over its windows, relative to the best height there, is
+least.  Then the vertical window from which the cooperative form beats the streaming
+kernel's own, whether the one-pass opening beats the two launches at all, the unit
 height of the wide-row kernel (uint8, vertical window 1, wx > 128) on the same
 images, and tile shapes of the tile kernel per window bucket.
 As in the benchmark, timed launches take turns over copies of their images that
@@ -62,7 +62,8 @@ SINGLE_KEYS = (("wave_rows", WAVE_ROWS, ((3, 3), (9, 9)), {}),
 # the streaming kernel's cooperative form (single images, run-total windows): its unit
 # heights over its windows, then the vertical window from which it beats the
 # streaming kernel's own form (1 x wy at COOP_MIN)
-COOP_ROWS = (32, 48, 64, 96, 128)
+COOP_ROWS = (48, 64, 96, 128, 192)
+COOP_WAVES = (4, 8, 16)
 COOP_WINDOWS = ((7, 63), (101, 101), (1, 155), (1, 255))
 COOP_MIN = (33, 63, 101, 155, 255)
 # unit heights of batched images, timed on the whole benchmark batch
@@ -292,17 +293,25 @@ def best_single_rows(torch, morph, dname, srcs, dsts, key, choices, base, window
 
 def coop_sweep(torch, morph, dname, srcs, dsts, base, iters=20, choices=COOP_ROWS,
                windows=COOP_WINDOWS, mins=COOP_MIN, tol=0.03):
-    """The cooperative form's unit height (least worst over `windows`, the form taken
-    from wy 17), then coop_min_wy: the smallest swept wy (1 x wy) from which it is
-    never slower than the streaming kernel's own form by more than `tol` (0 if it loses
-    at the largest).  Returns (coop_rows, coop_min_wy, height table, threshold rows)."""
-    rows_best, table = best_single_rows(torch, morph, dname, srcs, dsts, "coop_rows", choices,
-                                        dict(base, coop_min_wy=17), windows, iters)
+    """The cooperative form's waves a unit and unit height (the pair least worst over
+    `windows`, the form taken from wy 17), then coop_min_wy: the smallest swept wy
+    (1 x wy) from which it is never slower than the streaming kernel's own form by more
+    than `tol` (0 if it loses at the largest).  Returns (coop_waves, coop_rows,
+    coop_min_wy, height table, threshold rows)."""
+    table = []
+    for nw in COOP_WAVES:
+        _, t = best_single_rows(torch, morph, dname, srcs, dsts, "coop_rows", choices,
+                                dict(base, coop_min_wy=17, coop_waves=nw), windows, iters)
+        table += [dict(r, coop_waves=nw, coop=(nw, r["coop_rows"])) for r in t]
+    waves_best, rows_best = least_worst(table, "coop")
+    for r in table:
+        del r["coop"]
     rows = []
     for wy in mins:
         t = {}
         for name, m in (("stream", 0), ("coop", 17)):
-            _with_table(morph, {dname: dict(base, coop_min_wy=m, coop_rows=rows_best)})
+            _with_table(morph, {dname: dict(base, coop_min_wy=m, coop_rows=rows_best,
+                                            coop_waves=waves_best)})
             k = [0]
 
             def fn():
@@ -316,7 +325,7 @@ def coop_sweep(torch, morph, dname, srcs, dsts, base, iters=20, choices=COOP_ROW
         if r["coop_us"] > r["stream_us"] * (1 + tol):
             break
         thr = r["wy"]
-    return rows_best, thr, table, rows
+    return waves_best, rows_best, thr, table, rows
 
 
 def oc_rows_sweep(torch, morph, dname, srcs, dsts, key, choices, base, windows, iters=20):
@@ -481,15 +490,15 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
             _log("%s: %s %d" % (dname, key, best))
             result[dname + "_" + key + "_sweep"] = table
         _with_table(morph, {dname: base})
-        cr, cmin, ctab, crows = coop_sweep(
+        cw, cr, cmin, ctab, crows = coop_sweep(
             torch, morph, dname, srcs, dsts, base, 3 if R else (8 if quick else 20),
             choices=R["coop_rows"] if R else COOP_ROWS,
             windows=R["coop_windows"] if R else COOP_WINDOWS,
             mins=R["coop_min"] if R else COOP_MIN)
-        base.update(coop_rows=cr, coop_min_wy=cmin)
+        base.update(coop_waves=cw, coop_rows=cr, coop_min_wy=cmin)
         result[dname + "_coop_rows_sweep"] = ctab
         result[dname + "_coop_threshold_sweep"] = crows
-        _log("%s: coop_rows %d, coop_min_wy %d" % (dname, cr, cmin))
+        _log("%s: coop_waves %d, coop_rows %d, coop_min_wy %d" % (dname, cw, cr, cmin))
         _with_table(morph, {dname: base})
         oc_it = 3 if R else (8 if quick else 20)
         for key, choices, ws in (R["oc_keys"] if R else OC_KEYS):

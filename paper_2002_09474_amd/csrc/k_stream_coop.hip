@@ -1,6 +1,6 @@
 // The streaming kernel's cooperative form: vertical vHGW (§5.1.1) for single images
-// with large vertical windows, kCoopWaves waves of one workgroup sharing a unit of TB
-// output rows of one strip.
+// with large vertical windows, the NW waves of one workgroup (4, 8 or 16) sharing a unit of
+// TB output rows of one strip.
 //
 // With the input rows of the unit numbered from its first one (gy0 = y0 - ay) and cut
 // into blocks of wy rows, each block into runs of kStreamChunk rows, output row i
@@ -24,11 +24,10 @@ namespace morph {
 
 static_assert(kStreamChunk == SD && SD == 8, "runs of 8 rows");
 
-template <typename T, bool MAXOP>
-__global__ __launch_bounds__(NT) void stream_coop_kernel(TileJob J)
+template <typename T, bool MAXOP, int NW>
+__global__ __launch_bounds__(64 * NW) void stream_coop_kernel(TileJob J)
 {
     extern __shared__ uint32_t lds[];
-    static_assert(NT == 64 * kCoopWaves, "one workgroup of kCoopWaves waves per unit");
     const int unit = xcd_tile(blockIdx.x, gridDim.x);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -68,13 +67,13 @@ __global__ __launch_bounds__(NT) void stream_coop_kernel(TileJob J)
     auto run_rows = [&](int g) { return min(SD, wy - SD * (g % nr)); };
     auto run_start = [&](int g) { return (g / nr) * wy + SD * (g % nr); };
 
-    // 1. run totals: the wave's runs w, w + kCoopWaves, ..., the next one's loads in
+    // 1. run totals: the wave's runs w, w + NW, ..., the next one's loads in
     // flight while one is reduced
     {
         typename WaveLoader<T>::Raw ba[SD], bb[SD];
         auto total = [&](typename WaveLoader<T>::Raw(&cur)[SD], typename WaveLoader<T>::Raw(&nxt)[SD],
                          int g) __attribute__((always_inline)) -> bool {
-            const int gn = g + kCoopWaves;
+            const int gn = g + NW;
             if (gn < n_runs) issue8(nxt, run_start(gn));
             const int len = run_rows(g);
             uint32_t a01, a23;
@@ -94,7 +93,7 @@ __global__ __launch_bounds__(NT) void stream_coop_kernel(TileJob J)
         int g = wave;
         if (g < n_runs) {
             issue8(ba, run_start(g));
-            while (total(ba, bb, g) && total(bb, ba, g + kCoopWaves)) g += 2 * kCoopWaves;
+            while (total(ba, bb, g) && total(bb, ba, g + NW)) g += 2 * NW;
         }
     }
     __syncthreads();
@@ -102,7 +101,7 @@ __global__ __launch_bounds__(NT) void stream_coop_kernel(TileJob J)
     // 2. scans: S_b for b = 0 .. bmax, then P_{b+1} for b = 0 .. bmax, one a wave; the
     // run totals read SD at a time (independent LDS reads in flight together), then
     // folded in order
-    for (int q = wave; q < 2 * (bmax + 1); q += kCoopWaves) {
+    for (int q = wave; q < 2 * (bmax + 1); q += NW) {
         uint32_t a01 = id, a23 = id;
         if (q <= bmax) { // S_q[r] = op of runs r .. nr - 1 of block q
             const int b = q;
@@ -153,7 +152,7 @@ __global__ __launch_bounds__(NT) void stream_coop_kernel(TileJob J)
         (void *)J.dst, (short)0, (int)(uint32_t)min(dspan, (uint64_t)0xffffffffu), kBufferWord3);
     const uint32_t dvoff = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
     const int n_out = (bmax + 1) * nr;
-    for (int g = wave; g < n_out; g += kCoopWaves) {
+    for (int g = wave; g < n_out; g += NW) {
         const int i0 = run_start(g); // first output row of the run
         if (i0 >= rows) continue;
         const int b = g / nr, r = g % nr;
@@ -220,16 +219,24 @@ __global__ __launch_bounds__(NT) void stream_coop_kernel(TileJob J)
     }
 }
 
+template <int NW> static TileKernelFn pick_coop(const TileJob &job)
+{
+    return job.dtype == 0 ? (job.op ? stream_coop_kernel<uint8_t, true, NW>
+                                    : stream_coop_kernel<uint8_t, false, NW>)
+                          : (job.op ? stream_coop_kernel<uint16_t, true, NW>
+                                    : stream_coop_kernel<uint16_t, false, NW>);
+}
+
 hipError_t launch_stream_coop(const TileJob &job, hipStream_t stream)
 {
-    const TileKernelFn fn = job.dtype == 0 ? (job.op ? stream_coop_kernel<uint8_t, true>
-                                                     : stream_coop_kernel<uint8_t, false>)
-                                           : (job.op ? stream_coop_kernel<uint16_t, true>
-                                                     : stream_coop_kernel<uint16_t, false>);
+    if (job.coop != 4 && job.coop != 8 && job.coop != 16) return hipErrorInvalidValue;
+    const TileKernelFn fn = job.coop == 16 ? pick_coop<16>(job)
+                          : job.coop == 8  ? pick_coop<8>(job)
+                                           : pick_coop<4>(job);
     const int lds = coop_lds_bytes(job);
     hipError_t e = set_lds_limit((const void *)fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(job.tiles_x * job.tiles_y), dim3(NT), lds, stream, job);
+    hipLaunchKernelGGL(fn, dim3(job.tiles_x * job.tiles_y), dim3(64 * job.coop), lds, stream, job);
     return hipGetLastError();
 }
 

@@ -65,7 +65,8 @@ struct DtypeTuning {
     int h_vhgw;
     // single images on aligned rows with vertical vHGW in run totals and wy >= coop_min_wy
     // (0: never) take the streaming kernel's cooperative form, units of coop_rows rows
-    int coop_min_wy, coop_rows;
+    // shared by coop_waves waves (4, 8 or 16)
+    int coop_min_wy, coop_rows, coop_waves;
 };
 
 std::mutex g_tuning_mu;
@@ -74,9 +75,9 @@ std::mutex g_tuning_mu;
 // single images, 9 and 9 for the images of a batch; unit heights and tile shapes.
 const DtypeTuning k_builtin_tuning[2] = {
     {12, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 48, 32}}, 8, 96, 32, 4,
-     1, 16, 48, 48, 1, 9, 9, 1, 16, 9, 48, 8, 0, 63, 96},
-    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 16, 32}}, 8, 64, 64, 4,
-     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 48, 16, 0, 33, 96},
+     1, 16, 48, 64, 1, 9, 9, 1, 16, 9, 48, 8, 0, 33, 96, 8},
+    {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 48, 32}}, 8, 64, 24, 4,
+     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 48, 16, 0, 33, 96, 8},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -205,6 +206,13 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         const int r = (int)it->second.num;
         if (r < 8 || r > 1024 || r % 8) return false;
         t.coop_rows = r;
+    }
+    it = o.obj.find("coop_waves");
+    if (it != o.obj.end()) {
+        if (it->second.k != JVal::NUM) return false;
+        const int r = (int)it->second.num;
+        if (r != 4 && r != 8 && r != 16) return false;
+        t.coop_waves = r;
     }
     it = o.obj.find("oc_t_x");
     if (it != o.obj.end()) {
@@ -457,9 +465,9 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
         if (!batch && tu.coop_min_wy > 0 && j.wy >= tu.coop_min_wy && stream_two_level(j.wy) &&
             j.hm != PASS_VHGW && rows_aligned(j)) {
             TileJob c = j;
-            c.coop = 1;
+            c.coop = tu.coop_waves;
             c.TB = std::min(tu.coop_rows, (H + 7) / 8 * 8);
-            if (tu.fit_units) c.TB = fit_rows(c.TB, H, c.tiles_x * kCoopWaves);
+            if (tu.fit_units) c.TB = fit_rows(c.TB, H, c.tiles_x * c.coop);
             if (coop_lds_bytes(c) <= kCoopMaxLds) j = c;
         }
         j.tiles_y = (H + j.TB - 1) / j.TB;

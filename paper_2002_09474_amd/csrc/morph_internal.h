@@ -71,7 +71,7 @@ struct TileJob {
     int32_t kind;    // KernelKind
     int32_t op;      // 0 erode, 1 dilate
     int32_t dtype;   // 0 u8, 1 u16
-    int32_t coop;    // KIND_STREAM: 1 = the cooperative form (kCoopWaves waves a unit)
+    int32_t coop;    // KIND_STREAM: 0, or the cooperative form's waves a unit (4, 8, 16)
 };
 
 inline int lds_bytes(const TileJob &j)
@@ -99,11 +99,10 @@ hipError_t launch_wave_tall_kernel(const TileJob &job, hipStream_t stream);
 inline bool wave_tall(const TileJob &j) { return j.kind == KIND_WAVE && j.wy > kDirectMax; }
 hipError_t launch_stream_kernel(const TileJob &job, hipStream_t stream);
 // the streaming kernel's cooperative form (k_stream_coop.hip): single images, rows
-// aligned, vertical vHGW in run totals; a workgroup of kCoopWaves waves per unit of TB
-// output rows builds the unit's run totals, their scans and the output runs side by
-// side.  LDS: the unit's run totals, then S and P of each block (entries of 64 lanes x
-// 4 bytes for uint8, 8 for uint16).
-constexpr int kCoopWaves = 4;
+// aligned, vertical vHGW in run totals; a workgroup of j.coop waves (4, 8, 16) per unit
+// of TB output rows builds the unit's run totals, their scans and the output runs
+// side by side.  LDS: the unit's run totals, then S and P of each block (entries of 64
+// lanes x 4 bytes for uint8, 8 for uint16).
 constexpr int kCoopMaxLds = 64 * 1024;
 inline int coop_lds_bytes(const TileJob &j)
 {

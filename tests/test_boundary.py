@@ -371,7 +371,7 @@ def test_tuning_routes_tall_vertical_windows_to_the_cooperative_form(tmp_path):
         f.write_text(json.dumps({"u8": {"coop_min_wy": 0}}))
         morph.load_tuning(str(f))
         assert morph.resolve_plan("u8", 4096, 4096, 1, 255)["kernel"] == "stream"
-        for bad in ({"coop_rows": 12}, {"coop_rows": 2048}, {"coop_min_wy": -1}):
+        for bad in ({"coop_rows": 12}, {"coop_rows": 2048}, {"coop_min_wy": -1}, {"coop_waves": 5}):
             f.write_text(json.dumps({"u8": bad}))
             with pytest.raises(morph.MorphError):
                 morph.load_tuning(str(f))

@@ -496,7 +496,7 @@ def test_automatic_horizontal_vhgw_by_tuning_table(tmp_path):
 
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 def test_streaming_cooperative_form(dtype, tmp_path):
-    """The streaming kernel's cooperative form (four waves share a unit: run totals,
+    """The streaming kernel's cooperative form (4 to 16 waves share a unit: run totals,
     their scans and the output runs side by side), routed by the tuning table from
     vertical window 17: every vertical window form it meets (several blocks a unit, a
     block longer than the unit, windows not a multiple of 8, windows larger than the
@@ -508,9 +508,9 @@ def test_streaming_cooperative_form(dtype, tmp_path):
     f = tmp_path / "t.json"
     rng = np.random.default_rng(71)
     try:
-        for rows in (8, 64, 256):
+        for rows, waves in ((8, 4), (64, 8), (256, 4), (96, 8), (192, 16)):
             f.write_text(json.dumps({dn: {"coop_min_wy": 17, "coop_rows": rows,
-                                          "fit_units": 0, "t_y": 16}}))
+                                          "coop_waves": waves, "fit_units": 0, "t_y": 16}}))
             morph.load_tuning(str(f))
             for H, W in ((301, 776), (1000, 332), (40, 1032)):  # (rows aligned)
                 img = synth.uniform(H, W, dtype, seed=H + W + rows)
@@ -519,7 +519,7 @@ def test_streaming_cooperative_form(dtype, tmp_path):
                     p = morph.resolve_plan(dn, H, W, wx, wy)
                     # (uint16 units of 256 rows can need more than the form's 64 KB of
                     # LDS: those keep the streaming kernel)
-                    if wy <= H and (dn == "u8" or rows <= 64):
+                    if wy <= H and (dn == "u8" or rows <= 96):
                         assert p["kernel"] == "stream_coop", (H, W, wx, wy, p)
                     ay = int(rng.choice([-1, 0, wy - 1]))
                     _check(img, "erode" if wy % 2 else "dilate", wx, wy, -1, ay)
