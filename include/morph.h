@@ -115,8 +115,8 @@ typedef struct morph_plan {
 #define MORPH_KERNEL_STREAM 2 /* one wave per strip streaming down the rows */
 #define MORPH_KERNEL_ROWS 3   /* wy = 1, wide wx: one wave per strip, 16 pixels a lane */
 #define MORPH_KERNEL_STREAM_COOP 4 /* the streaming kernel's cooperative form: 4 to 16
-                                      waves share a unit (single images, tall vertical
-                                      windows; reported by morph_resolve_plan) */
+                                      waves share a unit (tall vertical windows;
+                                      reported by morph_resolve_plan) */
 
 /* Erosion, uint8 (§2 Eq. (1)).  See the conventions above for every argument. */
 int morph_erode(const void *src, void *dst, int H, int W, size_t pitch, int wx, int wy,
@@ -374,6 +374,9 @@ int morph_transpose_blocks(const void *src, void *dst, int64_t n_blocks, int dty
  *                       kernel's cooperative form (0: never)
  *   coop_rows           output rows of its units (a multiple of 8, 8 .. 1024)
  *   coop_waves          waves sharing one of its units (4, 8 or 16)
+ *   batch_coop_min_wy, batch_coop_rows, batch_coop_waves  the same three for the
+ *                       images of a batch (their cooperative units run as a dispatch
+ *                       of their own; 0: never)
  *   fit_units           0 / 1: a single image, or a batch, whose wave and streaming
  *                       units would number under about 2048 gets shorter ones (in
  *                       steps of 8 rows, no fewer than 8; a batch only while its tile

@@ -18,7 +18,8 @@ and the paper's vHGW, are timed against each other (h_vhgw).
 The thresholds of batched images are then chosen on the whole benchmark batch
 (direct passes that leave the fused dispatch can cost it more than they save).
 Unit heights of batched images are then chosen on the whole 512-image batch of the
-benchmark (one key at a time), those of single images on 4096x4096 images: the wave
+benchmark (one key at a time; then whether its run-total streaming units should take
+the cooperative form), those of single images on 4096x4096 images: the wave
 kernel's over 3x3 and 9x9, its tall form's over 15x15 and 1x31, the streaming
 kernel's ring form at 15x15 with vHGW forced and its run-total form over 7x63,
 101x101 and 1x255, its cooperative form's (with its waves a unit) over 7x63, 101x101,
@@ -475,6 +476,19 @@ def _tune(torch, morph, synth, dev, out_path, quick, reduced):
             base[key] = best
             _log("%s: %s %d" % (dname, key, best))
             result[dname + "_" + key + "_sweep"] = table
+        # the run-total streaming units in the cooperative form (a dispatch of their own)
+        # against the fused dispatch: on or off
+        bc = []
+        for cmin in (0, 17):
+            t = dict(base, batch_coop_min_wy=cmin, batch_coop_rows=64, batch_coop_waves=4)
+            _with_table(morph, {dname: t})
+            bc.append({"batch_coop_min_wy": cmin,
+                       "us": round(_time_batches(torch, morph, copies, it), 2)})
+        base["batch_coop_min_wy"] = min(bc, key=lambda r: r["us"])["batch_coop_min_wy"]
+        if base["batch_coop_min_wy"]:
+            base.update(batch_coop_rows=64, batch_coop_waves=4)
+        result[dname + "_batch_coop_check"] = bc
+        _log("%s: batch_coop_min_wy %d" % (dname, base["batch_coop_min_wy"]))
         del copies
         _with_table(morph, {dname: base})
         g = torch.Generator(device=dev).manual_seed(3)

@@ -25,10 +25,8 @@ namespace morph {
 static_assert(kStreamChunk == SD && SD == 8, "runs of 8 rows");
 
 template <typename T, bool MAXOP, int NW>
-__global__ __launch_bounds__(64 * NW) void stream_coop_kernel(TileJob J)
+__device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uint32_t *lds)
 {
-    extern __shared__ uint32_t lds[];
-    const int unit = xcd_tile(blockIdx.x, gridDim.x);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int sx = unit % J.tiles_x, sy = unit / J.tiles_x;
@@ -219,6 +217,27 @@ __global__ __launch_bounds__(64 * NW) void stream_coop_kernel(TileJob J)
     }
 }
 
+template <typename T, bool MAXOP, int NW>
+__global__ __launch_bounds__(64 * NW) void stream_coop_kernel(TileJob J)
+{
+    extern __shared__ uint32_t lds[];
+    stream_coop_body<T, MAXOP, NW>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+// The batch form: one workgroup of NW waves per unit of the group's jobs.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void batch_coop_kernel(BatchTables bt)
+{
+    extern __shared__ uint32_t lds[];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= bt.n_tiles) return; // (the whole workgroup leaves)
+    const int jb = bt.tile_job[t];
+    const TileJob J = bt.jobs[jb];
+    const int u = (int)(t - bt.tile_start[jb]);
+    if (J.op) stream_coop_body<T, true, NW>(J, u, lds);
+    else stream_coop_body<T, false, NW>(J, u, lds);
+}
+
 template <int NW> static TileKernelFn pick_coop(const TileJob &job)
 {
     return job.dtype == 0 ? (job.op ? stream_coop_kernel<uint8_t, true, NW>
@@ -237,6 +256,21 @@ hipError_t launch_stream_coop(const TileJob &job, hipStream_t stream)
     hipError_t e = set_lds_limit((const void *)fn, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(job.tiles_x * job.tiles_y), dim3(64 * job.coop), lds, stream, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_coop(const BatchTables &t, int dtype, int waves, int grid, int lds,
+                             hipStream_t stream)
+{
+    typedef void (*BatchFn)(BatchTables);
+    BatchFn fn;
+    if (waves == 16) fn = dtype == 0 ? batch_coop_kernel<uint8_t, 16> : batch_coop_kernel<uint16_t, 16>;
+    else if (waves == 8) fn = dtype == 0 ? batch_coop_kernel<uint8_t, 8> : batch_coop_kernel<uint16_t, 8>;
+    else if (waves == 4) fn = dtype == 0 ? batch_coop_kernel<uint8_t, 4> : batch_coop_kernel<uint16_t, 4>;
+    else return hipErrorInvalidValue;
+    hipError_t e = set_lds_limit((const void *)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * waves), lds, stream, t);
     return hipGetLastError();
 }
 

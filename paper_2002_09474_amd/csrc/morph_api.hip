@@ -65,8 +65,10 @@ struct DtypeTuning {
     int h_vhgw;
     // single images on aligned rows with vertical vHGW in run totals and wy >= coop_min_wy
     // (0: never) take the streaming kernel's cooperative form, units of coop_rows rows
-    // shared by coop_waves waves (4, 8 or 16)
+    // shared by coop_waves waves (4, 8 or 16); the same three for the images of a batch
+    // (whose cooperative units run as a dispatch of their own)
     int coop_min_wy, coop_rows, coop_waves;
+    int batch_coop_min_wy, batch_coop_rows, batch_coop_waves;
 };
 
 std::mutex g_tuning_mu;
@@ -75,9 +77,9 @@ std::mutex g_tuning_mu;
 // single images, 9 and 9 for the images of a batch; unit heights and tile shapes.
 const DtypeTuning k_builtin_tuning[2] = {
     {12, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 48, 32}}, 8, 96, 32, 4,
-     1, 16, 48, 64, 1, 9, 9, 1, 16, 9, 48, 8, 0, 33, 96, 8},
+     1, 16, 48, 64, 1, 9, 9, 1, 16, 9, 48, 8, 0, 33, 96, 8, 0, 96, 8},
     {16, 31, {{9, 32, 64}, {16, 64, 32}, {32, 64, 32}, {64, 64, 32}, {1 << 30, 48, 32}}, 8, 64, 24, 4,
-     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 48, 16, 0, 33, 96, 8},
+     1, 16, 64, 64, 1, 9, 9, 1, 8, 9, 48, 16, 0, 33, 96, 8, 0, 96, 8},
 };
 DtypeTuning g_tuning[2] = {k_builtin_tuning[0], k_builtin_tuning[1]};
 
@@ -193,26 +195,36 @@ bool read_dtype_tuning(const JVal &o, DtypeTuning &t)
         if (r < kWaveRows || r > 8 * kWaveRows || r % kWaveRows) return false;
         t.*ck.field = r;
     }
-    it = o.obj.find("coop_min_wy");
-    if (it != o.obj.end()) {
-        if (it->second.k != JVal::NUM) return false;
-        const int r = (int)it->second.num;
-        if (r < 0) return false;
-        t.coop_min_wy = r;
-    }
-    it = o.obj.find("coop_rows");
-    if (it != o.obj.end()) {
-        if (it->second.k != JVal::NUM) return false;
-        const int r = (int)it->second.num;
-        if (r < 8 || r > 1024 || r % 8) return false;
-        t.coop_rows = r;
-    }
-    it = o.obj.find("coop_waves");
-    if (it != o.obj.end()) {
-        if (it->second.k != JVal::NUM) return false;
-        const int r = (int)it->second.num;
-        if (r != 4 && r != 8 && r != 16) return false;
-        t.coop_waves = r;
+    const struct {
+        const char *min_wy, *rows, *waves;
+        int DtypeTuning::*f_min_wy, DtypeTuning::*f_rows, DtypeTuning::*f_waves;
+    } coop_keys[] = {{"coop_min_wy", "coop_rows", "coop_waves", &DtypeTuning::coop_min_wy,
+                      &DtypeTuning::coop_rows, &DtypeTuning::coop_waves},
+                     {"batch_coop_min_wy", "batch_coop_rows", "batch_coop_waves",
+                      &DtypeTuning::batch_coop_min_wy, &DtypeTuning::batch_coop_rows,
+                      &DtypeTuning::batch_coop_waves}};
+    for (const auto &ck : coop_keys) {
+        it = o.obj.find(ck.min_wy);
+        if (it != o.obj.end()) {
+            if (it->second.k != JVal::NUM) return false;
+            const int r = (int)it->second.num;
+            if (r < 0) return false;
+            t.*ck.f_min_wy = r;
+        }
+        it = o.obj.find(ck.rows);
+        if (it != o.obj.end()) {
+            if (it->second.k != JVal::NUM) return false;
+            const int r = (int)it->second.num;
+            if (r < 8 || r > 1024 || r % 8) return false;
+            t.*ck.f_rows = r;
+        }
+        it = o.obj.find(ck.waves);
+        if (it != o.obj.end()) {
+            if (it->second.k != JVal::NUM) return false;
+            const int r = (int)it->second.num;
+            if (r != 4 && r != 8 && r != 16) return false;
+            t.*ck.f_waves = r;
+        }
     }
     it = o.obj.find("oc_t_x");
     if (it != o.obj.end()) {
@@ -460,14 +472,16 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
                                                : (batch ? tu.batch_stream_rows : tu.stream_rows),
                         H);
         if (!batch && tu.fit_units) j.TB = fit_rows(j.TB, H, j.tiles_x);
-        // single images with tall vertical windows on aligned rows: the cooperative
-        // form, whose taller units re-read fewer halo rows with as many waves
-        if (!batch && tu.coop_min_wy > 0 && j.wy >= tu.coop_min_wy && stream_two_level(j.wy) &&
-            j.hm != PASS_VHGW && rows_aligned(j)) {
+        // tall vertical windows on aligned rows: the cooperative form, whose taller
+        // units re-read fewer halo rows with as many waves (single images and batches
+        // by keys of their own)
+        const int cmin = batch ? tu.batch_coop_min_wy : tu.coop_min_wy;
+        if (cmin > 0 && j.wy >= cmin && stream_two_level(j.wy) && j.hm != PASS_VHGW &&
+            rows_aligned(j)) {
             TileJob c = j;
-            c.coop = tu.coop_waves;
-            c.TB = std::min(tu.coop_rows, (H + 7) / 8 * 8);
-            if (tu.fit_units) c.TB = fit_rows(c.TB, H, c.tiles_x * c.coop);
+            c.coop = batch ? tu.batch_coop_waves : tu.coop_waves;
+            c.TB = std::min(batch ? tu.batch_coop_rows : tu.coop_rows, (H + 7) / 8 * 8);
+            if (!batch && tu.fit_units) c.TB = fit_rows(c.TB, H, c.tiles_x * c.coop);
             if (coop_lds_bytes(c) <= kCoopMaxLds) j = c;
         }
         j.tiles_y = (H + j.TB - 1) / j.TB;
@@ -893,6 +907,7 @@ struct BatchGroup {
     int job0 = 0, njobs = 0; // jobs [job0, job0 + njobs) of the (group-sorted) table
     int64_t tiles = 0;
     int lds = 0, grid = 0, dtype = 0, kind = 0, variant = 0, phase = 0;
+    int waves = 0; // the cooperative form's waves a unit (streaming variant 2)
     bool aligned = true;
 };
 
@@ -908,10 +923,11 @@ struct WsPatch {
 // two vertical forms (LDS ring for wy <= kStreamRingMaxWy, run totals above) and for
 // the wave kernel its two forms (vertical windows up to kDirectMax, tall beyond)
 // group classes: tile, wave, streaming (ring), streaming (run totals), wide rows, wave
-// (tall)
-static constexpr int kGroupClasses = kKinds + 2;
+// (tall), streaming (cooperative form)
+static constexpr int kGroupClasses = kKinds + 3;
 static constexpr int kClassRows = kKinds;          // wide rows
 static constexpr int kClassWaveTall = kKinds + 1;  // tall wave units
+static constexpr int kClassCoop = kKinds + 2;      // cooperative streaming units
 static constexpr int kPhaseGroups = 4 * kGroupClasses;
 // an opening or closing descriptor is two jobs: its first operation (src into the
 // workspace) in phase 0 with every erosion and dilation, its second (workspace into
@@ -1025,7 +1041,8 @@ int morph_batch_create(int max_images, int64_t max_tiles, morph_batch_t *out)
 static int group_of(const TileJob &j, int phase)
 {
     int k = j.kind;
-    if (j.kind == KIND_STREAM && stream_two_level(j.wy)) k = KIND_STREAM + 1;
+    if (j.kind == KIND_STREAM && j.coop) k = kClassCoop;
+    else if (j.kind == KIND_STREAM && stream_two_level(j.wy)) k = KIND_STREAM + 1;
     else if (j.kind == KIND_ROWS) k = kClassRows;
     else if (wave_tall(j)) k = kClassWaveTall;
     return phase * kPhaseGroups + 4 * k + 2 * j.dtype + (job_rows_aligned(j) ? 0 : 1);
@@ -1035,8 +1052,8 @@ static int group_of(const TileJob &j, int phase)
 // groups (run totals, then ring), then the tile, wave and wide-row groups.
 static int group_order(int gi)
 {
-    static const int order[kGroupClasses] = {KIND_STREAM + 1, KIND_STREAM, kClassWaveTall,
-                                             KIND_TILE, KIND_WAVE, kClassRows};
+    static const int order[kGroupClasses] = {kClassCoop, KIND_STREAM + 1, KIND_STREAM,
+                                             kClassWaveTall, KIND_TILE, KIND_WAVE, kClassRows};
     const int ph = gi / kPhaseGroups, r = gi % kPhaseGroups;
     return ph * kPhaseGroups + 4 * order[r / 4] + r % 4;
 }
@@ -1165,10 +1182,13 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
         G.kind = jobs[g][0].kind;
         G.dtype = jobs[g][0].dtype;
         G.aligned = job_rows_aligned(jobs[g][0]);
-        G.variant = ((G.kind == KIND_STREAM && stream_two_level(jobs[g][0].wy)) ||
-                     wave_tall(jobs[g][0]))
+        // streaming: 1 run totals, 2 the cooperative form; wave: 1 the tall form
+        G.variant = (G.kind == KIND_STREAM && jobs[g][0].coop) ? 2
+                    : ((G.kind == KIND_STREAM && stream_two_level(jobs[g][0].wy)) ||
+                       wave_tall(jobs[g][0]))
                         ? 1
                         : 0;
+        G.waves = jobs[g][0].coop;
         G.phase = g / kPhaseGroups;
         int64_t t = 0;
         for (size_t q = 0; q < jobs[g].size(); q++) {
@@ -1186,7 +1206,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
             // one wave per unit, four per workgroup: the grid covers every unit
             G.grid = (int)std::max<int64_t>((t + 3) / 4, 1);
         } else if (G.kind == KIND_STREAM) {
-            // one single-wave workgroup per unit
+            // one workgroup per unit (single-wave, or the cooperative form's)
             G.grid = (int)std::max<int64_t>(t, 1);
         } else {
             const int per_cu = std::max(1, std::min(8, kMaxLdsBytes / std::max(G.lds + 64, 1)));
@@ -1211,7 +1231,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
                        return x.job0 == y.job0 && x.njobs == y.njobs && x.tiles == y.tiles &&
                               x.lds == y.lds && x.grid == y.grid && x.dtype == y.dtype &&
                               x.aligned == y.aligned && x.kind == y.kind &&
-                              x.variant == y.variant && x.phase == y.phase;
+                              x.variant == y.variant && x.phase == y.phase && x.waves == y.waves;
                    });
     if (!same_layout) drop_graph(b);
     b->groups = groups;
@@ -1235,6 +1255,7 @@ int morph_batch_set(morph_batch_t b, const morph_desc *descs, int n, hipStream_t
 static int fused_class(const BatchGroup &G)
 {
     if (!tuning_for(G.dtype).fuse) return -1;
+    if (G.kind == KIND_STREAM && G.variant == 2) return -1; // (workgroups of several waves)
     if (G.kind == KIND_STREAM) return G.variant ? 0 : 1;
     return (G.kind == KIND_WAVE && !G.variant) ? 2 : -1;
 }
@@ -1282,7 +1303,8 @@ static hipError_t launch_groups(morph_batch *b, hipStream_t stream)
     for (size_t g = 0; g < b->groups.size(); g++) {
         const BatchGroup &G = b->groups[g];
         if (fused_class(G) >= 0 || G.phase != ph) continue;
-        hipError_t e = launch_batch(tabs[g], G.kind, G.variant, G.dtype, G.aligned, G.grid, G.lds, stream);
+        hipError_t e = launch_batch(tabs[g], G.kind, G.variant, G.waves, G.dtype, G.aligned, G.grid,
+                                    G.lds, stream);
         if (e != hipSuccess) return e;
     }
     }

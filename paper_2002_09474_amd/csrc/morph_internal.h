@@ -74,9 +74,24 @@ struct TileJob {
     int32_t coop;    // KIND_STREAM: 0, or the cooperative form's waves a unit (4, 8, 16)
 };
 
+// the streaming kernel's cooperative form (k_stream_coop.hip): rows
+// aligned, vertical vHGW in run totals; a workgroup of j.coop waves (4, 8, 16) per unit
+// of TB output rows builds the unit's run totals, their scans and the output runs
+// side by side.  LDS: the unit's run totals, then S and P of each block (entries of 64
+// lanes x 4 bytes for uint8, 8 for uint16).
+constexpr int kCoopMaxLds = 64 * 1024;
+inline int coop_lds_bytes(const TileJob &j)
+{
+    const int rows = j.TB < j.H ? j.TB : j.H;
+    const int nr = stream_runs(j.wy), bmax = (rows - 1) / j.wy;
+    const int tail = rows + j.wy - 1 - (bmax + 1) * j.wy;
+    const int n_runs = (bmax + 1) * nr + (nr < (tail + 7) / 8 ? nr : (tail + 7) / 8);
+    return (n_runs + 2 * (bmax + 1) * (nr + 1)) * 64 * (j.dtype ? 8 : 4);
+}
 inline int lds_bytes(const TileJob &j)
 {
     if (j.kind == KIND_WAVE || j.kind == KIND_ROWS) return 0;
+    if (j.kind == KIND_STREAM && j.coop) return coop_lds_bytes(j);
     if (j.kind == KIND_STREAM) // per single-wave workgroup, 64 lanes x 4 (u8) / 8 (u16)
                                // bytes per entry: run totals and suffixes, or the ring
         return (stream_two_level(j.wy) ? 2 * stream_runs(j.wy) + 1 : stream_ring_entries(j.wy)) *
@@ -98,20 +113,6 @@ hipError_t launch_wave_kernel(const TileJob &job, hipStream_t stream);
 hipError_t launch_wave_tall_kernel(const TileJob &job, hipStream_t stream);
 inline bool wave_tall(const TileJob &j) { return j.kind == KIND_WAVE && j.wy > kDirectMax; }
 hipError_t launch_stream_kernel(const TileJob &job, hipStream_t stream);
-// the streaming kernel's cooperative form (k_stream_coop.hip): single images, rows
-// aligned, vertical vHGW in run totals; a workgroup of j.coop waves (4, 8, 16) per unit
-// of TB output rows builds the unit's run totals, their scans and the output runs
-// side by side.  LDS: the unit's run totals, then S and P of each block (entries of 64
-// lanes x 4 bytes for uint8, 8 for uint16).
-constexpr int kCoopMaxLds = 64 * 1024;
-inline int coop_lds_bytes(const TileJob &j)
-{
-    const int rows = j.TB < j.H ? j.TB : j.H;
-    const int nr = stream_runs(j.wy), bmax = (rows - 1) / j.wy;
-    const int tail = rows + j.wy - 1 - (bmax + 1) * j.wy;
-    const int n_runs = (bmax + 1) * nr + (nr < (tail + 7) / 8 ? nr : (tail + 7) / 8);
-    return (n_runs + 2 * (bmax + 1) * (nr + 1)) * 64 * (j.dtype ? 8 : 4);
-}
 hipError_t launch_stream_coop(const TileJob &job, hipStream_t stream);
 hipError_t launch_rows_kernel(const TileJob &job, hipStream_t stream);
 // the morphological gradient of a wave-kernel job (kind KIND_WAVE, rows aligned):
@@ -155,8 +156,8 @@ struct BatchTables {
     unsigned long long *counter; // device: [0] next tile, [1] workgroups finished (both 0
                                  // between launches); not used by wave groups
 };
-hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, bool aligned, int grid,
-                        int lds, hipStream_t stream);
+hipError_t launch_batch(const BatchTables &t, int kind, int variant, int waves, int dtype, bool aligned,
+                        int grid, int lds, hipStream_t stream);
 // One dispatch for the wave and streaming groups of one element type and row
 // alignment: classes 0 (streaming, run totals), 1 (streaming, LDS ring) and 2
 // (wave), one single-wave workgroup per unit, class c taking blocks
@@ -186,6 +187,9 @@ hipError_t launch_batch_rows(const BatchTables &t, int dtype, bool aligned, int 
                              hipStream_t stream);
 hipError_t launch_batch_stream(const BatchTables &t, bool runs, int dtype, bool aligned, int grid,
                                int lds, hipStream_t stream);
+// the cooperative form's batch kernel: one workgroup of `waves` waves per unit
+hipError_t launch_batch_coop(const BatchTables &t, int dtype, int waves, int grid, int lds,
+                             hipStream_t stream);
 // output quads of a stream-kernel strip for a horizontal window wx (worst-case
 // origin offset 3): the last one's input, 4Q + 3 + wx + 2, must lie in 64 quads
 inline int stream_quads(int wx) { return (250 - wx) / 4 + 1; }

@@ -16,14 +16,16 @@ hipError_t launch_tile_job(const TileJob &job, hipStream_t stream)
     }
 }
 
-hipError_t launch_batch(const BatchTables &t, int kind, int variant, int dtype, bool aligned,
-                        int grid, int lds, hipStream_t stream)
+hipError_t launch_batch(const BatchTables &t, int kind, int variant, int waves, int dtype,
+                        bool aligned, int grid, int lds, hipStream_t stream)
 {
     switch (kind) {
     case KIND_ROWS: return launch_batch_rows(t, dtype, aligned, grid, stream);
     case KIND_WAVE: return variant ? launch_batch_wave_tall(t, dtype, aligned, grid, stream)
                                    : launch_batch_wave(t, dtype, aligned, grid, stream);
-    case KIND_STREAM: return launch_batch_stream(t, variant != 0, dtype, aligned, grid, lds, stream);
+    case KIND_STREAM:
+        if (variant == 2) return launch_batch_coop(t, dtype, waves, grid, lds, stream);
+        return launch_batch_stream(t, variant != 0, dtype, aligned, grid, lds, stream);
     default: return launch_batch_tile(t, dtype, aligned, grid, lds, stream);
     }
 }

@@ -371,7 +371,15 @@ def test_tuning_routes_tall_vertical_windows_to_the_cooperative_form(tmp_path):
         f.write_text(json.dumps({"u8": {"coop_min_wy": 0}}))
         morph.load_tuning(str(f))
         assert morph.resolve_plan("u8", 4096, 4096, 1, 255)["kernel"] == "stream"
-        for bad in ({"coop_rows": 12}, {"coop_rows": 2048}, {"coop_min_wy": -1}, {"coop_waves": 5}):
+        # batches by keys of their own
+        f.write_text(json.dumps({"u8": {"batch_coop_min_wy": 33, "batch_coop_rows": 64,
+                                        "batch_coop_waves": 4}}))
+        morph.load_tuning(str(f))
+        p = morph.resolve_plan("u8", 1000, 1000, 7, 63, batch=True)
+        assert (p["kernel"], p["tile_h"]) == ("stream_coop", 64)
+        assert morph.resolve_plan("u8", 4096, 4096, 1, 255)["kernel"] == "stream"
+        for bad in ({"coop_rows": 12}, {"coop_rows": 2048}, {"coop_min_wy": -1}, {"coop_waves": 5},
+                    {"batch_coop_waves": 2}, {"batch_coop_rows": 0}):
             f.write_text(json.dumps({"u8": bad}))
             with pytest.raises(morph.MorphError):
                 morph.load_tuning(str(f))

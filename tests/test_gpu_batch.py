@@ -46,18 +46,24 @@ def _want(it):
                         it["ax"], it["ay"], method="direct")
 
 
-@pytest.mark.parametrize("fuse,fit,ty", [(1, 1, 0), (0, 1, 0), (1, 0, 0), (1, 1, 31), (0, 1, 31)])
-def test_batch_matches_oracle_and_single_calls(fuse, fit, ty, tmp_path):
+@pytest.mark.parametrize("fuse,fit,ty,coop", [(1, 1, 0, 0), (0, 1, 0, 0), (1, 0, 0, 0),
+                                              (1, 1, 31, 0), (0, 1, 31, 0), (1, 1, 0, 17),
+                                              (1, 0, 16, 17)])
+def test_batch_matches_oracle_and_single_calls(fuse, fit, ty, coop, tmp_path):
     """With the wave and streaming groups fused into one dispatch per element type
     and row alignment (the default) and launched one group at a time; with units
     shortened to fill the GPU (the default for a batch this small) and at the tuned
     batch heights; with vertical windows up to 31 direct (the wave kernel's tall
-    form, a dispatch of its own)."""
+    form, a dispatch of its own); with the run-total streaming units in the cooperative
+    form (a dispatch of its own, 4 and 8 waves a unit)."""
     import json
     f = tmp_path / "t.json"
     t = {"fuse": fuse, "fit_units": fit}
     if ty:
         t["batch_t_y"] = ty
+    if coop:
+        t.update(batch_coop_min_wy=coop, batch_coop_rows=24 if fit else 64,
+                 batch_coop_waves=4 if fit else 8)
     f.write_text(json.dumps({"u8": t, "u16": t}))
     morph.load_tuning(str(f))
     try:
