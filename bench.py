@@ -413,8 +413,8 @@ def kernel_label(group):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-budget", type=float, default=10.0,
                     help="seconds of oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -588,7 +588,9 @@ def main():
 
 
 def _run_extras(res, args, torch, morph, synth, dev, want):
-    steps = max(10, args.steps)
+    # each extra line replays a graph of many launches, steps // 2 times: at most 40
+    # steps keeps every line within a fraction of a second
+    steps = min(max(10, args.steps), 40)
     if want("c3"):
         _log("4096x4096 kernels")
         res["c3_4096"] = c3_lines(torch, morph, dev, steps)

@@ -54,44 +54,55 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
     const RunTable<T> pre(lds + (n_runs + (bmax + 1) * (nr + 1)) * ent); // P_{b+1}[r]
 
     const uint32_t pitch = (uint32_t)J.pitch;
-    // rows r0 .. r0 + SD - 1 of the unit (clamped into the image)
-    auto issue8 = [&](typename WaveLoader<T>::Raw(&buf)[SD], int r0) {
+    using Raw = typename WaveLoader<T>::Raw;
+    // rows r0 .. r0 + len - 1 of the unit (clamped into the image) into buf[0 .. len - 1].
+    // For uint8 buf[len ..] repeat row r0 + len - 1, which leaves every min / max over
+    // the buffer and every suffix and prefix up to len unchanged, so that the folds
+    // below take all SD rows without a test per row (measured faster for uint8, slower
+    // at large windows for uint16, which keeps the tests).
+    constexpr bool kDup = sizeof(T) == 1;
+    auto issue8 = [&](Raw(&buf)[SD], int r0, int len) __attribute__((always_inline)) {
         uint32_t so[SD];
 #pragma unroll
-        for (int k = 0; k < SD; k++) so[k] = (uint32_t)min(max(gy0 + r0 + k, 0), J.H - 1) * pitch;
+        for (int k = 0; k < SD; k++)
+            so[k] = (uint32_t)min(max(gy0 + r0 + (kDup ? min(k, len - 1) : k), 0), J.H - 1) * pitch;
 #pragma unroll
         for (int k = 0; k < SD; k++) buf[k] = L.issue_at(__builtin_amdgcn_readfirstlane(so[k]));
     };
     auto run_rows = [&](int g) { return min(SD, wy - SD * (g % nr)); };
     auto run_start = [&](int g) { return (g / nr) * wy + SD * (g % nr); };
 
-    // 1. run totals: the wave's runs w, w + NW, ..., the next one's loads in
-    // flight while one is reduced
+    // 1. run totals: the wave's runs w, w + NW, ..., the next one's loads in flight
+    // while one is reduced
     {
-        typename WaveLoader<T>::Raw ba[SD], bb[SD];
-        auto total = [&](typename WaveLoader<T>::Raw(&cur)[SD], typename WaveLoader<T>::Raw(&nxt)[SD],
-                         int g) __attribute__((always_inline)) -> bool {
-            const int gn = g + NW;
-            if (gn < n_runs) issue8(nxt, run_start(gn));
-            const int len = run_rows(g);
-            uint32_t a01, a23;
-            L.widen(cur[0], a01, a23);
+        constexpr int D = 2; // (deeper measured slower: the registers cost occupancy)
+        Raw buf[D][SD];
 #pragma unroll
-            for (int k = 1; k < SD; k++) {
-                uint32_t x01, x23;
-                L.widen(cur[k], x01, x23);
-                if (k < len) {
-                    a01 = pk<MAXOP>(a01, x01);
-                    a23 = pk<MAXOP>(a23, x23);
+        for (int d = 0; d < D - 1; d++) {
+            const int gd = wave + d * NW;
+            if (gd < n_runs) issue8(buf[d], run_start(gd), run_rows(gd));
+        }
+        for (int g = wave; g < n_runs; g += D * NW) {
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+                const int gc = g + d * NW;
+                if (gc >= n_runs) break;
+                const int gn = gc + (D - 1) * NW;
+                if (gn < n_runs) issue8(buf[(d + D - 1) % D], run_start(gn), run_rows(gn));
+                const int len = run_rows(gc);
+                uint32_t a01, a23;
+                L.widen(buf[d][0], a01, a23);
+#pragma unroll
+                for (int k = 1; k < SD; k++) {
+                    uint32_t x01, x23;
+                    L.widen(buf[d][k], x01, x23);
+                    if (kDup || k < len) {
+                        a01 = pk<MAXOP>(a01, x01);
+                        a23 = pk<MAXOP>(a23, x23);
+                    }
                 }
+                tot.put(gc, a01, a23);
             }
-            tot.put(g, a01, a23);
-            return gn < n_runs;
-        };
-        int g = wave;
-        if (g < n_runs) {
-            issue8(ba, run_start(g));
-            while (total(ba, bb, g) && total(bb, ba, g + NW)) g += 2 * NW;
         }
     }
     __syncthreads();
@@ -138,7 +149,9 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
     }
     __syncthreads();
 
-    // 3. output runs (b, r) whose first row is an output, dealt out over the waves
+    // 3. output runs (b, r) whose first row is an output: the wave's runs g = wave,
+    // wave + NW, ... (increasing first rows, so the first one past the unit ends them),
+    // each reading its rows of blocks b and b + 1
     const Doubling S(J.wx, co);
     const bool hdirect = J.hm != PASS_DOUBLING; // direct (wx <= kDirectMax) or none
     const int Q = (J.TW >> 2) * sx + lane;
@@ -149,15 +162,10 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
     const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)J.dst, (short)0, (int)(uint32_t)min(dspan, (uint64_t)0xffffffffu), kBufferWord3);
     const uint32_t dvoff = (uint32_t)Q * 4u * (uint32_t)sizeof(T);
-    const int n_out = (bmax + 1) * nr;
-    for (int g = wave; g < n_out; g += NW) {
+    auto out_run = [&](Raw(&xb)[SD], Raw(&zb)[SD], int g) __attribute__((always_inline)) {
         const int i0 = run_start(g); // first output row of the run
-        if (i0 >= rows) continue;
         const int b = g / nr, r = g % nr;
         const int len = run_rows(g);
-        typename WaveLoader<T>::Raw xb[SD], zb[SD];
-        issue8(xb, i0);      // block b's run r: the suffix side
-        issue8(zb, i0 + wy); // block b + 1's run r: the prefix side
         uint32_t s01, s23, p01, p23;
         suf.get(b * (nr + 1) + r + 1, s01, s23);
         pre.get(b * (nr + 1) + r, p01, p23);
@@ -166,7 +174,7 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
         for (int k = SD - 1; k >= 0; k--) {
             uint32_t x01, x23;
             L.widen(xb[k], x01, x23);
-            if (k < len) {
+            if (kDup || k < len) {
                 s01 = pk<MAXOP>(s01, x01);
                 s23 = pk<MAXOP>(s23, x23);
             }
@@ -214,6 +222,13 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
                         Px<T>::store(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W, o01[k], o23[k]);
             }
         }
+    };
+    const int n_out = (bmax + 1) * nr;
+    for (int g = wave; g < n_out && run_start(g) < rows; g += NW) {
+        Raw xb[SD], zb[SD];
+        issue8(xb, run_start(g), run_rows(g));      // block b's run r: the suffix side
+        issue8(zb, run_start(g) + wy, run_rows(g)); // block b + 1's run r: the prefix side
+        out_run(xb, zb, g);
     }
 }
 

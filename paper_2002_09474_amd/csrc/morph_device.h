@@ -2273,13 +2273,22 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
         if constexpr (RUNS) {
             if (t + cnt >= wy) issue8(hnxt, gy0 + t + cnt - wy);
             // this run's total, for the block's S
+            // (full chunks, the common case, fold without a test per row)
             uint32_t r01 = x01[0], r23 = x23[0];
+            if (full) {
 #pragma unroll
-            for (int k = 1; k < SD; k++)
-                if (full || k < cnt) {
+                for (int k = 1; k < SD; k++) {
                     r01 = pk<MAXOP>(r01, x01[k]);
                     r23 = pk<MAXOP>(r23, x23[k]);
                 }
+            } else {
+#pragma unroll
+                for (int k = 1; k < SD; k++)
+                    if (k < cnt) {
+                        r01 = pk<MAXOP>(r01, x01[k]);
+                        r23 = pk<MAXOP>(r23, x23[k]);
+                    }
+            }
             tot.put(j / SD, r01, r23);
         } else if (fill) {
             if (full) {
@@ -2301,14 +2310,22 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
                 suf.get(j / SD + 1, s01, s23);
 #pragma unroll
                 for (int k = 0; k < SD; k++) L.widen(hcur[k], o01[k], o23[k]);
+                if (runlen == SD) {
 #pragma unroll
-                for (int k = SD - 1; k >= 0; k--) {
-                    if (k < runlen) {
-                        s01 = pk<MAXOP>(s01, o01[k]);
-                        s23 = pk<MAXOP>(s23, o23[k]);
+                    for (int k = SD - 1; k >= 0; k--) {
+                        s01 = o01[k] = pk<MAXOP>(s01, o01[k]);
+                        s23 = o23[k] = pk<MAXOP>(s23, o23[k]);
                     }
-                    o01[k] = s01;
-                    o23[k] = s23;
+                } else {
+#pragma unroll
+                    for (int k = SD - 1; k >= 0; k--) {
+                        if (k < runlen) {
+                            s01 = pk<MAXOP>(s01, o01[k]);
+                            s23 = pk<MAXOP>(s23, o23[k]);
+                        }
+                        o01[k] = s01;
+                        o23[k] = s23;
+                    }
                 }
             } else {
 #pragma unroll

@@ -440,7 +440,7 @@ def test_thresholds_route_windows_to_the_direct_passes():
         # beyond the compiled windows the automatic plan takes the large-window passes
         morph.set_thresholds("u8", 40, 40)
         for wx, wy in ((17, 3), (3, 32), (31, 33)):
-            assert morph.resolve_plan("u8", 300, 700, wx, wy)["kernel"] in ("stream", "wave")
+            assert morph.resolve_plan("u8", 300, 700, wx, wy)["kernel"] in ("stream", "stream_coop", "wave")
             _check(img, "erode", wx, wy)
     finally:
         morph.set_thresholds("u8", *t0)
