@@ -523,5 +523,19 @@ def test_streaming_cooperative_form(dtype, tmp_path):
                         assert p["kernel"] == "stream_coop", (H, W, wx, wy, p)
                     ay = int(rng.choice([-1, 0, wy - 1]))
                     _check(img, "erode" if wy % 2 else "dilate", wx, wy, -1, ay)
+        # sources and destinations starting 1..3 pixels past a 4-pixel boundary (row
+        # pitch still aligned, so the form is taken), at the table's shape
+        morph.load_tuning(None)
+        H, W = 150, 520
+        for off in (1, 2, 3):
+            img = synth.uniform(H, W, dtype, seed=80 + off)
+            d, _ = to_dev(img, pitch_elems=W + 4 * off, offset_elems=off)
+            for wx, wy, ax in ((1, 101, -1), (31, 63, 0), (9, 40, 8), (101, 101, -1)):
+                assert morph.resolve_plan(dn, H, W, wx, wy)["kernel"] == "stream_coop"
+                out = empty_like_dev(d)[0]
+                morph.apply("dilate", d, wx, wy, ax, -1, out=out)
+                torch.cuda.synchronize()
+                assert np.array_equal(to_host(out), _ref(img, "dilate", wx, wy, ax, -1)), (
+                    off, wx, wy)
     finally:
         morph.load_tuning(None)
