@@ -50,8 +50,15 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
     const int n_runs = (bmax + 1) * nr + min(nr, (tail + SD - 1) / SD);
     const RunTable<T> tot(lds);                                  // n_runs totals
     const int ent = 64 * (sizeof(T) == 1 ? 1 : 2);               // dwords an entry
-    const RunTable<T> suf(lds + n_runs * ent);                   // S_b[r], b <= bmax
-    const RunTable<T> pre(lds + (n_runs + (bmax + 1) * (nr + 1)) * ent); // P_{b+1}[r]
+    // S_b[r] (b <= bmax) and P_{b+1}[r] after the totals.  With one block of outputs
+    // (bmax 0) block 0 needs only S and block 1 only P, so for uint16, whose LDS limits
+    // the workgroups a CU holds at the largest windows, both scans overwrite the totals
+    // they read: S_0[r] at entry r (r < nr), P_1[r] at entry nr + r - 1 (r >= 1), and
+    // S_0[nr], P_1[0] (the identity) are not stored (uint8, held back by its registers
+    // instead, measured 1-3% slower so)
+    const bool inplace = sizeof(T) == 2 && bmax == 0;
+    const RunTable<T> suf(lds + (inplace ? 0 : n_runs * ent));
+    const RunTable<T> pre(lds + (inplace ? (nr - 1) * ent : (n_runs + (bmax + 1) * (nr + 1)) * ent));
 
     const uint32_t pitch = (uint32_t)J.pitch;
     using Raw = typename WaveLoader<T>::Raw;
@@ -114,7 +121,7 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
         uint32_t a01 = id, a23 = id;
         if (q <= bmax) { // S_q[r] = op of runs r .. nr - 1 of block q
             const int b = q;
-            suf.put(b * (nr + 1) + nr, id, id);
+            if (!inplace) suf.put(b * (nr + 1) + nr, id, id);
             for (int r1 = nr; r1 > 0; r1 -= SD) { // runs r1 - 1 down to max(r1 - SD, 0)
                 uint32_t v01[SD], v23[SD];
 #pragma unroll
@@ -131,7 +138,7 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
         } else { // P_{b+1}[r] = op of runs 0 .. r - 1 of block b + 1, for the runs it has
             const int b = q - (bmax + 1);
             const int have = min(nr, n_runs - (b + 1) * nr); // runs of block b + 1 held
-            pre.put(b * (nr + 1), id, id);
+            if (!inplace) pre.put(b * (nr + 1), id, id);
             for (int r0 = 0; r0 < have; r0 += SD) { // runs r0 .. r0 + SD - 1
                 uint32_t v01[SD], v23[SD];
 #pragma unroll
@@ -166,9 +173,9 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
         const int i0 = run_start(g); // first output row of the run
         const int b = g / nr, r = g % nr;
         const int len = run_rows(g);
-        uint32_t s01, s23, p01, p23;
-        suf.get(b * (nr + 1) + r + 1, s01, s23);
-        pre.get(b * (nr + 1) + r, p01, p23);
+        uint32_t s01 = id, s23 = id, p01 = id, p23 = id;
+        if (!inplace || r + 1 < nr) suf.get(b * (nr + 1) + r + 1, s01, s23);
+        if (!inplace || r > 0) pre.get(b * (nr + 1) + r, p01, p23);
         uint32_t o01[SD], o23[SD];
 #pragma unroll
         for (int k = SD - 1; k >= 0; k--) {

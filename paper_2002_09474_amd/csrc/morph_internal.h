@@ -78,7 +78,8 @@ struct TileJob {
 // aligned, vertical vHGW in run totals; a workgroup of j.coop waves (4, 8, 16) per unit
 // of TB output rows builds the unit's run totals, their scans and the output runs
 // side by side.  LDS: the unit's run totals, then S and P of each block (entries of 64
-// lanes x 4 bytes for uint8, 8 for uint16).
+// lanes x 4 bytes for uint8, 8 for uint16); a uint16 unit with one block of outputs
+// (bmax 0) writes its two scans over the totals and needs the totals' entries only.
 constexpr int kCoopMaxLds = 64 * 1024;
 inline int coop_lds_bytes(const TileJob &j)
 {
@@ -86,7 +87,8 @@ inline int coop_lds_bytes(const TileJob &j)
     const int nr = stream_runs(j.wy), bmax = (rows - 1) / j.wy;
     const int tail = rows + j.wy - 1 - (bmax + 1) * j.wy;
     const int n_runs = (bmax + 1) * nr + (nr < (tail + 7) / 8 ? nr : (tail + 7) / 8);
-    return (n_runs + 2 * (bmax + 1) * (nr + 1)) * 64 * (j.dtype ? 8 : 4);
+    const bool inplace = j.dtype == 1 && bmax == 0;
+    return (n_runs + (inplace ? 0 : 2 * (bmax + 1) * (nr + 1))) * 64 * (j.dtype ? 8 : 4);
 }
 inline int lds_bytes(const TileJob &j)
 {
