@@ -60,7 +60,7 @@ __device__ __forceinline__ void oc_direct_rows_co(int wx, int co, uint32_t *v01,
 }
 
 // OPENING: erosion then dilation, else dilation then erosion.
-template <typename T, bool OPENING, int WY>
+template <typename T, bool OPENING, int WY, bool NTS>
 __device__ __forceinline__ void oc_wave_body(const TileJob &J, int unit)
 {
     constexpr bool MAX1 = !OPENING, MAX2 = OPENING; // op of each stage
@@ -173,10 +173,11 @@ __device__ __forceinline__ void oc_wave_body(const TileJob &J, int unit)
                 for (int m = 0; m < KR; m++) {
                     if (y + m < y1) {
                         if constexpr (sizeof(T) == 1) {
-                            store_u32((uintptr_t)(drow + off), perm(w23[m], w01[m], SEL_NARROW));
+                            store_u32<NTS>((uintptr_t)(drow + off),
+                                           perm(w23[m], w01[m], SEL_NARROW));
                         } else {
-                            store_u32((uintptr_t)(drow + off), w01[m]);
-                            store_u32((uintptr_t)(drow + off + 4), w23[m]);
+                            store_u32<NTS>((uintptr_t)(drow + off), w01[m]);
+                            store_u32<NTS>((uintptr_t)(drow + off + 4), w23[m]);
                         }
                     }
                     drow += J.dpitch;
@@ -184,7 +185,7 @@ __device__ __forceinline__ void oc_wave_body(const TileJob &J, int unit)
             } else {
 #pragma unroll
                 for (int m = 0; m < KR; m++) {
-                    if (y + m < y1) Px<T>::store(drow, 4 * Q, J.W, w01[m], w23[m]);
+                    if (y + m < y1) Px<T>::template store<NTS>(drow, 4 * Q, J.W, w01[m], w23[m]);
                     drow += J.dpitch;
                 }
             }
@@ -195,32 +196,40 @@ __device__ __forceinline__ void oc_wave_body(const TileJob &J, int unit)
     }
 }
 
+template <typename T, bool OPENING, bool TALL, bool NTS>
+__device__ __forceinline__ void oc_wave_dispatch(const TileJob &J, int u)
+{
+    if constexpr (TALL) {
+        switch (J.wy) {
+#define OC_WY(W)                                                                             \
+    case W: oc_wave_body<T, OPENING, W, NTS>(J, u); break;
+            OC_WY(10) OC_WY(11) OC_WY(12) OC_WY(13) OC_WY(14)
+#undef OC_WY
+        default: oc_wave_body<T, OPENING, 15, NTS>(J, u); break;
+        }
+    } else {
+        switch (J.wy) {
+#define OC_WY(W)                                                                             \
+    case W: oc_wave_body<T, OPENING, W, NTS>(J, u); break;
+            OC_WY(1) OC_WY(2) OC_WY(3) OC_WY(4) OC_WY(5) OC_WY(6) OC_WY(7) OC_WY(8)
+#undef OC_WY
+        default: oc_wave_body<T, OPENING, 9, NTS>(J, u); break;
+        }
+    }
+}
+
 // TALL: vertical windows kDirectMax + 1 .. kOcWaveMaxWy (a longer queue and ring, a
 // kernel of its own so that the short windows keep their occupancy)
-template <typename T, bool OPENING, bool TALL>
+// NTS: non-temporal destination stores (plain where a later launch reads the
+// destination again: TileJob::keep)
+template <typename T, bool OPENING, bool TALL, bool NTS>
 __global__ __launch_bounds__(NT) void oc_wave_kernel(TileJob J)
 {
     const int units = J.tiles_x * J.tiles_y;
     const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
                                                  (int)(threadIdx.x >> 6));
     if (u >= units) return; // the whole wave leaves
-    if constexpr (TALL) {
-        switch (J.wy) {
-#define OC_WY(W)                                                                             \
-    case W: oc_wave_body<T, OPENING, W>(J, u); break;
-            OC_WY(10) OC_WY(11) OC_WY(12) OC_WY(13) OC_WY(14)
-#undef OC_WY
-        default: oc_wave_body<T, OPENING, 15>(J, u); break;
-        }
-    } else {
-        switch (J.wy) {
-#define OC_WY(W)                                                                             \
-    case W: oc_wave_body<T, OPENING, W>(J, u); break;
-            OC_WY(1) OC_WY(2) OC_WY(3) OC_WY(4) OC_WY(5) OC_WY(6) OC_WY(7) OC_WY(8)
-#undef OC_WY
-        default: oc_wave_body<T, OPENING, 9>(J, u); break;
-        }
-    }
+    oc_wave_dispatch<T, OPENING, TALL, NTS>(J, u);
 }
 
 template <typename T>
@@ -228,8 +237,11 @@ hipError_t launch_openclose_wave_t(const TileJob &job, hipStream_t stream)
 {
     typedef void (*Fn)(TileJob);
     const bool tall = job.wy > kDirectMax;
-    const Fn fn = job.op ? (tall ? oc_wave_kernel<T, true, true> : oc_wave_kernel<T, true, false>)
-                         : (tall ? oc_wave_kernel<T, false, true> : oc_wave_kernel<T, false, false>);
+    const Fn fn = job.keep
+        ? (job.op ? (tall ? oc_wave_kernel<T, true, true, false> : oc_wave_kernel<T, true, false, false>)
+                  : (tall ? oc_wave_kernel<T, false, true, false> : oc_wave_kernel<T, false, false, false>))
+        : (job.op ? (tall ? oc_wave_kernel<T, true, true, true> : oc_wave_kernel<T, true, false, true>)
+                  : (tall ? oc_wave_kernel<T, false, true, true> : oc_wave_kernel<T, false, false, true>));
     const int units = job.tiles_x * job.tiles_y;
     hipLaunchKernelGGL(fn, dim3((units + 3) / 4), dim3(NT), 0, stream, job);
     return hipGetLastError();

@@ -4,7 +4,9 @@
 
 namespace morph {
 
-template <typename T, bool MAXOP, bool AL>
+// NTS: non-temporal destination stores (plain where a later launch reads the
+// destination again: TileJob::keep)
+template <typename T, bool MAXOP, bool AL, bool NTS>
 __global__ __launch_bounds__(NT) void rows_kernel(TileJob J)
 {
     const int units = J.tiles_x * J.tiles_y;
@@ -12,18 +14,24 @@ __global__ __launch_bounds__(NT) void rows_kernel(TileJob J)
                                                  (int)(threadIdx.x >> 6));
     if (u >= units) return; // the whole wave leaves
     __shared__ __align__(16) uint32_t lds[4 * kRowsWaveLdsDwords];
-    rows_body<T, MAXOP, AL>(J, u, lds + (threadIdx.x >> 6) * kRowsWaveLdsDwords);
+    uint32_t *wl = lds + (threadIdx.x >> 6) * kRowsWaveLdsDwords;
+    rows_body<T, MAXOP, AL, NTS>(J, u, wl);
+}
+
+template <bool NTS> static TileKernelFn pick_rows_kernel_n(const TileJob &j)
+{
+    const bool al = rows_aligned(j);
+    if (j.dtype == 0) {
+        if (j.op) return al ? rows_kernel<uint8_t, true, true, NTS> : rows_kernel<uint8_t, true, false, NTS>;
+        return al ? rows_kernel<uint8_t, false, true, NTS> : rows_kernel<uint8_t, false, false, NTS>;
+    }
+    if (j.op) return al ? rows_kernel<uint16_t, true, true, NTS> : rows_kernel<uint16_t, true, false, NTS>;
+    return al ? rows_kernel<uint16_t, false, true, NTS> : rows_kernel<uint16_t, false, false, NTS>;
 }
 
 static TileKernelFn pick_rows_kernel(const TileJob &j)
 {
-    const bool al = rows_aligned(j);
-    if (j.dtype == 0) {
-        if (j.op) return al ? rows_kernel<uint8_t, true, true> : rows_kernel<uint8_t, true, false>;
-        return al ? rows_kernel<uint8_t, false, true> : rows_kernel<uint8_t, false, false>;
-    }
-    if (j.op) return al ? rows_kernel<uint16_t, true, true> : rows_kernel<uint16_t, true, false>;
-    return al ? rows_kernel<uint16_t, false, true> : rows_kernel<uint16_t, false, false>;
+    return j.keep ? pick_rows_kernel_n<false>(j) : pick_rows_kernel_n<true>(j);
 }
 
 // The batch form of the wide-row kernel: one wave per unit, four per workgroup.
@@ -38,8 +46,8 @@ __global__ __launch_bounds__(NT) void batch_rows_kernel(BatchTables bt)
     const int u = (int)(t - bt.tile_start[jb]);
     __shared__ __align__(16) uint32_t lds[4 * kRowsWaveLdsDwords];
     uint32_t *wl = lds + (threadIdx.x >> 6) * kRowsWaveLdsDwords;
-    if (J.op) rows_body<T, true, AL>(J, u, wl);
-    else rows_body<T, false, AL>(J, u, wl);
+    if (J.op) rows_body<T, true, AL, false>(J, u, wl);
+    else rows_body<T, false, AL, false>(J, u, wl);
 }
 
 

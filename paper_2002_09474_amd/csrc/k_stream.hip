@@ -5,31 +5,38 @@
 namespace morph {
 
 // XV: the horizontal pass is the cross-lane vHGW (a plan that asks for vHGW along x).
-template <typename T, bool MAXOP, bool AL, bool RUNS, bool XV>
+// NTS: non-temporal destination stores (plain where a later launch reads the
+// destination again: TileJob::keep)
+template <typename T, bool MAXOP, bool AL, bool RUNS, bool XV, bool NTS>
 __global__ __launch_bounds__(64) void stream_kernel(TileJob J)
 {
     extern __shared__ uint32_t lds[];
-    stream_body<T, MAXOP, AL, RUNS, XV>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+    stream_body<T, MAXOP, AL, RUNS, XV, NTS>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
-template <bool RUNS, bool XV>
+template <bool RUNS, bool XV, bool NTS>
 static TileKernelFn pick_stream_kernel_v(const TileJob &j)
 {
     const bool al = rows_aligned(j);
     if (j.dtype == 0) {
-        if (j.op) return al ? stream_kernel<uint8_t, true, true, RUNS, XV> : stream_kernel<uint8_t, true, false, RUNS, XV>;
-        return al ? stream_kernel<uint8_t, false, true, RUNS, XV> : stream_kernel<uint8_t, false, false, RUNS, XV>;
+        if (j.op) return al ? stream_kernel<uint8_t, true, true, RUNS, XV, NTS> : stream_kernel<uint8_t, true, false, RUNS, XV, NTS>;
+        return al ? stream_kernel<uint8_t, false, true, RUNS, XV, NTS> : stream_kernel<uint8_t, false, false, RUNS, XV, NTS>;
     }
-    if (j.op) return al ? stream_kernel<uint16_t, true, true, RUNS, XV> : stream_kernel<uint16_t, true, false, RUNS, XV>;
-    return al ? stream_kernel<uint16_t, false, true, RUNS, XV> : stream_kernel<uint16_t, false, false, RUNS, XV>;
+    if (j.op) return al ? stream_kernel<uint16_t, true, true, RUNS, XV, NTS> : stream_kernel<uint16_t, true, false, RUNS, XV, NTS>;
+    return al ? stream_kernel<uint16_t, false, true, RUNS, XV, NTS> : stream_kernel<uint16_t, false, false, RUNS, XV, NTS>;
 }
 
 static TileKernelFn pick_stream_kernel(const TileJob &j)
 {
     const bool xv = j.hm == PASS_VHGW;
+    if (j.keep) {
+        if (stream_two_level(j.wy))
+            return xv ? pick_stream_kernel_v<true, true, false>(j) : pick_stream_kernel_v<true, false, false>(j);
+        return xv ? pick_stream_kernel_v<false, true, false>(j) : pick_stream_kernel_v<false, false, false>(j);
+    }
     if (stream_two_level(j.wy))
-        return xv ? pick_stream_kernel_v<true, true>(j) : pick_stream_kernel_v<true, false>(j);
-    return xv ? pick_stream_kernel_v<false, true>(j) : pick_stream_kernel_v<false, false>(j);
+        return xv ? pick_stream_kernel_v<true, true, true>(j) : pick_stream_kernel_v<true, false, true>(j);
+    return xv ? pick_stream_kernel_v<false, true, true>(j) : pick_stream_kernel_v<false, false, true>(j);
 }
 
 // The batch form of the stream kernel: one single-wave workgroup per unit.
@@ -42,8 +49,8 @@ __global__ __launch_bounds__(64) void batch_stream_kernel(BatchTables bt)
     const int jb = bt.tile_job[t];
     const TileJob J = bt.jobs[jb];
     const int u = (int)(t - bt.tile_start[jb]);
-    if (J.op) stream_body<T, true, AL, RUNS>(J, u, lds);
-    else stream_body<T, false, AL, RUNS>(J, u, lds);
+    if (J.op) stream_body<T, true, AL, RUNS, false, false>(J, u, lds);
+    else stream_body<T, false, AL, RUNS, false, false>(J, u, lds);
 }
 
 

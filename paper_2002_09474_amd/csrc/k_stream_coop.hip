@@ -24,7 +24,7 @@ namespace morph {
 
 static_assert(kStreamChunk == SD && SD == 8, "runs of 8 rows");
 
-template <typename T, bool MAXOP, int NW>
+template <typename T, bool MAXOP, int NW, bool NTS = true>
 __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uint32_t *lds)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -213,12 +213,11 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
                 for (int k = 0; k < SD; k++, so += (uint32_t)J.dpitch) {
                     if (k < cnt) {
                         if constexpr (sizeof(T) == 1) {
-                            __builtin_amdgcn_raw_buffer_store_b32(perm(o23[k], o01[k], SEL_NARROW),
-                                                                  drs, (int)dvoff, (int)so, 0);
+                            buffer_store_nt<NTS>(perm(o23[k], o01[k], SEL_NARROW), drs, (int)dvoff,
+                                            (int)so);
                         } else {
-                            __builtin_amdgcn_raw_buffer_store_b32(o01[k], drs, (int)dvoff, (int)so, 0);
-                            __builtin_amdgcn_raw_buffer_store_b32(o23[k], drs, (int)dvoff + 4,
-                                                                  (int)so, 0);
+                            buffer_store_nt<NTS>(o01[k], drs, (int)dvoff, (int)so);
+                            buffer_store_nt<NTS>(o23[k], drs, (int)dvoff + 4, (int)so);
                         }
                     }
                 }
@@ -226,7 +225,8 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
 #pragma unroll
                 for (int k = 0; k < SD; k++)
                     if (k < cnt)
-                        Px<T>::store(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W, o01[k], o23[k]);
+                        Px<T>::template store<NTS>(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W,
+                                                   o01[k], o23[k]);
             }
         }
     };
@@ -239,11 +239,13 @@ __device__ __forceinline__ void stream_coop_body(const TileJob &J, int unit, uin
     }
 }
 
-template <typename T, bool MAXOP, int NW>
+// NTS: non-temporal destination stores (plain where a later launch reads the
+// destination again: TileJob::keep)
+template <typename T, bool MAXOP, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) void stream_coop_kernel(TileJob J)
 {
     extern __shared__ uint32_t lds[];
-    stream_coop_body<T, MAXOP, NW>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
+    stream_coop_body<T, MAXOP, NW, NTS>(J, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 // The batch form: one workgroup of NW waves per unit of the group's jobs.
@@ -256,16 +258,20 @@ __global__ __launch_bounds__(64 * NW) void batch_coop_kernel(BatchTables bt)
     const int jb = bt.tile_job[t];
     const TileJob J = bt.jobs[jb];
     const int u = (int)(t - bt.tile_start[jb]);
-    if (J.op) stream_coop_body<T, true, NW>(J, u, lds);
-    else stream_coop_body<T, false, NW>(J, u, lds);
+    if (J.op) stream_coop_body<T, true, NW, false>(J, u, lds);
+    else stream_coop_body<T, false, NW, false>(J, u, lds);
 }
 
+template <int NW, bool NTS> static TileKernelFn pick_coop_n(const TileJob &job)
+{
+    return job.dtype == 0 ? (job.op ? stream_coop_kernel<uint8_t, true, NW, NTS>
+                                    : stream_coop_kernel<uint8_t, false, NW, NTS>)
+                          : (job.op ? stream_coop_kernel<uint16_t, true, NW, NTS>
+                                    : stream_coop_kernel<uint16_t, false, NW, NTS>);
+}
 template <int NW> static TileKernelFn pick_coop(const TileJob &job)
 {
-    return job.dtype == 0 ? (job.op ? stream_coop_kernel<uint8_t, true, NW>
-                                    : stream_coop_kernel<uint8_t, false, NW>)
-                          : (job.op ? stream_coop_kernel<uint16_t, true, NW>
-                                    : stream_coop_kernel<uint16_t, false, NW>);
+    return job.keep ? pick_coop_n<NW, false>(job) : pick_coop_n<NW, true>(job);
 }
 
 hipError_t launch_stream_coop(const TileJob &job, hipStream_t stream)

@@ -5,31 +5,34 @@
 namespace morph {
 
 // XV: the horizontal pass is the cross-lane vHGW (a plan that asks for vHGW along x).
-template <typename T, bool MAXOP, bool AL, bool XV>
+// NTS: non-temporal destination stores (plain where a later launch reads the
+// destination again: TileJob::keep)
+template <typename T, bool MAXOP, bool AL, bool XV, bool NTS>
 __global__ __launch_bounds__(NT) void wave_kernel(TileJob J)
 {
     const int units = J.tiles_x * J.tiles_y;
     const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
                                                  (int)(threadIdx.x >> 6));
     if (u >= units) return; // the whole wave leaves
-    wave_body<T, MAXOP, AL, false, XV>(J, u);
+    wave_body<T, MAXOP, AL, false, XV, NTS>(J, u);
 }
 
-template <bool XV>
+template <bool XV, bool NTS>
 static TileKernelFn pick_wave_kernel_x(const TileJob &j)
 {
     const bool al = rows_aligned(j);
     if (j.dtype == 0) {
-        if (j.op) return al ? wave_kernel<uint8_t, true, true, XV> : wave_kernel<uint8_t, true, false, XV>;
-        return al ? wave_kernel<uint8_t, false, true, XV> : wave_kernel<uint8_t, false, false, XV>;
+        if (j.op) return al ? wave_kernel<uint8_t, true, true, XV, NTS> : wave_kernel<uint8_t, true, false, XV, NTS>;
+        return al ? wave_kernel<uint8_t, false, true, XV, NTS> : wave_kernel<uint8_t, false, false, XV, NTS>;
     }
-    if (j.op) return al ? wave_kernel<uint16_t, true, true, XV> : wave_kernel<uint16_t, true, false, XV>;
-    return al ? wave_kernel<uint16_t, false, true, XV> : wave_kernel<uint16_t, false, false, XV>;
+    if (j.op) return al ? wave_kernel<uint16_t, true, true, XV, NTS> : wave_kernel<uint16_t, true, false, XV, NTS>;
+    return al ? wave_kernel<uint16_t, false, true, XV, NTS> : wave_kernel<uint16_t, false, false, XV, NTS>;
 }
 
 static TileKernelFn pick_wave_kernel(const TileJob &j)
 {
-    return j.hm == PASS_VHGW ? pick_wave_kernel_x<true>(j) : pick_wave_kernel_x<false>(j);
+    if (j.hm == PASS_VHGW) return j.keep ? pick_wave_kernel_x<true, false>(j) : pick_wave_kernel_x<true, true>(j);
+    return j.keep ? pick_wave_kernel_x<false, false>(j) : pick_wave_kernel_x<false, true>(j);
 }
 
 template <typename T>
@@ -151,8 +154,8 @@ __global__ __launch_bounds__(NT) void batch_wave_kernel(BatchTables bt)
     const int jb = bt.tile_job[t];
     const TileJob J = bt.jobs[jb];
     const int u = (int)(t - bt.tile_start[jb]);
-    if (J.op) wave_body<T, true, AL>(J, u);
-    else wave_body<T, false, AL>(J, u);
+    if (J.op) wave_body<T, true, AL, false, false, false>(J, u);
+    else wave_body<T, false, AL, false, false, false>(J, u);
 }
 
 

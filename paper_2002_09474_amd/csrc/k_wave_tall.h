@@ -6,14 +6,16 @@
 
 namespace morph {
 
-template <typename T, bool MAXOP, bool AL>
+// NTS: non-temporal destination stores (plain where a later launch reads the
+// destination again: TileJob::keep)
+template <typename T, bool MAXOP, bool AL, bool NTS>
 __global__ __launch_bounds__(NT) void wave_tall_kernel(TileJob J)
 {
     const int units = J.tiles_x * J.tiles_y;
     const int u = __builtin_amdgcn_readfirstlane(4 * xcd_tile(blockIdx.x, gridDim.x) +
                                                  (int)(threadIdx.x >> 6));
     if (u >= units) return; // the whole wave leaves
-    wave_body<T, MAXOP, AL, true>(J, u);
+    wave_body<T, MAXOP, AL, true, false, NTS>(J, u);
 }
 
 // Batch form: one wave per unit of the group's tile table, four per workgroup.
@@ -26,16 +28,21 @@ __global__ __launch_bounds__(NT) void batch_wave_tall_kernel(BatchTables bt)
     const int jb = bt.tile_job[t];
     const TileJob J = bt.jobs[jb];
     const int u = (int)(t - bt.tile_start[jb]);
-    if (J.op) wave_body<T, true, AL, true>(J, u);
-    else wave_body<T, false, AL, true>(J, u);
+    if (J.op) wave_body<T, true, AL, true, false, false>(J, u);
+    else wave_body<T, false, AL, true, false, false>(J, u);
+}
+
+template <typename T, bool NTS> static TileKernelFn pick_wave_tall(const TileJob &job)
+{
+    const bool al = rows_aligned(job);
+    return job.op ? (al ? wave_tall_kernel<T, true, true, NTS> : wave_tall_kernel<T, true, false, NTS>)
+                  : (al ? wave_tall_kernel<T, false, true, NTS> : wave_tall_kernel<T, false, false, NTS>);
 }
 
 template <typename T>
 hipError_t launch_wave_tall_t(const TileJob &job, hipStream_t stream)
 {
-    const bool al = rows_aligned(job);
-    const TileKernelFn fn = job.op ? (al ? wave_tall_kernel<T, true, true> : wave_tall_kernel<T, true, false>)
-                                   : (al ? wave_tall_kernel<T, false, true> : wave_tall_kernel<T, false, false>);
+    const TileKernelFn fn = job.keep ? pick_wave_tall<T, false>(job) : pick_wave_tall<T, true>(job);
     const int units = job.tiles_x * job.tiles_y;
     hipLaunchKernelGGL(fn, dim3((units + 3) / 4), dim3(NT), 0, stream, job);
     return hipGetLastError();

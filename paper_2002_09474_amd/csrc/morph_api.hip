@@ -372,6 +372,7 @@ int plan_job(int op, int dtype, const void *src, void *dst, int H, int W, size_t
     j.ay = aye;
     j.op = op;
     j.dtype = dtype;
+    j.keep = 0;
 
     const DtypeTuning tu = tuning_for(dtype);
     const int mx = plan ? plan->method_x : MORPH_METHOD_AUTO;
@@ -599,12 +600,15 @@ bool plan_openclose_wave(bool opening, int dtype, const void *src, void *dst, in
     return (int64_t)j.tiles_x * j.tiles_y <= INT32_MAX - 4;
 }
 
+// keep: a later launch of the same call reads dst (an intermediate image)
 int run_single(int op, int dtype, const void *src, void *dst, int H, int W, size_t pitch, int wx,
-               int wy, int ax, int ay, const morph_plan *plan, hipStream_t stream)
+               int wy, int ax, int ay, const morph_plan *plan, hipStream_t stream,
+               bool keep = false)
 {
     TileJob j;
     int rc = plan_job(op, dtype, src, dst, H, W, pitch, pitch, wx, wy, ax, ay, plan, j);
     if (rc != MORPH_OK) return rc;
+    j.keep = keep ? 1 : 0;
     hipError_t e = launch_tile_job(j, stream);
     if (e != hipSuccess) return hip_fail(e);
     return MORPH_OK;
@@ -639,10 +643,11 @@ static int run_gradient(int dtype, const void *src, void *dst, int H, int W, siz
         return MORPH_ENOMEM;
     if (ranges_overlap(workspace, span, src, span) || ranges_overlap(workspace, span, dst, span))
         return MORPH_EALIAS;
-    rc = run_single(MORPH_OP_DILATE, dtype, src, dst, H, W, pitch, wx, wy, ax, ay, plan, stream);
+    rc = run_single(MORPH_OP_DILATE, dtype, src, dst, H, W, pitch, wx, wy, ax, ay, plan, stream,
+                    true);
     if (rc != MORPH_OK) return rc;
     rc = run_single(MORPH_OP_ERODE, dtype, src, workspace, H, W, pitch, wx, wy, ax, ay, plan,
-                    stream);
+                    stream, true);
     if (rc != MORPH_OK) return rc;
     if ((e = launch_subtract(workspace, dst, H, W, pitch, dtype, false, stream)) != hipSuccess)
         return hip_fail(e);
@@ -673,6 +678,7 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
         TileJob oj;
         if (plan_openclose_wave(opens, dtype, src, dst, H, W, pitch, wx, wy, anchor_x, anchor_y,
                                 oj)) {
+            oj.keep = op == MORPH_OP_TOPHAT || op == MORPH_OP_BLACKHAT; // (subtraction reads dst)
             hipError_t e = launch_openclose_wave(oj, stream);
             if (e == hipSuccess && (op == MORPH_OP_TOPHAT || op == MORPH_OP_BLACKHAT))
                 e = launch_subtract(src, dst, H, W, pitch, dtype, op == MORPH_OP_TOPHAT, stream);
@@ -686,10 +692,10 @@ int morph_apply(int op, int dtype, const void *src, void *dst, int H, int W, siz
     // (top-hat: src - opening; black-hat: closing - src)
     const int first = opens ? MORPH_OP_ERODE : MORPH_OP_DILATE;
     rc = run_single(first, dtype, src, workspace, H, W, pitch, wx, wy, anchor_x, anchor_y, plan,
-                    stream);
+                    stream, true);
     if (rc != MORPH_OK) return rc;
     rc = run_single(1 - first, dtype, workspace, dst, H, W, pitch, wx, wy, anchor_x, anchor_y,
-                    plan, stream);
+                    plan, stream, op == MORPH_OP_TOPHAT || op == MORPH_OP_BLACKHAT);
     if (rc != MORPH_OK || op == MORPH_OP_OPEN || op == MORPH_OP_CLOSE) return rc;
     hipError_t e = launch_subtract(src, dst, H, W, pitch, dtype, op == MORPH_OP_TOPHAT, stream);
     return e == hipSuccess ? MORPH_OK : hip_fail(e);

@@ -73,9 +73,27 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
 // Word 3 of a raw (untyped, unswizzled) buffer resource on gfx9-family GPUs.
 constexpr int kBufferWord3 = 0x00020000;
 __device__ __forceinline__ uint32_t load_u32(uintptr_t a) { return *(const GLOBAL uint32_t *)a; }
-__device__ __forceinline__ void store_u32(uintptr_t a, uint32_t v) { *(GLOBAL uint32_t *)a = v; }
-__device__ __forceinline__ void store_u8(uintptr_t a, uint8_t v) { *(GLOBAL uint8_t *)a = v; }
-__device__ __forceinline__ void store_u16(uintptr_t a, uint16_t v) { *(GLOBAL uint16_t *)a = v; }
+// Single images' output pixels are written once and not read again by the launch:
+// their stores are non-temporal (NTS), which leaves L2 to the input rows (4096x4096
+// uint8 3x3 11.8 -> 9.6 us).  Batches keep plain stores (non-temporal ones made the
+// 512-image batch 6% slower).  kStoreCpol: the non-temporal bit of a buffer store's
+// cache-policy operand.
+constexpr int kStoreCpol = 2;
+template <bool NTS = true> __device__ __forceinline__ void store_u32(uintptr_t a, uint32_t v)
+{
+    if constexpr (NTS) __builtin_nontemporal_store(v, (GLOBAL uint32_t *)a);
+    else *(GLOBAL uint32_t *)a = v;
+}
+template <bool NTS = true> __device__ __forceinline__ void store_u8(uintptr_t a, uint8_t v)
+{
+    if constexpr (NTS) __builtin_nontemporal_store(v, (GLOBAL uint8_t *)a);
+    else *(GLOBAL uint8_t *)a = v;
+}
+template <bool NTS = true> __device__ __forceinline__ void store_u16(uintptr_t a, uint16_t v)
+{
+    if constexpr (NTS) __builtin_nontemporal_store(v, (GLOBAL uint16_t *)a);
+    else *(GLOBAL uint16_t *)a = v;
+}
 
 // Replace the 16-bit lanes of pixels outside [0, W) by the identity.
 __device__ __forceinline__ void mask_quad(int gx, int W, uint32_t id, uint32_t &p01,
@@ -117,17 +135,18 @@ template <> struct Px<uint8_t> {
         if (!inside) mask_quad(gx, W, id, p01, p23);
     }
     // Store pixels gx .. gx+3 (gx >= 0) of which those < W are written.
+    template <bool NTS = true>
     static __device__ __forceinline__ void store(uint8_t *row, int gx, int W, uint32_t p01,
                                                  uint32_t p23)
     {
         const uintptr_t ba = (uintptr_t)row + gx;
         const uint32_t d = perm(p23, p01, SEL_NARROW);
         if (gx + 4 <= W && (ba & 3u) == 0) {
-            store_u32(ba, d);
+            store_u32<NTS>(ba, d);
         } else {
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                if (gx + j < W) store_u8(ba + j, (uint8_t)(d >> (8 * j)));
+                if (gx + j < W) store_u8<NTS>(ba + j, (uint8_t)(d >> (8 * j)));
         }
     }
 };
@@ -154,21 +173,33 @@ template <> struct Px<uint16_t> {
         }
         if (!inside) mask_quad(gx, W, id, p01, p23);
     }
+    template <bool NTS = true>
     static __device__ __forceinline__ void store(uint8_t *row, int gx, int W, uint32_t p01,
                                                  uint32_t p23)
     {
         const uintptr_t ba = (uintptr_t)row + 2 * (uintptr_t)gx;
         if (gx + 4 <= W && (ba & 3u) == 0) {
-            store_u32(ba, p01);
-            store_u32(ba + 4, p23);
+            store_u32<NTS>(ba, p01);
+            store_u32<NTS>(ba + 4, p23);
         } else {
             const uint32_t v[2] = {p01, p23};
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                if (gx + j < W) store_u16(ba + 2 * j, (uint16_t)(v[j >> 1] >> (16 * (j & 1))));
+                if (gx + j < W) store_u16<NTS>(ba + 2 * j, (uint16_t)(v[j >> 1] >> (16 * (j & 1))));
         }
     }
 };
+
+// A buffer store of the destination, non-temporal or plain (the cache-policy operand
+// is an immediate).  (The policy is a template argument throughout: a run-time choice
+// between two otherwise identical stores is merged by the compiler into one plain
+// store.)
+template <bool NTS>
+__device__ __forceinline__ void buffer_store_nt(uint32_t v, __amdgpu_buffer_rsrc_t rs, int voff,
+                                                int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(v, rs, voff, soff, NTS ? kStoreCpol : 0);
+}
 
 // One tile row of four columns into the row-pair LDS layout (16-bit stores, so two
 // work units may fill the two halves of the same dwords).
@@ -1525,7 +1556,7 @@ static_assert(kDirectMaxTall == 31, "tall vertical windows compiled");
 // so fewer waves fit a SIMD; a kernel of its own); else 1 .. kDirectMax.
 // XV: the horizontal pass is the cross-lane vHGW (wx <= kStreamMaxWx; a kernel of its
 // own, for single images whose plan asks for it).
-template <typename T, bool MAXOP, bool AL, bool TALL = false, bool XV = false>
+template <typename T, bool MAXOP, bool AL, bool TALL = false, bool XV = false, bool NTS = true>
 __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
 {
     constexpr int RING = ring_rows<TALL>();
@@ -1608,10 +1639,11 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
                 for (int m = 0; m < KR; m++) {
                     if (y + m < y1) {
                         if constexpr (sizeof(T) == 1) {
-                            store_u32((uintptr_t)(drow + o), perm(v23[m], v01[m], SEL_NARROW));
+                            store_u32<NTS>((uintptr_t)(drow + o),
+                                           perm(v23[m], v01[m], SEL_NARROW));
                         } else {
-                            store_u32((uintptr_t)(drow + o), v01[m]);
-                            store_u32((uintptr_t)(drow + o + 4), v23[m]);
+                            store_u32<NTS>((uintptr_t)(drow + o), v01[m]);
+                            store_u32<NTS>((uintptr_t)(drow + o + 4), v23[m]);
                         }
                     }
                     drow += J.dpitch;
@@ -1619,7 +1651,7 @@ __device__ __forceinline__ void wave_body(const TileJob &J, int unit)
             } else {
 #pragma unroll
                 for (int m = 0; m < KR; m++) {
-                    if (y + m < y1) Px<T>::store(drow, 4 * Q, J.W, v01[m], v23[m]);
+                    if (y + m < y1) Px<T>::template store<NTS>(drow, 4 * Q, J.W, v01[m], v23[m]);
                     drow += J.dpitch;
                 }
             }
@@ -1899,7 +1931,7 @@ __device__ __forceinline__ void final16_u16(const uint32_t *e, uint32_t *row, ui
                            __builtin_amdgcn_alignbit(b[j + 1], b[j], sh1));
 }
 
-template <typename T, bool MAXOP, bool AL>
+template <typename T, bool MAXOP, bool AL, bool NTS = true>
 __device__ __forceinline__ void rows_body(const TileJob &J, int unit, uint32_t *lds)
 {
     constexpr int RG = rows_group<T>();
@@ -1982,17 +2014,18 @@ __device__ __forceinline__ void rows_body(const TileJob &J, int unit, uint32_t *
                 if (fast_store) {
                     const uintptr_t a = (uintptr_t)(drow + ES * xo);
 #pragma unroll
-                    for (int j = 0; j < 4 * ES; j++) store_u32(a + 4 * j, o[j]);
+                    for (int j = 0; j < 4 * ES; j++) store_u32<NTS>(a + 4 * j, o[j]);
                 } else if constexpr (sizeof(T) == 1) {
 #pragma unroll
                     for (int j = 0; j < 16; j++)
                         if (xo + j < J.W)
-                            store_u8((uintptr_t)(drow + xo + j), (uint8_t)(o[j >> 2] >> (8 * (j & 3))));
+                            store_u8<NTS>((uintptr_t)(drow + xo + j),
+                                          (uint8_t)(o[j >> 2] >> (8 * (j & 3))));
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; q++)
                         if (xo + 4 * q < J.W)
-                            Px<T>::store(drow, xo + 4 * q, J.W, o[2 * q], o[2 * q + 1]);
+                            Px<T>::template store<NTS>(drow, xo + 4 * q, J.W, o[2 * q], o[2 * q + 1]);
                 }
             }
         }
@@ -2183,7 +2216,7 @@ template <> struct RunTable<uint16_t> {
 // keeps 2 stream_runs(wy) + 1 small LDS entries instead of a ring of wy rows, at the
 // price of a second (cached) load of every row: a win where the ring's LDS would
 // limit the waves resident per CU.
-template <typename T, bool MAXOP, bool AL, bool RUNS, bool XV = false>
+template <typename T, bool MAXOP, bool AL, bool RUNS, bool XV = false, bool NTS = true>
 __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t *lds)
 {
     const int lane = threadIdx.x & 63;
@@ -2366,13 +2399,11 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
                     for (int k = 0; k < SD; k++, so += (uint32_t)J.dpitch) {
                         if (full || k < cnt) {
                             if constexpr (sizeof(T) == 1) {
-                                __builtin_amdgcn_raw_buffer_store_b32(
-                                    perm(o23[k], o01[k], SEL_NARROW), drs, (int)dvoff, (int)so, 0);
+                                buffer_store_nt<NTS>(perm(o23[k], o01[k], SEL_NARROW), drs,
+                                                (int)dvoff, (int)so);
                             } else {
-                                __builtin_amdgcn_raw_buffer_store_b32(o01[k], drs, (int)dvoff,
-                                                                      (int)so, 0);
-                                __builtin_amdgcn_raw_buffer_store_b32(o23[k], drs, (int)dvoff + 4,
-                                                                      (int)so, 0);
+                                buffer_store_nt<NTS>(o01[k], drs, (int)dvoff, (int)so);
+                                buffer_store_nt<NTS>(o23[k], drs, (int)dvoff + 4, (int)so);
                             }
                         }
                     }
@@ -2380,7 +2411,7 @@ __device__ __forceinline__ void stream_body(const TileJob &J, int unit, uint32_t
 #pragma unroll
                     for (int k = 0; k < SD; k++)
                         if (k < cnt)
-                            Px<T>::store(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W, o01[k],
+                            Px<T>::template store<NTS>(J.dst + (int64_t)(y + k) * J.dpitch, 4 * Q, J.W, o01[k],
                                          o23[k]);
                 }
             }
@@ -2450,14 +2481,14 @@ __global__ __launch_bounds__(64) void batch_fused_kernel(FusedTables ft)
     const TileJob J = bt.jobs[jb];
     const int u = (int)(t - bt.tile_start[jb]);
     if (c == 0) {
-        if (J.op) stream_body<T, true, AL, true>(J, u, lds);
-        else stream_body<T, false, AL, true>(J, u, lds);
+        if (J.op) stream_body<T, true, AL, true, false, false>(J, u, lds);
+        else stream_body<T, false, AL, true, false, false>(J, u, lds);
     } else if (c == 1) {
-        if (J.op) stream_body<T, true, AL, false>(J, u, lds);
-        else stream_body<T, false, AL, false>(J, u, lds);
+        if (J.op) stream_body<T, true, AL, false, false, false>(J, u, lds);
+        else stream_body<T, false, AL, false, false, false>(J, u, lds);
     } else {
-        if (J.op) wave_body<T, true, AL>(J, u);
-        else wave_body<T, false, AL>(J, u);
+        if (J.op) wave_body<T, true, AL, false, false, false>(J, u);
+        else wave_body<T, false, AL, false, false, false>(J, u);
     }
 }
 

@@ -72,6 +72,8 @@ struct TileJob {
     int32_t op;      // 0 erode, 1 dilate
     int32_t dtype;   // 0 u8, 1 u16
     int32_t coop;    // KIND_STREAM: 0, or the cooperative form's waves a unit (4, 8, 16)
+    int32_t keep;    // 1: a later launch of the same call reads dst (an intermediate), so
+                     // single-image kernels store it plainly, else non-temporally
 };
 
 // the streaming kernel's cooperative form (k_stream_coop.hip): rows
