@@ -15,6 +15,20 @@
 // checks.  One read and one write of every element, 2 sizeof(T) bytes a pixel.
 #include "morph_internal.h"
 
+// The destination is written once and not read again by the launch: non-temporal
+// stores keep it from displacing the source rows other workgroups still read from L2.
+typedef uint32_t tr_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void tr_store16(uint8_t *q, uint32_t a, uint32_t b, uint32_t c,
+                                           uint32_t d)
+{
+    const tr_u32x4 v = {a, b, c, d};
+    __builtin_nontemporal_store(v, reinterpret_cast<tr_u32x4 *>(q));
+}
+__device__ __forceinline__ void tr_store4(uint8_t *q, uint32_t v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<uint32_t *>(q));
+}
+
 namespace morph {
 namespace {
 
@@ -131,7 +145,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(const uint8_t *__restric
         const int orow = x0 + row;
         if (full) {
             uint8_t *q = dst + (int64_t)orow * dpitch + (int64_t)y0 * es + 16 * s;
-            *reinterpret_cast<uint4 *>(q) = make_uint4(a.x, a.y, b.x, b.y);
+            tr_store16(q, a.x, a.y, b.x, b.y);
         } else if (orow < W) {
             const uint32_t d[4] = {a.x, a.y, b.x, b.y};
             T *q = reinterpret_cast<T *>(dst + (int64_t)orow * dpitch);
@@ -162,7 +176,7 @@ __global__ __launch_bounds__(256) void transpose_blocks_u8_kernel(const uint8_t 
     for (int k = 0; k < 4; k++) in[k] = *reinterpret_cast<const uint32_t *>(p + (4 * qy + k) * 16 + 4 * qx);
     transpose4x4_u8(in, o);
 #pragma unroll
-    for (int c = 0; c < 4; c++) *reinterpret_cast<uint32_t *>(q + (4 * qx + c) * 16 + 4 * qy) = o[c];
+    for (int c = 0; c < 4; c++) tr_store4(q + (4 * qx + c) * 16 + 4 * qy, o[c]);
 }
 
 __global__ __launch_bounds__(256) void transpose_blocks_u16_kernel(const uint8_t *__restrict__ src,
@@ -178,8 +192,8 @@ __global__ __launch_bounds__(256) void transpose_blocks_u16_kernel(const uint8_t
     uint8_t *q = dst + blk * 128;
     const uint32_t a = *reinterpret_cast<const uint32_t *>(p + (2 * qy) * 16 + 4 * qx);
     const uint32_t b = *reinterpret_cast<const uint32_t *>(p + (2 * qy + 1) * 16 + 4 * qx);
-    *reinterpret_cast<uint32_t *>(q + (2 * qx) * 16 + 4 * qy) = (a & 0xffffu) | (b << 16);
-    *reinterpret_cast<uint32_t *>(q + (2 * qx + 1) * 16 + 4 * qy) = (a >> 16) | (b & 0xffff0000u);
+    tr_store4(q + (2 * qx) * 16 + 4 * qy, (a & 0xffffu) | (b << 16));
+    tr_store4(q + (2 * qx + 1) * 16 + 4 * qy, (a >> 16) | (b & 0xffff0000u));
 }
 
 } // namespace
